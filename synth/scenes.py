@@ -1,0 +1,180 @@
+"""Seeded synthetic scenes: the input data every run of the transport consumes.
+
+This module builds density grids, source and dust parameters and observer
+lists.  It holds none of the transport arithmetic (no point generation, no
+traversal, no scattering): it only samples analytic density laws at cell
+centres and scales them to a requested optical depth.  Both the CPU oracle
+and the GPU library take its output as plain arrays.
+
+Geometry and dust follow the paper's test problems (Sec. 5 flared disk,
+Eq. of the flared disk; Sec. 5 dust envelope; Sec. 7 sphere source), re-scaled
+to a unit box because the paper's au-scale parameters and grid resolutions are
+not reproducible here.  Readings:
+
+* density is sampled at cell centres (the paper only says densities are
+  precomputed on the mesh, Sec. 3.4);
+* the extinction scale is fixed by requiring that the grid optical depth
+  along the +x ray from the source equals the target.  With an even cell
+  count that ray runs along the y=z=0 cell faces, and the floor rule used by
+  the traversal puts it in the row j=k=n/2, so the normalisation sums that row.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+# sequence kinds (shared numbering of the C-ABI and of the oracle front end)
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX = 0, 1, 2, 3, 4
+KIND_NAMES = {SOBOL: "sobol", HALTON: "halton", NIEDERREITER2: "niederreiter2",
+              HAMMERSLEY: "hammersley", PHILOX: "philox"}
+KIND_BY_NAME = {v: k for k, v in KIND_NAMES.items()}
+
+POINT_SOURCE, SPHERE_SOURCE = 0, 1
+
+
+@dataclasses.dataclass
+class Scene:
+    name: str
+    n: Tuple[int, int, int]            # (nx, ny, nz)
+    lo: Tuple[float, float, float]
+    hi: Tuple[float, float, float]
+    kappa_rho: np.ndarray              # float32 [nz][ny][nx], x fastest
+    source: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    source_kind: int = POINT_SOURCE
+    r_star: float = 0.0
+    albedo: float = 0.6
+    g: float = 0.5
+    p_lin: float = 0.5
+    observers: List[Tuple[float, float]] = dataclasses.field(default_factory=list)  # (theta, phi) rad
+    npix: int = 64
+    half_width: float = 1.0
+    max_orders: int = 1
+    tau_min: float = 1e-8
+    fp64: bool = True
+    n_packets: int = 1 << 16
+
+    @property
+    def dims(self) -> int:
+        """Point dimension: 3 per flight, 2 more for a sphere-star emission point (Sec. 3.7)."""
+        base = 5 if self.source_kind == SPHERE_SOURCE else 3
+        return base + 3 * (self.max_orders - 1)
+
+    def replace(self, **kw) -> "Scene":
+        return dataclasses.replace(self, **kw)
+
+
+def cell_centres(n: int, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
+    h = (hi - lo) / n
+    return lo + (np.arange(n, dtype=np.float64) + 0.5) * h
+
+
+def _mesh(n: int):
+    c = cell_centres(n)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    return x, y, z
+
+
+def _scale_to_x_ray(rho: np.ndarray, target_tau: float) -> np.ndarray:
+    """Scale rho so that the sum of rho*h over row j=k=n/2, i>=n/2 equals target_tau."""
+    n = rho.shape[0]
+    h = 2.0 / n
+    row = rho[n // 2, n // 2, n // 2:]
+    s = float(np.sum(row.astype(np.float64)) * h)
+    if s <= 0.0:
+        raise ValueError("density is zero along the normalisation ray")
+    return rho * (target_tau / s)
+
+
+def envelope32(n_packets: int = 1 << 16) -> Scene:
+    """Spherical envelope rho ~ r^-2 on 0.05<r<1, 32^3 grid, radial tau 1, one observer at 45 deg."""
+    n = 32
+    x, y, z = _mesh(n)
+    r = np.sqrt(x * x + y * y + z * z)
+    rho = np.where((r > 0.05) & (r < 1.0), 1.0 / np.maximum(r, 1e-30) ** 2, 0.0)
+    kr = _scale_to_x_ray(rho, 1.0).astype(np.float32)
+    return Scene(name="envelope32", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+                 albedo=0.6, g=0.5, p_lin=0.5, observers=[(math.radians(45.0), 0.0)],
+                 npix=64, half_width=1.0, max_orders=1, fp64=True, n_packets=n_packets)
+
+
+def disk_density(n: int) -> np.ndarray:
+    """Flared disk rho ~ (R/R0)^-2.25 exp(-z^2/2h^2), h = 0.1 R^1.125, R0 = 1, 0.05<=R<=1."""
+    x, y, z = _mesh(n)
+    R = np.sqrt(x * x + y * y)
+    Rs = np.maximum(R, 1e-30)
+    hR = 0.1 * Rs ** 1.125
+    rho = Rs ** -2.25 * np.exp(-0.5 * (z / hR) ** 2)
+    return np.where((R >= 0.05) & (R <= 1.0), rho, 0.0)
+
+
+def disk128(n_packets: int = 1 << 22, n: int = 128) -> Scene:
+    """Flared disk, midplane tau 10, 20 orders, three inclinations, 256^2 images, FP32 transport."""
+    kr = _scale_to_x_ray(disk_density(n), 10.0).astype(np.float32)
+    obs = [(math.radians(t), 0.0) for t in (0.0, 45.0, 90.0)]
+    return Scene(name=f"disk{n}", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+                 albedo=0.5, g=0.6, p_lin=0.5, observers=obs, npix=256, half_width=1.0,
+                 max_orders=20, fp64=False, n_packets=n_packets)
+
+
+def lognormal_field(n: int, sigma: float, corr_voxels: float, seed: int) -> np.ndarray:
+    """exp(sigma*G - sigma^2/2) of a periodic Gaussian random field G (zero mean, unit variance)
+    whose correlation is exp(-r^2 / (2 corr^2)) in voxel units."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal((n, n, n))
+    d = np.minimum(np.arange(n), n - np.arange(n)).astype(np.float64)
+    d2 = d[:, None, None] ** 2 + d[None, :, None] ** 2 + d[None, None, :] ** 2
+    kern = np.exp(-d2 / (2.0 * corr_voxels ** 2))
+    P = np.fft.rfftn(kern).real
+    np.maximum(P, 0.0, out=P)
+    G = np.fft.irfftn(np.sqrt(P) * np.fft.rfftn(w), s=(n, n, n))
+    G -= G.mean()
+    G /= G.std()
+    return np.exp(sigma * G - 0.5 * sigma * sigma)
+
+
+def clumpy256(n_packets: int = 1 << 24, n: int = 256, seed: int = 1556) -> Scene:
+    """Clumpy envelope rho ~ r^-1.5 * lognormal(sigma=1, 8-voxel correlation), sphere star r*=0.02."""
+    x, y, z = _mesh(n)
+    r = np.sqrt(x * x + y * y + z * z)
+    base = np.where((r >= 0.05) & (r <= 1.0), np.maximum(r, 1e-30) ** -1.5, 0.0)
+    del x, y, z, r
+    rho = base * lognormal_field(n, 1.0, 8.0 * n / 256.0, seed)
+    kr = _scale_to_x_ray(rho, 3.0).astype(np.float32)
+    return Scene(name=f"clumpy{n}", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+                 source_kind=SPHERE_SOURCE, r_star=0.02, albedo=0.6, g=0.4, p_lin=0.5,
+                 observers=[(math.radians(60.0), 0.0)], npix=512, half_width=1.0,
+                 max_orders=1, fp64=False, n_packets=n_packets)
+
+
+def thin_sphere(n: int = 64, R: float = 0.9, tau_R: float = 0.01, npix: int = 64) -> Scene:
+    """Homogeneous sphere of radius R (cells whose centre lies inside), radial tau tau_R."""
+    x, y, z = _mesh(n)
+    r = np.sqrt(x * x + y * y + z * z)
+    rho = np.where(r <= R, 1.0, 0.0)
+    kr = _scale_to_x_ray(rho, tau_R).astype(np.float32)
+    return Scene(name=f"thin_sphere{n}", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+                 albedo=0.6, g=0.5, p_lin=0.5, observers=[(math.radians(45.0), 0.0)],
+                 npix=npix, half_width=1.0, max_orders=1, fp64=True)
+
+
+def uniform_cube(n: int, value: float) -> np.ndarray:
+    return np.full((n, n, n), value, dtype=np.float32)
+
+
+def random_grid(shape: Tuple[int, int, int], seed: int, zero_frac: float = 0.2) -> np.ndarray:
+    """Random positive cells with a share of empty ones; shape is (nz, ny, nx)."""
+    rng = np.random.default_rng(seed)
+    g = rng.uniform(0.1, 3.0, size=shape)
+    g[rng.uniform(size=shape) < zero_frac] = 0.0
+    return g.astype(np.float32)
+
+
+def scene_by_name(name: str, n_packets: Optional[int] = None) -> Scene:
+    table = {"envelope32": envelope32, "disk128": disk128, "clumpy256": clumpy256}
+    sc = table[name]()
+    if n_packets is not None:
+        sc = sc.replace(n_packets=n_packets)
+    return sc

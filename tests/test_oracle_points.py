@@ -1,0 +1,172 @@
+"""Pins of the oracle's point sets (Sec. 3.1) against definitions outside the oracle:
+scipy's unscrambled Sobol and Halton generators, exact rational radical inverses,
+numpy's Philox4x64-10, and brute-force (t,m,s)-net counts."""
+import itertools
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import tables
+
+
+def _scipy_sobol(dims, first, count):
+    from scipy.stats import qmc
+    eng = qmc.Sobol(dims, scramble=False, bits=32)
+    eng.fast_forward(first)
+    x = eng.random(count)
+    return np.round(x * 2.0 ** 32).astype(np.uint64).astype(np.uint32)
+
+
+@pytest.mark.parametrize("first,count", [(1, 4096), ((1 << 16) - 5, 16), ((1 << 20) - 3, 8)])
+def test_sobol_matches_scipy(first, count):
+    dims = 60
+    ours = O.points(O.SOBOL, dims, first, count)
+    ref = _scipy_sobol(dims, first, count)
+    assert np.array_equal(ours, ref)
+
+
+def test_sobol_high_columns_follow_scipy():
+    # columns beyond the ones read from scipy come from the recurrence; check one
+    # of them against scipy directly (point with Gray code 2^24 sits at index 2^25-1)
+    V = tables.sobol_columns(60)
+    ref = _scipy_sobol(60, (1 << 25) - 1, 1)[0]
+    assert np.array_equal(V[:, 24], ref)
+
+
+@pytest.mark.parametrize("kind", [O.SOBOL, O.NIEDERREITER2])
+def test_generator_matrix_is_unit_upper_triangular(kind):
+    # column b has its lowest set bit at 31-b: the 1-D projections are (0,m,1)-nets
+    mat, _ = O.seq_tables(kind, 60)
+    for d in range(60):
+        for b in range(32):
+            v = int(mat[d, b])
+            assert (v >> (31 - b)) & 1 == 1
+            assert v & ((1 << (31 - b)) - 1) == 0
+
+
+def _net_counts_ok(pts, m, t, dims):
+    """Every elementary box of volume 2^(t-m) holds exactly 2^t of the 2^m points."""
+    s = len(dims)
+    for comp in itertools.product(range(m - t + 1), repeat=s):
+        if sum(comp) != m - t:
+            continue
+        key = np.zeros(len(pts), dtype=np.int64)
+        for dd, di in zip(dims, comp):
+            key = (key << di) | (pts[:, dd].astype(np.int64) >> (32 - di) if di else 0)
+        counts = np.bincount(key, minlength=1 << (m - t))
+        if not np.all(counts == (1 << t)):
+            return False
+    return True
+
+
+def _first_pts(kind, dims, m):
+    # index 0 (the origin) plus indices 1 .. 2^m-1
+    body = O.points(kind, dims, 1, (1 << m) - 1)
+    return np.vstack([np.zeros((1, dims), dtype=np.uint32), body])
+
+
+@pytest.mark.parametrize("m", [4, 8, 12, 16])
+def test_sobol_nets(m):
+    pts = _first_pts(O.SOBOL, 8, m)
+    for d in range(8):
+        assert _net_counts_ok(pts, m, 0, [d])
+    assert _net_counts_ok(pts, m, 0, [0, 1])
+
+
+@pytest.mark.parametrize("m", [6, 9, 12])
+def test_niederreiter_nets(m):
+    polys = tables.irreducible_polys(4)
+    degs = [p.bit_length() - 1 for p in polys]
+    assert degs == [1, 1, 2, 3]
+    pts = _first_pts(O.NIEDERREITER2, 4, m)
+    for d in range(4):
+        assert _net_counts_ok(pts, m, 0, [d])
+    for s in range(2, 5):
+        t = sum(e - 1 for e in degs[:s])
+        assert _net_counts_ok(pts, m, t, list(range(s)))
+
+
+def test_niederreiter_first_two_dims_equal_sobol():
+    a = O.points(O.NIEDERREITER2, 2, 1, 5000)
+    b = O.points(O.SOBOL, 2, 1, 5000)
+    assert np.array_equal(a, b)
+
+
+def test_niederreiter_planted_mistake_breaks_net():
+    # a transposed matrix (a plausible bug) must fail the (t,m,s) check
+    cols = tables.niederreiter_columns(4).copy()
+    bits = np.array([[(int(cols[d, r]) >> (31 - j)) & 1 for r in range(32)] for d in range(4) for j in range(32)])
+    bits = bits.reshape(4, 32, 32).transpose(0, 2, 1)
+    bad = np.array([[sum(int(bits[d, j, r]) << (31 - j) for j in range(32)) for r in range(32)] for d in range(4)],
+                   dtype=np.uint32)
+    m = 10
+    idx = np.arange(1 << m, dtype=np.uint64)
+    gray = idx ^ (idx >> np.uint64(1))
+    pts = np.zeros((1 << m, 4), dtype=np.uint32)
+    for d in range(4):
+        for r in range(m):
+            sel = ((gray >> np.uint64(r)) & np.uint64(1)).astype(bool)
+            pts[sel, d] ^= bad[d, r]
+    assert not _net_counts_ok(pts, m, 3, [0, 1, 2, 3])
+
+
+def _radical_inverse_exact(i, b):
+    f, w = Fraction(0), Fraction(1, b)
+    while i:
+        f += (i % b) * w
+        i //= b
+        w /= b
+    return f
+
+
+@pytest.mark.parametrize("first", [1, 1000, (1 << 24) - 3, (1 << 32) - 6])
+def test_halton_exact_rationals(first):
+    dims = 60
+    ours = O.points(O.HALTON, dims, first, 5)
+    pr = tables.primes(dims)
+    for j in range(5):
+        for d in range(dims):
+            ref = int(_radical_inverse_exact(first + j, int(pr[d])) * (1 << 32))
+            assert int(ours[j, d]) == ref
+
+
+def test_halton_close_to_scipy():
+    from scipy.stats import qmc
+    dims = 20
+    x = qmc.Halton(dims, scramble=False).random(2001)[1:]
+    ours = O.points(O.HALTON, dims, 1, 2000).astype(np.float64) / 2.0 ** 32
+    assert np.max(np.abs(ours - x)) <= 2.0 ** -32 + 1e-15
+
+
+def test_hammersley_definition():
+    N = 3000
+    pts = O.points(O.HAMMERSLEY, 4, 1, N, n_total=N)
+    i = np.arange(1, N + 1, dtype=np.uint64)
+    dim0 = ((i << np.uint64(32)) // np.uint64(N)) & np.uint64(0xFFFFFFFF)
+    assert np.array_equal(pts[:, 0].astype(np.uint64), dim0)
+    # i/N exactly for a power-of-two N
+    N2 = 1 << 12
+    p2 = O.points(O.HAMMERSLEY, 2, 1, N2, n_total=N2)
+    assert np.array_equal(p2[:-1, 0].astype(np.uint64), np.arange(1, N2, dtype=np.uint64) << np.uint64(20))
+    assert p2[-1, 0] == 0
+    hal = O.points(O.HALTON, 3, 1, N)
+    assert np.array_equal(pts[:, 1:], hal)
+
+
+@pytest.mark.parametrize("seed", [0, 12345, 2 ** 63 + 7])
+def test_philox_matches_numpy(seed):
+    dims = 20
+    first = 7
+    ours = O.points(O.PHILOX, dims, first, 6, seed=seed)
+    for j in range(6):
+        i = first + j
+        for blk in range((dims + 7) // 8):
+            ctr = i | (blk << 64)
+            words = np.random.Philox(key=seed, counter=ctr - 1).random_raw(4)
+            w32 = []
+            for w in words:
+                w32 += [int(w) & 0xFFFFFFFF, int(w) >> 32]
+            for d in range(blk * 8, min(dims, blk * 8 + 8)):
+                assert int(ours[j, d]) == w32[d & 7]
