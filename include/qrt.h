@@ -1,0 +1,175 @@
+/*
+ * qrt.h -- C ABI of the MI355X quasi-Monte Carlo radiative-transfer library.
+ *
+ * The library transports photon packets of dust-continuum radiation through a
+ * Cartesian density mesh and images the scattered light, as in S. G. Shulman,
+ * "Quasi-Monte Carlo Radiative Transfer" (Astronomy and Computing).  Every
+ * packet is driven by one point of a low-discrepancy sequence (Sobol,
+ * Niederreiter base 2, Halton, Hammersley) or of a counter-based PRNG for the
+ * Monte Carlo baseline (Sec. 3.1, Sec. 3.7).  One packet goes through
+ * emission (Sec. 3.2, 3.3), optical depth to the mesh edge with a forced first
+ * scattering (Sec. 3.2), moves by optical depth on the mesh (Sec. 3.4),
+ * peel-off toward each observer before each scattering (Sec. 3.5, 3.6) and
+ * Henyey-Greenstein scattering with White's Mueller matrix (Sec. 2.2, 3.5).
+ *
+ * Conventions shared by all calls
+ *  - Every call returns QRT_OK (0) or a negative status; qrt_last_error()
+ *    gives a message, valid until the next call on the same context.
+ *  - No C++ exception crosses this interface.
+ *  - Host pointers are owned by the caller and only read or written during
+ *    the call.  Device pointers are HIP device addresses on the context's
+ *    device; a borrowed device grid must outlive every run that uses it.
+ *  - All GPU work goes to the context's HIP stream, in order.  Calls that
+ *    return host data synchronise that stream; the others only enqueue work.
+ *  - One context per host thread; a context is not thread safe.
+ *  - Packet indices are global and start at 1: the all-zero first point of
+ *    every low-discrepancy sequence is skipped (Sec. 3.1).  Runs over disjoint
+ *    index ranges add up, so a long run may be split into chunks and resumed.
+ *  - Images are in units of the source luminosity and hold scattered light
+ *    only (Sec. 3.4, 3.6).
+ */
+#ifndef QRT_H
+#define QRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define QRT_OK 0
+#define QRT_INVALID_ARG (-1)     /* a pointer, size or value is out of range */
+#define QRT_BAD_STATE (-2)       /* e.g. a run before the grid is set */
+#define QRT_HIP_ERROR (-3)       /* a HIP call failed; the message has hipGetErrorString */
+#define QRT_OUT_OF_MEMORY (-4)
+#define QRT_UNSUPPORTED (-5)     /* too many dimensions, Hammersley index beyond N, ... */
+#define QRT_NOT_TRAINED (-6)     /* surrogate peel-off requested without a trained network */
+
+/* point sets (Sec. 3.1) */
+#define QRT_SOBOL 0
+#define QRT_HALTON 1
+#define QRT_NIEDERREITER2 2
+#define QRT_HAMMERSLEY 3
+#define QRT_PHILOX 4
+
+/* grid ownership flags for qrt_set_grid */
+#define QRT_GRID_HOST_COPY 0      /* kappa_rho is a host pointer; copied */
+#define QRT_GRID_DEVICE_COPY 1    /* kappa_rho is a device pointer; copied */
+#define QRT_GRID_DEVICE_BORROW 2  /* kappa_rho is a device pointer; used in place */
+
+/* arithmetic of the transport */
+#define QRT_FP32 0                /* FP32 positions/directions/weights, FP64 optical depth and image sums */
+#define QRT_FP64 1                /* FP64 throughout */
+
+/* peel-off optical depth */
+#define QRT_PEEL_EXACT 0          /* exact mesh traversal toward the observer */
+#define QRT_PEEL_SURROGATE 1      /* trained network inside its validated domain, exact elsewhere */
+
+/* sphere-star emission order (Sec. 3.3) */
+#define QRT_EMIT_DIRECT 0
+
+#define QRT_MAX_DIMS 128          /* largest point dimension served */
+#define QRT_MAX_OBSERVERS 16
+
+typedef struct qrt_ctx qrt_ctx;
+
+/* Exact event counts accumulated over runs since the last reset. */
+typedef struct {
+    int64_t packets;      /* packets started */
+    int64_t visits;       /* mesh cells entered by every traversal (Sec. 3.4) */
+    int64_t peels;        /* peel-off contributions binned into an image */
+    int64_t peel_rays;    /* peel-off traversals toward observers */
+    int64_t escapes;      /* packets that left the mesh during a free flight */
+    int64_t tau_cuts;     /* packets ended because tau1 < tau_min (Sec. 3.2) */
+    int64_t scatterings;  /* scattering events (each is followed by its peel-offs) */
+    int64_t occluded;     /* peel-off rays blocked by a sphere star */
+    int64_t surrogate;    /* peel-off optical depths taken from the network */
+    int64_t fallbacks;    /* surrogate requests answered by exact traversal */
+} qrt_counters;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+   (a hipStream_t; NULL selects the null stream).  *out is NULL on failure. */
+int qrt_create(qrt_ctx **out, int device, void *hip_stream);
+
+/* Release the context and all library-owned device memory.  NULL is a no-op. */
+void qrt_destroy(qrt_ctx *ctx);
+
+/* Message of the last failing call on ctx (never NULL). */
+const char *qrt_last_error(const qrt_ctx *ctx);
+
+/* Change the stream later calls enqueue on. */
+int qrt_set_stream(qrt_ctx *ctx, void *hip_stream);
+
+/* Density mesh (Sec. 2.1, 3.4): nx*ny*nz cells over the box [lo, hi]; each cell
+   holds the constant extinction kappa*rho (FP32), laid out [nz][ny][nx] with x
+   fastest.  flags is one of QRT_GRID_*.  Cells must be finite and >= 0. */
+int qrt_set_grid(qrt_ctx *ctx, int nx, int ny, int nz, const double lo[3], const double hi[3],
+                 const float *kappa_rho, int flags);
+
+/* Isotropic point source at (x, y, z), which must lie inside the box (Sec. 3.2). */
+int qrt_set_point_source(qrt_ctx *ctx, double x, double y, double z);
+
+/* Uniform-brightness spherical star of the given radius centred at (x, y, z)
+   (Sec. 3.3); order must be QRT_EMIT_DIRECT.  The star blocks peel-off rays
+   that pass through it. */
+int qrt_set_sphere_source(qrt_ctx *ctx, double x, double y, double z, double radius, int order);
+
+/* Dust (Sec. 2.1-2.3): albedo in [0,1], HG asymmetry |g| < 1, maximum linear
+   polarisation p_lin in [0,1]; p_circ must be 0 (circular polarisation unused). */
+int qrt_set_dust(qrt_ctx *ctx, double albedo, double g, double p_lin, double p_circ);
+
+/* Observers at infinity in directions (theta[i], phi[i]) (radians, Sec. 3.6),
+   1 <= n_obs <= QRT_MAX_OBSERVERS.  Each image is npix x npix pixels covering
+   [-half_width, half_width]^2 in image axes e_x = (-sin phi, cos phi, 0),
+   e_y = o x e_x.  Resets the images. */
+int qrt_set_observers(qrt_ctx *ctx, int n_obs, const double *theta, const double *phi, int npix,
+                      double half_width);
+
+/* Point set (Sec. 3.1): kind QRT_*, seed (PRNG key; ignored by the
+   low-discrepancy kinds) and n_total (Hammersley's N, 1 <= N < 2^32;
+   ignored by the others). */
+int qrt_set_sequence(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total);
+
+/* Transport (Sec. 3.2, 3.5): at most max_orders scatterings (1 .. 42 for a
+   point source), tau_min cut-off of the first flight, precision QRT_FP32 or
+   QRT_FP64, peel_mode QRT_PEEL_EXACT or QRT_PEEL_SURROGATE. */
+int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precision, int peel_mode);
+
+/* Transport packets first_index .. first_index+count-1 (first_index >= 1) and
+   add their contributions to the images.  Asynchronous on the context stream. */
+int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
+
+/* Copy image obs (npix*npix doubles each, [iy][ix]) of Stokes I, Q, U to host
+   buffers (any may be NULL).  normalized = 1 divides by the number of packets
+   run since the last reset.  Synchronises the stream. */
+int qrt_read_images(qrt_ctx *ctx, int obs, double *I, double *Q, double *U, int normalized);
+
+/* Device address of the FP64 image accumulators [n_obs][3][npix][npix]
+   (unnormalised sums), owned by the context. */
+int qrt_image_device_ptr(qrt_ctx *ctx, double **dev_ptr);
+
+/* Zero the images, the packet count and the counters. */
+int qrt_reset_images(qrt_ctx *ctx);
+
+/* Counters accumulated since the last reset.  Synchronises the stream. */
+int qrt_get_counters(qrt_ctx *ctx, qrt_counters *out);
+
+/* Coordinates of points first .. first+count-1, dims each, as unsigned 0.32
+   fixed point, row-major [count][dims] (Sec. 3.1).  out is a device pointer
+   when out_on_device = 1 (then asynchronous), else a host pointer. */
+int qrt_generate_points(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total, uint64_t first,
+                        uint64_t count, int dims, uint32_t *out, int out_on_device);
+
+/* Optical depth from (p[3*i]) along unit (k[3*i]) to the mesh edge for n rays,
+   at the context precision; visits (may be NULL) gets cells entered per ray.
+   All pointers are device pointers; asynchronous (Sec. 3.4). */
+int qrt_trace_tau(qrt_ctx *ctx, int64_t n, const double *p, const double *k, double *tau,
+                  int64_t *visits);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QRT_H */

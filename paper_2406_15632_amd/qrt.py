@@ -1,0 +1,228 @@
+"""Python binding of libqrt (include/qrt.h): argument marshalling only.
+
+Every function of the C ABI is exposed under its own name (qrt_create,
+qrt_run, ...) on the loaded library; the Context class below wraps a context
+with numpy / torch conveniences.  All transport work runs in the HIP kernels of
+libqrt.so: this module never computes any part of the method, and it raises
+if the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqrt.so")
+
+QRT_OK, QRT_INVALID_ARG, QRT_BAD_STATE, QRT_HIP_ERROR = 0, -1, -2, -3
+QRT_OUT_OF_MEMORY, QRT_UNSUPPORTED, QRT_NOT_TRAINED = -4, -5, -6
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX = 0, 1, 2, 3, 4
+GRID_HOST_COPY, GRID_DEVICE_COPY, GRID_DEVICE_BORROW = 0, 1, 2
+FP32, FP64 = 0, 1
+PEEL_EXACT, PEEL_SURROGATE = 0, 1
+EMIT_DIRECT = 0
+MAX_DIMS, MAX_OBSERVERS = 128, 16
+
+
+class qrt_counters(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("packets", "visits", "peels", "peel_rays", "escapes", "tau_cuts",
+                                         "scatterings", "occluded", "surrogate", "fallbacks")]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_P = C.c_void_p
+_D3 = C.POINTER(C.c_double)
+# exported symbol -> (restype, argtypes); the C-ABI surface checked by the tests
+SIGNATURES = {
+    "qrt_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int, _P]),
+    "qrt_destroy": (None, [_P]),
+    "qrt_last_error": (C.c_char_p, [_P]),
+    "qrt_set_stream": (C.c_int, [_P, _P]),
+    "qrt_set_grid": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _D3, _D3, _P, C.c_int]),
+    "qrt_set_point_source": (C.c_int, [_P, C.c_double, C.c_double, C.c_double]),
+    "qrt_set_sphere_source": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int]),
+    "qrt_set_dust": (C.c_int, [_P, C.c_double, C.c_double, C.c_double, C.c_double]),
+    "qrt_set_observers": (C.c_int, [_P, C.c_int, _D3, _D3, C.c_int, C.c_double]),
+    "qrt_set_sequence": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64]),
+    "qrt_set_transport": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.c_int]),
+    "qrt_run": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
+    "qrt_read_images": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
+    "qrt_image_device_ptr": (C.c_int, [_P, C.POINTER(C.c_void_p)]),
+    "qrt_reset_images": (C.c_int, [_P]),
+    "qrt_get_counters": (C.c_int, [_P, C.POINTER(qrt_counters)]),
+    "qrt_generate_points": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
+                                      _P, C.c_int]),
+    "qrt_trace_tau": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+}
+
+_lib: Optional[C.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libqrt.so; raises if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2406_15632_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class QRTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libqrt error {code}: {msg}")
+        self.code = code
+
+
+def _d3(v: Sequence[float]):
+    return (C.c_double * 3)(*[float(x) for x in v])
+
+
+def _current_stream_handle() -> int:
+    import torch
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One library context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.lib = load()
+        if stream is None:
+            stream = _current_stream_handle()
+        h = C.c_void_p()
+        rc = self.lib.qrt_create(C.byref(h), device, C.c_void_p(stream))
+        if rc != QRT_OK:
+            raise QRTError(rc, "qrt_create failed")
+        self.h = h
+        self._keep = []
+
+    def _ck(self, rc: int):
+        if rc != QRT_OK:
+            raise QRTError(rc, self.lib.qrt_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.qrt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -------- configuration
+    def set_stream(self, stream: int):
+        self._ck(self.lib.qrt_set_stream(self.h, C.c_void_p(stream)))
+
+    def set_grid(self, kappa_rho, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0)):
+        """kappa_rho: float32 [nz][ny][nx], a numpy array (copied) or a CUDA torch tensor (borrowed)."""
+        nz, ny, nx = kappa_rho.shape
+        if isinstance(kappa_rho, np.ndarray):
+            a = np.ascontiguousarray(kappa_rho, dtype=np.float32)
+            self._ck(self.lib.qrt_set_grid(self.h, nx, ny, nz, _d3(lo), _d3(hi), a.ctypes.data, GRID_HOST_COPY))
+        else:
+            import torch
+            t = kappa_rho
+            if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("device grid must be a contiguous float32 CUDA tensor")
+            self._keep = [t]
+            self._ck(self.lib.qrt_set_grid(self.h, nx, ny, nz, _d3(lo), _d3(hi), C.c_void_p(t.data_ptr()),
+                                           GRID_DEVICE_BORROW))
+
+    def set_point_source(self, x=0.0, y=0.0, z=0.0):
+        self._ck(self.lib.qrt_set_point_source(self.h, x, y, z))
+
+    def set_sphere_source(self, x, y, z, radius, order=EMIT_DIRECT):
+        self._ck(self.lib.qrt_set_sphere_source(self.h, x, y, z, radius, order))
+
+    def set_dust(self, albedo, g, p_lin, p_circ=0.0):
+        self._ck(self.lib.qrt_set_dust(self.h, albedo, g, p_lin, p_circ))
+
+    def set_observers(self, observers: Sequence[Tuple[float, float]], npix: int, half_width: float):
+        th = (C.c_double * len(observers))(*[o[0] for o in observers])
+        ph = (C.c_double * len(observers))(*[o[1] for o in observers])
+        self.n_obs, self.npix = len(observers), npix
+        self._ck(self.lib.qrt_set_observers(self.h, len(observers), th, ph, npix, half_width))
+
+    def set_sequence(self, kind: int, seed: int = 0, n_total: int = 0):
+        self._ck(self.lib.qrt_set_sequence(self.h, kind, seed, n_total))
+
+    def set_transport(self, max_orders: int, tau_min: float = 1e-8, precision: int = FP32,
+                      peel_mode: int = PEEL_EXACT):
+        self._ck(self.lib.qrt_set_transport(self.h, max_orders, tau_min, precision, peel_mode))
+
+    def set_scene(self, sc, kind: int = SOBOL, seed: int = 0, n_total: Optional[int] = None, grid=None,
+                  precision: Optional[int] = None):
+        """Configure everything from a synth.Scene (grid may be a device tensor to borrow)."""
+        self.set_grid(sc.kappa_rho if grid is None else grid, sc.lo, sc.hi)
+        if sc.source_kind == 1:
+            self.set_sphere_source(*sc.source, sc.r_star)
+        else:
+            self.set_point_source(*sc.source)
+        self.set_dust(sc.albedo, sc.g, sc.p_lin)
+        self.set_observers(sc.observers, sc.npix, sc.half_width)
+        self.set_sequence(kind, seed, sc.n_packets if n_total is None else n_total)
+        prec = (FP64 if sc.fp64 else FP32) if precision is None else precision
+        self.set_transport(sc.max_orders, sc.tau_min, prec)
+
+    # -------- work
+    def run(self, first: int, count: int):
+        self._ck(self.lib.qrt_run(self.h, first, count))
+
+    def reset_images(self):
+        self._ck(self.lib.qrt_reset_images(self.h))
+
+    def read_images(self, normalized: bool = True) -> np.ndarray:
+        """[n_obs][3][npix][npix] float64 (I, Q, U)."""
+        out = np.zeros((self.n_obs, 3, self.npix, self.npix), dtype=np.float64)
+        for o in range(self.n_obs):
+            self._ck(self.lib.qrt_read_images(self.h, o, out[o, 0].ctypes.data, out[o, 1].ctypes.data,
+                                              out[o, 2].ctypes.data, int(normalized)))
+        return out
+
+    def image_device_ptr(self) -> int:
+        p = C.c_void_p()
+        self._ck(self.lib.qrt_image_device_ptr(self.h, C.byref(p)))
+        return int(p.value or 0)
+
+    def counters(self) -> dict:
+        c = qrt_counters()
+        self._ck(self.lib.qrt_get_counters(self.h, C.byref(c)))
+        return c.as_dict()
+
+    def generate_points(self, kind: int, first: int, count: int, dims: int, seed: int = 0,
+                        n_total: int = 0) -> np.ndarray:
+        out = np.zeros((count, dims), dtype=np.uint32)
+        self._ck(self.lib.qrt_generate_points(self.h, kind, seed, n_total, first, count, dims,
+                                              out.ctypes.data, 0))
+        return out
+
+    def generate_points_device(self, kind: int, first: int, count: int, dims: int, out_tensor, seed: int = 0,
+                               n_total: int = 0):
+        self._ck(self.lib.qrt_generate_points(self.h, kind, seed, n_total, first, count, dims,
+                                              C.c_void_p(out_tensor.data_ptr()), 1))
+
+    def trace_tau(self, p_dev, k_dev, tau_dev, visits_dev=None):
+        n = p_dev.shape[0]
+        self._ck(self.lib.qrt_trace_tau(self.h, n, C.c_void_p(p_dev.data_ptr()), C.c_void_p(k_dev.data_ptr()),
+                                        C.c_void_p(tau_dev.data_ptr()),
+                                        C.c_void_p(visits_dev.data_ptr()) if visits_dev is not None else None))

@@ -1,0 +1,300 @@
+"""GPU <-> oracle parity through the C ABI (libqrt.so on gfx950).
+
+Gates (the FP64 ones are per pixel):
+  * points: bit-exact uint32, every kind, indices from 1 up to 2^32-1;
+  * FP64 transport: |dI| <= 1e-5 I_oracle where I_oracle > 1e-6 max I, else
+    <= 1e-11 max I; |dQ|, |dU| <= 1e-5 I_oracle (+1e-11 max I); pixels the oracle
+    leaves at zero stay zero; event counters equal;
+  * FP32 transport (FP32 rays, FP64 optical-depth and image sums) against the
+    FP64 oracle: total flux per Stokes within 1e-5 of total I, 8x8-binned image
+    RMS within 1e-4.  Pixel-level FP32 differences are rounding re-binnings
+    (an FP32 position moves a contribution to the neighbouring pixel), not errors.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2406_15632_amd import qrt
+    qrt.load()
+    return qrt
+
+
+@pytest.fixture()
+def ctx(Q):
+    c = Q.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_images(ctx, Q, sc, kind, first, count, seed=0, n_total=None, precision=None, chunks=None):
+    ctx.set_scene(sc, kind=kind, seed=seed, n_total=n_total, precision=precision)
+    ctx.reset_images()
+    if chunks is None:
+        ctx.run(first, count)
+    else:
+        f = first
+        for c in chunks:
+            ctx.run(f, c)
+            f += c
+        assert f == first + count
+    img = ctx.read_images(normalized=False)
+    return img / count, ctx.counters()
+
+
+def assert_fp64_parity(g, o):
+    for ob in range(o.shape[0]):
+        Ig, Io = g[ob, 0], o[ob, 0]
+        mx = Io.max()
+        assert mx > 0
+        big = Io > 1e-6 * mx
+        dI = np.abs(Ig - Io)
+        assert np.all(dI[big] <= 1e-5 * Io[big]), f"obs {ob}: max rel {np.max(dI[big] / Io[big]):.3e}"
+        assert np.all(dI[~big] <= 1e-11 * mx)
+        for s in (1, 2):
+            d = np.abs(g[ob, s] - o[ob, s])
+            assert np.all(d <= 1e-5 * Io + 1e-11 * mx), f"obs {ob} stokes {s}"
+        assert np.all(Ig[Io == 0] == 0)
+
+
+def assert_counters_equal(cg, co):
+    for k in ("packets", "visits", "peels", "peel_rays", "escapes", "tau_cuts", "scatterings", "occluded"):
+        assert cg[k] == co[k], f"{k}: gpu {cg[k]} oracle {co[k]}"
+
+
+# ------------------------------------------------------------------ points
+POINT_RANGES = [(1, 4096), ((1 << 16) - 3, 9), ((1 << 24) - 2, 5), ((1 << 32) - 8, 7)]
+
+
+@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX])
+@pytest.mark.parametrize("dims", [3, 60, 128])
+def test_points_bit_exact(ctx, Q, kind, dims):
+    for first, count in POINT_RANGES:
+        n_total = (1 << 32) - 1 if kind == O.HAMMERSLEY else 0
+        _say(f"points kind={kind} dims={dims} first={first} count={count}")
+        g = ctx.generate_points(kind, first, count, dims, seed=12345, n_total=n_total)
+        o = O.points(kind, dims, first, count, seed=12345, n_total=n_total)
+        assert np.array_equal(g, o)
+    if kind == O.PHILOX:
+        g = ctx.generate_points(kind, (1 << 40) + 3, 5, dims, seed=7)
+        o = O.points(kind, dims, (1 << 40) + 3, 5, seed=7)
+        assert np.array_equal(g, o)
+
+
+def test_hammersley_first_coordinate_at_N(ctx, Q):
+    for N in (1000, 1 << 22, 3 * (1 << 20) + 7):
+        _say(f"hammersley N={N}")
+        g = ctx.generate_points(O.HAMMERSLEY, N - 5, 6, 4, n_total=N)
+        o = O.points(O.HAMMERSLEY, 4, N - 5, 6, n_total=N)
+        assert np.array_equal(g, o)
+        assert g[-1, 0] == 0
+
+
+def test_points_device_output(ctx, Q):
+    import torch
+    out = torch.zeros((1000, 60), dtype=torch.int32, device="cuda")
+    ctx.generate_points_device(O.SOBOL, 1, 1000, 60, out)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy().view(np.uint32)
+    assert np.array_equal(g, O.points(O.SOBOL, 60, 1, 1000))
+
+
+# ------------------------------------------------------------------ traversal
+@pytest.mark.parametrize("precision", [1, 0])
+def test_trace_tau_matches_oracle(ctx, Q, precision):
+    import torch
+    shape = (21, 18, 25)
+    kr = scenes.random_grid(shape, seed=4)
+    sc = scenes.Scene(name="g", n=(25, 18, 21), lo=(-1.0, -0.7, -1.2), hi=(1.1, 0.8, 1.0), kappa_rho=kr,
+                      observers=[(0.0, 0.0)])
+    ctx.set_grid(sc.kappa_rho, sc.lo, sc.hi)
+    ctx.set_transport(1, 1e-8, precision)
+    rng = np.random.default_rng(9)
+    n = 5000
+    p = rng.uniform(np.array(sc.lo) + 1e-3, np.array(sc.hi) - 1e-3, size=(n, 3))
+    k = rng.standard_normal((n, 3))
+    k /= np.linalg.norm(k, axis=1)[:, None]
+    k[:50] = [[1, 0, 0], [0, -1, 0], [0, 0, 1], [-1, 0, 0], [0.6, 0.8, 0]] * 10
+    if precision == 0:   # FP32 rays: compare rays the FP32 path represents exactly
+        p = p.astype(np.float32).astype(np.float64)
+        k = k.astype(np.float32).astype(np.float64)
+    pd = torch.tensor(p, device="cuda")
+    kd = torch.tensor(k, device="cuda")
+    tau = torch.zeros(n, dtype=torch.float64, device="cuda")
+    vis = torch.zeros(n, dtype=torch.int64, device="cuda")
+    _say(f"trace_tau precision={precision}")
+    ctx.trace_tau(pd, kd, tau, vis)
+    torch.cuda.synchronize()
+    tg, vg = tau.cpu().numpy(), vis.cpu().numpy()
+    osc = O.OracleScene(sc)
+    to = np.zeros(n)
+    vo = np.zeros(n, dtype=np.int64)
+    for i in range(n):
+        to[i], vo[i] = O.tau_ray(osc, p[i], k[i])
+    if precision == 1:
+        assert np.allclose(tg, to, rtol=1e-12, atol=1e-13)
+        assert np.array_equal(vg, vo)
+    else:
+        assert np.allclose(tg, to, rtol=2e-5, atol=1e-6)
+        assert np.mean(vg == vo) > 0.99
+
+
+# ------------------------------------------------------------------ FP64 transport parity
+def test_envelope32_fp64_parity(ctx, Q):
+    sc = scenes.envelope32()
+    _say("envelope32 FP64 sobol 2^16")
+    g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, sc.n_packets)
+    o, co, _ = O.run(sc, O.SOBOL, count=sc.n_packets, nthreads=8)
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
+@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX])
+def test_small_disk_multi_order_fp64_parity(ctx, Q, kind):
+    sc = scenes.disk128(n=32).replace(npix=64, fp64=True, n_packets=1 << 14)
+    _say(f"disk32 FP64 20 orders kind={kind}")
+    g, cg = gpu_images(ctx, Q, sc, kind, 1, sc.n_packets, seed=12345)
+    o, co, _ = O.run(sc, kind, count=sc.n_packets, seed=12345, nthreads=8)
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
+def test_disk128_fp64_parity(ctx, Q):
+    sc = scenes.disk128().replace(fp64=True, n_packets=1 << 16)
+    _say("disk128 FP64 sobol 2^16")
+    g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, sc.n_packets)
+    o, co, _ = O.run(sc, O.SOBOL, count=sc.n_packets, nthreads=8)
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
+def test_clumpy256_sphere_star_fp64_parity(ctx, Q):
+    sc = scenes.clumpy256().replace(fp64=True, n_packets=1 << 16)
+    _say("clumpy256 FP64 sphere star halton 2^16")
+    g, cg = gpu_images(ctx, Q, sc, O.HALTON, 1, sc.n_packets)
+    o, co, _ = O.run(sc, O.HALTON, count=sc.n_packets, nthreads=8)
+    assert co["occluded"] > 0
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
+# ------------------------------------------------------------------ FP32 transport against the FP64 oracle
+def _binned_rms(a, b, f=8):
+    n = a.shape[-1] // f
+    A = a.reshape(n, f, n, f).sum(axis=(1, 3))
+    B = b.reshape(n, f, n, f).sum(axis=(1, 3))
+    return np.linalg.norm(A - B) / np.linalg.norm(B)
+
+
+@pytest.mark.parametrize("name,count", [("envelope32", 1 << 18), ("disk128", 1 << 16)])
+def test_fp32_transport_against_fp64_oracle(ctx, Q, name, count):
+    sc = scenes.scene_by_name(name, n_packets=count)
+    _say(f"{name} FP32 vs FP64 oracle, {count} packets")
+    g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, count, precision=Q.FP32)
+    o, co, _ = O.run(sc, O.SOBOL, count=count, nthreads=8)
+    for ob in range(o.shape[0]):
+        tot = o[ob, 0].sum()
+        for s in range(3):
+            assert abs(g[ob, s].sum() - o[ob, s].sum()) <= 1e-5 * tot, f"obs {ob} stokes {s}"
+        assert _binned_rms(g[ob, 0], o[ob, 0]) <= 1e-4
+    assert cg["packets"] == co["packets"]
+    assert abs(cg["visits"] - co["visits"]) <= 1e-3 * co["visits"]
+
+
+# ------------------------------------------------------------------ chunks, edges, errors
+def test_chunked_runs_add_up(ctx, Q):
+    sc = scenes.envelope32()
+    n = sc.n_packets
+    _say("envelope32 chunked vs single")
+    a, ca = gpu_images(ctx, Q, sc, O.SOBOL, 1, n)
+    b, cb = gpu_images(ctx, Q, sc, O.SOBOL, 1, n, chunks=[1, 255, 12345, n - 12601])
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * a.max())
+    assert ca == cb
+
+
+def test_ragged_and_empty_runs(ctx, Q):
+    sc = scenes.envelope32()
+    ctx.set_scene(sc)
+    ctx.reset_images()
+    _say("empty run")
+    ctx.run(1, 0)
+    assert ctx.read_images().sum() == 0
+    for first, count in ((1, 1), (2, 257), (7777, 1000)):
+        _say(f"ragged run first={first} count={count}")
+        g, cg = gpu_images(ctx, Q, sc, O.HALTON, first, count)
+        o, co, _ = O.run(sc, O.HALTON, first=first, count=count)
+        if o[0, 0].max() > 0:
+            assert_fp64_parity(g, o)
+        else:
+            assert np.all(g == 0)
+        assert_counters_equal(cg, co)
+
+
+def test_errors_are_reported(ctx, Q):
+    from paper_2406_15632_amd.qrt import QRTError
+    with pytest.raises(QRTError) as e:
+        ctx.run(1, 10)
+    assert e.value.code == Q.QRT_BAD_STATE
+    sc = scenes.envelope32()
+    ctx.set_scene(sc)
+    with pytest.raises(QRTError) as e:
+        ctx.run(0, 10)
+    assert e.value.code == Q.QRT_INVALID_ARG
+    ctx.set_sequence(Q.HAMMERSLEY, 0, 100)
+    with pytest.raises(QRTError) as e:
+        ctx.run(90, 20)
+    assert e.value.code == Q.QRT_UNSUPPORTED
+    ctx.set_sequence(Q.SOBOL)
+    with pytest.raises(QRTError) as e:
+        ctx.run((1 << 32) - 5, 10)
+    assert e.value.code == Q.QRT_UNSUPPORTED
+    ctx.set_transport(43, 1e-8, Q.FP64)
+    with pytest.raises(QRTError) as e:
+        ctx.run(1, 10)
+    assert e.value.code == Q.QRT_UNSUPPORTED
+    with pytest.raises(QRTError):
+        ctx.set_dust(1.5, 0.5, 0.5)
+    with pytest.raises(QRTError):
+        ctx.set_dust(0.5, 0.5, 0.5, 0.1)
+    with pytest.raises(QRTError):
+        ctx.set_point_source(2.0, 0.0, 0.0)
+
+
+# ------------------------------------------------------------------ full benchmark size
+def test_disk128_full_size_properties(ctx, Q):
+    """The benchmark configuration (2^22 packets per sequence, FP32): the run
+    covers every packet, images are finite with |Q|,|U| <= I per pixel, and the
+    last 2^12 packets, run alone, match the FP64 oracle on those packets."""
+    sc = scenes.disk128()
+    N = sc.n_packets
+    for kind in (O.SOBOL, O.HAMMERSLEY):
+        _say(f"disk128 full size kind={kind}")
+        g, cg = gpu_images(ctx, Q, sc, kind, 1, N, n_total=N)
+        assert cg["packets"] == N
+        assert np.all(np.isfinite(g))
+        I, Qs, U = g[:, 0], g[:, 1], g[:, 2]
+        assert np.all(I >= 0)
+        assert np.all(np.abs(Qs) <= I * (1 + 1e-6) + 1e-300) and np.all(np.abs(U) <= I * (1 + 1e-6) + 1e-300)
+        tail = 1 << 12
+        gt, ct = gpu_images(ctx, Q, sc, kind, N - tail + 1, tail, n_total=N)
+        ot, co, _ = O.run(sc, kind, first=N - tail + 1, count=tail, n_total=N, nthreads=8)
+        for ob in range(ot.shape[0]):
+            tot = ot[ob, 0].sum()
+            for s in range(3):
+                assert abs(gt[ob, s].sum() - ot[ob, s].sum()) <= 1e-5 * tot
+        assert ct["packets"] == co["packets"] and ct["scatterings"] == co["scatterings"]
