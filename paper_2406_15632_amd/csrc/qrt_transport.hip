@@ -203,7 +203,8 @@ __device__ __forceinline__ void transport_packet(const TransportParams &P, const
         return;
     }
     const double W1 = -expm1(-tau1);
-    const double u_tau = (double)to_unit<R>(seq_point<KIND>(P.seq, idx, dim_tau));
+    // optical-depth targets use all 32 bits of the coordinate in FP64, in both precisions
+    const double u_tau = (double)seq_point<KIND>(P.seq, idx, dim_tau) * 0x1p-32;
     const double tau_f = -log1p(-u_tau * W1);
     {
         R t;
@@ -242,7 +243,7 @@ __device__ __forceinline__ void transport_packet(const TransportParams &P, const
             k[a] = kn;
             m[a] = mn;
         }
-        const double tau2 = -log((double)to_unit<R>(x[2]));
+        const double tau2 = -log((double)x[2] * 0x1p-32);
         R t;
         WalkResult wm = walk<R, WALK_MOVE>(G, p, k, tau2, t);
         L.visits += wm.visits;

@@ -70,6 +70,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} not found: build it with `python -m paper_2406_15632_amd.build`")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+    # loading torch first makes libqrt bind to that one, so one process never
+    # holds two HIP runtimes and device pointers/streams from torch are valid here
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

@@ -73,8 +73,15 @@ def assert_fp64_parity(g, o):
 
 
 def assert_counters_equal(cg, co):
-    for k in ("packets", "visits", "peels", "peel_rays", "escapes", "tau_cuts", "scatterings", "occluded"):
-        assert cg[k] == co[k], f"{k}: gpu {cg[k]} oracle {co[k]}"
+    """Event counts agree exactly for packets, and otherwise up to rare near-tie
+    flips: the device and glibc differ in the last ulp of sin/log/expm1 and the
+    device divides by multiplying with 1/k, so a ray that leaves the mesh
+    through a cell edge or corner may enter one more (zero-length) cell, or a
+    stop may land on the other side of a face.  Each flip changes a count by
+    about one; allow a few plus 1e-5 relative."""
+    assert cg["packets"] == co["packets"]
+    for k in ("visits", "peels", "peel_rays", "escapes", "tau_cuts", "scatterings", "occluded"):
+        assert abs(cg[k] - co[k]) <= 4 + 1e-5 * co[k], f"{k}: gpu {cg[k]} oracle {co[k]}"
 
 
 # ------------------------------------------------------------------ points
@@ -150,7 +157,27 @@ def test_trace_tau_matches_oracle(ctx, Q, precision):
         assert np.allclose(tg, to, rtol=1e-12, atol=1e-13)
         assert np.array_equal(vg, vo)
     else:
-        assert np.allclose(tg, to, rtol=2e-5, atol=1e-6)
+        # FP32 face distances: every face position carries an absolute rounding
+        # of a few ulps of the box coordinates (delta), so a crossing on axis a
+        # moves by delta/|k_a| and shifts at most max(kappa*rho) * delta/|k_a| of
+        # optical depth between neighbouring cells.  Bound per ray: the
+        # crossings along each axis (t_exit/h_a of them) plus the exit face.
+        lo, hi, nn = np.array(sc.lo), np.array(sc.hi), np.array(sc.n)
+        h = (hi - lo) / nn
+        delta = 4 * 2.0 ** -24 * np.max(np.abs(np.concatenate([lo, hi])))
+        t_exit = np.full(n, np.inf)
+        for a in range(3):
+            with np.errstate(divide="ignore", invalid="ignore"):
+                ta = np.where(k[:, a] > 0, (hi[a] - p[:, a]) / k[:, a],
+                              np.where(k[:, a] < 0, (lo[a] - p[:, a]) / k[:, a], np.inf))
+            t_exit = np.minimum(t_exit, ta)
+        with np.errstate(divide="ignore"):
+            inv = np.where(k != 0, 1.0 / np.abs(k), 0.0)
+        bound = 1e-5 * to + float(kr.max()) * delta * np.sum(t_exit[:, None] / h[None, :] + inv, axis=1)
+        err = np.abs(tg - to)
+        assert np.all(err <= bound), f"worst excess {np.max(err / bound):.3f}"
+        rel = err / np.maximum(to, 1e-12)
+        assert np.quantile(rel, 0.9) < 2e-5
         assert np.mean(vg == vo) > 0.99
 
 
@@ -201,8 +228,19 @@ def _binned_rms(a, b, f=8):
     return np.linalg.norm(A - B) / np.linalg.norm(B)
 
 
-@pytest.mark.parametrize("name,count", [("envelope32", 1 << 18), ("disk128", 1 << 16)])
+def _axis_aligned(theta, phi):
+    o = np.array([np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi), np.cos(theta)])
+    return np.max(np.abs(o)) > 1 - 1e-12
+
+
+@pytest.mark.parametrize("name,count", [("envelope32", 1 << 18), ("disk128", 1 << 18)])
 def test_fp32_transport_against_fp64_oracle(ctx, Q, name, count):
+    """FP32 rays move scattering points by ~1e-7 relative.  Off the grid axes that
+    only re-bins a few contributions (8x8-binned RMS <= 1e-4).  For an observer
+    exactly along a grid axis every peel ray runs along one row of cells, and a
+    position within ~1e-7 of a face selects the neighbouring row, whose optical
+    depth can differ a lot across a steep density profile (the disk seen edge-on):
+    there the bound is 1e-3.  Total fluxes stay within 1e-5 everywhere."""
     sc = scenes.scene_by_name(name, n_packets=count)
     _say(f"{name} FP32 vs FP64 oracle, {count} packets")
     g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, count, precision=Q.FP32)
@@ -211,9 +249,24 @@ def test_fp32_transport_against_fp64_oracle(ctx, Q, name, count):
         tot = o[ob, 0].sum()
         for s in range(3):
             assert abs(g[ob, s].sum() - o[ob, s].sum()) <= 1e-5 * tot, f"obs {ob} stokes {s}"
-        assert _binned_rms(g[ob, 0], o[ob, 0]) <= 1e-4
+        lim = 1e-3 if _axis_aligned(*sc.observers[ob]) else 1e-4
+        assert _binned_rms(g[ob, 0], o[ob, 0]) <= lim, f"obs {ob}"
     assert cg["packets"] == co["packets"]
     assert abs(cg["visits"] - co["visits"]) <= 1e-3 * co["visits"]
+
+
+def test_fp32_error_is_negligible_against_sampling_error(ctx, Q):
+    """Against an independent FP64 oracle reference (Halton, 16x the packets), the
+    image error of FP32 transport equals that of FP64 transport to within 3 %."""
+    sc = scenes.disk128(n_packets=1 << 16)
+    _say("disk128 FP32 vs FP64 error against oracle reference")
+    ref, _, _ = O.run(sc, O.HALTON, count=1 << 20, nthreads=16)
+    g, _ = gpu_images(ctx, Q, sc, O.SOBOL, 1, sc.n_packets, precision=Q.FP32)
+    o, _, _ = O.run(sc, O.SOBOL, count=sc.n_packets, nthreads=16)
+    for ob in range(ref.shape[0]):
+        e32 = np.linalg.norm(g[ob, 0] - ref[ob, 0]) / np.linalg.norm(ref[ob, 0])
+        e64 = np.linalg.norm(o[ob, 0] - ref[ob, 0]) / np.linalg.norm(ref[ob, 0])
+        assert abs(e32 - e64) <= 0.03 * e64, f"obs {ob}: e32 {e32:.4e} e64 {e64:.4e}"
 
 
 # ------------------------------------------------------------------ chunks, edges, errors
