@@ -55,6 +55,7 @@ struct qrt_ctx {
     // bookkeeping
     uint32_t *tables = nullptr;              // [sobol kMaxDims*32][nied kMaxDims*32][bases kMaxDims]
     unsigned long long *counters = nullptr;  // [CNT_COUNT]
+    unsigned long long *work = nullptr;      // packet counter of the persistent transport kernel
     uint64_t packets_run = 0;
     int grid_blocks = 0;
 };
@@ -154,15 +155,12 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     delete[] host;
     if (e == hipSuccess) e = hipMalloc(&c->counters, CNT_COUNT * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(c->counters, 0, CNT_COUNT * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long));
     if (e != hipSuccess) {
         qrt_destroy(c);
         return e == hipErrorOutOfMemory ? QRT_OUT_OF_MEMORY : QRT_HIP_ERROR;
     }
-    hipDeviceProp_t prop;
-    int cus = 256;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-        cus = prop.multiProcessorCount;
-    c->grid_blocks = cus * 8;
+    c->grid_blocks = 0;   // persistent grid: as many blocks as fit
     *out = c;
     return QRT_OK;
 }
@@ -177,6 +175,7 @@ void qrt_destroy(qrt_ctx *c)
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
     if (c->counters) (void)hipFree(c->counters);
+    if (c->work) (void)hipFree(c->work);
     delete c;
 }
 
@@ -396,7 +395,7 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     P.img = c->img;
     P.counters = c->counters;
     DeviceGuard dg(c->device);
-    HIP_TRY(c, launch_transport(P, c->precision, c->kind, first, count, c->grid_blocks, c->stream), "transport launch");
+    HIP_TRY(c, launch_transport(P, c->precision, c->kind, first, count, c->grid_blocks, c->work, c->stream), "transport launch");
     c->packets_run += count;
     return QRT_OK;
 }

@@ -39,8 +39,9 @@ struct TransportParams {
 };
 
 // transport launcher: precision 0 = FP32, 1 = FP64
+// persistent transport kernel; work is a device counter the launch resets
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first,
-                            uint64_t count, int grid_blocks, hipStream_t stream);
+                            uint64_t count, int grid_blocks, unsigned long long *work, hipStream_t stream);
 
 hipError_t launch_points(const SeqParams &S, int kind, uint64_t first, uint64_t count, int dims,
                          uint32_t *out, hipStream_t stream);

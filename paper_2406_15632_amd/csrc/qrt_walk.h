@@ -4,15 +4,23 @@
 // kappa*rho * (length inside the cell), and a packet moved by a given optical
 // depth stops inside the cell where the running sum reaches it.
 //
-// Cell walk (Amanatides & Woo 1987).  The starting cell is floor((p-lo)/h)
-// clamped to the mesh; each axis keeps the distance to its next face,
-// recomputed from the integer cell index after every step (no drift); an axis
-// whose direction component is zero never steps; ties step x before y before z.
-// The running optical depth is FP64 whatever the ray precision R, so long FP32
-// rays (hundreds of cells) do not lose digits.
-//
-// Visits (cells entered) are not counted per step: every step changes one cell
-// index by one, so the count follows from the start and end cells.
+// Cell walk (Amanatides & Woo 1987) kept as resumable per-lane state so that a
+// persistent kernel can interleave the walks of many packets:
+//  - the starting cell is floor((p-lo)/h) clamped to the mesh;
+//  - along each axis with a nonzero direction component, the distance to the
+//    j-th face ahead is fma(j, D, T0) (T0 the first face distance, D = h/|k|):
+//    one rounding per face, no drift;
+//  - the distance to the mesh boundary face of each axis uses the same
+//    expression, so the walk ends exactly when the face it is about to cross
+//    is a boundary face (tn >= t_exit); the cell index therefore never leaves
+//    the mesh;
+//  - ties step x before y before z; components below 1e-30 count as zero;
+//  - steps are taken in batches: the cells of B steps are computed first (they
+//    do not depend on the densities), then their B loads are issued together,
+//    then the optical depth is accumulated in order, in FP64, with the
+//    stop test of a move done per step.
+// Loads go through a buffer resource whose range is the mesh, so an address
+// outside the mesh could only read zero.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,7 +36,7 @@ struct DevGrid {
 
 template <typename R>
 struct RayGrid {
-    const float *__restrict__ kr;
+    __amdgpu_buffer_rsrc_t rsrc;
     int n[3];
     R lo[3], h[3];
 };
@@ -37,109 +45,173 @@ template <typename R>
 __device__ __forceinline__ RayGrid<R> ray_grid(const DevGrid &g)
 {
     RayGrid<R> r;
-    r.kr = g.kr;
+    const int bytes = g.nx * g.ny * g.nz * 4;
+    r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.kr, (short)0, bytes, 0x00020000);
     r.n[0] = g.nx; r.n[1] = g.ny; r.n[2] = g.nz;
     for (int a = 0; a < 3; ++a) { r.lo[a] = (R)g.lo[a]; r.h[a] = (R)g.h[a]; }
     return r;
 }
 
-struct WalkResult {
-    double tau;      // accumulated optical depth (to the edge, or the target when stopped)
-    uint32_t visits; // cells entered
-    bool stopped;    // MOVE: stopped inside the mesh
-};
-
 template <typename R> __device__ __forceinline__ R r_inf();
 template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
 
+template <typename R>
+__device__ __forceinline__ R load_kr(const RayGrid<R> &G, int cell)
+{
+    return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, cell * 4, 0, 0));
+}
+
 enum WalkMode { WALK_EDGE = 0, WALK_MOVE = 1 };
 
-// Walk from p along unit k.  WALK_EDGE: integrate to the mesh edge; t_out is the
-// exit distance.  WALK_MOVE: stop where the running optical depth reaches
-// target; t_out is the stop distance, or the exit distance if the edge comes first.
-template <typename R, int MODE>
-__device__ __forceinline__ WalkResult walk(const RayGrid<R> &G, const R p[3], const R k[3], double target,
-                                           R &t_out)
+// Per-lane walk state.  Scalar fields only: a selected array element would be
+// lowered to a private-memory load.
+template <typename R>
+struct Walk {
+    R T0x, T0y, T0z, Dx, Dy, Dz;   // face distances: fma(j, D, T0)
+    R jx, jy, jz;                  // faces crossed per axis
+    R tx, ty, tz;                  // next face distance per axis
+    R t, t_exit;
+    int cell, dx, dy, dz;          // linear cell index and its step per axis
+    double tau, target;
+    int mode;
+    bool done, stopped;
+    R t_out;                       // stop distance (MOVE), else exit distance
+    uint32_t visits;
+};
+
+template <typename R>
+__device__ __forceinline__ void axis_setup(const RayGrid<R> &G, int a, R p, R d, int stride, int &c, R &T0, R &D,
+                                           R &tb, int &dc)
 {
-    int c[3], s[3];
-    R tmax[3], invk[3], base[3];
-    int c0[3];
-    WalkResult res;
-    res.stopped = false;
-    // Termination: every step moves one cell index by one toward the mesh edge,
-    // provided the axis chosen has a nonzero step.  Non-finite positions or
-    // directions (never produced by the transport) would break that, so they
-    // end the walk at once; components below 1e-30 count as zero, which keeps
-    // 1/k and every face distance finite.
-    if (!(isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(k[0]) && isfinite(k[1]) &&
-          isfinite(k[2])) ||
-        !(fabs(k[0]) > (R)1e-30 || fabs(k[1]) > (R)1e-30 || fabs(k[2]) > (R)1e-30)) {
-        t_out = (R)0;
-        res.tau = 0.0;
-        res.visits = 0;
-        return res;
+    R f = floor((p - G.lo[a]) / G.h[a]);
+    f = f < (R)0 ? (R)0 : f;
+    f = f > (R)(G.n[a] - 1) ? (R)(G.n[a] - 1) : f;
+    c = (int)f;
+    const int s = d > (R)1e-30 ? 1 : (d < (R)-1e-30 ? -1 : 0);
+    if (s == 0) {
+        T0 = r_inf<R>();
+        D = (R)0;
+        tb = r_inf<R>();
+        dc = 0;
+    } else {
+        const R inv = (R)1 / d;
+        const R face0 = G.lo[a] + (R)(c + (s > 0 ? 1 : 0)) * G.h[a];
+        T0 = (face0 - p) * inv;
+        D = G.h[a] * fabs(inv);
+        const int J = s > 0 ? G.n[a] - 1 - c : c;
+        tb = fma((R)J, D, T0);
+        dc = s * stride;
     }
+}
+
+// Start a walk from p along unit d.  Returns false (and a finished walk with
+// tau = 0) for non-finite input or a zero direction.
+template <typename R>
+__device__ __forceinline__ bool walk_begin(Walk<R> &W, const RayGrid<R> &G, const R p[3], const R d[3], int mode,
+                                           double target)
+{
+    W.mode = mode;
+    W.target = target;
+    W.tau = 0.0;
+    W.t = (R)0;
+    W.t_out = (R)0;
+    W.stopped = false;
+    W.visits = 0;
+    W.jx = W.jy = W.jz = (R)0;
+    const bool ok = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(d[0]) && isfinite(d[1]) &&
+                    isfinite(d[2]) && (fabs(d[0]) > (R)1e-30 || fabs(d[1]) > (R)1e-30 || fabs(d[2]) > (R)1e-30);
+    if (!ok) {
+        W.done = true;
+        W.cell = 0;
+        W.dx = W.dy = W.dz = 0;
+        W.t_exit = (R)0;
+        W.T0x = W.T0y = W.T0z = W.tx = W.ty = W.tz = r_inf<R>();
+        W.Dx = W.Dy = W.Dz = (R)0;
+        return false;
+    }
+    W.done = false;
+    int cx, cy, cz;
+    R bx, by, bz;
+    axis_setup(G, 0, p[0], d[0], 1, cx, W.T0x, W.Dx, bx, W.dx);
+    axis_setup(G, 1, p[1], d[1], G.n[0], cy, W.T0y, W.Dy, by, W.dy);
+    axis_setup(G, 2, p[2], d[2], G.n[0] * G.n[1], cz, W.T0z, W.Dz, bz, W.dz);
+    W.tx = W.T0x; W.ty = W.T0y; W.tz = W.T0z;
+    W.t_exit = fmin(bx, fmin(by, bz));
+    W.cell = (cz * G.n[1] + cy) * G.n[0] + cx;
+    return true;
+}
+
+// B steps of a walk (no effect once done).  The cell sequence does not depend
+// on the densities, so the B cells are computed first and loaded together.
+template <typename R, int B>
+__device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
+{
+    if (W.done) return;
+    int cells[B];
+    R t0s[B], segs[B];
+    bool valid[B];
+    bool alive = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        R f = floor((p[a] - G.lo[a]) / G.h[a]);
-        f = f < (R)0 ? (R)0 : f;
-        f = f > (R)(G.n[a] - 1) ? (R)(G.n[a] - 1) : f;
-        c[a] = (int)f;
-        c0[a] = c[a];
-        s[a] = k[a] > (R)1e-30 ? 1 : (k[a] < (R)-1e-30 ? -1 : 0);
-        invk[a] = s[a] == 0 ? (R)0 : (R)1 / k[a];
-        // face(c) = lo + (c + [s>0]) h ; tmax = (face - p) / k
-        base[a] = G.lo[a] - p[a] + (s[a] > 0 ? G.h[a] : (R)0);
-        tmax[a] = s[a] == 0 ? r_inf<R>() : (base[a] + (R)c[a] * G.h[a]) * invk[a];
+    for (int b = 0; b < B; ++b) {
+        const bool mx = W.tx <= W.ty && W.tx <= W.tz;
+        const bool my = !mx && W.ty <= W.tz;
+        const bool mz = !mx && !my;
+        const R tn = fmin(W.tx, fmin(W.ty, W.tz));
+        valid[b] = alive;
+        cells[b] = W.cell;
+        t0s[b] = W.t;
+        const R seg = tn - W.t;
+        segs[b] = seg > (R)0 ? seg : (R)0;
+        W.t = tn > W.t ? tn : W.t;
+        // the face about to be crossed is a boundary face: the walk ends in this cell
+        const bool adv = tn < W.t_exit;
+        // cell step of the chosen axis as mask arithmetic (a select between
+        // struct fields would become a load from a selected address)
+        const int dc = (W.dx & -(int)mx) | (W.dy & -(int)my) | (W.dz & -(int)mz);
+        W.cell += dc & -(int)adv;
+        W.jx += (adv && mx) ? (R)1 : (R)0;
+        W.jy += (adv && my) ? (R)1 : (R)0;
+        W.jz += (adv && mz) ? (R)1 : (R)0;
+        W.tx = fma(W.jx, W.Dx, W.T0x);
+        W.ty = fma(W.jy, W.Dy, W.T0y);
+        W.tz = fma(W.jz, W.Dz, W.T0z);
+        alive = alive && adv;
     }
-    const int sy = G.n[0], sz = G.n[0] * G.n[1];
-    int cell = (c[2] * G.n[1] + c[1]) * G.n[0] + c[0];
-    R t = (R)0;
-    double tau = 0.0;
-    for (;;) {
-        int a;
-        if (tmax[0] <= tmax[1]) a = tmax[0] <= tmax[2] ? 0 : 2;
-        else a = tmax[1] <= tmax[2] ? 1 : 2;
-        R tn = a == 0 ? tmax[0] : (a == 1 ? tmax[1] : tmax[2]);
-        R seg = tn - t;
-        seg = seg < (R)0 ? (R)0 : seg;
-        R kr = (R)G.kr[cell];
-        double dtau = (double)(kr * seg);
-        if constexpr (MODE == WALK_MOVE) {
-            if (tau + dtau >= target) {
-                double rem = target - tau;
-                t_out = t + (rem > 0.0 ? (R)(rem / (double)kr) : (R)0);
-                res.stopped = true;
-                res.tau = rem > 0.0 ? target : tau;
-                res.visits = (uint32_t)(abs(c[0] - c0[0]) + abs(c[1] - c0[1]) + abs(c[2] - c0[2]) + 1);
-                return res;
-            }
-        }
-        tau += dtau;
-        t = tn > t ? tn : t;
-        if (a == 0) {
-            c[0] += s[0];
-            if ((unsigned)c[0] >= (unsigned)G.n[0]) break;
-            cell += s[0];
-            tmax[0] = (base[0] + (R)c[0] * G.h[0]) * invk[0];
-        } else if (a == 1) {
-            c[1] += s[1];
-            if ((unsigned)c[1] >= (unsigned)G.n[1]) break;
-            cell += s[1] * sy;
-            tmax[1] = (base[1] + (R)c[1] * G.h[1]) * invk[1];
+    R kr[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
+    bool done = false;
+    uint32_t nv = 0;
+    double tau = W.tau;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const bool use = valid[b] && !done;
+        nv += use ? 1u : 0u;
+        const double dtau = (double)(kr[b] * segs[b]);
+        if (W.mode == WALK_MOVE && use && tau + dtau >= W.target) {
+            const double rem = W.target - tau;
+            W.t_out = t0s[b] + (rem > 0.0 ? (R)(rem / (double)kr[b]) : (R)0);
+            tau = rem > 0.0 ? W.target : tau;
+            W.stopped = true;
+            done = true;
         } else {
-            c[2] += s[2];
-            if ((unsigned)c[2] >= (unsigned)G.n[2]) break;
-            cell += s[2] * sz;
-            tmax[2] = (base[2] + (R)c[2] * G.h[2]) * invk[2];
+            tau += use ? dtau : 0.0;
         }
     }
-    t_out = t;
-    res.tau = tau;
-    // the exiting step is counted by the index change but enters no cell
-    res.visits = (uint32_t)(abs(c[0] - c0[0]) + abs(c[1] - c0[1]) + abs(c[2] - c0[2]));
-    return res;
+    W.tau = tau;
+    W.visits += nv;
+    if (!done && !alive) {
+        done = true;
+        W.t_out = W.t;
+    }
+    W.done = done;
+}
+
+template <typename R, int B>
+__device__ __forceinline__ void walk_run(Walk<R> &W, const RayGrid<R> &G)
+{
+    while (!W.done) walk_batch<R, B>(W, G);
 }
 
 }  // namespace qrt
