@@ -146,8 +146,10 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
    run since the last reset.  Synchronises the stream. */
 int qrt_read_images(qrt_ctx *ctx, int obs, double *I, double *Q, double *U, int normalized);
 
-/* Device address of the FP64 image accumulators [n_obs][3][npix][npix]
-   (unnormalised sums), owned by the context. */
+/* Device address of the FP64 image sums [n_obs][3][npix][npix] (unnormalised),
+   owned by the context.  The kernels accumulate into several copies; this call
+   enqueues their fold into the returned array, which is therefore complete
+   once the stream reaches this point. */
 int qrt_image_device_ptr(qrt_ctx *ctx, double **dev_ptr);
 
 /* Zero the images, the packet count and the counters. */

@@ -9,7 +9,7 @@
 
 #include <string>
 
-#include "../../include/qrt.h"
+#include "qrt.h"
 #include "qrt_internal.h"
 
 namespace qrt {
@@ -55,9 +55,9 @@ struct qrt_ctx {
     // bookkeeping
     uint32_t *tables = nullptr;              // [sobol kMaxDims*32][nied kMaxDims*32][bases kMaxDims]
     unsigned long long *counters = nullptr;  // [CNT_COUNT]
-    unsigned long long *work = nullptr;      // packet counter of the persistent transport kernel
+    TransportBuffers tb = {};                // packet and ray queues of the transport
+    uint64_t tb_packets = 0;                 // packets the queues hold
     uint64_t packets_run = 0;
-    int grid_blocks = 0;
 };
 
 namespace {
@@ -127,6 +127,44 @@ int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, ui
     return QRT_OK;
 }
 
+// Queues for chunks of up to `packets` packets (at most kChunk) at the
+// context's precision and observer count; grown on demand, never shrunk.
+int ensure_queues(qrt_ctx *c, uint64_t count)
+{
+    uint64_t want = 1u << 16;
+    while (want < count && want < kChunk) want <<= 1;
+    if (want > kChunk) want = kChunk;
+    const size_t pb = packet_state_bytes(c->precision) * want;
+    const size_t rb = peel_ray_bytes(c->precision) * (want + 64) * (size_t)c->n_obs;
+    if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb_packets >= want) return QRT_OK;
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    if (c->tb.packet_bytes < pb || c->tb_packets < want) {
+        if (c->tb.packets) (void)hipFree(c->tb.packets);
+        c->tb.packets = nullptr;
+        c->tb.packet_bytes = 0;
+        HIP_TRY(c, hipMalloc(&c->tb.packets, pb), "packet queue");
+        c->tb.packet_bytes = pb;
+    }
+    if (c->tb.peel_bytes < rb) {
+        if (c->tb.peels) (void)hipFree(c->tb.peels);
+        c->tb.peels = nullptr;
+        c->tb.peel_bytes = 0;
+        HIP_TRY(c, hipMalloc(&c->tb.peels, rb), "peel-ray queue");
+        c->tb.peel_bytes = rb;
+    }
+    if (c->tb_packets < want) {
+        uint32_t **lists[4] = {&c->tb.live[0], &c->tb.live[1], &c->tb.order, &c->tb.keys};
+        for (uint32_t **l : lists) {
+            if (*l) (void)hipFree(*l);
+            *l = nullptr;
+        }
+        c->tb_packets = 0;
+        for (uint32_t **l : lists) HIP_TRY(c, hipMalloc(l, want * sizeof(uint32_t)), "packet lists");
+        c->tb_packets = want;
+    }
+    return QRT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -155,12 +193,12 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     delete[] host;
     if (e == hipSuccess) e = hipMalloc(&c->counters, CNT_COUNT * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(c->counters, 0, CNT_COUNT * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMalloc(&c->work, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->tb.q, sizeof(Queues));
+    if (e == hipSuccess) e = hipMalloc(&c->tb.hist, sizeof(uint32_t) << kSortBits);
     if (e != hipSuccess) {
         qrt_destroy(c);
         return e == hipErrorOutOfMemory ? QRT_OUT_OF_MEMORY : QRT_HIP_ERROR;
     }
-    c->grid_blocks = 0;   // persistent grid: as many blocks as fit
     *out = c;
     return QRT_OK;
 }
@@ -175,7 +213,14 @@ void qrt_destroy(qrt_ctx *c)
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
     if (c->counters) (void)hipFree(c->counters);
-    if (c->work) (void)hipFree(c->work);
+    if (c->tb.packets) (void)hipFree(c->tb.packets);
+    if (c->tb.peels) (void)hipFree(c->tb.peels);
+    for (int i = 0; i < 2; ++i)
+        if (c->tb.live[i]) (void)hipFree(c->tb.live[i]);
+    if (c->tb.q) (void)hipFree(c->tb.q);
+    if (c->tb.order) (void)hipFree(c->tb.order);
+    if (c->tb.keys) (void)hipFree(c->tb.keys);
+    if (c->tb.hist) (void)hipFree(c->tb.hist);
     delete c;
 }
 
@@ -295,7 +340,7 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
     if (npix < 1 || npix > 8192) return fail(c, QRT_INVALID_ARG, "npix must be in 1..8192");
     if (!(half_width > 0.0) || !isfinite(half_width)) return fail(c, QRT_INVALID_ARG, "half_width must be > 0");
     DeviceGuard dg(c->device);
-    const size_t elems = (size_t)n_obs * 3 * (size_t)npix * (size_t)npix;
+    const size_t elems = (size_t)n_obs * 3 * (size_t)npix * (size_t)npix;   // one copy
     if (elems != c->img_elems) {
         if (c->img) {
             HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
@@ -303,7 +348,7 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
             c->img = nullptr;
             c->img_elems = 0;
         }
-        HIP_TRY(c, hipMalloc(&c->img, elems * sizeof(double)), "image allocation");
+        HIP_TRY(c, hipMalloc(&c->img, elems * kImageCopies * sizeof(double)), "image allocation");
         c->img_elems = elems;
     }
     for (int i = 0; i < n_obs; ++i) {
@@ -395,7 +440,14 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     P.img = c->img;
     P.counters = c->counters;
     DeviceGuard dg(c->device);
-    HIP_TRY(c, launch_transport(P, c->precision, c->kind, first, count, c->grid_blocks, c->work, c->stream), "transport launch");
+    rc = ensure_queues(c, count);
+    if (rc) return rc;
+    // chunks never exceed the queue capacity
+    for (uint64_t done = 0; done < count;) {
+        const uint64_t n = count - done < c->tb_packets ? count - done : c->tb_packets;
+        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream), "transport launch");
+        done += n;
+    }
     c->packets_run += count;
     return QRT_OK;
 }
@@ -407,6 +459,7 @@ int qrt_read_images(qrt_ctx *c, int obs, double *I, double *Q, double *U, int no
     if (obs < 0 || obs >= c->n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
     DeviceGuard dg(c->device);
     const size_t plane = (size_t)c->npix * c->npix;
+    HIP_TRY(c, launch_fold_images(c->img, c->img_elems, c->stream), "image fold");
     double *dst[3] = {I, Q, U};
     for (int s = 0; s < 3; ++s)
         if (dst[s])
@@ -427,6 +480,8 @@ int qrt_image_device_ptr(qrt_ctx *c, double **dev_ptr)
 {
     if (!c || !dev_ptr) return QRT_INVALID_ARG;
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, launch_fold_images(c->img, c->img_elems, c->stream), "image fold");
     *dev_ptr = c->img;
     return QRT_OK;
 }
@@ -435,7 +490,8 @@ int qrt_reset_images(qrt_ctx *c)
 {
     if (!c) return QRT_INVALID_ARG;
     DeviceGuard dg(c->device);
-    if (c->img) HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_elems * sizeof(double), c->stream), "image reset");
+    if (c->img)
+        HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_elems * kImageCopies * sizeof(double), c->stream), "image reset");
     HIP_TRY(c, hipMemsetAsync(c->counters, 0, CNT_COUNT * sizeof(unsigned long long), c->stream), "counter reset");
     c->packets_run = 0;
     return QRT_OK;

@@ -11,6 +11,8 @@ namespace qrt {
 
 constexpr int kMaxDims = 128;
 constexpr int kMaxObs = 16;
+constexpr uint64_t kChunk = 1ull << 22;   // packets per transport chunk (queue capacity)
+constexpr int kImageCopies = 8;           // image accumulators written by different XCDs, folded on read
 
 // counter slots in the device counter array
 enum CounterSlot {
@@ -34,14 +36,60 @@ struct TransportParams {
     SeqParams seq;
     int max_orders;
     double tau_min;
-    double *img;                   // [n_obs][3][npix][npix]
+    double *img;                   // [kImageCopies][n_obs][3][npix][npix]
     unsigned long long *counters;  // [CNT_COUNT]
 };
 
-// transport launcher: precision 0 = FP32, 1 = FP64
-// persistent transport kernel; work is a device counter the launch resets
+// A scattered packet between kernels: position, direction, reference axis,
+// Stokes weight, the optical depth of its next flight, point index and
+// bookkeeping.
+template <typename R>
+struct alignas(16) PacketState {
+    R p[3], k[3], m[3], S[3];
+    double target;
+    uint64_t idx;
+    uint32_t next_dim, order;
+};
+
+// A peel-off ray waiting for its optical depth: start point, Stokes
+// contribution before attenuation, pixel offset and observer.
+template <typename R>
+struct alignas(16) PeelRay {
+    R p[3], c[3];
+    uint32_t pix, obs;
+};
+
+// Device-side queue counters of one chunk.
+struct Queues {
+    uint32_t n_live[2];   // live packets per ping-pong list
+    unsigned long long work[4];   // work counters of the persistent kernels
+};
+
+constexpr int kSortBits = 16;                 // bins of the coherence sorts: 2^kSortBits
+
+// Device buffers of the transport (owned by the context).
+struct TransportBuffers {
+    void *packets;        // PacketState<R>[chunk]
+    void *peels;          // PeelRay<R>[n_obs * (chunk + 64)], blocks of 64 per observer
+    uint32_t *live[2];    // slot lists (ping-pong by scattering order)
+    uint32_t *order;      // [chunk] packets or live slots in coherence order
+    uint32_t *keys;       // [chunk] sort keys
+    uint32_t *hist;       // [2^kSortBits] sort histogram / placement cursors
+    Queues *q;
+    size_t packet_bytes, peel_bytes;
+};
+
+size_t packet_state_bytes(int precision);
+size_t peel_ray_bytes(int precision);
+
+// One chunk of packets first .. first+count-1 (count <= kChunk) through every
+// scattering order: first flight, then per order a scatter kernel and a walk
+// kernel.  All launches go to stream.
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first,
-                            uint64_t count, int grid_blocks, unsigned long long *work, hipStream_t stream);
+                            uint64_t count, const TransportBuffers &B, hipStream_t stream);
+
+// img[0 .. n) += img[c n .. (c+1) n) for every further copy c, which is cleared
+hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream);
 
 hipError_t launch_points(const SeqParams &S, int kind, uint64_t first, uint64_t count, int dims,
                          uint32_t *out, hipStream_t stream);

@@ -1,5 +1,5 @@
-// Photon-packet transport kernel (Shulman, "Quasi-Monte Carlo Radiative
-// Transfer", Sec. 3.2-3.7).
+// Photon-packet transport (Shulman, "Quasi-Monte Carlo Radiative Transfer",
+// Sec. 3.2-3.7) as a wavefront of kernels over packet queues in HBM.
 //
 // What one packet does: emission (Sec. 3.2 point source, Sec. 3.3 sphere star
 // in direct order) -> optical depth tau1 to the mesh edge; end if
@@ -10,461 +10,654 @@
 // update with White's Mueller matrix (Sec. 2.2) divided by the sampled P11,
 // free flight tau2 = -ln w; end when the packet leaves the mesh.
 //
-// How the GPU runs it: a persistent kernel in which every lane owns one packet
-// and one mesh walk at a time.  A packet is a small state machine whose states
-// start walks (tau1, the forced move, each peel-off ray, each free flight); all
-// walks of all lanes share one batched walk loop (qrt_walk.h), so lanes stay in
-// the memory-bound inner loop while their packets are at different stages.
-// Packet events (emission, scattering, peel-off bookkeeping) run only when at
-// least a quarter of the wave's walks have finished.  Waves take packet
-// indices from a global counter 64 at a time.
+// How the GPU runs a chunk of packets:
+//   k_first    persistent; per packet: emission, walk to the edge (tau1), the
+//              forced-flight walk; survivors are appended to a live list.
+//   per scattering order:
+//   k_scatter  one lane per live packet: albedo, the peel-off contribution and
+//              pixel for every observer (appended as peel rays), then the new
+//              direction, Stokes vector and flight depth.
+//   k_walk     persistent; walks every peel ray (adding e^-tau times its
+//              contribution to the image) and every flight (survivors go to the
+//              next live list).
+// Only the two persistent kernels walk the mesh; their per-ray events are a
+// few loads and stores, so they keep a small register footprint and high
+// occupancy.  All physics runs in k_first's events and in k_scatter, which is
+// convergent.  Waves of the persistent kernels take work 64 items at a time
+// from a global counter and refill lanes once a quarter of the wave is idle.
 //
-// Point coordinates are generated on demand from the packet index: flight k
-// uses coordinates 3(k-1) .. 3(k-1)+2 (sphere star: 0..4 for the first
-// flight, then 5 + 3(k-2) ..); a packet that ends early never computes the
-// rest (Sec. 3.7).
+// Point coordinates are generated from the packet index: flight k uses
+// coordinates 3(k-1) .. 3(k-1)+2 (sphere star: 0..4 for the first flight, then
+// 5 + 3(k-2) ..); a packet that ends early never computes the rest (Sec. 3.7).
 //
-// Stokes frames: the packet carries its direction k and a unit reference axis
-// m perpendicular to k (n = k x m); Q > 0 means polarisation along m.  A
-// rotation of the reference axis by psi (m' = cos psi m + sin psi n) maps
-// (Q, U) to (Q cos 2psi + U sin 2psi, -Q sin 2psi + U cos 2psi).  A scattering
-// by (Theta, i1) uses the scattering-plane axis m_in = cos i1 m + sin i1 n;
-// then k' = cos Theta k + sin Theta m_in and m' = cos Theta m_in - sin Theta k.
-// The initial axis is the orthonormal completion of k of Duff et al. (2017).
-// Images use e_x = (-sin phi, cos phi, 0) and e_y = o x e_x.
+// Stokes frames and the scattering geometry are described in qrt_physics.h: a
+// scattering by (Theta, i1) uses the scattering-plane axis
+// m_in = cos i1 m + sin i1 n; then k' = cos Theta k + sin Theta m_in and
+// m' = cos Theta m_in - sin Theta k.  The initial axis is the orthonormal
+// completion of k of Duff et al. (2017).  Images use e_x = (-sin phi, cos phi, 0)
+// and e_y = o x e_x.
 //
 // Precision R: float (FP32 positions, directions, Stokes; FP64 optical-depth
 // sums, optical-depth targets and image sums) or double throughout.
 #include <hip/hip_runtime.h>
 
 #include "qrt_internal.h"
+#include "qrt_physics.h"
 
 namespace qrt {
 
-template <typename R> __device__ __forceinline__ void sincos_2pi(R u, R &s, R &c);
-template <> __device__ __forceinline__ void sincos_2pi<float>(float u, float &s, float &c) { sincospif(2.0f * u, &s, &c); }
-template <> __device__ __forceinline__ void sincos_2pi<double>(double u, double &s, double &c) { sincospi(2.0 * u, &s, &c); }
+constexpr int kWalkBatch = 4;
+constexpr uint32_t kNoPixel = 0xFFFFFFFFu;   // a peel ray that is off the image or blocked
 
-template <typename R> __device__ __forceinline__ R dot3(const R a[3], const R b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
-template <typename R> __device__ __forceinline__ void cross3(const R a[3], const R b[3], R o[3])
+__host__ __device__ __forceinline__ size_t peel_slot(uint32_t i, int ob, int n_obs)
 {
-    o[0] = a[1] * b[2] - a[2] * b[1];
-    o[1] = a[2] * b[0] - a[0] * b[2];
-    o[2] = a[0] * b[1] - a[1] * b[0];
+    return ((size_t)(i >> 6) * (size_t)n_obs + (size_t)ob) * 64 + (i & 63);
+}
+constexpr int kWaveRefill = 64;   // refill a wave once all its lanes are idle: keeps its rays coherent
+
+size_t packet_state_bytes(int precision)
+{
+    return precision == 1 ? sizeof(PacketState<double>) : sizeof(PacketState<float>);
+}
+size_t peel_ray_bytes(int precision) { return precision == 1 ? sizeof(PeelRay<double>) : sizeof(PeelRay<float>); }
+
+__device__ __forceinline__ void flush_counter(unsigned long long *dst, uint64_t v)
+{
+    const uint64_t s = wave_sum_u64(v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
 }
 
-template <typename R>
-__device__ __forceinline__ R hg_cos(R g, R v)
-{
-    R c;
-    if (fabs(g) < (R)1e-6) {
-        c = (R)2 * v - (R)1;
-    } else {
-        R f = ((R)1 - g * g) / ((R)1 - g + (R)2 * g * v);
-        c = ((R)1 + g * g - f * f) / ((R)2 * g);
+// Wave-uniform pool of work items [next, end), 64 at a time: the first block of
+// every wave is fixed by its wave index (no atomic at start-up, when every
+// wave would hit the same counter at once), later blocks come from a global
+// counter that starts after the fixed ones.
+struct WorkPool {
+    uint64_t next = 0, end = 0;
+    bool dry = false, started = false;
+
+    // returns true for a lane that received an item (in `item`)
+    __device__ __forceinline__ bool take(bool want, uint64_t total, unsigned long long *ctr, uint64_t &item)
+    {
+        bool got = false;
+        uint64_t need = __ballot(want);
+        while (need && !dry) {
+            if (next >= end) {
+                const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+                uint64_t base;
+                if (!started) {
+                    base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+                    started = true;
+                } else {
+                    unsigned long long b = 0;
+                    if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, 64ull);
+                    base = nwaves * 64 + __shfl(b, 0, 64);
+                }
+                next = base;
+                end = base + 64 < total ? base + 64 : total;
+                if (next >= total) {
+                    dry = true;
+                    break;
+                }
+            }
+            const uint64_t avail = end - next;
+            const uint64_t n = (uint64_t)__popcll(need);
+            const uint64_t take_n = n < avail ? n : avail;
+            const uint64_t rank = (uint64_t)__popcll(need & lanes_below_mask());
+            if (want && !got && rank < take_n) {
+                item = next + rank;
+                got = true;
+            }
+            next += take_n;
+            need = __ballot(want && !got);
+        }
+        return got;
     }
-    return c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
-}
-
-// White's approximation: P11 (Henyey-Greenstein), P12/P11, P33/P11
-template <typename R>
-__device__ __forceinline__ void mueller(R g, R p_lin, R c, R &p11, R &r12, R &r33)
-{
-    R den = (R)1 + g * g - (R)2 * g * c;
-    p11 = ((R)1 - g * g) / (den * sqrt(den));
-    R c2 = c * c;
-    R inv = (R)1 / ((R)1 + c2);
-    r12 = -p_lin * ((R)1 - c2) * inv;
-    r33 = (R)2 * c * inv;
-}
-
-template <typename R>
-__device__ __forceinline__ void rotate_stokes(R S[3], R cpsi, R spsi)
-{
-    R c2 = cpsi * cpsi - spsi * spsi, s2 = (R)2 * spsi * cpsi;
-    R q = S[1] * c2 + S[2] * s2;
-    R u = -S[1] * s2 + S[2] * c2;
-    S[1] = q;
-    S[2] = u;
-}
-
-// orthonormal completion of a unit vector (Duff et al. 2017): m with k x m = n
-template <typename R>
-__device__ __forceinline__ void basis_of(const R k[3], R m[3])
-{
-    R sg = k[2] >= (R)0 ? (R)1 : (R)-1;
-    R a = (R)-1 / (sg + k[2]);
-    R b = k[0] * k[1] * a;
-    m[0] = (R)1 + sg * k[0] * k[0] * a;
-    m[1] = sg * b;
-    m[2] = -sg * k[0];
-}
-
-struct LocalCounters {
-    uint64_t visits;
-    uint32_t packets, peels, peel_rays, escapes, tau_cuts, scatterings, occluded;
 };
 
-enum Phase : int {
-    PH_NEED = 0,    // wants a packet index
-    PH_EMIT = 1,    // has a fresh index
-    PH_T1 = 2,      // walking to the mesh edge from the source
-    PH_FORCED = 3,  // walking the forced first flight
-    PH_PEEL = 4,    // walking a peel-off ray
-    PH_FLIGHT = 5,  // walking a free flight
-    PH_DONE = 6     // no packets left
-};
+// --------------------------------------------------------------------------
+// coherence sorts
+// --------------------------------------------------------------------------
+// Mesh walks are bound by the rate of distinct cache lines that a wave's
+// loads touch.  Lanes of a wave that walk nearly the same cells share lines,
+// so the packets of a chunk are counting-sorted by emission direction
+// (octahedral map, 2 x 8 bits) before their first flights: a wave then walks
+// 64 nearly parallel rays from the source.  The order only changes which lanes
+// run which packets; every packet is computed as before.
+
+__device__ __forceinline__ uint32_t interleave2(uint32_t qu, uint32_t qv, int bits)
+{
+    uint32_t key = 0;
+    for (int b = 0; b < bits; ++b) key |= ((qu >> b) & 1u) << (2 * b) | ((qv >> b) & 1u) << (2 * b + 1);
+    return key;
+}
 
 template <typename R>
-struct Packet {
-    uint64_t idx;
-    R p[3], k[3], m[3], S[3];
-    R c[3];        // pending peel-off contribution before attenuation
-    int pix;       // its pixel offset within the observer's I plane
-    int phase, order, next_dim, obs;
-};
+__device__ __forceinline__ uint32_t direction_key(const R k[3])
+{
+    const R s = fabs(k[0]) + fabs(k[1]) + fabs(k[2]);
+    R u = k[0] / s, v = k[1] / s;
+    if (k[2] < (R)0) {
+        const R uu = ((R)1 - fabs(v)) * (u >= (R)0 ? (R)1 : (R)-1);
+        const R vv = ((R)1 - fabs(u)) * (v >= (R)0 ? (R)1 : (R)-1);
+        u = uu;
+        v = vv;
+    }
+    int qu = (int)((u + (R)1) * (R)128), qv = (int)((v + (R)1) * (R)128);
+    qu = qu < 0 ? 0 : (qu > 255 ? 255 : qu);
+    qv = qv < 0 ? 0 : (qv > 255 ? 255 : qv);
+    return interleave2((uint32_t)qu, (uint32_t)qv, 8);
+}
 
+template <typename R, int KIND, int SRC>
+__device__ __forceinline__ void emit(const TransportParams &P, uint64_t idx, R p[3], R k[3]);
+
+template <typename R, int KIND, int SRC>
+__global__ void __launch_bounds__(256) k_key_emit(const TransportParams P, uint64_t first, uint32_t count,
+                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ hist)
+{
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
+        R p[3], k[3];
+        emit<R, KIND, SRC>(P, first + j, p, k);
+        const uint32_t key = direction_key(k);
+        keys[j] = key;
+        atomicAdd(hist + key, 1u);
+    }
+}
+
+// exclusive prefix sum of the 2^kSortBits bins, one block of 1024 lanes
+__global__ void __launch_bounds__(1024) k_scan_bins(uint32_t *__restrict__ hist)
+{
+    constexpr int nb = 1 << kSortBits, per = nb / 1024;
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    uint32_t sum = 0;
+    for (int i = 0; i < per; ++i) sum += hist[t * per + i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int i = 0; i < per; ++i) {
+        const uint32_t h = hist[t * per + i];
+        hist[t * per + i] = run;
+        run += h;
+    }
+}
+
+// place item i (or items[i]) at the next free position of its bin
+__global__ void __launch_bounds__(256) k_place(const uint32_t *__restrict__ keys, uint32_t count,
+                                               const uint32_t *__restrict__ items, uint32_t *__restrict__ hist,
+                                               uint32_t *__restrict__ out)
+{
+    const uint32_t n = count;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t pos = atomicAdd(hist + keys[i], 1u);
+        out[pos] = items ? items[i] : i;
+    }
+}
+
+// --------------------------------------------------------------------------
+// first flight
+// --------------------------------------------------------------------------
+template <typename R, int KIND, int SRC>
+__device__ __forceinline__ void emit(const TransportParams &P, uint64_t idx, R p[3], R k[3])
+{
+    if constexpr (SRC == 1) {
+        // direct order: v1,v2 -> point on the star; v3,v4 -> local direction
+        // (cos theta_l = sqrt(v4): uniform-brightness surface); v5 -> tau
+        uint32_t xa[3], xb[3];
+        seq_triple<KIND>(P.seq, idx, 0, xa);
+        seq_triple<KIND>(P.seq, idx, 2, xb);
+        R spe, cpe, spl, cpl;
+        sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
+        const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
+        const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
+        sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
+        const R ctl = sqrt(to_unit<R>(xb[1]));
+        const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
+        const R ne[3] = {ste * cpe, ste * spe, cte};
+        const R t1[3] = {cte * cpe, cte * spe, -ste};
+        const R t2[3] = {-spe, cpe, (R)0};
+        for (int a = 0; a < 3; ++a) {
+            p[a] = (R)P.src[a] + (R)P.r_star * ne[a];
+            k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
+        }
+    } else {
+        uint32_t x[3];
+        seq_triple<KIND>(P.seq, idx, 0, x);
+        R sp, cp;
+        sincos_2pi<R>(to_unit<R>(x[0]), sp, cp);
+        const R ct = (R)2 * to_unit<R>(x[1]) - (R)1;
+        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+        p[0] = (R)P.src[0]; p[1] = (R)P.src[1]; p[2] = (R)P.src[2];
+        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+    }
+}
+
+enum FirstPhase : int { FF_IDLE = 0, FF_EDGE = 1, FF_FORCED = 2 };
+
+template <typename R, int KIND, int SRC>
+__global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t first, uint32_t count,
+                                               const uint32_t *__restrict__ order,
+                                               PacketState<R> *__restrict__ pks, uint32_t *__restrict__ live0,
+                                               Queues *__restrict__ Q)
+{
+    const RayGrid<R> G = ray_grid<R>(P.grid);
+    uint64_t n_visits = 0;
+    uint32_t n_packets = 0, n_cuts = 0;
+    int phase = FF_IDLE;
+    uint32_t j = 0;
+    R p[3] = {(R)0, (R)0, (R)0}, k[3] = {(R)0, (R)0, (R)1};
+    R S0 = (R)0;
+    Walk<R> W;
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        bool append = false;
+        if (W.done && phase == FF_EDGE) {
+            n_visits += W.visits;
+            const double tau1 = W.tau;
+            if (tau1 < P.tau_min) {
+                n_cuts++;
+                phase = FF_IDLE;
+            } else {
+                const double W1 = -expm1(-tau1);
+                // optical-depth targets use all 32 bits of the coordinate in FP64, in both precisions
+                const double u = (double)seq_point<KIND>(P.seq, first + j, SRC == 1 ? 4 : 2) * 0x1p-32;
+                S0 = (R)W1;
+                walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
+                phase = FF_FORCED;
+            }
+        } else if (W.done && phase == FF_FORCED) {
+            n_visits += W.visits;
+            // if rounding lets the walk reach the edge first, scatter at the exit point
+            PacketState<R> s;
+            for (int a = 0; a < 3; ++a) {
+                s.p[a] = p[a] + W.t_out * k[a];
+                s.k[a] = k[a];
+            }
+            basis_of(k, s.m);
+            s.S[0] = S0; s.S[1] = (R)0; s.S[2] = (R)0;
+            s.target = 0.0;
+            s.idx = first + j;
+            s.next_dim = 0;
+            s.order = 1;
+            pks[j] = s;
+            append = true;
+            phase = FF_IDLE;
+        }
+        const uint32_t pos = wave_append(append, &Q->n_live[0]);
+        if (append) live0[pos] = j;
+        uint64_t item = 0;
+        if (pool.take(phase == FF_IDLE, count, &Q->work[0], item)) {
+            j = order[item];
+            n_packets++;
+            emit<R, KIND, SRC>(P, first + j, p, k);
+            walk_begin(W, G, p, k, WALK_EDGE, 0.0);
+            phase = FF_EDGE;
+        }
+        if (__ballot(phase != FF_IDLE) == 0 && pool.dry) break;
+        for (;;) {
+            walk_batch<R, kWalkBatch>(W, G);
+            if (__popcll(__ballot(W.done || phase == FF_IDLE)) >= kWaveRefill) break;
+        }
+    }
+    flush_counter(P.counters + CNT_PACKETS, n_packets);
+    flush_counter(P.counters + CNT_TAU_CUTS, n_cuts);
+    flush_counter(P.counters + CNT_VISITS, n_visits);
+}
+
+// --------------------------------------------------------------------------
+// scattering: albedo, peel-off contributions, new direction
+// --------------------------------------------------------------------------
 template <typename R>
-struct SharedObs {
+struct ObsTable {
     R o[kMaxObs][3], ex[kMaxObs][3], ey[kMaxObs][3];
 };
 
-// Set up the next peel-off ray of the current scattering, or move on.  Returns
-// true when a walk was started.
-template <typename R, int SRC>
-__device__ __forceinline__ bool next_peel(const TransportParams &P, const RayGrid<R> &G, const SharedObs<R> &SO,
-                                          Packet<R> &pk, Walk<R> &W, LocalCounters &L)
+template <typename R>
+__device__ __forceinline__ void load_obs(const TransportParams &P, ObsTable<R> &T)
 {
-    const R Rw = (R)P.half_width;
-    while (pk.obs < P.n_obs) {
-        const int ob = pk.obs;
-        R o[3] = {SO.o[ob][0], SO.o[ob][1], SO.o[ob][2]};
-        R ex[3] = {SO.ex[ob][0], SO.ex[ob][1], SO.ex[ob][2]};
-        R ey[3] = {SO.ey[ob][0], SO.ey[ob][1], SO.ey[ob][2]};
-        const R X = dot3(pk.p, ex), Y = dot3(pk.p, ey);
-        const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)P.npix);
-        const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)P.npix);
-        if (!(fx >= (R)0 && fy >= (R)0 && fx < (R)P.npix && fy < (R)P.npix)) { pk.obs++; continue; }
-        if constexpr (SRC == 1) {
-            R d[3] = {pk.p[0] - (R)P.src[0], pk.p[1] - (R)P.src[1], pk.p[2] - (R)P.src[2]};
-            const R b = dot3(d, o), cc = dot3(d, d) - (R)(P.r_star * P.r_star);
-            if (b < (R)0 && b * b > cc) { L.occluded++; pk.obs++; continue; }
-        }
-        R n[3];
-        cross3(pk.k, pk.m, n);
-        R c = dot3(pk.k, o);
-        c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
-        const R s = sqrt(fmax((R)0, (R)1 - c * c));
-        R St[3] = {pk.S[0], pk.S[1], pk.S[2]};
-        R mi[3];
-        if (s < (R)1e-12) {
-            mi[0] = pk.m[0]; mi[1] = pk.m[1]; mi[2] = pk.m[2];
-        } else {
-            const R inv_s = (R)1 / s;
-            for (int a = 0; a < 3; ++a) mi[a] = (o[a] - c * pk.k[a]) * inv_s;
-            rotate_stokes(St, dot3(pk.m, mi), dot3(n, mi));
-        }
-        R p11, r12, r33;
-        mueller((R)P.g, (R)P.p_lin, c, p11, r12, r33);
-        const R w = p11 * (R)(0.25 / 3.14159265358979323846);
-        R Sp[3] = {w * (St[0] + r12 * St[1]), w * (r12 * St[0] + St[1]), w * (r33 * St[2])};
-        R mo[3], no[3];
-        for (int a = 0; a < 3; ++a) mo[a] = c * mi[a] - s * pk.k[a];
-        cross3(o, mo, no);
-        rotate_stokes(Sp, dot3(mo, ex), dot3(no, ex));
-        pk.c[0] = Sp[0]; pk.c[1] = Sp[1]; pk.c[2] = Sp[2];
-        pk.pix = (int)fy * P.npix + (int)fx;
-        walk_begin(W, G, pk.p, o, WALK_EDGE, 0.0);
-        pk.phase = PH_PEEL;
-        return true;
-    }
-    return false;
-}
-
-// Advance a lane's packet from a finished walk (or a fresh index) to its next
-// walk; leaves the lane in PH_NEED when the packet is over.
-template <typename R, int KIND, int SRC>
-__device__ __forceinline__ void advance(const TransportParams &P, const RayGrid<R> &G, const SharedObs<R> &SO,
-                                        Packet<R> &pk, Walk<R> &W, LocalCounters &L)
-{
-    bool scatter = false;
-    if (pk.phase == PH_EMIT) {
-        L.packets++;
-        const uint64_t idx = pk.idx;
-        if constexpr (SRC == 1) {
-            // direct order: v1,v2 -> point on the star; v3,v4 -> local direction
-            // (cos theta_l = sqrt(v4): uniform-brightness surface); v5 -> tau
-            uint32_t xa[3], xb[3];
-            seq_triple<KIND>(P.seq, idx, 0, xa);
-            seq_triple<KIND>(P.seq, idx, 2, xb);
-            R spe, cpe, spl, cpl;
-            sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
-            const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
-            const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
-            sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
-            const R ctl = sqrt(to_unit<R>(xb[1]));
-            const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
-            const R ne[3] = {ste * cpe, ste * spe, cte};
-            const R t1[3] = {cte * cpe, cte * spe, -ste};
-            const R t2[3] = {-spe, cpe, (R)0};
-            for (int a = 0; a < 3; ++a) {
-                pk.p[a] = (R)P.src[a] + (R)P.r_star * ne[a];
-                pk.k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
-            }
-            pk.next_dim = 5;
-        } else {
-            uint32_t x[3];
-            seq_triple<KIND>(P.seq, idx, 0, x);
-            R sp, cp;
-            sincos_2pi<R>(to_unit<R>(x[0]), sp, cp);
-            const R ct = (R)2 * to_unit<R>(x[1]) - (R)1;
-            const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-            pk.p[0] = (R)P.src[0]; pk.p[1] = (R)P.src[1]; pk.p[2] = (R)P.src[2];
-            pk.k[0] = st * cp; pk.k[1] = st * sp; pk.k[2] = ct;
-            pk.next_dim = 3;
-        }
-        walk_begin(W, G, pk.p, pk.k, WALK_EDGE, 0.0);
-        pk.phase = PH_T1;
-        return;
-    } else if (pk.phase == PH_T1) {
-        L.visits += W.visits;
-        const double tau1 = W.tau;
-        if (tau1 < P.tau_min) {
-            L.tau_cuts++;
-            pk.phase = PH_NEED;
-            return;
-        }
-        const double W1 = -expm1(-tau1);
-        const int dim_tau = SRC == 1 ? 4 : 2;
-        // optical-depth targets use all 32 bits of the coordinate in FP64, in both precisions
-        const double u_tau = (double)seq_point<KIND>(P.seq, pk.idx, dim_tau) * 0x1p-32;
-        const double tau_f = -log1p(-u_tau * W1);
-        pk.S[0] = (R)W1; pk.S[1] = (R)0; pk.S[2] = (R)0;
-        walk_begin(W, G, pk.p, pk.k, WALK_MOVE, tau_f);
-        pk.phase = PH_FORCED;
-        return;
-    } else if (pk.phase == PH_FORCED) {
-        L.visits += W.visits;
-        // if rounding lets the walk reach the edge first, scatter at the exit point
-        for (int a = 0; a < 3; ++a) pk.p[a] += W.t_out * pk.k[a];
-        basis_of(pk.k, pk.m);
-        pk.order = 1;
-        scatter = true;
-    } else if (pk.phase == PH_FLIGHT) {
-        L.visits += W.visits;
-        if (!W.stopped) {
-            L.escapes++;
-            pk.phase = PH_NEED;
-            return;
-        }
-        for (int a = 0; a < 3; ++a) pk.p[a] += W.t_out * pk.k[a];
-        pk.order++;
-        scatter = true;
-    } else if (pk.phase == PH_PEEL) {
-        L.visits += W.visits;
-        L.peel_rays++;
-        L.peels++;
-        const double att = exp(-W.tau);
-        const size_t plane = (size_t)P.npix * (size_t)P.npix;
-        double *base = P.img + (size_t)pk.obs * 3 * plane + (size_t)pk.pix;
-        unsafeAtomicAdd(base, att * (double)pk.c[0]);
-        unsafeAtomicAdd(base + plane, att * (double)pk.c[1]);
-        unsafeAtomicAdd(base + 2 * plane, att * (double)pk.c[2]);
-        pk.obs++;
-    } else {
-        return;   // PH_NEED / PH_DONE: nothing to advance
-    }
-    if (scatter) {
-        L.scatterings++;
-        const R albedo = (R)P.albedo;
-        pk.S[0] *= albedo; pk.S[1] *= albedo; pk.S[2] *= albedo;
-        pk.obs = 0;
-    }
-    // peel-off toward the remaining observers of this scattering
-    if (next_peel<R, SRC>(P, G, SO, pk, W, L)) return;
-    if (pk.order == P.max_orders) {
-        pk.phase = PH_NEED;
-        return;
-    }
-    // new direction: i1 from the first number of the triple, cos(Theta) from the second
-    uint32_t x[3];
-    seq_triple<KIND>(P.seq, pk.idx, pk.next_dim, x);
-    pk.next_dim += 3;
-    R si, ci;
-    sincos_2pi<R>(to_unit<R>(x[0]), si, ci);
-    const R ct = hg_cos<R>((R)P.g, to_unit<R>(x[1]));
-    const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-    R n[3], mi[3];
-    cross3(pk.k, pk.m, n);
-    for (int a = 0; a < 3; ++a) mi[a] = ci * pk.m[a] + si * n[a];
-    rotate_stokes(pk.S, ci, si);
-    R p11, r12, r33;
-    mueller((R)P.g, (R)P.p_lin, ct, p11, r12, r33);
-    const R I1 = pk.S[0] + r12 * pk.S[1], Q1 = r12 * pk.S[0] + pk.S[1], U1 = r33 * pk.S[2];
-    pk.S[0] = I1; pk.S[1] = Q1; pk.S[2] = U1;
-    for (int a = 0; a < 3; ++a) {
-        const R kn = ct * pk.k[a] + st * mi[a];
-        const R mn = ct * mi[a] - st * pk.k[a];
-        pk.k[a] = kn;
-        pk.m[a] = mn;
-    }
-    const double tau2 = -log((double)x[2] * 0x1p-32);
-    walk_begin(W, G, pk.p, pk.k, WALK_MOVE, tau2);
-    pk.phase = PH_FLIGHT;
-}
-
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
-{
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ void flush_counters(const LocalCounters &L, unsigned long long *cnt)
-{
-    uint64_t vals[CNT_SCATTERINGS + 2] = {L.packets, L.visits, L.peels, L.peel_rays, L.escapes, L.tau_cuts,
-                                          L.scatterings, L.occluded};
-    const bool lead = (threadIdx.x & 63) == 0;
-#pragma unroll
-    for (int i = 0; i < CNT_SCATTERINGS + 2; ++i) {
-        uint64_t s = wave_sum_u64(vals[i]);
-        if (lead && s) atomicAdd(cnt + i, (unsigned long long)s);
-    }
-}
-
-constexpr int kWalkBatch = 4;
-constexpr int kWaveRefill = 16;   // handle packet events once this many lanes of a wave are idle
-
-template <typename R, int KIND, int SRC>
-__global__ void __launch_bounds__(256) k_transport(const TransportParams P, uint64_t first, uint64_t count,
-                                                   unsigned long long *__restrict__ work)
-{
-    __shared__ SharedObs<R> SO;
-    for (int i = threadIdx.x; i < P.n_obs; i += blockDim.x) {
+    for (int i = threadIdx.x; i < P.n_obs; i += blockDim.x)
         for (int a = 0; a < 3; ++a) {
-            SO.o[i][a] = (R)P.obs[i].o[a];
-            SO.ex[i][a] = (R)P.obs[i].ex[a];
-            SO.ey[i][a] = (R)P.obs[i].ey[a];
+            T.o[i][a] = (R)P.obs[i].o[a];
+            T.ex[i][a] = (R)P.obs[i].ex[a];
+            T.ey[i][a] = (R)P.obs[i].ey[a];
         }
-    }
     __syncthreads();
-    const RayGrid<R> G = ray_grid<R>(P.grid);
-    LocalCounters L = {};
-    Packet<R> pk;
-    pk.phase = PH_NEED;
-    pk.idx = 0;
-    Walk<R> W;
-    W.done = true;
-    W.visits = 0;
+}
+
+template <typename R, int KIND, int SRC>
+__global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
+                                                 const uint32_t *__restrict__ live_in, int in,
+                                                 PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+{
+    __shared__ ObsTable<R> T;
+    load_obs(P, T);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // counters of the walk that follows
+        Q->n_live[in ^ 1] = 0;
+        Q->work[1] = 0;
+    }
+    const uint32_t n = Q->n_live[in];
     const int lane = threadIdx.x & 63;
-    const uint64_t lanes_below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    // wave-uniform pool of packet offsets [pool_next, pool_end)
-    uint64_t pool_next = 0, pool_end = 0;
-    bool pool_dry = false;
-    for (;;) {
-        // give packets to lanes that need one, then advance every lane whose walk
-        // ended; twice, because a packet can end during its events
-        for (int pass = 0; pass < 2; ++pass) {
-            uint64_t need = __ballot(pk.phase == PH_NEED);
-            while (need && !pool_dry) {
-                if (pool_next >= pool_end) {
-                    unsigned long long base = 0;
-                    if (lane == 0) base = atomicAdd(work, 64ull);
-                    base = __shfl(base, 0, 64);
-                    pool_next = base;
-                    pool_end = base + 64 < count ? base + 64 : count;
-                    if (pool_next >= count) {
-                        pool_dry = true;
-                        break;
+    const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const R Rw = (R)P.half_width;
+    uint32_t n_scat = 0, n_occ = 0;
+    for (uint32_t base = wave0; base < n; base += stride) {
+        const uint32_t i = base + (uint32_t)lane;
+        const bool valid = i < n;
+        const uint32_t slot = valid ? live_in[i] : 0;
+        PacketState<R> s = {};
+        if (valid) {
+            s = pks[slot];
+            n_scat++;
+            const R albedo = (R)P.albedo;
+            s.S[0] *= albedo; s.S[1] *= albedo; s.S[2] *= albedo;
+        }
+        R n_ax[3];
+        cross3(s.k, s.m, n_ax);
+        for (int ob = 0; ob < P.n_obs; ++ob) {
+            bool vis = false;
+            R c3[3] = {(R)0, (R)0, (R)0};
+            uint32_t pix = 0;
+            if (valid) {
+                const R o[3] = {T.o[ob][0], T.o[ob][1], T.o[ob][2]};
+                const R ex[3] = {T.ex[ob][0], T.ex[ob][1], T.ex[ob][2]};
+                const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
+                const R X = dot3(s.p, ex), Y = dot3(s.p, ey);
+                const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)P.npix);
+                const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)P.npix);
+                vis = fx >= (R)0 && fy >= (R)0 && fx < (R)P.npix && fy < (R)P.npix;
+                if constexpr (SRC == 1) {
+                    if (vis) {
+                        R d[3] = {s.p[0] - (R)P.src[0], s.p[1] - (R)P.src[1], s.p[2] - (R)P.src[2]};
+                        const R b = dot3(d, o), cc = dot3(d, d) - (R)(P.r_star * P.r_star);
+                        if (b < (R)0 && b * b > cc) {   // the star blocks the ray
+                            n_occ++;
+                            vis = false;
+                        }
                     }
                 }
-                const uint64_t avail = pool_end - pool_next;
-                const uint64_t take = (uint64_t)__popcll(need) < avail ? (uint64_t)__popcll(need) : avail;
-                const uint64_t rank = (uint64_t)__popcll(need & lanes_below);
-                if (pk.phase == PH_NEED && rank < take) {
-                    pk.idx = first + pool_next + rank;
-                    pk.phase = PH_EMIT;
+                if (vis) {
+                    R c = dot3(s.k, o);
+                    c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
+                    const R sn = sqrt(fmax((R)0, (R)1 - c * c));
+                    R St[3] = {s.S[0], s.S[1], s.S[2]};
+                    R mi[3];
+                    if (sn < (R)1e-12) {
+                        mi[0] = s.m[0]; mi[1] = s.m[1]; mi[2] = s.m[2];
+                    } else {
+                        const R inv_s = (R)1 / sn;
+                        for (int a = 0; a < 3; ++a) mi[a] = (o[a] - c * s.k[a]) * inv_s;
+                        rotate_stokes(St, dot3(s.m, mi), dot3(n_ax, mi));
+                    }
+                    R p11, r12, r33;
+                    mueller((R)P.g, (R)P.p_lin, c, p11, r12, r33);
+                    const R w = p11 * (R)(0.25 / 3.14159265358979323846);
+                    c3[0] = w * (St[0] + r12 * St[1]);
+                    c3[1] = w * (r12 * St[0] + St[1]);
+                    c3[2] = w * (r33 * St[2]);
+                    R mo[3], no[3];
+                    for (int a = 0; a < 3; ++a) mo[a] = c * mi[a] - sn * s.k[a];
+                    cross3(o, mo, no);
+                    rotate_stokes(c3, dot3(mo, ex), dot3(no, ex));
+                    pix = (uint32_t)((int)fy * P.npix + (int)fx);
                 }
-                pool_next += take;
-                need = __ballot(pk.phase == PH_NEED);
             }
-            if (pool_dry && pk.phase == PH_NEED) pk.phase = PH_DONE;
-            if (pk.phase == PH_EMIT || (W.done && pk.phase != PH_NEED && pk.phase != PH_DONE))
-                advance<R, KIND, SRC>(P, G, SO, pk, W, L);
+            {
+                // slot layout: blocks of 64 rays, one observer per block, observers
+                // cycling between blocks: a wave walks 64 neighbouring packets'
+                // rays toward one observer while concurrent waves spread their
+                // image writes over all observers.  Invisible rays and the lanes
+                // past the end of the list are marked.
+                PeelRay<R> r;
+                r.p[0] = s.p[0]; r.p[1] = s.p[1]; r.p[2] = s.p[2];
+                r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
+                r.pix = (valid && vis) ? pix : kNoPixel;
+                r.obs = (uint32_t)ob;
+                peels[peel_slot(i, ob, P.n_obs)] = r;
+            }
         }
-        if (__ballot(pk.phase != PH_DONE) == 0) break;
-        // walk until enough lanes need events
+        if (valid && order < P.max_orders) {
+            // new direction: i1 from the first number of the triple, cos(Theta) from the second
+            const int dim = (SRC == 1 ? 5 : 3) + 3 * (order - 1);
+            uint32_t x[3];
+            seq_triple<KIND>(P.seq, s.idx, dim, x);
+            R si, ci;
+            sincos_2pi<R>(to_unit<R>(x[0]), si, ci);
+            const R ct = hg_cos<R>((R)P.g, to_unit<R>(x[1]));
+            const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+            R mi[3];
+            for (int a = 0; a < 3; ++a) mi[a] = ci * s.m[a] + si * n_ax[a];
+            rotate_stokes(s.S, ci, si);
+            R p11, r12, r33;
+            mueller((R)P.g, (R)P.p_lin, ct, p11, r12, r33);
+            const R I1 = s.S[0] + r12 * s.S[1], Q1 = r12 * s.S[0] + s.S[1], U1 = r33 * s.S[2];
+            s.S[0] = I1; s.S[1] = Q1; s.S[2] = U1;
+            for (int a = 0; a < 3; ++a) {
+                const R kn = ct * s.k[a] + st * mi[a];
+                const R mn = ct * mi[a] - st * s.k[a];
+                s.k[a] = kn;
+                s.m[a] = mn;
+            }
+            // free flight tau2 = -ln w, all 32 bits of w in FP64
+            s.target = -log((double)x[2] * 0x1p-32);
+            pks[slot] = s;
+        }
+    }
+    flush_counter(P.counters + CNT_SCATTERINGS, n_scat);
+    flush_counter(P.counters + CNT_OCCLUDED, n_occ);
+}
+
+// --------------------------------------------------------------------------
+// walks of one order: peel-off rays, then flights
+// --------------------------------------------------------------------------
+enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
+                                              const uint32_t *__restrict__ live_in, int in,
+                                              uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
+                                              Queues *__restrict__ Q)
+{
+    __shared__ R s_o[kMaxObs][3];
+    for (int i = threadIdx.x; i < P.n_obs; i += blockDim.x)
+        for (int a = 0; a < 3; ++a) s_o[i][a] = (R)P.obs[i].o[a];
+    __syncthreads();
+    const RayGrid<R> G = ray_grid<R>(P.grid);
+    const uint64_t n_live = Q->n_live[in];
+    const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t n_move = order < P.max_orders ? n_live : 0;
+    const uint64_t total = n_peel + n_move;
+    const size_t plane = (size_t)P.npix * (size_t)P.npix;
+    // image copy of this block (blocks go round-robin to the XCDs)
+    double *img_copy = P.img + (size_t)(blockIdx.x % kImageCopies) * (size_t)P.n_obs * 3 * plane;
+    uint64_t n_visits = 0;
+    uint32_t n_peels = 0, n_esc = 0;
+    int kind = WI_NONE;
+    uint32_t slot = 0, pix = 0, obs = 0;
+    R c3[3] = {(R)0, (R)0, (R)0};
+    Walk<R> W;
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        bool append = false;
+        if (W.done && kind == WI_PEEL) {
+            n_visits += W.visits;
+            n_peels++;
+            const double att = exp(-W.tau);
+            double *dst = img_copy + (size_t)obs * 3 * plane + (size_t)pix;
+            unsafeAtomicAdd(dst, att * (double)c3[0]);
+            unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
+            unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
+            kind = WI_NONE;
+        } else if (W.done && kind == WI_MOVE) {
+            n_visits += W.visits;
+            if (W.stopped) {
+                PacketState<R> *ps = pks + slot;
+                R q[3];
+                for (int a = 0; a < 3; ++a) q[a] = ps->p[a] + W.t_out * ps->k[a];
+                for (int a = 0; a < 3; ++a) ps->p[a] = q[a];
+                append = true;
+            } else {
+                n_esc++;
+            }
+            kind = WI_NONE;
+        }
+        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
+        if (append) live_out[pos] = slot;
+        uint64_t item = 0;
+        if (pool.take(kind == WI_NONE, total, &Q->work[1], item)) {
+            if (item < n_peel) {
+                const PeelRay<R> r = peels[item];
+                if (r.pix != kNoPixel) {
+                    const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
+                    c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                    pix = r.pix;
+                    obs = r.obs;
+                    walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                    kind = WI_PEEL;
+                }
+            } else {
+                slot = live_in[item - n_peel];
+                const PacketState<R> *ps = pks + slot;
+                const R p0[3] = {ps->p[0], ps->p[1], ps->p[2]};
+                const R k0[3] = {ps->k[0], ps->k[1], ps->k[2]};
+                walk_begin(W, G, p0, k0, WALK_MOVE, ps->target);
+                kind = WI_MOVE;
+            }
+        }
+        if (__ballot(kind != WI_NONE) == 0) {
+            if (pool.dry) break;
+            continue;   // every item just taken was an invisible peel ray
+        }
         for (;;) {
             walk_batch<R, kWalkBatch>(W, G);
-            const uint64_t idle = __ballot(W.done || pk.phase == PH_DONE || pk.phase == PH_NEED);
-            if (__popcll(idle) >= kWaveRefill) break;
+            if (__popcll(__ballot(W.done || kind == WI_NONE)) >= kWaveRefill) break;
         }
     }
-    flush_counters(L, P.counters);
+    flush_counter(P.counters + CNT_VISITS, n_visits);
+    flush_counter(P.counters + CNT_PEELS, n_peels);
+    flush_counter(P.counters + CNT_PEEL_RAYS, n_peels);
+    flush_counter(P.counters + CNT_ESCAPES, n_esc);
 }
 
-// blocks of 256 that fit on the device at once (the kernel is persistent)
-template <typename R, int KIND, int SRC>
-static int resident_blocks()
+// --------------------------------------------------------------------------
+// launch sequence
+// --------------------------------------------------------------------------
+template <typename F>
+static int resident_blocks_of(F kernel)
 {
-    static int cached = 0;
-    if (cached == 0) {
-        int per_cu = 0, dev = 0;
-        hipDeviceProp_t prop;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_transport<R, KIND, SRC>, 256, 0) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        (void)hipGetDevice(&dev);
-        int cus = 256;
-        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
-            cus = prop.multiProcessorCount;
-        cached = per_cu * cus;
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    (void)hipGetDevice(&dev);
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    return per_cu * cus;
+}
+
+template <typename R, int KIND, int SRC>
+static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
+                            hipStream_t st)
+{
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
+    if (!nb_first) {
+        nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
+        nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC>);
+        nb_walk = resident_blocks_of(k_walk<R>);
     }
-    return cached;
-}
-
-template <typename R, int KIND, int SRC>
-static hipError_t launch_one(const TransportParams &P, uint64_t first, uint64_t count, int cap,
-                             unsigned long long *work, hipStream_t st)
-{
-    const uint64_t need = (count + 255) / 256;
-    int blocks = resident_blocks<R, KIND, SRC>();
-    if (cap > 0 && blocks > cap) blocks = cap;
-    if ((uint64_t)blocks > need) blocks = (int)need;
-    hipLaunchKernelGGL((k_transport<R, KIND, SRC>), dim3(blocks), dim3(256), 0, st, P, first, count, work);
-    return hipGetLastError();
+    PacketState<R> *pks = (PacketState<R> *)B.packets;
+    PeelRay<R> *peels = (PeelRay<R> *)B.peels;
+    const size_t hist_bytes = sizeof(uint32_t) << kSortBits;
+    const uint32_t cblocks = (count + 255) / 256;
+    const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
+    hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
+    if (e == hipSuccess) e = hipMemsetAsync(B.hist, 0, hist_bytes, st);
+    if (e != hipSuccess) return e;
+    // first flights in emission-direction order
+    hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys, B.hist);
+    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, st, B.hist);
+    hipLaunchKernelGGL(k_place, dim3(b_elem), dim3(256), 0, st, (const uint32_t *)B.keys, count,
+                       (const uint32_t *)nullptr, B.hist, B.order);
+    const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
+    hipLaunchKernelGGL((k_first<R, KIND, SRC>), dim3(bf), dim3(256), 0, st, P, first, count,
+                       (const uint32_t *)B.order, pks, B.live[0], B.q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
+    for (int order = 1; order <= P.max_orders; ++order) {
+        const int in = (order - 1) & 1;
+        hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order, pks,
+                           (const uint32_t *)B.live[in], in, peels, B.q);
+        hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
+                           in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <typename R, int KIND>
-static hipError_t launch_src(const TransportParams &P, uint64_t first, uint64_t count, int cap,
-                             unsigned long long *work, hipStream_t st)
+static hipError_t run_src(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
+                          hipStream_t st)
 {
-    if (P.src_kind == 1) return launch_one<R, KIND, 1>(P, first, count, cap, work, st);
-    return launch_one<R, KIND, 0>(P, first, count, cap, work, st);
+    if (P.src_kind == 1) return run_chunk<R, KIND, 1>(P, first, count, B, st);
+    return run_chunk<R, KIND, 0>(P, first, count, B, st);
 }
 
 template <typename R>
-static hipError_t launch_kind(const TransportParams &P, int kind, uint64_t first, uint64_t count, int blocks,
-                              unsigned long long *work, hipStream_t st)
+static hipError_t run_kind(const TransportParams &P, int kind, uint64_t first, uint32_t count,
+                           const TransportBuffers &B, hipStream_t st)
 {
     switch (kind) {
-    case SEQ_SOBOL: return launch_src<R, SEQ_SOBOL>(P, first, count, blocks, work, st);
-    case SEQ_HALTON: return launch_src<R, SEQ_HALTON>(P, first, count, blocks, work, st);
-    case SEQ_NIED2: return launch_src<R, SEQ_NIED2>(P, first, count, blocks, work, st);
-    case SEQ_HAMMERSLEY: return launch_src<R, SEQ_HAMMERSLEY>(P, first, count, blocks, work, st);
-    case SEQ_PHILOX: return launch_src<R, SEQ_PHILOX>(P, first, count, blocks, work, st);
+    case SEQ_SOBOL: return run_src<R, SEQ_SOBOL>(P, first, count, B, st);
+    case SEQ_HALTON: return run_src<R, SEQ_HALTON>(P, first, count, B, st);
+    case SEQ_NIED2: return run_src<R, SEQ_NIED2>(P, first, count, B, st);
+    case SEQ_HAMMERSLEY: return run_src<R, SEQ_HAMMERSLEY>(P, first, count, B, st);
+    case SEQ_PHILOX: return run_src<R, SEQ_PHILOX>(P, first, count, B, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first, uint64_t count,
-                            int grid_blocks, unsigned long long *work, hipStream_t stream)
+                            const TransportBuffers &B, hipStream_t stream)
 {
-    if (count == 0) return hipSuccess;
-    hipError_t e = hipMemsetAsync(work, 0, sizeof(unsigned long long), stream);
-    if (e != hipSuccess) return e;
-    // grid_blocks > 0 caps the persistent grid (otherwise: every block that fits)
-    if (precision == 1) return launch_kind<double>(P, kind, first, count, grid_blocks, work, stream);
-    return launch_kind<float>(P, kind, first, count, grid_blocks, work, stream);
+    for (uint64_t done = 0; done < count;) {
+        const uint32_t n = (uint32_t)(count - done < kChunk ? count - done : kChunk);
+        hipError_t e = precision == 1 ? run_kind<double>(P, kind, first + done, n, B, stream)
+                                      : run_kind<float>(P, kind, first + done, n, B, stream);
+        if (e != hipSuccess) return e;
+        done += n;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------- image copies
+// add copies 1.. into copy 0 and clear them
+__global__ void __launch_bounds__(256) k_fold_images(double *__restrict__ img, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        double s = img[i];
+        for (int c = 1; c < kImageCopies; ++c) {
+            s += img[c * n + i];
+            img[c * n + i] = 0.0;
+        }
+        img[i] = s;
+    }
+}
+
+hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    size_t need = (n + 255) / 256;
+    int blocks = (int)(need < 4096 ? need : 4096);
+    hipLaunchKernelGGL(k_fold_images, dim3(blocks), dim3(256), 0, stream, img, n);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- optical depth of given rays

@@ -144,13 +144,17 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const RayGrid<R> &G, cons
 
 // B steps of a walk (no effect once done).  The cell sequence does not depend
 // on the densities, so the B cells are computed first and loaded together.
+// After the exit step the remaining steps of a batch repeat the last cell with
+// zero length: they add nothing and are not counted as visits.  The stop
+// position of a move is computed once, after the batch, for the step that
+// reached the target.
 template <typename R, int B>
 __device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
 {
     if (W.done) return;
     int cells[B];
     R t0s[B], segs[B];
-    bool valid[B];
+    uint32_t nv = 0;
     bool alive = true;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -158,7 +162,7 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
         const bool my = !mx && W.ty <= W.tz;
         const bool mz = !mx && !my;
         const R tn = fmin(W.tx, fmin(W.ty, W.tz));
-        valid[b] = alive;
+        nv += alive ? 1u : 0u;
         cells[b] = W.cell;
         t0s[b] = W.t;
         const R seg = tn - W.t;
@@ -181,31 +185,36 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
     R kr[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
-    bool done = false;
-    uint32_t nv = 0;
     double tau = W.tau;
+    bool hit = false;
+    double rem = 0.0;
+    R kr_hit = (R)1, t0_hit = (R)0;
+    uint32_t nv_hit = 0;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const bool use = valid[b] && !done;
-        nv += use ? 1u : 0u;
         const double dtau = (double)(kr[b] * segs[b]);
-        if (W.mode == WALK_MOVE && use && tau + dtau >= W.target) {
-            const double rem = W.target - tau;
-            W.t_out = t0s[b] + (rem > 0.0 ? (R)(rem / (double)kr[b]) : (R)0);
-            tau = rem > 0.0 ? W.target : tau;
-            W.stopped = true;
-            done = true;
-        } else {
-            tau += use ? dtau : 0.0;
-        }
+        const bool h = W.mode == WALK_MOVE && !hit && tau + dtau >= W.target;
+        rem = h ? W.target - tau : rem;
+        kr_hit = h ? kr[b] : kr_hit;
+        t0_hit = h ? t0s[b] : t0_hit;
+        nv_hit = h ? (uint32_t)(b + 1) : nv_hit;
+        hit = hit || h;
+        tau += hit ? 0.0 : dtau;
+    }
+    if (hit) {
+        W.t_out = t0_hit + (rem > 0.0 ? (R)((R)rem / kr_hit) : (R)0);
+        W.tau = rem > 0.0 ? W.target : tau;
+        W.stopped = true;
+        W.done = true;
+        W.visits += nv_hit < nv ? nv_hit : nv;
+        return;
     }
     W.tau = tau;
     W.visits += nv;
-    if (!done && !alive) {
-        done = true;
+    if (!alive) {
+        W.done = true;
         W.t_out = W.t;
     }
-    W.done = done;
 }
 
 template <typename R, int B>
