@@ -1,20 +1,26 @@
 """Benchmark of the QMC radiative-transfer hot path on one MI355X.
 
-One step = the whole transport of the flared-disk workload: a 128^3 FP32 mesh,
-point source, up to 20 scatterings, three observers with 256^2 Stokes I/Q/U
-images, and 2^22 packets for each of five point sets (Sobol, Halton,
-Niederreiter-2, Hammersley with N = 2^22, Philox PRNG), FP32 rays with FP64
-optical-depth and image sums.  The mesh is resident in HBM before timing.
+One step = the whole transport of the flared-disk workload (disk128): a 128^3
+FP32 mesh, point source, up to 20 scatterings, three observers with 256^2
+Stokes I/Q/U images, and 2^22 packets for each of five point sets (Sobol,
+Halton, Niederreiter-2, Hammersley with N = 2^22, Philox PRNG); FP32 rays with
+FP64 optical-depth and image sums.  The mesh is resident in HBM before timing.
 
-Prints one JSON line: photon packets/s over the timed steps, the roofline of
-the transport kernel (algorithmic bytes: 4 B per voxel visit + 24 B per peel
-contribution, exact counts from the kernel's counters, over the kernel time
-measured with HIP events on the launch stream), and the CPU oracle timed on a
-bounded sample of the same workload.
+The JSON line carries
+  value         photon packets/s over the timed steps (HIP events);
+  roofline      of the transport step: algorithmic bytes (4 B per voxel visit +
+                24 B per peel-off contribution, exact counts from the kernels'
+                counters) over the transport time measured with HIP events on
+                the launch stream; HBM traffic from committed rocprofv3 counters
+                when the kernel sources are unchanged since they were taken;
+  time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
+                the speed-up of each over the Monte Carlo (Philox) baseline;
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +33,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 KIND_ORDER = ("sobol", "halton", "niederreiter2", "hammersley", "philox")
 PHILOX_SEED = 12345
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_disk128.txt")
 
 
 def parse():
@@ -36,8 +43,39 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=1 << 22, help="packets per point set per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18, help="oracle packets per point set")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="oracle packets per point set")
+    ap.add_argument("--no-time-to-error", action="store_true")
+    ap.add_argument("--ref-log2", type=int, default=30, help="log2 packets of the reference images")
+    ap.add_argument("--sweep-log2", type=int, default=26, help="largest log2 packets of the error sweep")
     return ap.parse_args()
+
+
+def transport_source_hash() -> str:
+    """Hash of the sources that define the transport kernels (traffic counters
+    taken on other sources do not describe this build)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2406_15632_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per transport launch from the committed counter summary, or
+    None when it is missing or was taken on other kernel sources."""
+    from paper_2406_15632_amd.profile_report import read_traffic
+    try:
+        d = read_traffic(TRAFFIC_FILE)
+    except OSError:
+        return None
+    if d.get("source_hash") != transport_source_hash():
+        return None
+    try:
+        return float(d["bytes_per_step_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(sc, n_sample: int):
@@ -45,6 +83,8 @@ def cpu_baseline(sc, n_sample: int):
     from oracle import oracle as O
     from synth import scenes
     threads = max(1, min(16, os.cpu_count() or 1))
+    for name in KIND_ORDER:   # build the generator tables outside the timing
+        O.seq_tables(scenes.KIND_BY_NAME[name], sc.dims)
     t0 = time.perf_counter()
     for name in KIND_ORDER:
         kind = scenes.KIND_BY_NAME[name]
@@ -52,15 +92,71 @@ def cpu_baseline(sc, n_sample: int):
     dt = time.perf_counter() - t0
     total = n_sample * len(KIND_ORDER)
     return {"value": total / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sample} packets of each of the 5 point sets of the same disk128 workload "
-                      f"(FP64 oracle, OpenMP over packet ranges), {dt:.1f} s"}
+            "sample": f"first {n_sample} packets of each of the 5 point sets of the disk128 workload "
+                      f"(FP64 oracle, OpenMP over packet ranges, {threads} threads), {dt:.1f} s"}
+
+
+def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int):
+    """Image RMS error (I, all observers) against an independent high-N reference
+    versus kernel time, N = 2^12 .. 2^sweep_log2; Sobol is scored against a
+    Halton reference and every other set against a Sobol reference; the PRNG
+    errors are averaged over seeds (4 below 2^24 packets, 2 above) and run to
+    4x the largest quasi-random size, since they converge more slowly."""
+    import numpy as np
+    import torch
+
+    from paper_2406_15632_amd import metrics
+
+    def run(kind, n, seed=PHILOX_SEED):
+        ctx.set_sequence(kind, seed, n)
+        ctx.reset_images()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.run(1, n)
+        e1.record(stream)
+        img = ctx.read_images()
+        return img[:, 0], e0.elapsed_time(e1) * 1e-3
+
+    n_ref = 1 << ref_log2
+    ref_s, _ = run(qrt.SOBOL, n_ref)
+    ref_h, _ = run(qrt.HALTON, n_ref)
+    floor = metrics.rms_error(ref_s, ref_h)
+    names = {qrt.SOBOL: "sobol", qrt.HALTON: "halton", qrt.NIEDERREITER2: "niederreiter2",
+             qrt.HAMMERSLEY: "hammersley", qrt.PHILOX: "philox"}
+    curves = {}
+    for kind in kinds:
+        ref = ref_h if kind == qrt.SOBOL else ref_s
+        pts = []
+        top = sweep_log2 + (2 if kind == qrt.PHILOX else 0)   # MC needs ~4x the packets
+        for lg in range(12, top + 1):
+            seeds = ((1, 2, 3, 4) if lg < 24 else (1, 2)) if kind == qrt.PHILOX else (PHILOX_SEED,)
+            errs, ts = [], []
+            for sd in seeds:
+                img, t = run(kind, 1 << lg, sd)
+                errs.append(metrics.rms_error(img, ref))
+                ts.append(t)
+            pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg))
+        curves[names[kind]] = pts
+    targets = (0.05, 0.01, 0.003)
+    out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor,
+           "rms_error_by_log2_packets": {k: {int(p[2]).bit_length() - 1: round(p[1], 6) for p in v}
+                                         for k, v in curves.items()},
+           "time_s": {}, "speedup_vs_mc": {}}
+    for k, pts in curves.items():
+        ts = [p[0] for p in pts]
+        es = [p[1] for p in pts]
+        out["time_s"][k] = [metrics.time_to_error(ts, es, tg) if tg >= 3 * floor else None for tg in targets]
+    mc = out["time_s"]["philox"]
+    for k, tt in out["time_s"].items():
+        out["speedup_vs_mc"][k] = [(m / t if (m is not None and t) else None) for m, t in zip(mc, tt)]
+    return out
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described in DESIGN.md)"}))
+                                   "(DESIGN.md describes how the path would shard)"}))
         sys.exit(2)
     import torch
 
@@ -106,11 +202,12 @@ def main():
     cnt = ctx.counters()
     per_kind_ms = {KIND_ORDER[j]: sum(launch_events[s][j][0].elapsed_time(launch_events[s][j][1])
                                       for s in range(args.steps)) / args.steps for j in range(len(kinds))}
-    kernel_ms = sum(per_kind_ms.values()) * args.steps
+    transport_ms = sum(per_kind_ms.values()) * args.steps
     n_launch = args.steps * len(kinds)
     alg_bytes = 4.0 * cnt["visits"] + 24.0 * cnt["peels"]
-    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    achieved = alg_bytes / (transport_ms * 1e-3) / 1e9
     packets = args.steps * len(kinds) * N
+    traffic = committed_traffic() if N == 1 << 22 else None
     result = {
         "metric": "photon packets/s (QMC radiative transfer, disk128 workload)",
         "value": packets / (elapsed_ms * 1e-3),
@@ -138,16 +235,20 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "kernel": "k_transport<float,*,point>",
+            "traffic": traffic,
+            "kernel": "transport step qrt_run: k_key_emit, k_scan_bins, k_place, k_first, "
+                      "then per scattering order k_scatter and k_walk",
             "alg_bytes_per_launch": alg_bytes / n_launch,
-            "avg_launch_ms": kernel_ms / n_launch,
+            "avg_launch_ms": transport_ms / n_launch,
         },
         "per_sequence_packets_per_s": {k: N / (v * 1e-3) for k, v in per_kind_ms.items()},
         "counters_per_packet": {k: cnt[k] / cnt["packets"] for k in ("visits", "peels", "scatterings",
                                                                    "escapes", "tau_cuts")},
         "wall_s": wall,
     }
+    if not args.no_time_to_error:
+        result["time_to_error"] = time_to_error_sweep(ctx, qrt, sc, kinds, stream, args.ref_log2,
+                                                      args.sweep_log2)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()
