@@ -47,13 +47,20 @@ class _Scene(C.Structure):
         ("mat", C.POINTER(C.c_uint32)), ("bases", C.POINTER(C.c_uint32)),
         ("seed", C.c_uint64), ("n_total", C.c_uint64),
         ("max_orders", C.c_int64), ("tau_min", C.c_double),
+        ("peel_mode", C.c_int64), ("mlp", C.POINTER(C.c_float)),
+        ("dom_center", C.c_double * 3),
+        ("dom_r_in", C.c_double), ("dom_r_out", C.c_double), ("dom_h0", C.c_double),
+        ("dom_beta", C.c_double), ("dom_zmax", C.c_double),
+        ("dom_nr", C.c_int64), ("dom_nz", C.c_int64),
+        ("dom_valid", C.POINTER(C.c_uint8)),
     ]
 
 
 class Counters(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("packets", "visits", "peels", "peel_rays", "escapes",
                                          "tau_cuts", "scatterings", "occluded")] + \
-               [(f, C.c_double) for f in ("e_direct", "e_absorbed", "e_escaped", "e_remaining")]
+               [(f, C.c_double) for f in ("e_direct", "e_absorbed", "e_escaped", "e_remaining")] + \
+               [(f, C.c_int64) for f in ("surrogate", "fallbacks")]
 
     def as_dict(self) -> Dict[str, float]:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -83,6 +90,10 @@ def lib() -> C.CDLL:
         L.oracle_quad_flux.argtypes = [C.POINTER(_Scene), C.c_int64, C.c_int64, C.c_int64, C.c_int64]
         L.oracle_quad_flux.restype = C.c_double
         L.oracle_quad_pixels.argtypes = [C.POINTER(_Scene), C.c_int64, C.c_int64, C.c_int64, C.c_void_p]
+        L.oracle_mlp_batch.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.oracle_mlp_tau.argtypes = [C.POINTER(_Scene), C.c_void_p, C.c_int64]
+        L.oracle_mlp_tau.restype = C.c_double
+        L.oracle_dom_cells.argtypes = [C.POINTER(_Scene), C.c_int64, C.c_void_p, C.c_void_p]
         _lib = L
     return _lib
 
@@ -113,10 +124,24 @@ def points(kind: int, dims: int, first: int, count: int, seed: int = 0, n_total:
     return out
 
 
+class Surrogate:
+    """Surrogate peel-off set-up: FP32 network parameters (layout of
+    oracle/mlp.py), the cylindrical domain and its validity mask
+    [n_obs][n_r][n_z] (1 = network allowed)."""
+
+    def __init__(self, params, center, r_in, r_out, h0, beta, zmax_over_h, valid):
+        self.params = np.ascontiguousarray(params, dtype=np.float32)
+        self.center = tuple(float(c) for c in center)
+        self.r_in, self.r_out, self.h0, self.beta, self.zmax = map(float, (r_in, r_out, h0, beta, zmax_over_h))
+        self.valid = np.ascontiguousarray(valid, dtype=np.uint8)
+        assert self.valid.ndim == 3
+
+
 class OracleScene:
     """Keeps the numpy buffers alive behind a _Scene structure."""
 
-    def __init__(self, sc, kind: int = SOBOL, seed: int = 0, n_total: Optional[int] = None):
+    def __init__(self, sc, kind: int = SOBOL, seed: int = 0, n_total: Optional[int] = None,
+                 surrogate: Optional[Surrogate] = None):
         self.sc = sc
         self.kr = np.ascontiguousarray(sc.kappa_rho, dtype=np.float32)
         th = np.array([o[0] for o in sc.observers] or [0.0], dtype=np.float64)
@@ -145,6 +170,16 @@ class OracleScene:
         s.n_total = n_total if n_total is not None else sc.n_packets
         s.max_orders = sc.max_orders
         s.tau_min = sc.tau_min
+        self.surrogate = surrogate
+        if surrogate is not None:
+            sg = surrogate
+            s.peel_mode = 1
+            s.mlp = sg.params.ctypes.data_as(C.POINTER(C.c_float))
+            s.dom_center = (C.c_double * 3)(*sg.center)
+            s.dom_r_in, s.dom_r_out, s.dom_h0, s.dom_beta, s.dom_zmax = \
+                sg.r_in, sg.r_out, sg.h0, sg.beta, sg.zmax
+            s.dom_nr, s.dom_nz = sg.valid.shape[1], sg.valid.shape[2]
+            s.dom_valid = sg.valid.ctypes.data_as(C.POINTER(C.c_uint8))
         self.s = s
 
 
@@ -175,11 +210,12 @@ EVENT_FIELDS = ("px", "py", "pz", "X", "Y", "I", "Q", "U", "cos_obs", "order", "
 
 def run(sc, kind: int = SOBOL, first: int = 1, count: Optional[int] = None, seed: int = 0,
         n_total: Optional[int] = None, nthreads: int = 1, max_events: int = 0,
-        normalize: bool = True):
+        normalize: bool = True, surrogate: Optional[Surrogate] = None):
     """Run packets first..first+count-1 of a scene.  Returns (images [n_obs][3][npix][npix],
-    counters dict, events array or None).  Images are divided by count when normalize."""
+    counters dict, events array or None).  Images are divided by count when normalize.
+    With `surrogate`, peel-off optical depths inside valid cells come from the network."""
     count = sc.n_packets if count is None else count
-    osc = OracleScene(sc, kind, seed, n_total)
+    osc = OracleScene(sc, kind, seed, n_total, surrogate)
     img = np.zeros((len(sc.observers), 3, sc.npix, sc.npix), dtype=np.float64)
     cnt = Counters()
     ev = np.zeros((max_events, len(EVENT_FIELDS)), dtype=np.float64) if max_events else None
@@ -193,6 +229,31 @@ def run(sc, kind: int = SOBOL, first: int = 1, count: Optional[int] = None, seed
     if ev is not None:
         ev = ev[: nev.value]
     return img, cnt.as_dict(), ev
+
+
+def mlp_batch(params, X) -> np.ndarray:
+    """Raw outputs of the C network (bfloat16 emulation) for inputs X[n][5]."""
+    th = np.ascontiguousarray(params, dtype=np.float32)
+    Xa = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.zeros(len(Xa))
+    lib().oracle_mlp_batch(th.ctypes.data, len(Xa), Xa.ctypes.data, y.ctypes.data)
+    return y
+
+
+def mlp_tau(sc, surrogate: Surrogate, p, obs: int) -> float:
+    """Clamped network optical depth from position p toward observer obs."""
+    osc = OracleScene(sc, surrogate=surrogate)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    return lib().oracle_mlp_tau(C.byref(osc.s), pa.ctypes.data, obs)
+
+
+def dom_cells(sc, surrogate: Surrogate, p) -> np.ndarray:
+    """Domain cell index ir * n_z + iz (or -1) of positions p[n][3]."""
+    osc = OracleScene(sc, surrogate=surrogate)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(len(pa), dtype=np.int64)
+    lib().oracle_dom_cells(C.byref(osc.s), len(pa), pa.ctypes.data, out.ctypes.data)
+    return out
 
 
 def max_threads() -> int:

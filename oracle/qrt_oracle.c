@@ -61,11 +61,20 @@ typedef struct {
     uint64_t seed, n_total;
     int64_t max_orders;
     double tau_min;
+    /* surrogate peel-off optical depth (not part of the paper; network and
+       domain as described in oracle/mlp.py) */
+    int64_t peel_mode;            /* 0 exact traversal, 1 network inside its valid cells */
+    const float *mlp;             /* 12929 FP32 parameters */
+    double dom_center[3];
+    double dom_r_in, dom_r_out, dom_h0, dom_beta, dom_zmax;
+    int64_t dom_nr, dom_nz;
+    const uint8_t *dom_valid;     /* [n_obs][nr][nz], 1 = network allowed */
 } og_scene;
 
 typedef struct {
     int64_t packets, visits, peels, peel_rays, escapes, tau_cuts, scatterings, occluded;
     double e_direct, e_absorbed, e_escaped, e_remaining;
+    int64_t surrogate, fallbacks;
 } og_counters;
 
 /* ------------------------------------------------------------------------- */
@@ -314,6 +323,92 @@ static void og_make_obs(double th, double ph, og_obs *O)
     og_cross(O->o, O->ex, O->ey);
 }
 
+/* ------------------------------------------------------------------------- */
+/* surrogate peel-off optical depth (an addition to the method: a network     */
+/* replaces the traversal toward the observer inside a validated domain)      */
+/* ------------------------------------------------------------------------- */
+
+/* FP32 rounding, then bfloat16 rounding to nearest with ties to even */
+static double og_bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* 5 -> 64 -> 64 -> 64 -> 64 -> 1 ReLU network; inputs, weights and hidden
+   activations in bfloat16, sums in FP64, biases as given. */
+static double og_mlp(const float *th, const double xin[5])
+{
+    static const int sizes[6] = {5, 64, 64, 64, 64, 1};
+    double a[64], z[64];
+    for (int i = 0; i < 5; ++i) a[i] = og_bf16(xin[i]);
+    const float *W = th;
+    for (int l = 0; l < 5; ++l) {
+        int ni = sizes[l], no = sizes[l + 1];
+        const float *b = W + ni * no;
+        for (int o = 0; o < no; ++o) {
+            double acc = (double)b[o];
+            for (int i = 0; i < ni; ++i) acc += og_bf16((double)W[i * no + o]) * a[i];
+            z[o] = acc;
+        }
+        if (l < 4)
+            for (int o = 0; o < no; ++o) a[o] = og_bf16(z[o] > 0.0 ? z[o] : 0.0);
+        W = b + no;
+    }
+    return z[0];
+}
+
+/* Cell of p in the cylindrical domain around dom_center (R bins over
+   [r_in, r_out), z/h(R) bins over (-zmax, zmax), h = h0 R^beta); -1 outside. */
+static int64_t og_dom_cell(const og_scene *S, const double p[3])
+{
+    double dx = p[0] - S->dom_center[0], dy = p[1] - S->dom_center[1], dz = p[2] - S->dom_center[2];
+    double R = sqrt(dx * dx + dy * dy);
+    if (!(R >= S->dom_r_in && R < S->dom_r_out)) return -1;
+    double zh = dz / (S->dom_h0 * pow(R, S->dom_beta));
+    if (!(fabs(zh) < S->dom_zmax)) return -1;
+    int64_t ir = (int64_t)floor((R - S->dom_r_in) / (S->dom_r_out - S->dom_r_in) * (double)S->dom_nr);
+    int64_t iz = (int64_t)floor((zh + S->dom_zmax) / (2.0 * S->dom_zmax) * (double)S->dom_nz);
+    if (ir < 0 || ir >= S->dom_nr || iz < 0 || iz >= S->dom_nz) return -1;
+    return ir * S->dom_nz + iz;
+}
+
+/* Network inputs: position mapped from the box to [-1,1], observer angles
+   2 theta / pi - 1 and phi / pi - 1, each rounded to FP32. */
+static void og_mlp_inputs(const og_scene *S, const double p[3], int obs, double x[5])
+{
+    for (int a = 0; a < 3; ++a)
+        x[a] = (double)(float)(2.0 * (p[a] - S->lo[a]) / (S->hi[a] - S->lo[a]) - 1.0);
+    x[3] = (double)(float)(2.0 * S->obs_theta[obs] / OG_PI - 1.0);
+    x[4] = (double)(float)(S->obs_phi[obs] / OG_PI - 1.0);
+}
+
+double oracle_mlp_tau(const og_scene *S, const double p[3], int64_t obs)
+{
+    double x[5];
+    og_mlp_inputs(S, p, (int)obs, x);
+    double t = og_mlp(S->mlp, x);
+    return t > 0.0 ? t : 0.0;
+}
+
+/* Raw network outputs (no clamp) for n input rows X[n][5]. */
+int oracle_mlp_batch(const float *th, int64_t n, const double *X, double *y)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = og_mlp(th, X + 5 * i);
+    return 0;
+}
+
+/* Domain cells (ir * nz + iz, or -1) of n positions p[n][3]. */
+int oracle_dom_cells(const og_scene *S, int64_t n, const double *p, int64_t *cell)
+{
+    for (int64_t i = 0; i < n; ++i) cell[i] = og_dom_cell(S, p + 3 * i);
+    return 0;
+}
+
 /* event log record for tests: p[3], X, Y, I, Q, U, cos(Theta_obs), order, obs */
 #define OG_EVENT_WORDS 11
 
@@ -365,9 +460,17 @@ static void og_peel(const og_scene *S, const double p[3], const double k[3], con
     og_cross(O->o, mout, nout);
     og_rotate(Sp, og_dot(mout, O->ex), og_dot(nout, O->ex));
     int64_t vis = 0;
-    double tau = og_walk(S, p, O->o, 0, 0.0, NULL, NULL, &vis);
-    sink->C->visits += vis;
-    sink->C->peel_rays++;
+    double tau;
+    int64_t cell = S->peel_mode == 1 ? og_dom_cell(S, p) : -1;
+    if (cell >= 0 && S->dom_valid[(int64_t)obs * S->dom_nr * S->dom_nz + cell]) {
+        tau = oracle_mlp_tau(S, p, obs);
+        sink->C->surrogate++;
+    } else {
+        tau = og_walk(S, p, O->o, 0, 0.0, NULL, NULL, &vis);
+        sink->C->visits += vis;
+        sink->C->peel_rays++;
+        if (S->peel_mode == 1) sink->C->fallbacks++;
+    }
     double att = exp(-tau);
     int64_t ix = (int64_t)fx, iy = (int64_t)fy;
     size_t base = ((size_t)obs * 3) * (size_t)S->npix * (size_t)S->npix + (size_t)iy * (size_t)S->npix + (size_t)ix;
@@ -515,6 +618,7 @@ static void og_add_counters(og_counters *a, const og_counters *b)
     a->scatterings += b->scatterings; a->occluded += b->occluded;
     a->e_direct += b->e_direct; a->e_absorbed += b->e_absorbed;
     a->e_escaped += b->e_escaped; a->e_remaining += b->e_remaining;
+    a->surrogate += b->surrogate; a->fallbacks += b->fallbacks;
 }
 
 /* Run packets first .. first+count-1 and ADD their (unnormalised) Stokes sums to
