@@ -134,7 +134,8 @@ int qrt_set_sequence(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total);
 
 /* Transport (Sec. 3.2, 3.5): at most max_orders scatterings (1 .. 42 for a
    point source), tau_min cut-off of the first flight, precision QRT_FP32 or
-   QRT_FP64, peel_mode QRT_PEEL_EXACT or QRT_PEEL_SURROGATE. */
+   QRT_FP64, peel_mode QRT_PEEL_EXACT or QRT_PEEL_SURROGATE (needs network
+   parameters and a domain, else QRT_NOT_TRAINED; see the surrogate section). */
 int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precision, int peel_mode);
 
 /* Transport packets first_index .. first_index+count-1 (first_index >= 1) and
@@ -169,6 +170,110 @@ int qrt_generate_points(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total,
    All pointers are device pointers; asynchronous (Sec. 3.4). */
 int qrt_trace_tau(qrt_ctx *ctx, int64_t n, const double *p, const double *k, double *tau,
                   int64_t *visits);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate peel-off optical depth.
+ *
+ * An addition to the paper's method: the paper finds that integrating optical
+ * depth along rays takes almost all of the run time (Sec. 3.1), and the
+ * peel-off rays toward the observers (Sec. 3.6) are most of those rays.
+ * Inside a validated domain the surrogate replaces the traversal of a
+ * peel-off ray by a small network tau_hat(x, y, z, theta_obs, phi_obs):
+ *   5 inputs -> 4 hidden layers of 64 ReLU units -> 1 output, clamped at 0.
+ * Inputs: position mapped from the mesh box to [-1, 1] per axis (FP64, then
+ * rounded to FP32), 2 theta / pi - 1 and phi / pi - 1 of the observer.
+ * Inference and training run on the matrix cores in bfloat16 with FP32
+ * accumulation; FP32 master weights and Adam moments.
+ * Parameters: QRT_MLP_PARAMS FP32 values, layer by layer, each W[in][out]
+ * row-major followed by b[out]: W0 5x64, b0, W1 64x64, b1, W2, b2, W3, b3,
+ * W4 64x1, b4.
+ * Domain: cylinder around `center`, R in [r_in, r_out) in n_r equal bins and
+ * z / h(R) in (-zmax, zmax) in n_z equal bins, h(R) = h0 R^beta (a flared
+ * disk's scale height); a mask [n_obs][n_r][n_z] marks the cells where the
+ * network is used.  Every other peel-off ray is traversed exactly (the
+ * fallback), so a zero mask reproduces the exact transport.
+ * Samples: rows of 4 floats (x, y, z, observer index) with FP32 labels tau.
+ * ------------------------------------------------------------------------- */
+
+#define QRT_MLP_PARAMS 12929
+
+typedef struct {
+    int64_t steps;        /* Adam steps */
+    int32_t batch;        /* samples per step: a multiple of 64 in 64 .. 65536 */
+    int32_t init;         /* 1: fresh random initialisation from seed; 0: continue from the current parameters */
+    float lr, lr_final;   /* learning rate, cosine-decayed from lr to lr_final over the steps */
+    float beta1, beta2, eps;
+    float tau_cap;        /* regression target min(tau, tau_cap) */
+    float weight_floor;   /* sample weight exp(-target) + weight_floor */
+    uint64_t seed;        /* initialisation and batch selection */
+} qrt_train_cfg;
+
+typedef struct {
+    double loss_first;    /* weighted squared error over all samples before and after training */
+    double loss_final;
+    int64_t steps;
+} qrt_train_report;
+
+typedef struct {
+    int64_t cells;        /* n_obs * n_r * n_z */
+    int64_t valid_cells;  /* cells marked for the network */
+    int64_t samples;      /* validation samples inside the domain */
+    int64_t samples_valid;/* ... of which in valid cells */
+    double max_err_valid; /* largest relative transmission error of a valid cell */
+} qrt_mask_report;
+
+/* Network parameters from / to the host (n = QRT_MLP_PARAMS).  Setting them
+   resets the Adam moments.  Synchronous. */
+int qrt_mlp_set_params(qrt_ctx *ctx, const float *params, int64_t n);
+int qrt_mlp_get_params(qrt_ctx *ctx, float *params, int64_t n);
+
+/* Random parameters: weights uniform in +-sqrt(6 / fan_in), biases 0. */
+int qrt_mlp_init(qrt_ctx *ctx, uint64_t seed);
+
+/* Raw network outputs y[n] (not clamped) for normalised inputs X[n][5].
+   Device pointers; asynchronous. */
+int qrt_mlp_forward(qrt_ctx *ctx, int64_t n, const float *X, float *y);
+
+/* grad[QRT_MLP_PARAMS] = gradient of sum_j dy[j] * y[j] over rows X[n][5]
+   (1 <= n <= 2^24).  Device pointers; asynchronous. */
+int qrt_mlp_backward(qrt_ctx *ctx, int64_t n, const float *X, const float *dy, float *grad);
+
+/* Domain of the surrogate; clears the mask (no cell uses the network).
+   Changing the observers clears the mask too. */
+int qrt_surrogate_set_domain(qrt_ctx *ctx, const double center[3], double r_in, double r_out, double h0,
+                             double beta, double zmax_over_h, int n_r, int n_z);
+
+/* Mask [n_obs][n_r][n_z] (1 = use the network) from / to the host. */
+int qrt_surrogate_set_mask(qrt_ctx *ctx, const uint8_t *mask);
+int qrt_surrogate_get_mask(qrt_ctx *ctx, uint8_t *mask);
+
+/* Normalised network inputs X[n][5] of sample rows pos_obs[n][4].  Device
+   pointers; asynchronous. */
+int qrt_surrogate_inputs(qrt_ctx *ctx, int64_t n, const float *pos_obs, float *X);
+
+/* Training samples from a pilot run: Philox packets (key seed) of the current
+   scene, exact peel-off, chunk by chunk until n visible peel-off rays inside
+   the domain are captured; of all captured rays the n with the smallest hash
+   of their bytes are kept (a reproducible uniform subsample).  Labels are the
+   exact FP64 optical depths toward the observer.  pos_obs[n][4] and tau[n]
+   are device pointers; *pilot_packets (may be NULL) gets the packets run.
+   Resets the images and counters.  Synchronous; 1 <= n <= 2^26. */
+int qrt_surrogate_sample(qrt_ctx *ctx, int64_t n, uint64_t seed, float *pos_obs, float *tau,
+                         int64_t *pilot_packets);
+
+/* Adam on the weighted squared error of the network against min(tau, cap)
+   with weights exp(-min(tau, cap)) + weight_floor, batches drawn by a hash of
+   (seed, step, position).  Device sample buffers; rep may be NULL.
+   Synchronous (reads the loss before and after). */
+int qrt_surrogate_train(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, const qrt_train_cfg *cfg,
+                        qrt_train_report *rep);
+
+/* Builds the mask from validation samples: a cell (observer, R bin, z bin)
+   is valid when it holds at least min_count samples and
+   sum |exp(-tau_hat) - exp(-tau)| <= max_err * sum exp(-tau) over them.
+   Device sample buffers; rep may be NULL.  Synchronous. */
+int qrt_surrogate_validate(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, double max_err,
+                           int64_t min_count, qrt_mask_report *rep);
 
 #ifdef __cplusplus
 }

@@ -7,10 +7,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "qrt.h"
 #include "qrt_internal.h"
+#include "qrt_mlp.h"
 
 namespace qrt {
 void niederreiter2_columns(int dims, uint32_t *out);
@@ -58,6 +61,21 @@ struct qrt_ctx {
     TransportBuffers tb = {};                // packet and ray queues of the transport
     uint64_t tb_packets = 0;                 // packets the queues hold
     uint64_t packets_run = 0;
+    // surrogate network: parameters, Adam moments, weight tiles
+    float *mlp = nullptr;                    // [3][kMlpParams]: parameters, m, v
+    void *tiles = nullptr;                   // kMlpTiles x 64 lanes x 16 bytes
+    bool has_mlp = false;
+    int64_t adam_t = 0;                      // Adam steps taken since the parameters were set
+    float *part = nullptr;                   // per-wave gradients
+    size_t part_elems = 0;
+    float *train_x = nullptr;                // normalised training inputs
+    size_t train_x_elems = 0;
+    // surrogate domain and validity mask
+    bool has_domain = false;
+    double dom_center[3] = {0, 0, 0};
+    double dom_r_in = 0, dom_r_out = 0, dom_h0 = 0, dom_beta = 0, dom_zmax = 0;
+    int dom_nr = 0, dom_nz = 0;
+    uint8_t *dom_valid = nullptr;            // [QRT_MAX_OBSERVERS][nr][nz] on the device
 };
 
 namespace {
@@ -221,6 +239,11 @@ void qrt_destroy(qrt_ctx *c)
     if (c->tb.order) (void)hipFree(c->tb.order);
     if (c->tb.keys) (void)hipFree(c->tb.keys);
     if (c->tb.hist) (void)hipFree(c->tb.hist);
+    if (c->mlp) (void)hipFree(c->mlp);
+    if (c->tiles) (void)hipFree(c->tiles);
+    if (c->part) (void)hipFree(c->part);
+    if (c->train_x) (void)hipFree(c->train_x);
+    if (c->dom_valid) (void)hipFree(c->dom_valid);
     delete c;
 }
 
@@ -359,6 +382,9 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
     c->npix = npix;
     c->half_width = half_width;
     c->has_obs = true;
+    if (c->dom_valid)   // a mask is validated for given observer directions
+        HIP_TRY(c, hipMemsetAsync(c->dom_valid, 0, (size_t)QRT_MAX_OBSERVERS * c->dom_nr * c->dom_nz, c->stream),
+                "mask reset");
     return qrt_reset_images(c);
 }
 
@@ -382,7 +408,8 @@ int qrt_set_transport(qrt_ctx *c, int max_orders, double tau_min, int precision,
     if (precision != QRT_FP32 && precision != QRT_FP64) return fail(c, QRT_INVALID_ARG, "unknown precision");
     if (peel_mode != QRT_PEEL_EXACT && peel_mode != QRT_PEEL_SURROGATE)
         return fail(c, QRT_INVALID_ARG, "unknown peel mode");
-    if (peel_mode == QRT_PEEL_SURROGATE) return fail(c, QRT_NOT_TRAINED, "no trained surrogate network");
+    if (peel_mode == QRT_PEEL_SURROGATE && (!c->has_mlp || !c->has_domain))
+        return fail(c, QRT_NOT_TRAINED, "the surrogate needs network parameters and a domain");
     c->max_orders = max_orders;
     c->tau_min = tau_min;
     c->precision = precision;
@@ -403,17 +430,24 @@ static DevGrid dev_grid(const qrt_ctx *c)
     return g;
 }
 
-int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
+static InputMap input_map(const qrt_ctx *c)
 {
-    if (!c) return QRT_INVALID_ARG;
-    if (!c->has_grid || !c->has_source || !c->has_obs)
-        return fail(c, QRT_BAD_STATE, "set grid, source and observers before running");
-    if (point_dims(c) > kMaxDims)
-        return fail(c, QRT_UNSUPPORTED, "%d point dimensions exceed the %d served", point_dims(c), kMaxDims);
-    int rc = check_index_range(c, c->kind, c->n_total, first, count);
-    if (rc) return rc;
-    if (count == 0) return QRT_OK;
-    TransportParams P;
+    InputMap M;
+    memset(&M, 0, sizeof(M));
+    for (int a = 0; a < 3; ++a) {
+        M.lo[a] = c->lo[a];
+        M.ext[a] = c->hi[a] - c->lo[a];
+    }
+    for (int i = 0; i < c->n_obs; ++i) {
+        M.obs_in[i][0] = (float)(2.0 * c->theta[i] / 3.14159265358979323846 - 1.0);
+        M.obs_in[i][1] = (float)(c->phi[i] / 3.14159265358979323846 - 1.0);
+    }
+    M.n_obs = c->n_obs;
+    return M;
+}
+
+static void transport_params(const qrt_ctx *c, TransportParams &P)
+{
     memset(&P, 0, sizeof(P));
     P.grid = dev_grid(c);
     P.src_kind = c->src_kind;
@@ -439,6 +473,44 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     P.tau_min = c->tau_min;
     P.img = c->img;
     P.counters = c->counters;
+    P.peel_mode = c->peel_mode;
+    if (c->has_domain) {
+        SurrogateParams &S = P.sur;
+        for (int a = 0; a < 3; ++a) S.center[a] = c->dom_center[a];
+        S.r_in = c->dom_r_in; S.r_out = c->dom_r_out; S.h0 = c->dom_h0; S.beta = c->dom_beta; S.zmax = c->dom_zmax;
+        S.n_r = c->dom_nr;
+        S.n_z = c->dom_nz;
+        S.valid = c->dom_valid;
+        S.params = c->mlp;
+        S.tiles = c->tiles;
+        const InputMap M = input_map(c);
+        for (int a = 0; a < 3; ++a) {
+            S.lo[a] = M.lo[a];
+            S.ext[a] = M.ext[a];
+        }
+        memcpy(S.obs_in, M.obs_in, sizeof(S.obs_in));
+    }
+}
+
+static int run_checks(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, uint64_t count)
+{
+    if (!c->has_grid || !c->has_source || !c->has_obs)
+        return fail(c, QRT_BAD_STATE, "set grid, source and observers before running");
+    if (point_dims(c) > kMaxDims)
+        return fail(c, QRT_UNSUPPORTED, "%d point dimensions exceed the %d served", point_dims(c), kMaxDims);
+    if (c->peel_mode == QRT_PEEL_SURROGATE && (!c->has_mlp || !c->has_domain))
+        return fail(c, QRT_NOT_TRAINED, "the surrogate needs network parameters and a domain");
+    return check_index_range(c, kind, n_total, first, count);
+}
+
+int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
+{
+    if (!c) return QRT_INVALID_ARG;
+    int rc = run_checks(c, c->kind, c->n_total, first, count);
+    if (rc) return rc;
+    if (count == 0) return QRT_OK;
+    TransportParams P;
+    transport_params(c, P);
     DeviceGuard dg(c->device);
     rc = ensure_queues(c, count);
     if (rc) return rc;
@@ -553,6 +625,449 @@ int qrt_trace_tau(qrt_ctx *c, int64_t n, const double *p, const double *k, doubl
     if (n < 0 || (n > 0 && (!p || !k || !tau))) return fail(c, QRT_INVALID_ARG, "bad ray buffers");
     DeviceGuard dg(c->device);
     HIP_TRY(c, launch_trace_tau(dev_grid(c), c->precision, n, p, k, tau, visits, c->stream), "trace launch");
+    return QRT_OK;
+}
+
+// ---------------------------------------------------------------- surrogate network
+
+static uint64_t host_splitmix64(uint64_t &state)
+{
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+static int ensure_mlp(qrt_ctx *c)
+{
+    if (c->mlp) return QRT_OK;
+    HIP_TRY(c, hipMalloc(&c->mlp, 3 * (size_t)kMlpParams * sizeof(float)), "network parameters");
+    HIP_TRY(c, hipMalloc(&c->tiles, (size_t)kMlpTiles * 64 * 16), "weight tiles");
+    HIP_TRY(c, hipMemsetAsync(c->tiles, 0, (size_t)kMlpTiles * 64 * 16, c->stream), "weight tiles");
+    return QRT_OK;
+}
+
+static int ensure_part(qrt_ctx *c, size_t blocks)
+{
+    const size_t want = blocks * (size_t)kMlpParams;
+    if (c->part_elems >= want) return QRT_OK;
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    if (c->part) (void)hipFree(c->part);
+    c->part = nullptr;
+    c->part_elems = 0;
+    HIP_TRY(c, hipMalloc(&c->part, want * sizeof(float)), "gradient buffer");
+    c->part_elems = want;
+    return QRT_OK;
+}
+
+static int ensure_train_x(qrt_ctx *c, size_t n)
+{
+    const size_t want = n * kMlpIn;
+    if (c->train_x_elems >= want) return QRT_OK;
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    if (c->train_x) (void)hipFree(c->train_x);
+    c->train_x = nullptr;
+    c->train_x_elems = 0;
+    HIP_TRY(c, hipMalloc(&c->train_x, want * sizeof(float)), "training inputs");
+    c->train_x_elems = want;
+    return QRT_OK;
+}
+
+// host copy of the domain cell rule used by the kernels
+static int host_dom_cell(const qrt_ctx *c, double x, double y, double z)
+{
+    const double dx = x - c->dom_center[0], dy = y - c->dom_center[1], dz = z - c->dom_center[2];
+    const double R = sqrt(dx * dx + dy * dy);
+    if (!(R >= c->dom_r_in && R < c->dom_r_out)) return -1;
+    const double zh = dz / (c->dom_h0 * pow(R, c->dom_beta));
+    if (!(fabs(zh) < c->dom_zmax)) return -1;
+    const int ir = (int)floor((R - c->dom_r_in) / (c->dom_r_out - c->dom_r_in) * (double)c->dom_nr);
+    const int iz = (int)floor((zh + c->dom_zmax) / (2.0 * c->dom_zmax) * (double)c->dom_nz);
+    if (ir < 0 || ir >= c->dom_nr || iz < 0 || iz >= c->dom_nz) return -1;
+    return ir * c->dom_nz + iz;
+}
+
+int qrt_mlp_set_params(qrt_ctx *c, const float *params, int64_t n)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!params || n != kMlpParams) return fail(c, QRT_INVALID_ARG, "the network has %d parameters", kMlpParams);
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(params[i])) return fail(c, QRT_INVALID_ARG, "parameter %lld is not finite", (long long)i);
+    DeviceGuard dg(c->device);
+    int rc = ensure_mlp(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->mlp, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice, c->stream),
+            "parameter copy");
+    HIP_TRY(c, hipMemsetAsync(c->mlp + kMlpParams, 0, 2 * (size_t)kMlpParams * sizeof(float), c->stream),
+            "moment reset");
+    HIP_TRY(c, launch_mlp_pack(c->mlp, c->tiles, c->stream), "tile pack");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "parameter sync");
+    c->has_mlp = true;
+    c->adam_t = 0;
+    return QRT_OK;
+}
+
+int qrt_mlp_get_params(qrt_ctx *c, float *params, int64_t n)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!params || n != kMlpParams) return fail(c, QRT_INVALID_ARG, "the network has %d parameters", kMlpParams);
+    if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, hipMemcpyAsync(params, c->mlp, kMlpParams * sizeof(float), hipMemcpyDeviceToHost, c->stream),
+            "parameter copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "parameter sync");
+    return QRT_OK;
+}
+
+int qrt_mlp_init(qrt_ctx *c, uint64_t seed)
+{
+    if (!c) return QRT_INVALID_ARG;
+    std::vector<float> h(kMlpParams, 0.0f);
+    uint64_t st = seed;
+    for (int l = 0; l < 5; ++l) {
+        const double lim = sqrt(6.0 / (double)mlp_fan_in(l));
+        const int nw = mlp_fan_in(l) * mlp_fan_out(l);
+        for (int i = 0; i < nw; ++i) {
+            const double u = (double)(host_splitmix64(st) >> 11) * 0x1p-53;
+            h[mlp_w_off(l) + i] = (float)((2.0 * u - 1.0) * lim);
+        }
+    }
+    return qrt_mlp_set_params(c, h.data(), kMlpParams);
+}
+
+int qrt_mlp_forward(qrt_ctx *c, int64_t n, const float *X, float *y)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
+    if (n < 0 || (n > 0 && (!X || !y))) return fail(c, QRT_INVALID_ARG, "bad buffers");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, launch_mlp_forward(c->mlp, c->tiles, X, (uint64_t)n, y, c->stream), "forward launch");
+    return QRT_OK;
+}
+
+int qrt_mlp_backward(qrt_ctx *c, int64_t n, const float *X, const float *dy, float *grad)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
+    if (n < 1 || !X || !dy || !grad) return fail(c, QRT_INVALID_ARG, "bad buffers");
+    if (n > (int64_t)1 << 24) return fail(c, QRT_UNSUPPORTED, "at most 2^24 rows per call");
+    DeviceGuard dg(c->device);
+    const int blocks = (int)((n + 63) / 64);
+    int rc = ensure_part(c, (size_t)blocks);
+    if (rc) return rc;
+    MlpBatch sel;
+    memset(&sel, 0, sizeof(sel));
+    HIP_TRY(c, launch_mlp_grad(1, c->mlp, c->tiles, X, (uint64_t)n, nullptr, dy, sel, blocks, c->part, c->stream),
+            "gradient launch");
+    HIP_TRY(c, launch_mlp_reduce(c->part, blocks, grad, c->stream), "gradient reduce");
+    return QRT_OK;
+}
+
+int qrt_surrogate_set_domain(qrt_ctx *c, const double center[3], double r_in, double r_out, double h0, double beta,
+                             double zmax_over_h, int n_r, int n_z)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!center || !(r_in >= 0.0) || !(r_out > r_in) || !(h0 > 0.0) || !isfinite(beta) || !(zmax_over_h > 0.0) ||
+        !isfinite(r_out) || !isfinite(h0) || !isfinite(zmax_over_h))
+        return fail(c, QRT_INVALID_ARG, "bad domain: need 0 <= r_in < r_out, h0 > 0, zmax > 0");
+    if (n_r < 1 || n_z < 1 || n_r > 1024 || n_z > 1024) return fail(c, QRT_INVALID_ARG, "bins must be in 1..1024");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    if (c->dom_valid) (void)hipFree(c->dom_valid);
+    c->dom_valid = nullptr;
+    c->has_domain = false;
+    const size_t bytes = (size_t)QRT_MAX_OBSERVERS * n_r * n_z;
+    HIP_TRY(c, hipMalloc(&c->dom_valid, bytes), "mask allocation");
+    HIP_TRY(c, hipMemsetAsync(c->dom_valid, 0, bytes, c->stream), "mask reset");
+    for (int a = 0; a < 3; ++a) c->dom_center[a] = center[a];
+    c->dom_r_in = r_in; c->dom_r_out = r_out; c->dom_h0 = h0; c->dom_beta = beta; c->dom_zmax = zmax_over_h;
+    c->dom_nr = n_r;
+    c->dom_nz = n_z;
+    c->has_domain = true;
+    return QRT_OK;
+}
+
+int qrt_surrogate_set_mask(qrt_ctx *c, const uint8_t *mask)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_domain || !c->has_obs) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
+    if (!mask) return fail(c, QRT_INVALID_ARG, "null mask");
+    DeviceGuard dg(c->device);
+    const size_t bytes = (size_t)c->n_obs * c->dom_nr * c->dom_nz;
+    HIP_TRY(c, hipMemcpyAsync(c->dom_valid, mask, bytes, hipMemcpyHostToDevice, c->stream), "mask copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "mask sync");
+    return QRT_OK;
+}
+
+int qrt_surrogate_get_mask(qrt_ctx *c, uint8_t *mask)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_domain || !c->has_obs) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
+    if (!mask) return fail(c, QRT_INVALID_ARG, "null mask");
+    DeviceGuard dg(c->device);
+    const size_t bytes = (size_t)c->n_obs * c->dom_nr * c->dom_nz;
+    HIP_TRY(c, hipMemcpyAsync(mask, c->dom_valid, bytes, hipMemcpyDeviceToHost, c->stream), "mask copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "mask sync");
+    return QRT_OK;
+}
+
+int qrt_surrogate_inputs(qrt_ctx *c, int64_t n, const float *pos_obs, float *X)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_grid || !c->has_obs) return fail(c, QRT_BAD_STATE, "set grid and observers first");
+    if (n < 0 || (n > 0 && (!pos_obs || !X))) return fail(c, QRT_INVALID_ARG, "bad buffers");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), X, c->stream), "input launch");
+    return QRT_OK;
+}
+
+int qrt_surrogate_sample(qrt_ctx *c, int64_t n, uint64_t seed, float *pos_obs, float *tau, int64_t *pilot_packets)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_domain) return fail(c, QRT_BAD_STATE, "set a surrogate domain first");
+    if (n < 1 || !pos_obs || !tau) return fail(c, QRT_INVALID_ARG, "bad buffers");
+    if (n > (int64_t)1 << 26) return fail(c, QRT_UNSUPPORTED, "at most 2^26 samples");
+    int rc = run_checks(c, QRT_PHILOX, 0, 1, 1);
+    if (rc) return rc;
+    DeviceGuard dg(c->device);
+    // chunk size: every packet scatters at most max_orders times toward n_obs observers
+    const uint64_t per_packet = (uint64_t)c->max_orders * (uint64_t)c->n_obs;
+    uint64_t chunk = 1ull << 16;
+    while (chunk > 256 && chunk * per_packet > (1ull << 24)) chunk >>= 1;
+    const uint64_t capacity = chunk * per_packet;
+    rc = ensure_queues(c, chunk);
+    if (rc) return rc;
+    float *cap = nullptr;
+    uint32_t *cap_count = nullptr;
+    double *pk = nullptr, *tau64 = nullptr;
+    std::vector<float> all;
+    uint64_t first = 1;
+    int save_mode = c->peel_mode;
+    hipError_t e = hipMalloc(&cap, capacity * 4 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&cap_count, sizeof(uint32_t));
+    TransportParams P;
+    c->peel_mode = QRT_PEEL_EXACT;
+    transport_params(c, P);
+    c->peel_mode = save_mode;
+    P.seq = seq_params(c, QRT_PHILOX, seed, 0);
+    P.sur.cap = cap;
+    P.sur.cap_count = cap_count;
+    P.sur.cap_capacity = (uint32_t)capacity;
+    // pilot: chunks of Philox packets until enough in-domain peel rays are captured
+    while (e == hipSuccess && all.size() < (size_t)n * 4) {
+        if (first > (1ull << 36)) {
+            (void)hipFree(cap);
+            (void)hipFree(cap_count);
+            return fail(c, QRT_UNSUPPORTED, "the pilot finds too few peel-off rays inside the domain");
+        }
+        uint32_t got = 0;
+        e = hipMemsetAsync(cap_count, 0, sizeof(uint32_t), c->stream);
+        if (e == hipSuccess) e = launch_transport(P, c->precision, QRT_PHILOX, first, chunk, c->tb, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&got, cap_count, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) break;
+        if (got > capacity) got = (uint32_t)capacity;   // cannot happen: capacity bounds every chunk
+        const size_t old = all.size();
+        all.resize(old + (size_t)got * 4);
+        e = hipMemcpy(all.data() + old, cap, (size_t)got * 4 * sizeof(float), hipMemcpyDeviceToHost);
+        first += chunk;
+    }
+    (void)hipFree(cap);
+    (void)hipFree(cap_count);
+    if (e != hipSuccess) return hip_fail(c, e, "pilot run");
+    // canonical order: sort the captured rays by a hash of their bytes, keep the first n
+    const size_t m = all.size() / 4;
+    std::vector<std::pair<uint64_t, uint32_t>> key(m);
+    for (size_t i = 0; i < m; ++i) {
+        uint64_t a, b;
+        memcpy(&a, &all[4 * i], 8);
+        memcpy(&b, &all[4 * i + 2], 8);
+        uint64_t st = a ^ (b * 0xD6E8FEB86659FD93ull) ^ seed;
+        key[i] = {host_splitmix64(st), (uint32_t)i};
+    }
+    std::sort(key.begin(), key.end(), [&](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
+        if (x.first != y.first) return x.first < y.first;
+        return memcmp(&all[4 * (size_t)x.second], &all[4 * (size_t)y.second], 16) < 0;
+    });
+    std::vector<float> sel((size_t)n * 4);
+    std::vector<double> pk_h((size_t)n * 6);
+    for (int64_t j = 0; j < n; ++j) {
+        const float *r = &all[4 * (size_t)key[(size_t)j].second];
+        memcpy(&sel[4 * (size_t)j], r, 16);
+        int ob = (int)r[3];
+        ob = ob < 0 ? 0 : (ob >= c->n_obs ? c->n_obs - 1 : ob);
+        const double st = sin(c->theta[ob]), ct = cos(c->theta[ob]), sp = sin(c->phi[ob]), cp = cos(c->phi[ob]);
+        double *q = &pk_h[6 * (size_t)j];
+        q[0] = r[0]; q[1] = r[1]; q[2] = r[2];
+        q[3] = st * cp; q[4] = st * sp; q[5] = ct;
+    }
+    // labels: exact optical depth toward the observer (FP64 traversal)
+    e = hipMalloc(&pk, (size_t)n * 6 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&tau64, (size_t)n * sizeof(double));
+    std::vector<double> t64((size_t)n);
+    std::vector<double> p_h((size_t)n * 3), k_h((size_t)n * 3);
+    for (int64_t j = 0; j < n; ++j)
+        for (int a = 0; a < 3; ++a) {
+            p_h[3 * (size_t)j + a] = pk_h[6 * (size_t)j + a];
+            k_h[3 * (size_t)j + a] = pk_h[6 * (size_t)j + 3 + a];
+        }
+    if (e == hipSuccess) e = hipMemcpy(pk, p_h.data(), (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(pk + (size_t)n * 3, k_h.data(), (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_trace_tau(dev_grid(c), QRT_FP64, n, pk, pk + (size_t)n * 3, tau64, nullptr, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(t64.data(), tau64, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                                            c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(pk);
+    (void)hipFree(tau64);
+    if (e != hipSuccess) return hip_fail(c, e, "pilot labels");
+    std::vector<float> t32((size_t)n);
+    for (int64_t j = 0; j < n; ++j) t32[(size_t)j] = (float)t64[(size_t)j];
+    HIP_TRY(c, hipMemcpy(pos_obs, sel.data(), (size_t)n * 4 * sizeof(float), hipMemcpyHostToDevice), "sample copy");
+    HIP_TRY(c, hipMemcpy(tau, t32.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice), "label copy");
+    if (pilot_packets) *pilot_packets = (int64_t)(first - 1);
+    return qrt_reset_images(c);
+}
+
+static double mlp_loss(qrt_ctx *c, const float *X, const float *tau, uint64_t n, float cap, float wfloor, int &rc)
+{
+    rc = QRT_OK;
+    const int parts = mlp_loss_parts(n);
+    double *d = nullptr;
+    std::vector<double> h((size_t)parts);
+    hipError_t e = hipMalloc(&d, (size_t)parts * sizeof(double));
+    if (e == hipSuccess) e = launch_mlp_loss(c->mlp, c->tiles, X, tau, n, cap, wfloor, d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d, (size_t)parts * sizeof(double), hipMemcpyDeviceToHost,
+                                            c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (d) (void)hipFree(d);
+    if (e != hipSuccess) {
+        rc = hip_fail(c, e, "loss");
+        return 0.0;
+    }
+    double s = 0.0;
+    for (double v : h) s += v;
+    return n ? s / (double)n : 0.0;
+}
+
+int qrt_surrogate_train(qrt_ctx *c, int64_t n, const float *pos_obs, const float *tau, const qrt_train_cfg *cfg,
+                        qrt_train_report *rep)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!cfg || n < 1 || !pos_obs || !tau) return fail(c, QRT_INVALID_ARG, "bad arguments");
+    if (!c->has_grid || !c->has_obs) return fail(c, QRT_BAD_STATE, "set grid and observers first");
+    if (cfg->steps < 0 || cfg->batch < 64 || cfg->batch > 65536 || cfg->batch % 64)
+        return fail(c, QRT_INVALID_ARG, "batch must be a multiple of 64 in 64..65536");
+    if (!(cfg->lr > 0.0f) || !(cfg->lr_final >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
+        !(cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f) || !(cfg->eps > 0.0f) || !(cfg->tau_cap > 0.0f) ||
+        !(cfg->weight_floor >= 0.0f))
+        return fail(c, QRT_INVALID_ARG, "bad optimiser settings");
+    if (!cfg->init && !c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no parameters to continue from");
+    int rc = QRT_OK;
+    if (cfg->init && (rc = qrt_mlp_init(c, cfg->seed))) return rc;
+    DeviceGuard dg(c->device);
+    const int blocks = cfg->batch / 64;
+    if ((rc = ensure_part(c, (size_t)blocks))) return rc;
+    if ((rc = ensure_train_x(c, (size_t)n))) return rc;
+    HIP_TRY(c, launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), c->train_x, c->stream), "input launch");
+    const double l0 = mlp_loss(c, c->train_x, tau, (uint64_t)n, cfg->tau_cap, cfg->weight_floor, rc);
+    if (rc) return rc;
+    for (int64_t step = 0; step < cfg->steps; ++step) {
+        MlpBatch sel;
+        sel.seed = cfg->seed;
+        sel.step = (uint64_t)(c->adam_t + 1);
+        sel.batch = cfg->batch;
+        sel.cap = cfg->tau_cap;
+        sel.wfloor = cfg->weight_floor;
+        HIP_TRY(c, launch_mlp_grad(0, c->mlp, c->tiles, c->train_x, (uint64_t)n, tau, nullptr, sel, blocks, c->part,
+                                   c->stream),
+                "gradient launch");
+        c->adam_t++;
+        const double frac = cfg->steps > 1 ? (double)step / (double)(cfg->steps - 1) : 1.0;
+        AdamStep A;
+        A.lr = (float)(cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + cos(3.14159265358979323846 * frac)));
+        A.beta1 = cfg->beta1;
+        A.beta2 = cfg->beta2;
+        A.eps = cfg->eps;
+        A.c1 = (float)(1.0 / (1.0 - pow((double)cfg->beta1, (double)c->adam_t)));
+        A.c2 = (float)(1.0 / (1.0 - pow((double)cfg->beta2, (double)c->adam_t)));
+        HIP_TRY(c, launch_mlp_adam(c->mlp, c->mlp + kMlpParams, c->mlp + 2 * kMlpParams, c->part, blocks, A, c->tiles,
+                                   c->stream),
+                "update launch");
+    }
+    const double l1 = mlp_loss(c, c->train_x, tau, (uint64_t)n, cfg->tau_cap, cfg->weight_floor, rc);
+    if (rc) return rc;
+    if (rep) {
+        rep->loss_first = l0;
+        rep->loss_final = l1;
+        rep->steps = cfg->steps;
+    }
+    return QRT_OK;
+}
+
+int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const float *tau, double max_err,
+                           int64_t min_count, qrt_mask_report *rep)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
+    if (!c->has_domain || !c->has_obs || !c->has_grid) return fail(c, QRT_BAD_STATE, "set grid, observers, domain");
+    if (n < 1 || !pos_obs || !tau || !(max_err >= 0.0) || min_count < 1)
+        return fail(c, QRT_INVALID_ARG, "bad arguments");
+    DeviceGuard dg(c->device);
+    int rc = ensure_train_x(c, (size_t)n);
+    if (rc) return rc;
+    float *y = nullptr;
+    HIP_TRY(c, hipMalloc(&y, (size_t)n * sizeof(float)), "prediction buffer");
+    std::vector<float> hp((size_t)n * 4), ht((size_t)n), hy((size_t)n);
+    hipError_t e = launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), c->train_x, c->stream);
+    if (e == hipSuccess) e = launch_mlp_forward(c->mlp, c->tiles, c->train_x, (uint64_t)n, y, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), y, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hp.data(), pos_obs, (size_t)n * 16, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ht.data(), tau, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(y);
+    if (e != hipSuccess) return hip_fail(c, e, "validation");
+    const size_t cells = (size_t)c->dom_nr * c->dom_nz;
+    const size_t total = (size_t)c->n_obs * cells;
+    std::vector<double> num(total, 0.0), den(total, 0.0);
+    std::vector<int64_t> cnt(total, 0);
+    int64_t inside = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        const float *r = &hp[4 * (size_t)j];
+        const int ob = (int)r[3];
+        if (ob < 0 || ob >= c->n_obs) continue;
+        const int cell = host_dom_cell(c, r[0], r[1], r[2]);
+        if (cell < 0) continue;
+        inside++;
+        const double T = exp(-(double)ht[(size_t)j]);
+        const double Th = exp(-(double)(hy[(size_t)j] > 0.0f ? hy[(size_t)j] : 0.0f));
+        const size_t k = (size_t)ob * cells + (size_t)cell;
+        num[k] += fabs(Th - T);
+        den[k] += T;
+        cnt[k]++;
+    }
+    std::vector<uint8_t> mask(total, 0);
+    int64_t valid_cells = 0, samples_valid = 0;
+    double worst = 0.0;
+    for (size_t k = 0; k < total; ++k) {
+        if (cnt[k] >= min_count && den[k] > 0.0 && num[k] <= max_err * den[k]) {
+            mask[k] = 1;
+            valid_cells++;
+            samples_valid += cnt[k];
+            worst = std::max(worst, num[k] / den[k]);
+        }
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->dom_valid, mask.data(), total, hipMemcpyHostToDevice, c->stream), "mask copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "mask sync");
+    if (rep) {
+        rep->cells = (int64_t)total;
+        rep->valid_cells = valid_cells;
+        rep->samples = inside;
+        rep->samples_valid = samples_valid;
+        rep->max_err_valid = worst;
+    }
     return QRT_OK;
 }
 

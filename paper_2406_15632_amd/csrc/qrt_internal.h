@@ -24,6 +24,23 @@ struct DevObserver {
     double o[3], ex[3], ey[3];
 };
 
+// Surrogate peel-off: cylindrical domain with its validity mask, the network
+// (FP32 parameters for the biases, bfloat16 weight tiles), the input
+// normalisation, and the capture buffer of a pilot run (null when off).
+struct SurrogateParams {
+    double center[3];
+    double r_in, r_out, h0, beta, zmax;   // R in [r_in, r_out), |z| < zmax h0 R^beta
+    int n_r, n_z;
+    const uint8_t *valid;                 // [n_obs][n_r][n_z]
+    const float *params;                  // 12929 FP32
+    const void *tiles;                    // bfloat16 weight tiles
+    double lo[3], ext[3];                 // mesh box: inputs 2 (p - lo) / ext - 1
+    float obs_in[kMaxObs][2];             // 2 theta / pi - 1, phi / pi - 1
+    float *cap;                           // pilot capture: [cap_capacity][4] = x, y, z, observer
+    uint32_t *cap_count;
+    uint32_t cap_capacity;
+};
+
 struct TransportParams {
     DevGrid grid;
     int src_kind;            // 0 point, 1 sphere
@@ -38,6 +55,26 @@ struct TransportParams {
     double tau_min;
     double *img;                   // [kImageCopies][n_obs][3][npix][npix]
     unsigned long long *counters;  // [CNT_COUNT]
+    int peel_mode;                 // 0 exact traversal, 1 surrogate inside its valid cells
+    SurrogateParams sur;
+};
+
+// one training batch of the surrogate network
+struct MlpBatch {
+    uint64_t seed, step;
+    int batch;          // samples per step (64 per block)
+    float cap, wfloor;  // targets min(tau, cap); weights exp(-target) + wfloor
+};
+
+struct AdamStep {
+    float lr, beta1, beta2, eps;
+    float c1, c2;       // bias corrections 1/(1 - beta1^t), 1/(1 - beta2^t)
+};
+
+struct InputMap {
+    double lo[3], ext[3];
+    float obs_in[kMaxObs][2];
+    int n_obs;
 };
 
 // A scattered packet between kernels: position, direction, reference axis,
@@ -90,6 +127,21 @@ hipError_t launch_transport(const TransportParams &P, int precision, int kind, u
 
 // img[0 .. n) += img[c n .. (c+1) n) for every further copy c, which is cleared
 hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream);
+
+// surrogate network (qrt_mlp.hip); `tiles` holds kMlpTiles x 64 lanes x 8 bfloat16
+hipError_t launch_mlp_pack(const float *params, void *tiles, hipStream_t st);
+hipError_t launch_mlp_forward(const float *params, const void *tiles, const float *X, uint64_t n, float *y,
+                              hipStream_t st);
+int mlp_loss_parts(uint64_t n);
+hipError_t launch_mlp_loss(const float *params, const void *tiles, const float *X, const float *tau, uint64_t n,
+                           float cap, float wfloor, double *part, hipStream_t st);
+hipError_t launch_mlp_grad(int mode, const float *params, const void *tiles, const float *X, uint64_t n,
+                           const float *tau, const float *dy, const MlpBatch &sel, int n_blocks, float *part,
+                           hipStream_t st);
+hipError_t launch_mlp_adam(float *params, float *m, float *v, const float *part, int n_parts, const AdamStep &A,
+                           void *tiles, hipStream_t st);
+hipError_t launch_mlp_reduce(const float *part, int n_parts, float *out, hipStream_t st);
+hipError_t launch_mlp_inputs(const float *pos_obs, uint64_t n, const InputMap &M, float *X, hipStream_t st);
 
 hipError_t launch_points(const SeqParams &S, int kind, uint64_t first, uint64_t count, int dims,
                          uint32_t *out, hipStream_t stream);

@@ -42,6 +42,7 @@
 #include <hip/hip_runtime.h>
 
 #include "qrt_internal.h"
+#include "qrt_mlp.h"
 #include "qrt_physics.h"
 
 namespace qrt {
@@ -549,6 +550,108 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
 }
 
 // --------------------------------------------------------------------------
+// surrogate peel-off (an addition to the method): inside the validated
+// domain the network gives tau to the observer; the ray is then binned here
+// and marked done, so that the walk kernel skips it
+// --------------------------------------------------------------------------
+
+// cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
+__device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
+{
+    const double dx = x - S.center[0], dy = y - S.center[1], dz = z - S.center[2];
+    const double R = sqrt(dx * dx + dy * dy);
+    if (!(R >= S.r_in && R < S.r_out)) return -1;
+    const double zh = dz / (S.h0 * pow(R, S.beta));
+    if (!(fabs(zh) < S.zmax)) return -1;
+    const int ir = (int)floor((R - S.r_in) / (S.r_out - S.r_in) * (double)S.n_r);
+    const int iz = (int)floor((zh + S.zmax) / (2.0 * S.zmax) * (double)S.n_z);
+    if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
+    return ir * S.n_z + iz;
+}
+
+// One wave per block of 64 peel slots (one observer); the network runs on all
+// 64 lanes at once on the matrix cores, with its weights in registers.
+template <typename R>
+__global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, PeelRay<R> *__restrict__ peels,
+                                                  const Queues *__restrict__ Q, int in)
+{
+    __shared__ float bias[260];
+    mlp_bias_to_lds(bias, P.sur.params);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    MlpWeights W;
+    mlp_load(W, (const bf16x8 *)P.sur.tiles, lane);
+    const uint64_t n_live = Q->n_live[in];
+    const uint64_t n_blocks = (uint64_t)P.n_obs * ((n_live + 63) / 64);
+    const size_t plane = (size_t)P.npix * (size_t)P.npix;
+    double *img_copy = P.img + (size_t)(blockIdx.x % kImageCopies) * (size_t)P.n_obs * 3 * plane;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const size_t cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
+    uint32_t n_sur = 0, n_fb = 0;
+    for (uint64_t g = wave; g < n_blocks; g += waves) {
+        PeelRay<R> *rp = peels + g * 64 + lane;
+        const PeelRay<R> r = *rp;
+        const bool vis = r.pix != kNoPixel;
+        bool use = false;
+        if (vis) {
+            const int cell = dom_cell(P.sur, (double)r.p[0], (double)r.p[1], (double)r.p[2]);
+            use = cell >= 0 && P.sur.valid[(size_t)r.obs * cells + (size_t)cell] != 0;
+        }
+        n_fb += (vis && !use) ? 1u : 0u;
+        if (__ballot(use) == 0) continue;
+        const int ob = (int)r.obs < P.n_obs ? (int)r.obs : 0;
+        float x[kMlpIn];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = (float)(2.0 * ((double)r.p[a] - P.sur.lo[a]) / P.sur.ext[a] - 1.0);
+        x[3] = P.sur.obs_in[ob][0];
+        x[4] = P.sur.obs_in[ob][1];
+        const float t = mlp_wave(W, bias, x, lane);
+        if (use) {
+            const double att = exp(-(double)fmaxf(t, 0.0f));
+            double *dst = img_copy + (size_t)ob * 3 * plane + (size_t)r.pix;
+            unsafeAtomicAdd(dst, att * (double)r.c[0]);
+            unsafeAtomicAdd(dst + plane, att * (double)r.c[1]);
+            unsafeAtomicAdd(dst + 2 * plane, att * (double)r.c[2]);
+            rp->pix = kNoPixel;
+            n_sur++;
+        }
+    }
+    flush_counter(P.counters + CNT_SURROGATE, n_sur);
+    flush_counter(P.counters + CNT_FALLBACKS, n_fb);
+    flush_counter(P.counters + CNT_PEELS, n_sur);
+}
+
+// Pilot capture: (position, observer) of every visible peel ray inside the
+// surrogate domain, appended while the buffer has room (the count goes on).
+template <typename R>
+__global__ void __launch_bounds__(256) k_capture(const TransportParams P, const PeelRay<R> *__restrict__ peels,
+                                                 const Queues *__restrict__ Q, int in)
+{
+    const uint64_t n_live = Q->n_live[in];
+    const uint64_t n_slots = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint64_t base = t0 - (threadIdx.x & 63); base < n_slots; base += stride) {
+        const uint64_t i = base + (threadIdx.x & 63);
+        bool take = false;
+        PeelRay<R> r = {};
+        if (i < n_slots) {
+            r = peels[i];
+            take = r.pix != kNoPixel && dom_cell(P.sur, (double)r.p[0], (double)r.p[1], (double)r.p[2]) >= 0;
+        }
+        const uint32_t pos = wave_append(take, P.sur.cap_count);
+        if (take && pos < P.sur.cap_capacity) {
+            float *c = P.sur.cap + (size_t)pos * 4;
+            c[0] = (float)r.p[0];
+            c[1] = (float)r.p[1];
+            c[2] = (float)r.p[2];
+            c[3] = (float)r.obs;
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
 // launch sequence
 // --------------------------------------------------------------------------
 template <typename F>
@@ -567,11 +670,12 @@ template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
                             hipStream_t st)
 {
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_mlp = 0;
     if (!nb_first) {
         nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
         nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC>);
         nb_walk = resident_blocks_of(k_walk<R>);
+        nb_mlp = resident_blocks_of(k_peel_mlp<R>);
     }
     PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
@@ -595,6 +699,11 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         const int in = (order - 1) & 1;
         hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order, pks,
                            (const uint32_t *)B.live[in], in, peels, B.q);
+        if (P.sur.cap)
+            hipLaunchKernelGGL((k_capture<R>), dim3(bs), dim3(256), 0, st, P, (const PeelRay<R> *)peels,
+                               (const Queues *)B.q, in);
+        if (P.peel_mode == 1)
+            hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, peels, (const Queues *)B.q, in);
         hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
                            in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -25,6 +25,7 @@ FP32, FP64 = 0, 1
 PEEL_EXACT, PEEL_SURROGATE = 0, 1
 EMIT_DIRECT = 0
 MAX_DIMS, MAX_OBSERVERS = 128, 16
+MLP_PARAMS = 12929
 
 
 class qrt_counters(C.Structure):
@@ -33,6 +34,25 @@ class qrt_counters(C.Structure):
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class qrt_train_cfg(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("batch", C.c_int32), ("init", C.c_int32),
+                ("lr", C.c_float), ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("tau_cap", C.c_float), ("weight_floor", C.c_float), ("seed", C.c_uint64)]
+
+
+class qrt_train_report(C.Structure):
+    _fields_ = [("loss_first", C.c_double), ("loss_final", C.c_double), ("steps", C.c_int64)]
+
+
+class qrt_mask_report(C.Structure):
+    _fields_ = [("cells", C.c_int64), ("valid_cells", C.c_int64), ("samples", C.c_int64),
+                ("samples_valid", C.c_int64), ("max_err_valid", C.c_double)]
+
+
+def _as_dict(st):
+    return {f: getattr(st, f) for f, _ in st._fields_}
 
 
 _P = C.c_void_p
@@ -58,6 +78,21 @@ SIGNATURES = {
     "qrt_generate_points": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
                                       _P, C.c_int]),
     "qrt_trace_tau": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
+    "qrt_mlp_set_params": (C.c_int, [_P, _P, C.c_int64]),
+    "qrt_mlp_get_params": (C.c_int, [_P, _P, C.c_int64]),
+    "qrt_mlp_init": (C.c_int, [_P, C.c_uint64]),
+    "qrt_mlp_forward": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "qrt_mlp_backward": (C.c_int, [_P, C.c_int64, _P, _P, _P]),
+    "qrt_surrogate_set_domain": (C.c_int, [_P, _D3, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double,
+                                           C.c_int, C.c_int]),
+    "qrt_surrogate_set_mask": (C.c_int, [_P, _P]),
+    "qrt_surrogate_get_mask": (C.c_int, [_P, _P]),
+    "qrt_surrogate_inputs": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "qrt_surrogate_sample": (C.c_int, [_P, C.c_int64, C.c_uint64, _P, _P, C.POINTER(C.c_int64)]),
+    "qrt_surrogate_train": (C.c_int, [_P, C.c_int64, _P, _P, C.POINTER(qrt_train_cfg),
+                                      C.POINTER(qrt_train_report)]),
+    "qrt_surrogate_validate": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_int64,
+                                         C.POINTER(qrt_mask_report)]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -230,3 +265,64 @@ class Context:
         self._ck(self.lib.qrt_trace_tau(self.h, n, C.c_void_p(p_dev.data_ptr()), C.c_void_p(k_dev.data_ptr()),
                                         C.c_void_p(tau_dev.data_ptr()),
                                         C.c_void_p(visits_dev.data_ptr()) if visits_dev is not None else None))
+
+    # -------- surrogate peel-off (network inputs, samples and outputs are CUDA tensors)
+    def mlp_set_params(self, params: np.ndarray):
+        a = np.ascontiguousarray(params, dtype=np.float32)
+        self._ck(self.lib.qrt_mlp_set_params(self.h, a.ctypes.data, a.size))
+
+    def mlp_get_params(self) -> np.ndarray:
+        a = np.zeros(MLP_PARAMS, dtype=np.float32)
+        self._ck(self.lib.qrt_mlp_get_params(self.h, a.ctypes.data, a.size))
+        return a
+
+    def mlp_init(self, seed: int):
+        self._ck(self.lib.qrt_mlp_init(self.h, seed))
+
+    def mlp_forward(self, X, y):
+        self._ck(self.lib.qrt_mlp_forward(self.h, X.shape[0], C.c_void_p(X.data_ptr()), C.c_void_p(y.data_ptr())))
+
+    def mlp_backward(self, X, dy, grad):
+        self._ck(self.lib.qrt_mlp_backward(self.h, X.shape[0], C.c_void_p(X.data_ptr()), C.c_void_p(dy.data_ptr()),
+                                           C.c_void_p(grad.data_ptr())))
+
+    def surrogate_set_domain(self, center, r_in, r_out, h0, beta, zmax_over_h, n_r, n_z):
+        self.dom_shape = (n_r, n_z)
+        self._ck(self.lib.qrt_surrogate_set_domain(self.h, _d3(center), r_in, r_out, h0, beta, zmax_over_h,
+                                                   n_r, n_z))
+
+    def surrogate_set_mask(self, mask: np.ndarray):
+        a = np.ascontiguousarray(mask, dtype=np.uint8)
+        self._ck(self.lib.qrt_surrogate_set_mask(self.h, a.ctypes.data))
+
+    def surrogate_get_mask(self) -> np.ndarray:
+        a = np.zeros((self.n_obs,) + tuple(self.dom_shape), dtype=np.uint8)
+        self._ck(self.lib.qrt_surrogate_get_mask(self.h, a.ctypes.data))
+        return a
+
+    def surrogate_inputs(self, pos_obs, X):
+        self._ck(self.lib.qrt_surrogate_inputs(self.h, pos_obs.shape[0], C.c_void_p(pos_obs.data_ptr()),
+                                               C.c_void_p(X.data_ptr())))
+
+    def surrogate_sample(self, pos_obs, tau, seed: int) -> int:
+        n = C.c_int64(0)
+        self._ck(self.lib.qrt_surrogate_sample(self.h, pos_obs.shape[0], seed, C.c_void_p(pos_obs.data_ptr()),
+                                               C.c_void_p(tau.data_ptr()), C.byref(n)))
+        return int(n.value)
+
+    def surrogate_train(self, pos_obs, tau, steps: int, batch: int = 8192, lr: float = 2e-3,
+                        lr_final: float = 5e-5, init: bool = True, seed: int = 1, tau_cap: float = 12.0,
+                        weight_floor: float = 0.02, beta1: float = 0.9, beta2: float = 0.999,
+                        eps: float = 1e-8) -> dict:
+        cfg = qrt_train_cfg(steps=steps, batch=batch, init=int(init), lr=lr, lr_final=lr_final, beta1=beta1,
+                            beta2=beta2, eps=eps, tau_cap=tau_cap, weight_floor=weight_floor, seed=seed)
+        rep = qrt_train_report()
+        self._ck(self.lib.qrt_surrogate_train(self.h, pos_obs.shape[0], C.c_void_p(pos_obs.data_ptr()),
+                                              C.c_void_p(tau.data_ptr()), C.byref(cfg), C.byref(rep)))
+        return _as_dict(rep)
+
+    def surrogate_validate(self, pos_obs, tau, max_err: float = 0.02, min_count: int = 16) -> dict:
+        rep = qrt_mask_report()
+        self._ck(self.lib.qrt_surrogate_validate(self.h, pos_obs.shape[0], C.c_void_p(pos_obs.data_ptr()),
+                                                 C.c_void_p(tau.data_ptr()), max_err, min_count, C.byref(rep)))
+        return _as_dict(rep)

@@ -1,0 +1,264 @@
+"""Surrogate peel-off on the GPU against the oracle, through the C ABI.
+
+Gates:
+  * network forward and gradient: the BF16 matrix-core kernels against the
+    oracle's network with the same bfloat16 rounding points (relative
+    Frobenius error <= 1e-3, FP32 accumulation against FP64 sums); against the
+    plain FP64 network the forward pass stays within 5e-2, and the gradient no
+    further than the bfloat16 arithmetic itself (the emulating oracle is 6-7 %
+    from FP64 there: back-propagated errors are rounded at every layer);
+  * Adam: the first step moves every parameter with a non-zero gradient by
+    the learning rate (bias-corrected moments equal g and g^2);
+  * training: the GPU trainer fits the closed-form optical depth of a
+    homogeneous sphere;
+  * pilot samples: inside the domain, labels equal to the oracle's exact
+    traversal, reproducible;
+  * transport with the surrogate (FP64): images equal to the oracle's
+    surrogate transport per pixel within 2e-3 (a bfloat16 activation can
+    round the other way after FP32 instead of FP64 sums), surrogate and
+    fallback counts equal; a zero mask gives the exact transport.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from synth import scenes
+
+pytestmark = pytest.mark.gpu
+
+DISK_DOMAIN = dict(center=(0.0, 0.0, 0.0), r_in=0.05, r_out=1.0, h0=0.1, beta=1.125, zmax_over_h=3.0)
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def Q():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_2406_15632_amd import qrt
+    qrt.load()
+    return qrt
+
+
+@pytest.fixture()
+def ctx(Q):
+    c = Q.Context(0)
+    yield c
+    c.close()
+
+
+def _params(seed, out_bias=1.0):
+    rng = np.random.default_rng(seed)
+    layers = M.unpack(M.he_uniform(seed))
+    layers = [(W, rng.uniform(-0.2, 0.2, b.shape)) for W, b in layers]
+    layers[4] = (layers[4][0] * 0.5, np.array([out_bias]))
+    return M.pack(layers).astype(np.float32)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _small_disk(n=32, orders=3, npix=32):
+    return scenes.disk128(n_packets=1 << 12, n=n).replace(max_orders=orders, npix=npix, fp64=True)
+
+
+@pytest.mark.parametrize("n", [64, 1000])
+def test_mlp_forward_matches_oracle(ctx, Q, n):
+    import torch
+    _say(f"mlp forward n={n}")
+    sc = _small_disk()
+    ctx.set_scene(sc)
+    th = _params(40)
+    ctx.mlp_set_params(th)
+    X = np.random.default_rng(41).uniform(-1, 1, (n, 5)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    y = torch.zeros(n, dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(Xd, y)
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy().astype(np.float64)
+    ye, _ = M.forward(th.astype(np.float64), X.astype(np.float64), emulate_bf16=True)
+    y64, _ = M.forward(th.astype(np.float64), X.astype(np.float64))
+    assert _rel(yg, ye) <= 1e-3
+    assert _rel(yg, y64) <= 5e-2
+    assert np.array_equal(ctx.mlp_get_params(), th)
+
+
+@pytest.mark.parametrize("n", [64, 777])
+def test_mlp_gradient_matches_oracle(ctx, Q, n):
+    import torch
+    _say(f"mlp backward n={n}")
+    sc = _small_disk()
+    ctx.set_scene(sc)
+    th = _params(42)
+    ctx.mlp_set_params(th)
+    rng = np.random.default_rng(43)
+    X = rng.uniform(-1, 1, (n, 5)).astype(np.float32)
+    dy = rng.normal(size=n).astype(np.float32)
+    g = torch.zeros(Q.MLP_PARAMS, dtype=torch.float32, device="cuda")
+    ctx.mlp_backward(torch.from_numpy(X).cuda(), torch.from_numpy(dy).cuda(), g)
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    ge = M.backward(th.astype(np.float64), X.astype(np.float64), dy.astype(np.float64), emulate_bf16=True)
+    g64 = M.backward(th.astype(np.float64), X.astype(np.float64), dy.astype(np.float64))
+    # per layer block, weights and biases separately
+    for l, (w, b) in enumerate(M.OFFSETS):
+        nw = M.SIZES[l] * M.SIZES[l + 1]
+        for lo, hi in ((w, w + nw), (b, b + M.SIZES[l + 1])):
+            assert _rel(gg[lo:hi], ge[lo:hi]) <= 1e-3, (l, lo)
+    assert _rel(gg, g64) <= _rel(ge, g64) + 2e-3
+
+
+def test_adam_first_step_moves_by_the_learning_rate(ctx, Q):
+    import torch
+    _say("adam first step")
+    sc = _small_disk()
+    ctx.set_scene(sc)
+    th = _params(44)
+    ctx.mlp_set_params(th)
+    n = 4096
+    rng = np.random.default_rng(45)
+    pos = np.column_stack([rng.uniform(-0.9, 0.9, (n, 2)), rng.uniform(-0.05, 0.05, n),
+                           rng.integers(0, 3, n)]).astype(np.float32)
+    tau = rng.uniform(0.1, 3, n).astype(np.float32)
+    lr = 1e-3
+    ctx.surrogate_train(torch.from_numpy(pos).cuda(), torch.from_numpy(tau).cuda(), steps=1, batch=1024, lr=lr,
+                        lr_final=lr, init=False, seed=3)
+    th1 = ctx.mlp_get_params().astype(np.float64)
+    d = np.abs(th1 - th.astype(np.float64))
+    moved = d > 0
+    assert moved.mean() > 0.5
+    # lr g / (|g| + eps): equal to lr unless |g| is comparable to eps
+    assert np.all(d[moved] <= lr * (1 + 1e-5) + 1e-7)
+    assert np.median(d[moved]) > 0.99 * lr
+
+
+def test_training_fits_homogeneous_sphere_optical_depth(ctx, Q):
+    """Closed-form target: tau from p toward o in a homogeneous sphere of radius
+    R and extinction k is k (-p.o + sqrt(R^2 - |p|^2 + (p.o)^2))."""
+    import torch
+    _say("train on closed-form sphere optical depth")
+    sc = scenes.thin_sphere(n=32, npix=16)
+    ctx.set_scene(sc)
+    R, kr = 0.9, 3.0
+    rng = np.random.default_rng(46)
+    n = 1 << 16
+    p = rng.uniform(-R, R, (4 * n, 3))
+    p = p[np.linalg.norm(p, axis=1) < R][:n]
+    ob = rng.integers(0, len(sc.observers), len(p))
+    th = np.array([o[0] for o in sc.observers])[ob]
+    ph = np.array([o[1] for o in sc.observers])[ob]
+    o = np.stack([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)], 1)
+    po = np.sum(p * o, 1)
+    tau = kr * (-po + np.sqrt(R * R - np.sum(p * p, 1) + po * po))
+    pos = torch.from_numpy(np.column_stack([p, ob]).astype(np.float32)).cuda()
+    td = torch.from_numpy(tau.astype(np.float32)).cuda()
+    rep = ctx.surrogate_train(pos, td, steps=3000, batch=4096, lr=3e-3, lr_final=1e-4, seed=5, tau_cap=20.0,
+                              weight_floor=1.0)
+    assert rep["loss_final"] < 1e-2 * rep["loss_first"]
+    X = torch.zeros((len(p), 5), dtype=torch.float32, device="cuda")
+    ctx.surrogate_inputs(pos, X)
+    y = torch.zeros(len(p), dtype=torch.float32, device="cuda")
+    ctx.mlp_forward(X, y)
+    torch.cuda.synchronize()
+    err = y.cpu().numpy() - tau
+    assert np.sqrt(np.mean(err ** 2)) < 0.03 * np.sqrt(np.mean(tau ** 2))
+
+
+def test_pilot_samples_are_exact_and_reproducible(ctx, Q):
+    import torch
+    _say("pilot samples small disk")
+    sc = _small_disk()
+    ctx.set_scene(sc)
+    ctx.surrogate_set_domain(n_r=16, n_z=12, **DISK_DOMAIN)
+    n = 3000
+    pos = torch.zeros((n, 4), dtype=torch.float32, device="cuda")
+    tau = torch.zeros(n, dtype=torch.float32, device="cuda")
+    pilot = ctx.surrogate_sample(pos, tau, seed=77)
+    assert pilot > 0
+    P1, T1 = pos.cpu().numpy().copy(), tau.cpu().numpy().copy()
+    ctx.surrogate_sample(pos, tau, seed=77)
+    assert np.array_equal(pos.cpu().numpy(), P1) and np.array_equal(tau.cpu().numpy(), T1)
+    sg = O.Surrogate(np.zeros(M.N_PARAMS), valid=np.ones((3, 16, 12), np.uint8), **DISK_DOMAIN)
+    cells = O.dom_cells(sc, sg, P1[:, :3].astype(np.float64))
+    assert np.all(cells >= 0)
+    assert set(np.unique(P1[:, 3]).astype(int)) <= {0, 1, 2}
+    osc = O.OracleScene(sc)
+    for j in range(0, n, 7):
+        th, ph = sc.observers[int(P1[j, 3])]
+        o = (math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th))
+        t, _ = O.tau_ray(osc, P1[j, :3].astype(np.float64), o)
+        assert T1[j] == pytest.approx(t, rel=1e-6, abs=1e-30)
+    # the images and counters of the pilot are not kept
+    assert ctx.counters()["packets"] == 0
+
+
+def _sur_run_gpu(ctx, Q, sc, th, valid, count, kind=O.SOBOL):
+    ctx.set_scene(sc, kind=kind)
+    ctx.mlp_set_params(th)
+    ctx.surrogate_set_domain(n_r=valid.shape[1], n_z=valid.shape[2], **DISK_DOMAIN)
+    ctx.surrogate_set_mask(valid)
+    ctx.set_transport(sc.max_orders, sc.tau_min, Q.FP64, Q.PEEL_SURROGATE)
+    ctx.reset_images()
+    ctx.run(1, count)
+    return ctx.read_images(normalized=False) / count, ctx.counters()
+
+
+@pytest.mark.parametrize("fill", ["all", "half"])
+def test_surrogate_transport_matches_oracle(ctx, Q, fill):
+    _say(f"surrogate transport parity mask={fill}")
+    sc = _small_disk()
+    th = _params(47, out_bias=1.5)
+    rng = np.random.default_rng(48)
+    valid = np.ones((3, 16, 12), np.uint8) if fill == "all" else (rng.random((3, 16, 12)) < 0.5).astype(np.uint8)
+    count = 1 << 12
+    g, cg = _sur_run_gpu(ctx, Q, sc, th, valid, count)
+    sg = O.Surrogate(th, valid=valid, **DISK_DOMAIN)
+    o, co, _ = O.run(sc, O.SOBOL, 1, count, nthreads=8, surrogate=sg)
+    assert co["surrogate"] > 0
+    for k in ("surrogate", "fallbacks", "peels"):
+        assert abs(cg[k] - co[k]) <= 4 + 1e-5 * co[k], k
+    for ob in range(3):
+        Io = o[ob, 0]
+        mx = Io.max()
+        assert abs(g[ob, 0].sum() - Io.sum()) <= 1e-4 * Io.sum()
+        d = np.abs(g[ob, 0] - Io)
+        assert np.all(d <= 2e-3 * Io + 1e-11 * mx), f"obs {ob}: max rel {np.max(d / np.maximum(Io, 1e-300)):.3e}"
+        for s in (1, 2):
+            assert np.all(np.abs(g[ob, s] - o[ob, s]) <= 2e-3 * Io + 1e-11 * mx)
+
+
+def test_zero_mask_is_the_exact_transport(ctx, Q):
+    _say("surrogate zero mask vs exact")
+    sc = _small_disk()
+    count = 1 << 12
+    ctx.set_scene(sc)
+    ctx.reset_images()
+    ctx.run(1, count)
+    e = ctx.read_images(normalized=False)
+    ce = ctx.counters()
+    g, cg = _sur_run_gpu(ctx, Q, sc, _params(49), np.zeros((3, 16, 12), np.uint8), count)
+    assert cg["surrogate"] == 0 and cg["fallbacks"] == cg["peel_rays"] == ce["peel_rays"]
+    assert np.allclose(g * count, e, rtol=1e-12, atol=1e-300)
+
+
+def test_surrogate_requires_parameters_and_domain(ctx, Q):
+    sc = _small_disk()
+    ctx.set_scene(sc)
+    with pytest.raises(Q.QRTError) as ei:
+        ctx.set_transport(3, 1e-8, Q.FP64, Q.PEEL_SURROGATE)
+    assert ei.value.code == Q.QRT_NOT_TRAINED
+    ctx.mlp_init(1)
+    with pytest.raises(Q.QRTError):
+        ctx.set_transport(3, 1e-8, Q.FP64, Q.PEEL_SURROGATE)
+    ctx.surrogate_set_domain(n_r=4, n_z=4, **DISK_DOMAIN)
+    ctx.set_transport(3, 1e-8, Q.FP64, Q.PEEL_SURROGATE)
+    with pytest.raises(Q.QRTError):
+        ctx.mlp_set_params(np.zeros(10, np.float32))
