@@ -180,8 +180,10 @@ int qrt_trace_tau(qrt_ctx *ctx, int64_t n, const double *p, const double *k, dou
  * Inside a validated domain the surrogate replaces the traversal of a
  * peel-off ray by a small network tau_hat(x, y, z, theta_obs, phi_obs):
  *   5 inputs -> 4 hidden layers of 64 ReLU units -> 1 output, clamped at 0.
- * Inputs: position mapped from the mesh box to [-1, 1] per axis (FP64, then
- * rounded to FP32), 2 theta / pi - 1 and phi / pi - 1 of the observer.
+ * Inputs, in the coordinates of the domain below (computed in FP64, rounded
+ * to FP32): (x - c_x) / r_out, (y - c_y) / r_out, (z - c_z) / (zmax h(R))
+ * clamped to [-4, 4] (0 on the axis), 2 theta / pi - 1 and phi / pi - 1 of
+ * the observer.
  * Inference and training run on the matrix cores in bfloat16 with FP32
  * accumulation; FP32 master weights and Adam moments.
  * Parameters: QRT_MLP_PARAMS FP32 values, layer by layer, each W[in][out]
@@ -219,7 +221,7 @@ typedef struct {
     int64_t valid_cells;  /* cells marked for the network */
     int64_t samples;      /* validation samples inside the domain */
     int64_t samples_valid;/* ... of which in valid cells */
-    double max_err_valid; /* largest relative transmission error of a valid cell */
+    double max_err_valid; /* largest transmission error of a valid cell */
 } qrt_mask_report;
 
 /* Network parameters from / to the host (n = QRT_MLP_PARAMS).  Setting them
@@ -247,8 +249,8 @@ int qrt_surrogate_set_domain(qrt_ctx *ctx, const double center[3], double r_in, 
 int qrt_surrogate_set_mask(qrt_ctx *ctx, const uint8_t *mask);
 int qrt_surrogate_get_mask(qrt_ctx *ctx, uint8_t *mask);
 
-/* Normalised network inputs X[n][5] of sample rows pos_obs[n][4].  Device
-   pointers; asynchronous. */
+/* Network inputs X[n][5] of sample rows pos_obs[n][4] (needs a domain).
+   Device pointers; asynchronous. */
 int qrt_surrogate_inputs(qrt_ctx *ctx, int64_t n, const float *pos_obs, float *X);
 
 /* Training samples from a pilot run: Philox packets (key seed) of the current
@@ -269,11 +271,15 @@ int qrt_surrogate_train(qrt_ctx *ctx, int64_t n, const float *pos_obs, const flo
                         qrt_train_report *rep);
 
 /* Builds the mask from validation samples: a cell (observer, R bin, z bin)
-   is valid when it holds at least min_count samples and
-   sum |exp(-tau_hat) - exp(-tau)| <= max_err * sum exp(-tau) over them.
+   is valid when it holds at least min_count samples and its transmission
+   error  sum |exp(-tau_hat) - exp(-tau)| / sum max(exp(-tau), T_floor)
+   over them is at most max_err, where T_floor = floor_frac times the mean
+   transmission of that observer's samples in the domain (floor_frac = 0: the
+   plain relative error; a floor keeps cells whose light is too faint to
+   matter from failing on their relative error alone).
    Device sample buffers; rep may be NULL.  Synchronous. */
 int qrt_surrogate_validate(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, double max_err,
-                           int64_t min_count, qrt_mask_report *rep);
+                           double floor_frac, int64_t min_count, qrt_mask_report *rep);
 
 #ifdef __cplusplus
 }

@@ -6,8 +6,12 @@ imports it.
 The surrogate is not part of the paper.  It stands in for the exact mesh
 traversal of a peel-off ray (Sec. 3.4, 3.6), which the paper reports as the
 bulk of the run time (Sec. 3.1).  Network: 5 inputs (position x, y, z and
-observer theta, phi, each mapped to [-1, 1]) -> 4 hidden layers of 64 ReLU
-units -> 1 linear output, the optical depth to the observer.
+observer theta, phi, each mapped to [-1, 1] inside the domain) -> 4 hidden
+layers of 64 ReLU units -> 1 linear output, the optical depth to the observer.  The position
+enters in the coordinates of the surrogate's cylindrical domain (centre c,
+outer radius r_out, scale height h(R) = h0 R^beta, half-thickness zmax h):
+x = (p_x - c_x) / r_out, y = (p_y - c_y) / r_out, z = (p_z - c_z) / (zmax h(R)),
+so that the steep vertical profile of a flared disk becomes a smooth function.
 
 Flat parameter vector (12,929 values), layer by layer, each layer its weight
 matrix W[in][out] row-major followed by its bias b[out]:
@@ -157,11 +161,14 @@ def disk_cell(p, center, r_in, r_out, h0, beta, zmax_over_h, n_r, n_z):
     return np.where(ok, ir, -1), np.where(ok, iz, -1)
 
 
-def validity_mask(obs, ir, iz, tau, tau_hat, n_obs, n_r, n_z, max_err: float, min_count: int):
-    """Per (observer, R bin, z bin): relative transmission error
-    sum |exp(-tau_hat) - exp(-tau)| / sum exp(-tau) over the validation samples
-    in the cell; valid where at least min_count samples fall in it and the error
-    is at most max_err.  Returns (valid uint8, error, count) of shape [n_obs][n_r][n_z]."""
+def validity_mask(obs, ir, iz, tau, tau_hat, n_obs, n_r, n_z, max_err: float, min_count: int,
+                  floor_frac: float = 0.0):
+    """Per (observer, R bin, z bin): transmission error
+    sum |exp(-tau_hat) - exp(-tau)| / sum max(exp(-tau), T_floor) over the
+    validation samples in the cell, T_floor = floor_frac x the mean
+    transmission of the observer's samples in the domain; valid where at least
+    min_count samples fall in it and the error is at most max_err.
+    Returns (valid uint8, error, count) of shape [n_obs][n_r][n_z]."""
     err_num = np.zeros((n_obs, n_r, n_z))
     den = np.zeros((n_obs, n_r, n_z))
     cnt = np.zeros((n_obs, n_r, n_z), dtype=np.int64)
@@ -169,8 +176,9 @@ def validity_mask(obs, ir, iz, tau, tau_hat, n_obs, n_r, n_z, max_err: float, mi
     o, r, z = np.asarray(obs)[sel], ir[sel], iz[sel]
     T = np.exp(-np.asarray(tau, dtype=np.float64)[sel])
     Th = np.exp(-np.maximum(np.asarray(tau_hat, dtype=np.float64)[sel], 0.0))
+    t_mean = np.array([T[o == k].mean() if np.any(o == k) else 0.0 for k in range(n_obs)])
     np.add.at(err_num, (o, r, z), np.abs(Th - T))
-    np.add.at(den, (o, r, z), T)
+    np.add.at(den, (o, r, z), np.maximum(T, floor_frac * t_mean[o]))
     np.add.at(cnt, (o, r, z), 1)
     err = np.where(den > 0, err_num / np.where(den > 0, den, 1.0), np.inf)
     valid = ((cnt >= min_count) & (err <= max_err)).astype(np.uint8)

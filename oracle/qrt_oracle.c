@@ -377,12 +377,22 @@ static int64_t og_dom_cell(const og_scene *S, const double p[3])
     return ir * S->dom_nz + iz;
 }
 
-/* Network inputs: position mapped from the box to [-1,1], observer angles
-   2 theta / pi - 1 and phi / pi - 1, each rounded to FP32. */
+/* Network inputs in the domain's own coordinates, each rounded to FP32:
+   x and y relative to the centre over r_out, the height over the domain's
+   half-thickness zmax h(R) (clamped to [-4, 4], 0 on the axis), and the
+   observer angles 2 theta / pi - 1 and phi / pi - 1. */
 static void og_mlp_inputs(const og_scene *S, const double p[3], int obs, double x[5])
 {
-    for (int a = 0; a < 3; ++a)
-        x[a] = (double)(float)(2.0 * (p[a] - S->lo[a]) / (S->hi[a] - S->lo[a]) - 1.0);
+    double dx = p[0] - S->dom_center[0], dy = p[1] - S->dom_center[1], dz = p[2] - S->dom_center[2];
+    double R = sqrt(dx * dx + dy * dy);
+    double zn = 0.0;
+    if (R > 0.0) {
+        zn = dz / (S->dom_zmax * (S->dom_h0 * pow(R, S->dom_beta)));
+        zn = zn > 4.0 ? 4.0 : (zn < -4.0 ? -4.0 : zn);
+    }
+    x[0] = (double)(float)(dx / S->dom_r_out);
+    x[1] = (double)(float)(dy / S->dom_r_out);
+    x[2] = (double)(float)zn;
     x[3] = (double)(float)(2.0 * S->obs_theta[obs] / OG_PI - 1.0);
     x[4] = (double)(float)(S->obs_phi[obs] / OG_PI - 1.0);
 }

@@ -434,10 +434,11 @@ static InputMap input_map(const qrt_ctx *c)
 {
     InputMap M;
     memset(&M, 0, sizeof(M));
-    for (int a = 0; a < 3; ++a) {
-        M.lo[a] = c->lo[a];
-        M.ext[a] = c->hi[a] - c->lo[a];
-    }
+    for (int a = 0; a < 3; ++a) M.center[a] = c->dom_center[a];
+    M.r_out = c->dom_r_out;
+    M.h0 = c->dom_h0;
+    M.beta = c->dom_beta;
+    M.zmax = c->dom_zmax;
     for (int i = 0; i < c->n_obs; ++i) {
         M.obs_in[i][0] = (float)(2.0 * c->theta[i] / 3.14159265358979323846 - 1.0);
         M.obs_in[i][1] = (float)(c->phi[i] / 3.14159265358979323846 - 1.0);
@@ -476,19 +477,13 @@ static void transport_params(const qrt_ctx *c, TransportParams &P)
     P.peel_mode = c->peel_mode;
     if (c->has_domain) {
         SurrogateParams &S = P.sur;
-        for (int a = 0; a < 3; ++a) S.center[a] = c->dom_center[a];
-        S.r_in = c->dom_r_in; S.r_out = c->dom_r_out; S.h0 = c->dom_h0; S.beta = c->dom_beta; S.zmax = c->dom_zmax;
+        S.in = input_map(c);
+        S.r_in = c->dom_r_in;
         S.n_r = c->dom_nr;
         S.n_z = c->dom_nz;
         S.valid = c->dom_valid;
         S.params = c->mlp;
         S.tiles = c->tiles;
-        const InputMap M = input_map(c);
-        for (int a = 0; a < 3; ++a) {
-            S.lo[a] = M.lo[a];
-            S.ext[a] = M.ext[a];
-        }
-        memcpy(S.obs_in, M.obs_in, sizeof(S.obs_in));
     }
 }
 
@@ -814,7 +809,7 @@ int qrt_surrogate_get_mask(qrt_ctx *c, uint8_t *mask)
 int qrt_surrogate_inputs(qrt_ctx *c, int64_t n, const float *pos_obs, float *X)
 {
     if (!c) return QRT_INVALID_ARG;
-    if (!c->has_grid || !c->has_obs) return fail(c, QRT_BAD_STATE, "set grid and observers first");
+    if (!c->has_obs || !c->has_domain) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (n < 0 || (n > 0 && (!pos_obs || !X))) return fail(c, QRT_INVALID_ARG, "bad buffers");
     DeviceGuard dg(c->device);
     HIP_TRY(c, launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), X, c->stream), "input launch");
@@ -956,7 +951,7 @@ int qrt_surrogate_train(qrt_ctx *c, int64_t n, const float *pos_obs, const float
 {
     if (!c) return QRT_INVALID_ARG;
     if (!cfg || n < 1 || !pos_obs || !tau) return fail(c, QRT_INVALID_ARG, "bad arguments");
-    if (!c->has_grid || !c->has_obs) return fail(c, QRT_BAD_STATE, "set grid and observers first");
+    if (!c->has_obs || !c->has_domain) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (cfg->steps < 0 || cfg->batch < 64 || cfg->batch > 65536 || cfg->batch % 64)
         return fail(c, QRT_INVALID_ARG, "batch must be a multiple of 64 in 64..65536");
     if (!(cfg->lr > 0.0f) || !(cfg->lr_final >= 0.0f) || !(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f) ||
@@ -1007,12 +1002,12 @@ int qrt_surrogate_train(qrt_ctx *c, int64_t n, const float *pos_obs, const float
 }
 
 int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const float *tau, double max_err,
-                           int64_t min_count, qrt_mask_report *rep)
+                           double floor_frac, int64_t min_count, qrt_mask_report *rep)
 {
     if (!c) return QRT_INVALID_ARG;
     if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
     if (!c->has_domain || !c->has_obs || !c->has_grid) return fail(c, QRT_BAD_STATE, "set grid, observers, domain");
-    if (n < 1 || !pos_obs || !tau || !(max_err >= 0.0) || min_count < 1)
+    if (n < 1 || !pos_obs || !tau || !(max_err >= 0.0) || !(floor_frac >= 0.0) || min_count < 1)
         return fail(c, QRT_INVALID_ARG, "bad arguments");
     DeviceGuard dg(c->device);
     int rc = ensure_train_x(c, (size_t)n);
@@ -1033,6 +1028,9 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
     const size_t total = (size_t)c->n_obs * cells;
     std::vector<double> num(total, 0.0), den(total, 0.0);
     std::vector<int64_t> cnt(total, 0);
+    std::vector<int> cell_of((size_t)n, -1);
+    // mean transmission per observer over the samples inside the domain
+    std::vector<double> t_sum((size_t)c->n_obs, 0.0), t_cnt((size_t)c->n_obs, 0.0);
     int64_t inside = 0;
     for (int64_t j = 0; j < n; ++j) {
         const float *r = &hp[4 * (size_t)j];
@@ -1040,12 +1038,21 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
         if (ob < 0 || ob >= c->n_obs) continue;
         const int cell = host_dom_cell(c, r[0], r[1], r[2]);
         if (cell < 0) continue;
+        cell_of[(size_t)j] = cell;
         inside++;
+        t_sum[(size_t)ob] += exp(-(double)ht[(size_t)j]);
+        t_cnt[(size_t)ob] += 1.0;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        const int cell = cell_of[(size_t)j];
+        if (cell < 0) continue;
+        const int ob = (int)hp[4 * (size_t)j + 3];
+        const double floor_t = floor_frac * t_sum[(size_t)ob] / t_cnt[(size_t)ob];
         const double T = exp(-(double)ht[(size_t)j]);
         const double Th = exp(-(double)(hy[(size_t)j] > 0.0f ? hy[(size_t)j] : 0.0f));
         const size_t k = (size_t)ob * cells + (size_t)cell;
         num[k] += fabs(Th - T);
-        den[k] += T;
+        den[k] += T > floor_t ? T : floor_t;
         cnt[k]++;
     }
     std::vector<uint8_t> mask(total, 0);

@@ -24,18 +24,44 @@ struct DevObserver {
     double o[3], ex[3], ey[3];
 };
 
-// Surrogate peel-off: cylindrical domain with its validity mask, the network
-// (FP32 parameters for the biases, bfloat16 weight tiles), the input
-// normalisation, and the capture buffer of a pilot run (null when off).
-struct SurrogateParams {
+// Network inputs of the surrogate, in the coordinates of its cylindrical
+// domain (centre c, outer radius r_out, scale height h(R) = h0 R^beta,
+// half-thickness zmax h): (p_x - c_x) / r_out, (p_y - c_y) / r_out,
+// (p_z - c_z) / (zmax h(R)) clamped to [-4, 4] (0 on the axis), then
+// 2 theta / pi - 1 and phi / pi - 1 of the observer; each rounded to FP32.
+struct InputMap {
     double center[3];
-    double r_in, r_out, h0, beta, zmax;   // R in [r_in, r_out), |z| < zmax h0 R^beta
+    double r_out, h0, beta, zmax;
+    float obs_in[kMaxObs][2];
+    int n_obs;
+};
+
+__device__ __forceinline__ void mlp_inputs(const InputMap &M, double px, double py, double pz, int ob, float x[5])
+{
+    const double dx = px - M.center[0], dy = py - M.center[1], dz = pz - M.center[2];
+    const double R = sqrt(dx * dx + dy * dy);
+    double zn = 0.0;
+    if (R > 0.0) {
+        zn = dz / (M.zmax * (M.h0 * pow(R, M.beta)));
+        zn = zn > 4.0 ? 4.0 : (zn < -4.0 ? -4.0 : zn);
+    }
+    x[0] = (float)(dx / M.r_out);
+    x[1] = (float)(dy / M.r_out);
+    x[2] = (float)zn;
+    x[3] = M.obs_in[ob][0];
+    x[4] = M.obs_in[ob][1];
+}
+
+// Surrogate peel-off: cylindrical domain (R in [r_in, r_out), |z| < zmax h(R))
+// with its validity mask, the network (FP32 parameters for the biases,
+// bfloat16 weight tiles), and the capture buffer of a pilot run (null when off).
+struct SurrogateParams {
+    InputMap in;                          // domain geometry and input map
+    double r_in;
     int n_r, n_z;
     const uint8_t *valid;                 // [n_obs][n_r][n_z]
     const float *params;                  // 12929 FP32
     const void *tiles;                    // bfloat16 weight tiles
-    double lo[3], ext[3];                 // mesh box: inputs 2 (p - lo) / ext - 1
-    float obs_in[kMaxObs][2];             // 2 theta / pi - 1, phi / pi - 1
     float *cap;                           // pilot capture: [cap_capacity][4] = x, y, z, observer
     uint32_t *cap_count;
     uint32_t cap_capacity;
@@ -71,11 +97,7 @@ struct AdamStep {
     float c1, c2;       // bias corrections 1/(1 - beta1^t), 1/(1 - beta2^t)
 };
 
-struct InputMap {
-    double lo[3], ext[3];
-    float obs_in[kMaxObs][2];
-    int n_obs;
-};
+
 
 // A scattered packet between kernels: position, direction, reference axis,
 // Stokes weight, the optical depth of its next flight, point index and

@@ -7,8 +7,9 @@
 // Network: 5 inputs -> 4 hidden layers of 64 ReLU units -> 1 linear output.
 // Flat FP32 parameters (12,929), layer by layer: W_l[in][out] row-major, then
 // b_l[out]:  W0 5x64 | b0 | W1 64x64 | b1 | W2 | b2 | W3 | b3 | W4 64x1 | b4.
-// Inputs: position mapped from the mesh box to [-1, 1] per axis (computed in
-// FP64, rounded to FP32), 2 theta / pi - 1 and phi / pi - 1.
+// Inputs: position in the coordinates of the surrogate's cylindrical domain
+// (computed in FP64, rounded to FP32; see InputMap), 2 theta / pi - 1 and
+// phi / pi - 1 of the observer.
 //
 // Matrix-core mapping (v_mfma_f32_16x16x32_bf16, one wave):
 //   D[16x16] += A[16x32] B[32x16]; lane L holds row L%16 of A and column L%16
@@ -156,6 +157,76 @@ __device__ __forceinline__ float mlp_wave(const MlpWeights &W, const float *bias
         if ((lane >> 4) == nt) out = mine;
     }
     return out;
+}
+
+// The 64 queries of a wave through the network with the forward weight tiles
+// in LDS: each tile is read once and applied to all four 16-query tiles, so
+// one layer issues 16 independent matrix-core chains.  Query i is held by
+// lane i; returns lane i's raw output.  Every lane of the wave must call it.
+__device__ __forceinline__ float mlp_wave_lds(const bf16x8 *Wt, const float *bias, const float x[kMlpIn], int lane)
+{
+    bf16x8 xb[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const int src = nt * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xb[nt][q] = (__bf16)0.0f;
+#pragma unroll
+        for (int a = 0; a < kMlpIn; ++a) {
+            const float v = __shfl(x[a], src, 64);
+            if (lane < 16) xb[nt][a] = (__bf16)v;
+        }
+    }
+    f32x4 acc[4][4];   // [mt][nt]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bf16x8 a = Wt[fwd_tile(0, mt, 0) * 64 + lane];
+        const f32x4 b = bias_tile(bias, 0, mt, lane);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a, xb[nt], b);
+    }
+    bf16x8 h[4][2];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        h[nt][0] = relu_pack(acc[0][nt], acc[1][nt]);
+        h[nt][1] = relu_pack(acc[2][nt], acc[3][nt]);
+    }
+#pragma unroll
+    for (int l = 1; l <= 3; ++l) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8 a0 = Wt[fwd_tile(l, mt, 0) * 64 + lane];
+            const bf16x8 a1 = Wt[fwd_tile(l, mt, 1) * 64 + lane];
+            const f32x4 b = bias_tile(bias, l, mt, lane);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a0, h[nt][0], b);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) acc[mt][nt] = mfma(a1, h[nt][1], acc[mt][nt]);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            h[nt][0] = relu_pack(acc[0][nt], acc[1][nt]);
+            h[nt][1] = relu_pack(acc[2][nt], acc[3][nt]);
+        }
+    }
+    const bf16x8 a0 = Wt[fwd_tile(4, 0, 0) * 64 + lane];
+    const bf16x8 a1 = Wt[fwd_tile(4, 0, 1) * 64 + lane];
+    float out = 0.0f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        f32x4 o = {bias[256], 0.0f, 0.0f, 0.0f};
+        o = mfma(a0, h[nt][0], o);
+        o = mfma(a1, h[nt][1], o);
+        const float mine = __shfl(o[0], lane & 15, 64);
+        if ((lane >> 4) == nt) out = mine;
+    }
+    return out;
+}
+
+// Copy of the forward weight tiles into LDS, by the threads of one block.
+__device__ __forceinline__ void mlp_tiles_to_lds(bf16x8 *Wt, const bf16x8 *__restrict__ tiles)
+{
+    for (int i = threadIdx.x; i < kFwdTiles * 64; i += blockDim.x) Wt[i] = tiles[i];
 }
 
 // Copy of the biases into LDS (257 floats), by the threads of one block.

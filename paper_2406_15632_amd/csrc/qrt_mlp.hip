@@ -339,14 +339,26 @@ __global__ void __launch_bounds__(64) k_mlp_grad(const float *__restrict__ param
 }
 
 // ---------------------------------------------------------------- update
+// sum over the per-wave gradients of parameter p in a fixed order: eight
+// interleaved partial sums (independent loads in flight), then their sum
+__device__ __forceinline__ float sum_parts(const float *__restrict__ part, int n_parts, int p)
+{
+    float s[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    int w = 0;
+    for (; w + 8 <= n_parts; w += 8)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s[k] += part[(size_t)(w + k) * kMlpParams + p];
+    for (; w < n_parts; ++w) s[w & 7] += part[(size_t)w * kMlpParams + p];
+    return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 __global__ void __launch_bounds__(256) k_mlp_adam(float *__restrict__ params, float *__restrict__ m,
                                                   float *__restrict__ v, const float *__restrict__ part, int n_parts,
                                                   AdamStep A, __bf16 *__restrict__ tiles)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kMlpParams) return;
-    float g = 0.0f;
-    for (int w = 0; w < n_parts; ++w) g += part[(size_t)w * kMlpParams + p];
+    const float g = sum_parts(part, n_parts, p);
     const float mn = A.beta1 * m[p] + (1.0f - A.beta1) * g;
     const float vn = A.beta2 * v[p] + (1.0f - A.beta2) * g * g;
     m[p] = mn;
@@ -360,9 +372,7 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float *__restrict__ pa
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= kMlpParams) return;
-    float g = 0.0f;
-    for (int w = 0; w < n_parts; ++w) g += part[(size_t)w * kMlpParams + p];
-    out[p] = g;
+    out[p] = sum_parts(part, n_parts, p);
 }
 
 // ---------------------------------------------------------------- inputs
@@ -374,10 +384,10 @@ __global__ void __launch_bounds__(256) k_mlp_inputs(const float *__restrict__ po
     if (j >= n) return;
     int ob = (int)pos_obs[j * 4 + 3];
     ob = ob < 0 ? 0 : (ob >= M.n_obs ? M.n_obs - 1 : ob);
-    for (int a = 0; a < 3; ++a)
-        X[j * kMlpIn + a] = (float)(2.0 * ((double)pos_obs[j * 4 + a] - M.lo[a]) / M.ext[a] - 1.0);
-    X[j * kMlpIn + 3] = M.obs_in[ob][0];
-    X[j * kMlpIn + 4] = M.obs_in[ob][1];
+    float x[kMlpIn];
+    mlp_inputs(M, (double)pos_obs[j * 4], (double)pos_obs[j * 4 + 1], (double)pos_obs[j * 4 + 2], ob, x);
+#pragma unroll
+    for (int a = 0; a < kMlpIn; ++a) X[j * kMlpIn + a] = x[a];
 }
 
 // ---------------------------------------------------------------- launchers

@@ -558,40 +558,85 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
 // cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
 __device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
 {
-    const double dx = x - S.center[0], dy = y - S.center[1], dz = z - S.center[2];
+    const InputMap &D = S.in;
+    const double dx = x - D.center[0], dy = y - D.center[1], dz = z - D.center[2];
     const double R = sqrt(dx * dx + dy * dy);
-    if (!(R >= S.r_in && R < S.r_out)) return -1;
-    const double zh = dz / (S.h0 * pow(R, S.beta));
-    if (!(fabs(zh) < S.zmax)) return -1;
-    const int ir = (int)floor((R - S.r_in) / (S.r_out - S.r_in) * (double)S.n_r);
-    const int iz = (int)floor((zh + S.zmax) / (2.0 * S.zmax) * (double)S.n_z);
+    if (!(R >= S.r_in && R < D.r_out)) return -1;
+    const double zh = dz / (D.h0 * pow(R, D.beta));
+    if (!(fabs(zh) < D.zmax)) return -1;
+    const int ir = (int)floor((R - S.r_in) / (D.r_out - S.r_in) * (double)S.n_r);
+    const int iz = (int)floor((zh + D.zmax) / (2.0 * D.zmax) * (double)S.n_z);
     if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
     return ir * S.n_z + iz;
 }
 
-// One wave per block of 64 peel slots (one observer); the network runs on all
-// 64 lanes at once on the matrix cores, with its weights in registers.
+// Surrogate pass over the peel slots of one order.  Each wave scans blocks of
+// 64 slots, queues the visible rays that fall in valid cells of the domain in
+// LDS (network inputs and slot), and runs the network on the matrix cores
+// whenever 64 are queued, so every batch is full; the remainder is run at the
+// end.  The forward weight tiles sit in LDS and each is applied to the four
+// 16-query tiles of a batch in turn.
+constexpr int kMlpWaves = 4;    // waves per block
+constexpr int kMlpQueue = 128;  // queued rays per wave (a batch of 64 plus one block of 64)
+
+struct __align__(16) PeelMlpLds {
+    bf16x8 Wt[kFwdTiles * 64];
+    float bias[260];
+    float qx[kMlpWaves][kMlpIn][kMlpQueue];
+    uint32_t qslot[kMlpWaves][kMlpQueue];
+};
+
+// orders the wave's LDS accesses before and after this point
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R>
+__device__ __forceinline__ void peel_mlp_batch(const TransportParams &P, PeelMlpLds &L, int w, int lane, int count,
+                                               PeelRay<R> *__restrict__ peels, double *img_copy, size_t plane)
+{
+    const bool live = lane < count;
+    float x[kMlpIn];
+#pragma unroll
+    for (int a = 0; a < kMlpIn; ++a) x[a] = live ? L.qx[w][a][lane] : 0.0f;
+    const uint32_t slot = live ? L.qslot[w][lane] : 0u;
+    const float t = mlp_wave_lds(L.Wt, L.bias, x, lane);
+    if (live) {
+        PeelRay<R> *rp = peels + slot;
+        const PeelRay<R> r = *rp;
+        const double att = exp(-(double)fmaxf(t, 0.0f));
+        double *dst = img_copy + (size_t)r.obs * 3 * plane + (size_t)r.pix;
+        unsafeAtomicAdd(dst, att * (double)r.c[0]);
+        unsafeAtomicAdd(dst + plane, att * (double)r.c[1]);
+        unsafeAtomicAdd(dst + 2 * plane, att * (double)r.c[2]);
+        rp->pix = kNoPixel;
+    }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, PeelRay<R> *__restrict__ peels,
                                                   const Queues *__restrict__ Q, int in)
 {
-    __shared__ float bias[260];
-    mlp_bias_to_lds(bias, P.sur.params);
+    __shared__ PeelMlpLds L;
+    mlp_tiles_to_lds(L.Wt, (const bf16x8 *)P.sur.tiles);
+    mlp_bias_to_lds(L.bias, P.sur.params);
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    MlpWeights W;
-    mlp_load(W, (const bf16x8 *)P.sur.tiles, lane);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t n_live = Q->n_live[in];
     const uint64_t n_blocks = (uint64_t)P.n_obs * ((n_live + 63) / 64);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
     double *img_copy = P.img + (size_t)(blockIdx.x % kImageCopies) * (size_t)P.n_obs * 3 * plane;
-    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t wave = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const uint64_t waves = (uint64_t)gridDim.x * kMlpWaves;
+    const uint64_t wave = (uint64_t)blockIdx.x * kMlpWaves + w;
     const size_t cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
     uint32_t n_sur = 0, n_fb = 0;
+    int count = 0;   // queued rays of this wave (wave-uniform)
     for (uint64_t g = wave; g < n_blocks; g += waves) {
-        PeelRay<R> *rp = peels + g * 64 + lane;
-        const PeelRay<R> r = *rp;
+        const uint32_t slot = (uint32_t)(g * 64 + lane);
+        const PeelRay<R> r = peels[slot];
         const bool vis = r.pix != kNoPixel;
         bool use = false;
         if (vis) {
@@ -599,24 +644,33 @@ __global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, PeelR
             use = cell >= 0 && P.sur.valid[(size_t)r.obs * cells + (size_t)cell] != 0;
         }
         n_fb += (vis && !use) ? 1u : 0u;
-        if (__ballot(use) == 0) continue;
-        const int ob = (int)r.obs < P.n_obs ? (int)r.obs : 0;
-        float x[kMlpIn];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x[a] = (float)(2.0 * ((double)r.p[a] - P.sur.lo[a]) / P.sur.ext[a] - 1.0);
-        x[3] = P.sur.obs_in[ob][0];
-        x[4] = P.sur.obs_in[ob][1];
-        const float t = mlp_wave(W, bias, x, lane);
+        n_sur += use ? 1u : 0u;
+        const uint64_t m = __ballot(use);
+        if (m == 0) continue;
         if (use) {
-            const double att = exp(-(double)fmaxf(t, 0.0f));
-            double *dst = img_copy + (size_t)ob * 3 * plane + (size_t)r.pix;
-            unsafeAtomicAdd(dst, att * (double)r.c[0]);
-            unsafeAtomicAdd(dst + plane, att * (double)r.c[1]);
-            unsafeAtomicAdd(dst + 2 * plane, att * (double)r.c[2]);
-            rp->pix = kNoPixel;
-            n_sur++;
+            float x[kMlpIn];
+            mlp_inputs(P.sur.in, (double)r.p[0], (double)r.p[1], (double)r.p[2], (int)r.obs, x);
+            const int pos = count + (int)__popcll(m & lanes_below_mask());
+#pragma unroll
+            for (int a = 0; a < kMlpIn; ++a) L.qx[w][a][pos] = x[a];
+            L.qslot[w][pos] = slot;
+        }
+        count += (int)__popcll(m);
+        wave_lds_sync();
+        if (count >= 64) {
+            peel_mlp_batch<R>(P, L, w, lane, 64, peels, img_copy, plane);
+            // move the rest of the queue to its front (disjoint ranges)
+            const int rest = count - 64;
+            if (lane < rest) {
+#pragma unroll
+                for (int a = 0; a < kMlpIn; ++a) L.qx[w][a][lane] = L.qx[w][a][64 + lane];
+                L.qslot[w][lane] = L.qslot[w][64 + lane];
+            }
+            count = rest;
+            wave_lds_sync();
         }
     }
+    if (count > 0) peel_mlp_batch<R>(P, L, w, lane, count, peels, img_copy, plane);
     flush_counter(P.counters + CNT_SURROGATE, n_sur);
     flush_counter(P.counters + CNT_FALLBACKS, n_fb);
     flush_counter(P.counters + CNT_PEELS, n_sur);

@@ -91,7 +91,7 @@ SIGNATURES = {
     "qrt_surrogate_sample": (C.c_int, [_P, C.c_int64, C.c_uint64, _P, _P, C.POINTER(C.c_int64)]),
     "qrt_surrogate_train": (C.c_int, [_P, C.c_int64, _P, _P, C.POINTER(qrt_train_cfg),
                                       C.POINTER(qrt_train_report)]),
-    "qrt_surrogate_validate": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_int64,
+    "qrt_surrogate_validate": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_double, C.c_int64,
                                          C.POINTER(qrt_mask_report)]),
 }
 
@@ -321,8 +321,10 @@ class Context:
                                               C.c_void_p(tau.data_ptr()), C.byref(cfg), C.byref(rep)))
         return _as_dict(rep)
 
-    def surrogate_validate(self, pos_obs, tau, max_err: float = 0.02, min_count: int = 16) -> dict:
+    def surrogate_validate(self, pos_obs, tau, max_err: float = 0.02, floor_frac: float = 0.0,
+                           min_count: int = 16) -> dict:
         rep = qrt_mask_report()
         self._ck(self.lib.qrt_surrogate_validate(self.h, pos_obs.shape[0], C.c_void_p(pos_obs.data_ptr()),
-                                                 C.c_void_p(tau.data_ptr()), max_err, min_count, C.byref(rep)))
+                                                 C.c_void_p(tau.data_ptr()), max_err, floor_frac, min_count,
+                                                 C.byref(rep)))
         return _as_dict(rep)

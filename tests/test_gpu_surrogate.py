@@ -123,6 +123,7 @@ def test_adam_first_step_moves_by_the_learning_rate(ctx, Q):
     ctx.set_scene(sc)
     th = _params(44)
     ctx.mlp_set_params(th)
+    ctx.surrogate_set_domain(n_r=4, n_z=4, **DISK_DOMAIN)
     n = 4096
     rng = np.random.default_rng(45)
     pos = np.column_stack([rng.uniform(-0.9, 0.9, (n, 2)), rng.uniform(-0.05, 0.05, n),
@@ -147,6 +148,8 @@ def test_training_fits_homogeneous_sphere_optical_depth(ctx, Q):
     _say("train on closed-form sphere optical depth")
     sc = scenes.thin_sphere(n=32, npix=16)
     ctx.set_scene(sc)
+    # a domain that covers the sphere with inputs (x, y, z): r_out 1, h = 1, zmax 1
+    ctx.surrogate_set_domain((0.0, 0.0, 0.0), 0.0, 1.0, 1.0, 0.0, 1.0, 4, 4)
     R, kr = 0.9, 3.0
     rng = np.random.default_rng(46)
     n = 1 << 16

@@ -191,3 +191,25 @@ def test_validity_mask_counts():
     assert valid.sum() == 0
     valid, _, _ = M.validity_mask(obs, ir, iz, tau, tau_hat, 1, n_r, n_z, 0.02, 5)
     assert valid.sum() == 0
+
+
+def test_validity_mask_floor():
+    # one cell with faint light: relative error 50 %, but far below a floor of
+    # 0.5 x the observer's mean transmission, which a bright cell sets
+    center = (0.0, 0.0, 0.0)
+    R = 0.05 + 0.5 * 0.95
+    h = 0.1 * R ** 1.125
+    p = np.array([[R, 0, -2.5 * h]] * 4 + [[R, 0, 2.5 * h]] * 4)
+    ir, iz = M.disk_cell(p, center, 0.05, 1.0, 0.1, 1.125, 3.0, 1, 2)
+    assert list(iz) == [0] * 4 + [1] * 4
+    tau = np.array([8.0] * 4 + [0.1] * 4)
+    tau_hat = tau + np.array([0.5] * 4 + [0.0] * 4)
+    obs = np.zeros(8, dtype=np.int64)
+    v0, e0, _ = M.validity_mask(obs, ir, iz, tau, tau_hat, 1, 1, 2, 0.02, 4)
+    assert v0[0, 0, 0] == 0 and v0[0, 0, 1] == 1
+    T = np.exp(-tau)
+    floor = 0.5 * T.mean()
+    v1, e1, _ = M.validity_mask(obs, ir, iz, tau, tau_hat, 1, 1, 2, 0.02, 4, floor_frac=0.5)
+    expect = np.sum(np.abs(np.exp(-tau_hat[:4]) - T[:4])) / (4 * floor)
+    assert e1[0, 0, 0] == pytest.approx(expect, rel=1e-12)
+    assert v1[0, 0, 0] == 1 and v1[0, 0, 1] == 1

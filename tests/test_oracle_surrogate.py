@@ -87,7 +87,7 @@ def test_constant_network_changes_attenuation_only():
     assert np.array_equal(e0[~inside, 5:8], e1[~inside, 5:8])
 
 
-def test_mlp_tau_uses_box_normalised_inputs():
+def test_mlp_tau_uses_domain_coordinates():
     sc = _disk()
     rng = np.random.default_rng(8)
     layers = [(rng.normal(size=(M.SIZES[l], M.SIZES[l + 1])) * 0.3, rng.normal(size=M.SIZES[l + 1]) * 0.1)
@@ -97,7 +97,9 @@ def test_mlp_tau_uses_box_normalised_inputs():
     p = np.array([0.3, -0.2, 0.01])
     for ob in range(3):
         thv, phv = sc.observers[ob]
-        x = np.array([[float(np.float32(2 * (p[a] - sc.lo[a]) / (sc.hi[a] - sc.lo[a]) - 1)) for a in range(3)]
-                      + [float(np.float32(2 * thv / math.pi - 1)), float(np.float32(phv / math.pi - 1))]])
+        R = math.hypot(p[0], p[1])
+        zn = p[2] / (3.0 * 0.1 * R ** 1.125)          # z over zmax h(R) of the disk domain
+        x = np.array([[float(np.float32(p[0])), float(np.float32(p[1])), float(np.float32(zn)),
+                       float(np.float32(2 * thv / math.pi - 1)), float(np.float32(phv / math.pi - 1))]])
         y, _ = M.forward(th.astype(np.float64), x, emulate_bf16=True)
         assert O.mlp_tau(sc, sg, p, ob) == pytest.approx(max(y[0], 0.0), rel=1e-6, abs=1e-9)
