@@ -15,7 +15,13 @@ The JSON line carries
                 when the kernel sources are unchanged since they were taken;
   time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
                 the speed-up of each over the Monte Carlo (Philox) baseline;
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload.
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload;
+  surrogate     the learned peel-off on the same disk scene at 2^24 packets: pilot
+                sampling, GPU training and validation times, the share of
+                peel-off rays the network answers, the image bias against the
+                plain method, and the time to 1 % image RMS error of both;
+  workloads     packets/s of the other scenes (dust envelope 32^3 in FP64,
+                clumpy envelope 256^3 with a spherical star).
 """
 from __future__ import annotations
 
@@ -47,6 +53,8 @@ def parse():
     ap.add_argument("--no-time-to-error", action="store_true")
     ap.add_argument("--ref-log2", type=int, default=30, help="log2 packets of the reference images")
     ap.add_argument("--sweep-log2", type=int, default=26, help="largest log2 packets of the error sweep")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true")
     return ap.parse_args()
 
 
@@ -96,6 +104,105 @@ def cpu_baseline(sc, n_sample: int):
                       f"(FP64 oracle, OpenMP over packet ranges, {threads} threads), {dt:.1f} s"}
 
 
+DISK_DOMAIN = dict(center=(0.0, 0.0, 0.0), r_in=0.05, r_out=1.0, h0=0.1, beta=1.125, zmax_over_h=3.0)
+
+
+def _timed_run(ctx, stream, n):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.reset_images()
+    e0.record(stream)
+    ctx.run(1, n)
+    e1.record(stream)
+    img = ctx.read_images()
+    return img[:, 0], e0.elapsed_time(e1) * 1e-3
+
+
+def surrogate_section(ctx, qrt, sc, stream, ref):
+    """Learned peel-off on the disk scene: pilot samples (Philox, exact labels),
+    training on the GPU, validity mask, then plain against surrogate transport
+    of the same Sobol points; `ref` is an independent high-N image set (exact
+    Halton) or None."""
+    import numpy as np
+    import torch
+
+    from paper_2406_15632_amd import metrics
+
+    def sync_time(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    n_train, n_val = 1 << 20, 1 << 17
+    ctx.surrogate_set_domain(n_r=16, n_z=12, **DISK_DOMAIN)
+    pos = torch.zeros((n_train, 4), dtype=torch.float32, device="cuda")
+    tau = torch.zeros(n_train, dtype=torch.float32, device="cuda")
+    pilot, t_sample = sync_time(lambda: ctx.surrogate_sample(pos, tau, seed=101))
+    vpos = torch.zeros((n_val, 4), dtype=torch.float32, device="cuda")
+    vtau = torch.zeros(n_val, dtype=torch.float32, device="cuda")
+    ctx.surrogate_sample(vpos, vtau, seed=202)
+    steps = 20000
+    rep, t_train = sync_time(lambda: ctx.surrogate_train(pos, tau, steps=steps, batch=8192, lr=2e-3, lr_final=5e-5,
+                                                         seed=7, tau_cap=12.0, weight_floor=0.02))
+    mrep, t_val = sync_time(lambda: ctx.surrogate_validate(vpos, vtau, max_err=0.02, floor_frac=0.3, min_count=16))
+    N = 1 << 24
+    out = {"config": "disk128 scene, cylindrical domain R in [0.05, 1), |z| < 3 h(R), 16 x 12 cells per observer; "
+                     "2^20 pilot samples (Philox), 2^17 validation samples, 20000 Adam steps of 8192, "
+                     "cell error <= 2 % with a transmission floor of 0.3 x the observer mean; runs of 2^24 "
+                     "Sobol packets, FP32 transport",
+           "pilot_packets": pilot, "sample_s": t_sample, "train_s": t_train, "validate_s": t_val,
+           "train_loss": [rep["loss_first"], rep["loss_final"]], "mask": mrep}
+    curves = {}
+    for mode, name in ((qrt.PEEL_EXACT, "plain"), (qrt.PEEL_SURROGATE, "surrogate")):
+        ctx.set_sequence(qrt.SOBOL, PHILOX_SEED, N)
+        ctx.set_transport(sc.max_orders, sc.tau_min, qrt.FP32, mode)
+        pts = []
+        for lg in range(18, 25):
+            img, t = _timed_run(ctx, stream, 1 << lg)
+            if ref is not None:
+                pts.append((t, metrics.rms_error(img, ref), 1 << lg))
+        img, t = _timed_run(ctx, stream, N)
+        cnt = ctx.counters()
+        out[name] = {"packets_per_s": N / t, "ms": t * 1e3,
+                     "rms_error": metrics.rms_error(img, ref) if ref is not None else None,
+                     "surrogate_share_of_peels": cnt["surrogate"] / max(1, cnt["peels"]),
+                     "visits_per_packet": cnt["visits"] / cnt["packets"]}
+        out[name + "_image"] = img
+        curves[name] = pts
+    out["bias_rms_vs_plain"] = metrics.rms_error(out.pop("surrogate_image"), out.pop("plain_image"))
+    out["speedup_packets_per_s"] = out["surrogate"]["packets_per_s"] / out["plain"]["packets_per_s"]
+    if ref is not None:
+        t1 = {k: metrics.time_to_error([p[0] for p in v], [p[1] for p in v], 0.01) for k, v in curves.items()}
+        out["time_to_1pct_s"] = t1
+        out["speedup_at_1pct"] = (t1["plain"] / t1["surrogate"]) if (t1["plain"] and t1["surrogate"]) else None
+    ctx.set_transport(sc.max_orders, sc.tau_min, qrt.FP32, qrt.PEEL_EXACT)
+    return out
+
+
+def other_workloads(qrt, stream):
+    """Throughput of the dust envelope (32^3, single scattering, FP64) and the
+    clumpy envelope with a spherical star (256^3, FP32), Sobol, 2^24 packets."""
+    import torch
+
+    from synth import scenes
+    res = {}
+    for name, sc in (("envelope32", scenes.envelope32()), ("clumpy256", scenes.clumpy256())):
+        ctx = qrt.Context(0, stream.cuda_stream)
+        ctx.set_scene(sc, kind=qrt.SOBOL, grid=torch.from_numpy(sc.kappa_rho).cuda())
+        n = 1 << 24
+        _timed_run(ctx, stream, 1 << 20)          # warm-up
+        _, t = _timed_run(ctx, stream, n)
+        cnt = ctx.counters()
+        res[name] = {"packets_per_s": n / t, "ms": t * 1e3, "packets": n,
+                     "precision": "f64" if sc.fp64 else "f32",
+                     "visits_per_packet": cnt["visits"] / cnt["packets"],
+                     "algorithmic_GBps": (4.0 * cnt["visits"] + 24.0 * cnt["peels"]) / t / 1e9}
+        ctx.close()
+    return res
+
+
 def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int):
     """Image RMS error (I, all observers) against an independent high-N reference
     versus kernel time, N = 2^12 .. 2^sweep_log2; Sobol is scored against a
@@ -138,7 +245,7 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
             pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg))
         curves[names[kind]] = pts
     targets = (0.05, 0.01, 0.003)
-    out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor,
+    out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor, "_ref_halton": ref_h,
            "rms_error_by_log2_packets": {k: {int(p[2]).bit_length() - 1: round(p[1], 6) for p in v}
                                          for k, v in curves.items()},
            "time_s": {}, "speedup_vs_mc": {}}
@@ -246,9 +353,15 @@ def main():
                                                                    "escapes", "tau_cuts")},
         "wall_s": wall,
     }
+    ref = None
     if not args.no_time_to_error:
         result["time_to_error"] = time_to_error_sweep(ctx, qrt, sc, kinds, stream, args.ref_log2,
                                                       args.sweep_log2)
+        ref = result["time_to_error"].pop("_ref_halton")
+    if not args.no_surrogate:
+        result["surrogate"] = surrogate_section(ctx, qrt, sc, stream, ref)
+    if not args.no_workloads:
+        result["workloads"] = other_workloads(qrt, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()
