@@ -53,6 +53,7 @@ class _Scene(C.Structure):
         ("dom_beta", C.c_double), ("dom_zmax", C.c_double),
         ("dom_nr", C.c_int64), ("dom_nz", C.c_int64),
         ("dom_valid", C.POINTER(C.c_uint8)),
+        ("emit_order", C.c_int64),
     ]
 
 
@@ -170,6 +171,7 @@ class OracleScene:
         s.n_total = n_total if n_total is not None else sc.n_packets
         s.max_orders = sc.max_orders
         s.tau_min = sc.tau_min
+        s.emit_order = getattr(sc, "emit_order", 0)
         self.surrogate = surrogate
         if surrogate is not None:
             sg = surrogate

@@ -69,6 +69,7 @@ typedef struct {
     double dom_r_in, dom_r_out, dom_h0, dom_beta, dom_zmax;
     int64_t dom_nr, dom_nz;
     const uint8_t *dom_valid;     /* [n_obs][nr][nz], 1 = network allowed */
+    int64_t emit_order;           /* sphere star: 0 direct order, 1 inverse order (Sec. 3.3) */
 } og_scene;
 
 typedef struct {
@@ -503,7 +504,30 @@ static void og_peel(const og_scene *S, const double p[3], const double k[3], con
 static void og_emit(const og_scene *S, const og_seq *q, uint64_t idx, double p[3], double k[3],
                     int *dim_tau, int *next_dim)
 {
-    if (S->src_kind == OG_SPHERE) {
+    if (S->src_kind == OG_SPHERE && S->emit_order == 1) {
+        /* inverse order: v1,v2 -> propagation direction as for a point source,
+           v3 -> tau, v4,v5 -> emission point relative to that direction.
+           Reading: for a uniform-brightness surface the emission point seen
+           from a given direction k has density ~ max(0, n.k) over the star,
+           so its angle alpha to k follows cos(alpha) = sqrt(v5) and its
+           azimuth about k is 2 pi v4 (the printed "same equation" as the
+           direct emission point, weighted by the emitting hemisphere). */
+        double ph = 2.0 * OG_PI * og_u(q, idx, 0);
+        double ct = 2.0 * og_u(q, idx, 1) - 1.0;
+        double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        k[0] = st * cos(ph); k[1] = st * sin(ph); k[2] = ct;
+        double phr = 2.0 * OG_PI * og_u(q, idx, 3);
+        double ca = sqrt(og_u(q, idx, 4));
+        double sa = sqrt(fmax(0.0, 1.0 - ca * ca));
+        double t1[3] = {ct * cos(ph), ct * sin(ph), -st};
+        double t2[3] = {-sin(ph), cos(ph), 0.0};
+        for (int a = 0; a < 3; ++a) {
+            double n = ca * k[a] + sa * (cos(phr) * t1[a] + sin(phr) * t2[a]);
+            p[a] = S->src[a] + S->r_star * n;
+        }
+        *dim_tau = 2;
+        *next_dim = 5;
+    } else if (S->src_kind == OG_SPHERE) {
         /* direct order: v1,v2 -> point on the star, v3,v4 -> local direction, v5 -> tau.
            Reading: cos(theta_l) = sqrt(v4), a uniform-brightness (Lambertian) surface. */
         double phe = 2.0 * OG_PI * og_u(q, idx, 0);

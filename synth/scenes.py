@@ -45,6 +45,7 @@ class Scene:
     source: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     source_kind: int = POINT_SOURCE
     r_star: float = 0.0
+    emit_order: int = 0          # sphere star: 0 direct, 1 inverse order of the point coordinates
     albedo: float = 0.6
     g: float = 0.5
     p_lin: float = 0.5

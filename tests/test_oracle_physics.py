@@ -207,3 +207,42 @@ def test_qmc_beats_mc_on_envelope():
     e_sob = err(O.SOBOL)
     e_mc = np.mean([err(O.PHILOX, s) for s in (1, 2, 3)])
     assert e_sob < 0.5 * e_mc
+
+
+def test_sphere_star_inverse_order_emission():
+    """Inverse order (Sec. 3.3): the direction comes first and is exactly the
+    point-source direction of the same point; the emission point lies on the
+    star, on the hemisphere facing the direction with <n.k> = 2/3, and is
+    uniform over the star overall (the same joint law as the direct order)."""
+    base = scenes.envelope32().replace(source_kind=scenes.SPHERE_SOURCE, r_star=0.02)
+    inv = base.replace(emit_order=1)
+    n = 1 << 14
+    p, k = O.emit(inv, O.SOBOL, 1, n)
+    _, k_point = O.emit(scenes.envelope32(), O.SOBOL, 1, n)
+    assert np.array_equal(k, k_point)
+    r = np.linalg.norm(p, axis=1)
+    assert np.allclose(r, 0.02, rtol=1e-13)
+    nrm = p / r[:, None]
+    c = np.sum(nrm * k, axis=1)
+    assert c.min() >= 0.0
+    assert np.mean(c) == pytest.approx(2 / 3, abs=1e-3)
+    assert np.abs(nrm.mean(axis=0)).max() < 3e-3
+    assert np.mean(nrm[:, 2] ** 2) == pytest.approx(1 / 3, abs=3e-3)
+    # the cosine-weighted hemisphere: P(n.k <= c) = c^2
+    for cc in (0.25, 0.5, 0.75):
+        assert np.mean(c <= cc) == pytest.approx(cc * cc, abs=2e-3)
+
+
+def test_sphere_star_orders_agree():
+    """Direct and inverse order sample the same emission law, so their images
+    of one scene converge to the same result."""
+    sc = scenes.thin_sphere(n=32, npix=32, tau_R=0.3).replace(source_kind=scenes.SPHERE_SOURCE, r_star=0.1)
+    n = 1 << 16
+    a, _, _ = O.run(sc, O.SOBOL, 1, n, nthreads=8)
+    b, _, _ = O.run(sc.replace(emit_order=1), O.SOBOL, 1, n, nthreads=8)
+    fa, fb = a[0, 0].sum(), b[0, 0].sum()
+    assert fb == pytest.approx(fa, rel=2e-3)
+    # binned images agree within a few per cent (sampling error at 2^16)
+    A = a[0, 0].reshape(8, 4, 8, 4).sum(axis=(1, 3))
+    B = b[0, 0].reshape(8, 4, 8, 4).sum(axis=(1, 3))
+    assert np.linalg.norm(A - B) / np.linalg.norm(A) < 0.03
