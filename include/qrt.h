@@ -68,7 +68,8 @@ extern "C" {
 #define QRT_PEEL_SURROGATE 1      /* trained network inside its validated domain, exact elsewhere */
 
 /* sphere-star emission order (Sec. 3.3) */
-#define QRT_EMIT_DIRECT 0
+#define QRT_EMIT_DIRECT 0         /* v1,v2 emission point; v3,v4 local direction; v5 tau */
+#define QRT_EMIT_INVERSE 1        /* v1,v2 direction; v3 tau; v4,v5 emission point about the direction */
 
 #define QRT_MAX_DIMS 128          /* largest point dimension served */
 #define QRT_MAX_OBSERVERS 16
@@ -112,8 +113,14 @@ int qrt_set_grid(qrt_ctx *ctx, int nx, int ny, int nz, const double lo[3], const
 int qrt_set_point_source(qrt_ctx *ctx, double x, double y, double z);
 
 /* Uniform-brightness spherical star of the given radius centred at (x, y, z)
-   (Sec. 3.3); order must be QRT_EMIT_DIRECT.  The star blocks peel-off rays
-   that pass through it. */
+   (Sec. 3.3), emitting in the direct or the inverse order of the point
+   coordinates.  Direct: point on the star from (2 pi v1, cos = 2 v2 - 1),
+   local direction (2 pi v3, cos = sqrt(v4)) about the surface normal, tau
+   from v5.  Inverse: direction from (2 pi v1, cos = 2 v2 - 1), tau from v3,
+   emission point on the hemisphere facing the direction from (2 pi v4,
+   cos = sqrt(v5)) about it (a uniform-brightness surface seen from the
+   direction).  Both give the same joint law of point and direction.  The star
+   blocks peel-off rays that pass through it. */
 int qrt_set_sphere_source(qrt_ctx *ctx, double x, double y, double z, double radius, int order);
 
 /* Dust (Sec. 2.1-2.3): albedo in [0,1], HG asymmetry |g| < 1, maximum linear

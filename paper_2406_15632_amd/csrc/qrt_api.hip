@@ -118,7 +118,7 @@ int hip_fail(qrt_ctx *c, hipError_t e, const char *what)
 
 int point_dims(const qrt_ctx *c)
 {
-    return (c->src_kind == 1 ? 5 : 3) + 3 * (c->max_orders - 1);
+    return (c->src_kind >= 1 ? 5 : 3) + 3 * (c->max_orders - 1);
 }
 
 SeqParams seq_params(const qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total)
@@ -327,14 +327,15 @@ int qrt_set_sphere_source(qrt_ctx *c, double x, double y, double z, double radiu
 {
     if (!c) return QRT_INVALID_ARG;
     if (!c->has_grid) return fail(c, QRT_BAD_STATE, "set the grid before the source");
-    if (order != QRT_EMIT_DIRECT) return fail(c, QRT_UNSUPPORTED, "only the direct emission order is built");
+    if (order != QRT_EMIT_DIRECT && order != QRT_EMIT_INVERSE)
+        return fail(c, QRT_INVALID_ARG, "unknown emission order %d", order);
     if (!(radius > 0.0) || !isfinite(radius)) return fail(c, QRT_INVALID_ARG, "radius must be positive");
     for (int a = 0; a < 3; ++a) {
         const double p = a == 0 ? x : (a == 1 ? y : z);
         if (!(p - radius >= c->lo[a] && p + radius <= c->hi[a]))
             return fail(c, QRT_INVALID_ARG, "the star must lie inside the box");
     }
-    c->src_kind = 1;
+    c->src_kind = order == QRT_EMIT_INVERSE ? 2 : 1;
     c->src[0] = x; c->src[1] = y; c->src[2] = z;
     c->r_star = radius;
     c->has_source = true;

@@ -69,7 +69,7 @@ struct SurrogateParams {
 
 struct TransportParams {
     DevGrid grid;
-    int src_kind;            // 0 point, 1 sphere
+    int src_kind;            // 0 point, 1 sphere star (direct order), 2 sphere star (inverse order)
     double src[3];
     double r_star;
     double albedo, g, p_lin;

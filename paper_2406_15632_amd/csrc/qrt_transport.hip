@@ -204,10 +204,33 @@ __global__ void __launch_bounds__(256) k_place(const uint32_t *__restrict__ keys
 // --------------------------------------------------------------------------
 // first flight
 // --------------------------------------------------------------------------
+// SRC: 0 point source, 1 sphere star in direct order, 2 sphere star in inverse order
 template <typename R, int KIND, int SRC>
 __device__ __forceinline__ void emit(const TransportParams &P, uint64_t idx, R p[3], R k[3])
 {
-    if constexpr (SRC == 1) {
+    if constexpr (SRC == 2) {
+        // inverse order: v1,v2 -> propagation direction as for a point source,
+        // v3 -> tau, v4,v5 -> emission point relative to the direction:
+        // azimuth 2 pi v4 about k, cos(alpha) = sqrt(v5) (uniform-brightness
+        // surface seen from direction k: density ~ max(0, n.k))
+        uint32_t xa[3], xb[3];
+        seq_triple<KIND>(P.seq, idx, 0, xa);
+        seq_triple<KIND>(P.seq, idx, 2, xb);
+        R sp, cp, spr, cpr;
+        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
+        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
+        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+        sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
+        const R ca = sqrt(to_unit<R>(xb[2]));
+        const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
+        const R t1[3] = {ct * cp, ct * sp, -st};
+        const R t2[3] = {-sp, cp, (R)0};
+        for (int a = 0; a < 3; ++a) {
+            const R n = ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]);
+            p[a] = (R)P.src[a] + (R)P.r_star * n;
+        }
+    } else if constexpr (SRC == 1) {
         // direct order: v1,v2 -> point on the star; v3,v4 -> local direction
         // (cos theta_l = sqrt(v4): uniform-brightness surface); v5 -> tau
         uint32_t xa[3], xb[3];
@@ -375,7 +398,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
                 const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)P.npix);
                 const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)P.npix);
                 vis = fx >= (R)0 && fy >= (R)0 && fx < (R)P.npix && fy < (R)P.npix;
-                if constexpr (SRC == 1) {
+                if constexpr (SRC >= 1) {
                     if (vis) {
                         R d[3] = {s.p[0] - (R)P.src[0], s.p[1] - (R)P.src[1], s.p[2] - (R)P.src[2]};
                         const R b = dot3(d, o), cc = dot3(d, d) - (R)(P.r_star * P.r_star);
@@ -427,7 +450,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         }
         if (valid && order < P.max_orders) {
             // new direction: i1 from the first number of the triple, cos(Theta) from the second
-            const int dim = (SRC == 1 ? 5 : 3) + 3 * (order - 1);
+            const int dim = (SRC >= 1 ? 5 : 3) + 3 * (order - 1);
             uint32_t x[3];
             seq_triple<KIND>(P.seq, s.idx, dim, x);
             R si, ci;
@@ -770,6 +793,7 @@ static hipError_t run_src(const TransportParams &P, uint64_t first, uint32_t cou
                           hipStream_t st)
 {
     if (P.src_kind == 1) return run_chunk<R, KIND, 1>(P, first, count, B, st);
+    if (P.src_kind == 2) return run_chunk<R, KIND, 2>(P, first, count, B, st);
     return run_chunk<R, KIND, 0>(P, first, count, B, st);
 }
 

@@ -23,7 +23,7 @@ SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX = 0, 1, 2, 3, 4
 GRID_HOST_COPY, GRID_DEVICE_COPY, GRID_DEVICE_BORROW = 0, 1, 2
 FP32, FP64 = 0, 1
 PEEL_EXACT, PEEL_SURROGATE = 0, 1
-EMIT_DIRECT = 0
+EMIT_DIRECT, EMIT_INVERSE = 0, 1
 MAX_DIMS, MAX_OBSERVERS = 128, 16
 MLP_PARAMS = 12929
 
@@ -214,7 +214,7 @@ class Context:
         """Configure everything from a synth.Scene (grid may be a device tensor to borrow)."""
         self.set_grid(sc.kappa_rho if grid is None else grid, sc.lo, sc.hi)
         if sc.source_kind == 1:
-            self.set_sphere_source(*sc.source, sc.r_star)
+            self.set_sphere_source(*sc.source, sc.r_star, getattr(sc, "emit_order", EMIT_DIRECT))
         else:
             self.set_point_source(*sc.source)
         self.set_dust(sc.albedo, sc.g, sc.p_lin)

@@ -210,12 +210,26 @@ def test_disk128_fp64_parity(ctx, Q):
     assert_counters_equal(cg, co)
 
 
-def test_clumpy256_sphere_star_fp64_parity(ctx, Q):
-    sc = scenes.clumpy256().replace(fp64=True, n_packets=1 << 16)
-    _say("clumpy256 FP64 sphere star halton 2^16")
+@pytest.mark.parametrize("emit_order", [0, 1])
+def test_clumpy256_sphere_star_fp64_parity(ctx, Q, emit_order):
+    sc = scenes.clumpy256().replace(fp64=True, n_packets=1 << 16, emit_order=emit_order)
+    _say(f"clumpy256 FP64 sphere star (order {emit_order}) halton 2^16")
     g, cg = gpu_images(ctx, Q, sc, O.HALTON, 1, sc.n_packets)
     o, co, _ = O.run(sc, O.HALTON, count=sc.n_packets, nthreads=8)
     assert co["occluded"] > 0
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
+@pytest.mark.parametrize("kind", [O.SOBOL, O.PHILOX])
+def test_sphere_star_inverse_order_multi_order_fp64_parity(ctx, Q, kind):
+    """Inverse emission order with scatterings beyond the first: the point
+    dimensions after the first flight follow the same layout as the direct order."""
+    sc = scenes.thin_sphere(n=32, npix=32, tau_R=0.5).replace(
+        source_kind=scenes.SPHERE_SOURCE, r_star=0.1, emit_order=1, max_orders=4, fp64=True, n_packets=1 << 14)
+    _say(f"thin sphere star inverse order, 4 orders, kind {kind}")
+    g, cg = gpu_images(ctx, Q, sc, kind, 1, sc.n_packets, seed=5)
+    o, co, _ = O.run(sc, kind, count=sc.n_packets, seed=5, nthreads=8)
     assert_fp64_parity(g, o)
     assert_counters_equal(cg, co)
 
