@@ -21,7 +21,10 @@ The JSON line carries
                 peel-off rays the network answers, the image bias against the
                 plain method, and the time to 1 % image RMS error of both;
   workloads     packets/s of the other scenes (dust envelope 32^3 in FP64,
-                clumpy envelope 256^3 with a spherical star).
+                clumpy envelope 256^3 with a spherical star);
+  sphere_star   time to 5 % and 1 % image error for the spherical star in the
+                direct and the inverse order of the point coordinates against
+                Monte Carlo.
 """
 from __future__ import annotations
 
@@ -203,6 +206,59 @@ def other_workloads(qrt, stream):
     return res
 
 
+def sphere_star_section(qrt, stream):
+    """Time to a fixed image error for a spherical star (the clumpy envelope,
+    256^3, single scattering, 512^2 image): QMC (Sobol) in the direct and the
+    inverse order of the point coordinates, Hammersley in the inverse order,
+    and Monte Carlo (Philox, 2 seeds); pixels within the star's radius of the
+    centre are left out.  The reference is Halton in the direct order at 2^28
+    packets (Sobol is not used for it, being one of the compared sets)."""
+    import numpy as np
+    import torch
+
+    from paper_2406_15632_amd import metrics
+    from synth import scenes
+    sc0 = scenes.clumpy256()
+    mask = metrics.central_mask(sc0.npix, sc0.half_width, sc0.r_star)
+    f = 8   # 8 x 8 pixel bins: per-pixel shot noise of a 512^2 image would hide the point sets
+
+    def binned(img):
+        m = img * mask
+        return m.reshape(sc0.npix // f, f, sc0.npix // f, f).sum(axis=(1, 3))
+    grid = torch.from_numpy(sc0.kappa_rho).cuda()
+    ctx = qrt.Context(0, stream.cuda_stream)
+
+    def images(order, kind, n, seed=PHILOX_SEED):
+        sc = sc0.replace(emit_order=order)
+        ctx.set_scene(sc, kind=kind, seed=seed, n_total=n, grid=grid)
+        img, t = _timed_run(ctx, stream, n)
+        return img[0], t
+
+    ref = binned(images(0, qrt.HALTON, 1 << 28)[0])
+    variants = {"sobol_direct": (0, qrt.SOBOL, (PHILOX_SEED,)), "sobol_inverse": (1, qrt.SOBOL, (PHILOX_SEED,)),
+                "hammersley_inverse": (1, qrt.HAMMERSLEY, (PHILOX_SEED,)), "philox": (0, qrt.PHILOX, (1, 2))}
+    out = {"reference": "halton, direct order, 2^28 packets",
+           "error": "relative RMS of the 64^2 image of 8 x 8 pixel bins, star pixels left out",
+           "errors": {}, "time_s": {}}
+    for name, (order, kind, seeds) in variants.items():
+        pts = []
+        for lg in range(14, 25, 2):
+            e, t = [], []
+            for sd in seeds:
+                img, dt = images(order, kind, 1 << lg, sd)
+                e.append(metrics.rms_error(binned(img), ref))
+                t.append(dt)
+            pts.append((float(np.mean(t)), float(np.mean(e))))
+        out["errors"][name] = {14 + 2 * i: round(p[1], 5) for i, p in enumerate(pts)}
+        out["time_s"][name] = [metrics.time_to_error([p[0] for p in pts], [p[1] for p in pts], tg)
+                               for tg in (0.05, 0.01)]
+    mc = out["time_s"]["philox"]
+    out["speedup_vs_mc_at_5_1_pct"] = {k: [(m / t if (m and t) else None) for m, t in zip(mc, v)]
+                                       for k, v in out["time_s"].items()}
+    ctx.close()
+    return out
+
+
 def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int):
     """Image RMS error (I, all observers) against an independent high-N reference
     versus kernel time, N = 2^12 .. 2^sweep_log2; Sobol is scored against a
@@ -362,6 +418,7 @@ def main():
         result["surrogate"] = surrogate_section(ctx, qrt, sc, stream, ref)
     if not args.no_workloads:
         result["workloads"] = other_workloads(qrt, stream)
+        result["sphere_star"] = sphere_star_section(qrt, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()
