@@ -54,6 +54,7 @@ class _Scene(C.Structure):
         ("dom_nr", C.c_int64), ("dom_nz", C.c_int64),
         ("dom_valid", C.POINTER(C.c_uint8)),
         ("emit_order", C.c_int64),
+        ("order_images", C.c_int64),
     ]
 
 
@@ -212,13 +213,19 @@ EVENT_FIELDS = ("px", "py", "pz", "X", "Y", "I", "Q", "U", "cos_obs", "order", "
 
 def run(sc, kind: int = SOBOL, first: int = 1, count: Optional[int] = None, seed: int = 0,
         n_total: Optional[int] = None, nthreads: int = 1, max_events: int = 0,
-        normalize: bool = True, surrogate: Optional[Surrogate] = None):
+        normalize: bool = True, surrogate: Optional[Surrogate] = None, per_order: bool = False):
     """Run packets first..first+count-1 of a scene.  Returns (images [n_obs][3][npix][npix],
     counters dict, events array or None).  Images are divided by count when normalize.
-    With `surrogate`, peel-off optical depths inside valid cells come from the network."""
+    With `surrogate`, peel-off optical depths inside valid cells come from the network.
+    With `per_order`, the images are [max_orders][n_obs][3][npix][npix], one set per
+    scattering order."""
     count = sc.n_packets if count is None else count
     osc = OracleScene(sc, kind, seed, n_total, surrogate)
-    img = np.zeros((len(sc.observers), 3, sc.npix, sc.npix), dtype=np.float64)
+    shape = (len(sc.observers), 3, sc.npix, sc.npix)
+    if per_order:
+        osc.s.order_images = sc.max_orders
+        shape = (sc.max_orders,) + shape
+    img = np.zeros(shape, dtype=np.float64)
     cnt = Counters()
     ev = np.zeros((max_events, len(EVENT_FIELDS)), dtype=np.float64) if max_events else None
     nev = C.c_int64(0)

@@ -70,6 +70,7 @@ typedef struct {
     int64_t dom_nr, dom_nz;
     const uint8_t *dom_valid;     /* [n_obs][nr][nz], 1 = network allowed */
     int64_t emit_order;           /* sphere star: 0 direct order, 1 inverse order (Sec. 3.3) */
+    int64_t order_images;         /* 0: one image set; K: one set per scattering order 1..K */
 } og_scene;
 
 typedef struct {
@@ -484,8 +485,10 @@ static void og_peel(const og_scene *S, const double p[3], const double k[3], con
     }
     double att = exp(-tau);
     int64_t ix = (int64_t)fx, iy = (int64_t)fy;
-    size_t base = ((size_t)obs * 3) * (size_t)S->npix * (size_t)S->npix + (size_t)iy * (size_t)S->npix + (size_t)ix;
     size_t plane = (size_t)S->npix * (size_t)S->npix;
+    size_t base = ((size_t)obs * 3) * plane + (size_t)iy * (size_t)S->npix + (size_t)ix;
+    if (S->order_images > 0)   /* the image set of this scattering order */
+        base += (size_t)(order - 1) * (size_t)S->n_obs * 3 * plane;
     sink->img[base] += att * Sp[0];
     sink->img[base + plane] += att * Sp[1];
     sink->img[base + 2 * plane] += att * Sp[2];
@@ -665,7 +668,9 @@ int oracle_run(const og_scene *S, uint64_t first, uint64_t count, double *img, o
     og_seq q = {S->seq_kind, S->dims, S->mat, S->bases, S->seed, S->n_total};
     og_obs *obs = (og_obs *)malloc(sizeof(og_obs) * (size_t)S->n_obs);
     for (int o = 0; o < S->n_obs; ++o) og_make_obs(S->obs_theta[o], S->obs_phi[o], &obs[o]);
-    size_t img_n = (size_t)S->n_obs * 3 * (size_t)S->npix * (size_t)S->npix;
+    if (S->order_images > 0 && S->order_images < S->max_orders) return -1;
+    size_t img_n = (size_t)S->n_obs * 3 * (size_t)S->npix * (size_t)S->npix *
+                   (size_t)(S->order_images > 0 ? S->order_images : 1);
     int64_t zero = 0;
     if (n_events) *n_events = 0;
     if (nthreads <= 1 || events) {

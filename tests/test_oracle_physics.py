@@ -246,3 +246,17 @@ def test_sphere_star_orders_agree():
     A = a[0, 0].reshape(8, 4, 8, 4).sum(axis=(1, 3))
     B = b[0, 0].reshape(8, 4, 8, 4).sum(axis=(1, 3))
     assert np.linalg.norm(A - B) / np.linalg.norm(A) < 0.03
+
+
+def test_per_order_images_split_the_total():
+    """Images kept per scattering order add up to the total image, and every
+    contribution lands in the set of the order its event carries."""
+    sc = scenes.disk128(n_packets=1 << 10, n=32).replace(max_orders=5, npix=32, fp64=True)
+    tot, c0, ev = O.run(sc, O.SOBOL, 1, 512, max_events=100000, normalize=False)
+    per, c1, _ = O.run(sc, O.SOBOL, 1, 512, per_order=True, normalize=False)
+    assert per.shape == (5,) + tot.shape
+    assert np.allclose(per.sum(axis=0), tot, rtol=1e-12, atol=1e-300)
+    for k in range(5):
+        sel = ev[:, 9] == k + 1
+        assert per[k, :, 0].sum() == pytest.approx(ev[sel, 5].sum(), rel=1e-12, abs=1e-300)
+    assert per[1:, :, 0].sum() > 0
