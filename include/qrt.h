@@ -160,6 +160,17 @@ int qrt_read_images(qrt_ctx *ctx, int obs, double *I, double *Q, double *U, int 
    once the stream reaches this point. */
 int qrt_image_device_ptr(qrt_ctx *ctx, double **dev_ptr);
 
+/* Keep one image set per scattering order 1..max_orders (enable = 1) or one
+   summed set (enable = 0, the default).  Allocates max_orders times the image
+   memory and resets the images.  While it is on, max_orders cannot change,
+   qrt_read_images returns the sum over the orders, and qrt_image_device_ptr
+   is refused. */
+int qrt_set_order_images(qrt_ctx *ctx, int enable);
+
+/* Copy the images of scattering order `order` (1-based) of observer obs, as
+   qrt_read_images.  Synchronises the stream. */
+int qrt_read_order_images(qrt_ctx *ctx, int obs, int order, double *I, double *Q, double *U, int normalized);
+
 /* Zero the images, the packet count and the counters. */
 int qrt_reset_images(qrt_ctx *ctx);
 

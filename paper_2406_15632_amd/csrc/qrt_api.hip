@@ -47,7 +47,9 @@ struct qrt_ctx {
     double theta[QRT_MAX_OBSERVERS], phi[QRT_MAX_OBSERVERS];
     double half_width = 1.0;
     double *img = nullptr;
-    size_t img_elems = 0;
+    size_t img_elems = 0;                    // one copy of one set: n_obs * 3 * npix^2
+    int order_images = 0;                    // 0: one image set; K: one per scattering order
+    size_t img_alloc = 0;                    // doubles allocated
     // sequence and transport
     int kind = QRT_SOBOL;
     uint64_t seed = 0, n_total = 0;
@@ -180,6 +182,33 @@ int ensure_queues(qrt_ctx *c, uint64_t count)
         for (uint32_t **l : lists) HIP_TRY(c, hipMalloc(l, want * sizeof(uint32_t)), "packet lists");
         c->tb_packets = want;
     }
+    return QRT_OK;
+}
+
+size_t image_sets(const qrt_ctx *c) { return c->order_images > 0 ? (size_t)c->order_images : 1; }
+
+// image buffer for the current observers and image sets
+int ensure_images(qrt_ctx *c)
+{
+    const size_t want = c->img_elems * kImageCopies * image_sets(c);
+    if (want == c->img_alloc && c->img) return QRT_OK;
+    if (c->img) {
+        HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+        (void)hipFree(c->img);
+        c->img = nullptr;
+        c->img_alloc = 0;
+    }
+    HIP_TRY(c, hipMalloc(&c->img, want * sizeof(double)), "image allocation");
+    c->img_alloc = want;
+    return QRT_OK;
+}
+
+// fold the copies of every image set into its first copy
+int fold_images(qrt_ctx *c)
+{
+    for (size_t s = 0; s < image_sets(c); ++s)
+        HIP_TRY(c, launch_fold_images(c->img + s * kImageCopies * c->img_elems, c->img_elems, c->stream),
+                "image fold");
     return QRT_OK;
 }
 
@@ -364,17 +393,9 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
     if (npix < 1 || npix > 8192) return fail(c, QRT_INVALID_ARG, "npix must be in 1..8192");
     if (!(half_width > 0.0) || !isfinite(half_width)) return fail(c, QRT_INVALID_ARG, "half_width must be > 0");
     DeviceGuard dg(c->device);
-    const size_t elems = (size_t)n_obs * 3 * (size_t)npix * (size_t)npix;   // one copy
-    if (elems != c->img_elems) {
-        if (c->img) {
-            HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
-            (void)hipFree(c->img);
-            c->img = nullptr;
-            c->img_elems = 0;
-        }
-        HIP_TRY(c, hipMalloc(&c->img, elems * kImageCopies * sizeof(double)), "image allocation");
-        c->img_elems = elems;
-    }
+    c->img_elems = (size_t)n_obs * 3 * (size_t)npix * (size_t)npix;   // one copy of one set
+    int rc = ensure_images(c);
+    if (rc) return rc;
     for (int i = 0; i < n_obs; ++i) {
         c->theta[i] = theta[i];
         c->phi[i] = phi[i];
@@ -405,6 +426,8 @@ int qrt_set_transport(qrt_ctx *c, int max_orders, double tau_min, int precision,
 {
     if (!c) return QRT_INVALID_ARG;
     if (max_orders < 1) return fail(c, QRT_INVALID_ARG, "max_orders must be >= 1");
+    if (c->order_images > 0 && max_orders != c->order_images)
+        return fail(c, QRT_BAD_STATE, "turn the per-order images off before changing max_orders");
     if (!(tau_min >= 0.0) || !isfinite(tau_min)) return fail(c, QRT_INVALID_ARG, "tau_min must be >= 0");
     if (precision != QRT_FP32 && precision != QRT_FP64) return fail(c, QRT_INVALID_ARG, "unknown precision");
     if (peel_mode != QRT_PEEL_EXACT && peel_mode != QRT_PEEL_SURROGATE)
@@ -474,6 +497,7 @@ static void transport_params(const qrt_ctx *c, TransportParams &P)
     P.max_orders = c->max_orders;
     P.tau_min = c->tau_min;
     P.img = c->img;
+    P.order_images = c->order_images;
     P.counters = c->counters;
     P.peel_mode = c->peel_mode;
     if (c->has_domain) {
@@ -527,13 +551,24 @@ int qrt_read_images(qrt_ctx *c, int obs, double *I, double *Q, double *U, int no
     if (obs < 0 || obs >= c->n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
     DeviceGuard dg(c->device);
     const size_t plane = (size_t)c->npix * c->npix;
-    HIP_TRY(c, launch_fold_images(c->img, c->img_elems, c->stream), "image fold");
+    int rc = fold_images(c);
+    if (rc) return rc;
     double *dst[3] = {I, Q, U};
-    for (int s = 0; s < 3; ++s)
-        if (dst[s])
-            HIP_TRY(c, hipMemcpyAsync(dst[s], c->img + ((size_t)obs * 3 + s) * plane, plane * sizeof(double),
+    std::vector<double> tmp(image_sets(c) > 1 ? plane : 0);
+    for (size_t set = 0; set < image_sets(c); ++set) {
+        const double *base = c->img + set * kImageCopies * c->img_elems;
+        for (int s = 0; s < 3; ++s) {
+            if (!dst[s]) continue;
+            double *to = set == 0 ? dst[s] : tmp.data();
+            HIP_TRY(c, hipMemcpyAsync(to, base + ((size_t)obs * 3 + s) * plane, plane * sizeof(double),
                                       hipMemcpyDeviceToHost, c->stream),
                     "image copy");
+            if (set > 0) {
+                HIP_TRY(c, hipStreamSynchronize(c->stream), "image copy sync");
+                for (size_t i = 0; i < plane; ++i) dst[s][i] += tmp[i];
+            }
+        }
+    }
     HIP_TRY(c, hipStreamSynchronize(c->stream), "image copy sync");
     if (normalized && c->packets_run > 0) {
         const double inv = 1.0 / (double)c->packets_run;
@@ -548,9 +583,50 @@ int qrt_image_device_ptr(qrt_ctx *c, double **dev_ptr)
 {
     if (!c || !dev_ptr) return QRT_INVALID_ARG;
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
+    if (c->order_images > 0) return fail(c, QRT_BAD_STATE, "per-order images: read them with qrt_read_order_images");
     DeviceGuard dg(c->device);
-    HIP_TRY(c, launch_fold_images(c->img, c->img_elems, c->stream), "image fold");
+    int rc = fold_images(c);
+    if (rc) return rc;
     *dev_ptr = c->img;
+    return QRT_OK;
+}
+
+int qrt_set_order_images(qrt_ctx *c, int enable)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_obs) return fail(c, QRT_BAD_STATE, "set the observers first");
+    DeviceGuard dg(c->device);
+    c->order_images = enable ? c->max_orders : 0;
+    int rc = ensure_images(c);
+    if (rc) return rc;
+    return qrt_reset_images(c);
+}
+
+int qrt_read_order_images(qrt_ctx *c, int obs, int order, double *I, double *Q, double *U, int normalized)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
+    if (c->order_images <= 0) return fail(c, QRT_BAD_STATE, "per-order images are off");
+    if (obs < 0 || obs >= c->n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
+    if (order < 1 || order > c->order_images) return fail(c, QRT_INVALID_ARG, "order %d out of range", order);
+    DeviceGuard dg(c->device);
+    const size_t plane = (size_t)c->npix * c->npix;
+    int rc = fold_images(c);
+    if (rc) return rc;
+    const double *base = c->img + (size_t)(order - 1) * kImageCopies * c->img_elems;
+    double *dst[3] = {I, Q, U};
+    for (int s = 0; s < 3; ++s)
+        if (dst[s])
+            HIP_TRY(c, hipMemcpyAsync(dst[s], base + ((size_t)obs * 3 + s) * plane, plane * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream),
+                    "image copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "image copy sync");
+    if (normalized && c->packets_run > 0) {
+        const double inv = 1.0 / (double)c->packets_run;
+        for (int s = 0; s < 3; ++s)
+            if (dst[s])
+                for (size_t i = 0; i < plane; ++i) dst[s][i] *= inv;
+    }
     return QRT_OK;
 }
 
@@ -559,7 +635,7 @@ int qrt_reset_images(qrt_ctx *c)
     if (!c) return QRT_INVALID_ARG;
     DeviceGuard dg(c->device);
     if (c->img)
-        HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_elems * kImageCopies * sizeof(double), c->stream), "image reset");
+        HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_alloc * sizeof(double), c->stream), "image reset");
     HIP_TRY(c, hipMemsetAsync(c->counters, 0, CNT_COUNT * sizeof(unsigned long long), c->stream), "counter reset");
     c->packets_run = 0;
     return QRT_OK;

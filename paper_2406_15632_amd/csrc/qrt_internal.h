@@ -79,7 +79,8 @@ struct TransportParams {
     SeqParams seq;
     int max_orders;
     double tau_min;
-    double *img;                   // [kImageCopies][n_obs][3][npix][npix]
+    double *img;                   // [sets][kImageCopies][n_obs][3][npix][npix]
+    int order_images;              // 0: one set; K: one set per scattering order 1..K
     unsigned long long *counters;  // [CNT_COUNT]
     int peel_mode;                 // 0 exact traversal, 1 surrogate inside its valid cells
     SurrogateParams sur;

@@ -484,6 +484,13 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
+__device__ __forceinline__ double *image_copy(const TransportParams &P, int order, size_t plane)
+{
+    const size_t set = (size_t)P.n_obs * 3 * plane;
+    const size_t s = P.order_images > 0 ? (size_t)(order - 1) : 0;
+    return P.img + (s * kImageCopies + (size_t)(blockIdx.x % kImageCopies)) * set;
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
                                               const uint32_t *__restrict__ live_in, int in,
@@ -500,8 +507,9 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
-    // image copy of this block (blocks go round-robin to the XCDs)
-    double *img_copy = P.img + (size_t)(blockIdx.x % kImageCopies) * (size_t)P.n_obs * 3 * plane;
+    // image copy of this block (blocks go round-robin to the XCDs), in the
+    // set of this scattering order when orders are kept apart
+    double *img_copy = image_copy(P, order, plane);
     uint64_t n_visits = 0;
     uint32_t n_peels = 0, n_esc = 0;
     int kind = WI_NONE;
@@ -640,7 +648,7 @@ __device__ __forceinline__ void peel_mlp_batch(const TransportParams &P, PeelMlp
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, PeelRay<R> *__restrict__ peels,
+__global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, int order, PeelRay<R> *__restrict__ peels,
                                                   const Queues *__restrict__ Q, int in)
 {
     __shared__ PeelMlpLds L;
@@ -651,7 +659,7 @@ __global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, PeelR
     const uint64_t n_live = Q->n_live[in];
     const uint64_t n_blocks = (uint64_t)P.n_obs * ((n_live + 63) / 64);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
-    double *img_copy = P.img + (size_t)(blockIdx.x % kImageCopies) * (size_t)P.n_obs * 3 * plane;
+    double *img_copy = image_copy(P, order, plane);
     const uint64_t waves = (uint64_t)gridDim.x * kMlpWaves;
     const uint64_t wave = (uint64_t)blockIdx.x * kMlpWaves + w;
     const size_t cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
@@ -780,7 +788,8 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             hipLaunchKernelGGL((k_capture<R>), dim3(bs), dim3(256), 0, st, P, (const PeelRay<R> *)peels,
                                (const Queues *)B.q, in);
         if (P.peel_mode == 1)
-            hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, peels, (const Queues *)B.q, in);
+            hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, order, peels, (const Queues *)B.q,
+                               in);
         hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
                            in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;

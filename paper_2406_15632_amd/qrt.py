@@ -74,6 +74,8 @@ SIGNATURES = {
     "qrt_read_images": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_image_device_ptr": (C.c_int, [_P, C.POINTER(C.c_void_p)]),
     "qrt_reset_images": (C.c_int, [_P]),
+    "qrt_set_order_images": (C.c_int, [_P, C.c_int]),
+    "qrt_read_order_images": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_get_counters": (C.c_int, [_P, C.POINTER(qrt_counters)]),
     "qrt_generate_points": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
                                       _P, C.c_int]),
@@ -236,6 +238,17 @@ class Context:
         for o in range(self.n_obs):
             self._ck(self.lib.qrt_read_images(self.h, o, out[o, 0].ctypes.data, out[o, 1].ctypes.data,
                                               out[o, 2].ctypes.data, int(normalized)))
+        return out
+
+    def set_order_images(self, enable: bool):
+        self._ck(self.lib.qrt_set_order_images(self.h, int(enable)))
+
+    def read_order_images(self, order: int, normalized: bool = True) -> np.ndarray:
+        """[n_obs][3][npix][npix] float64 of one scattering order (1-based)."""
+        out = np.zeros((self.n_obs, 3, self.npix, self.npix), dtype=np.float64)
+        for o in range(self.n_obs):
+            self._ck(self.lib.qrt_read_order_images(self.h, o, order, out[o, 0].ctypes.data, out[o, 1].ctypes.data,
+                                                    out[o, 2].ctypes.data, int(normalized)))
         return out
 
     def image_device_ptr(self) -> int:

@@ -365,3 +365,28 @@ def test_disk128_full_size_properties(ctx, Q):
             for s in range(3):
                 assert abs(gt[ob, s].sum() - ot[ob, s].sum()) <= 1e-5 * tot
         assert ct["packets"] == co["packets"] and ct["scatterings"] == co["scatterings"]
+
+
+def test_per_order_images_fp64_parity(ctx, Q):
+    """One image set per scattering order: each equals the oracle's set of that
+    order per pixel, and together they add up to the total image."""
+    sc = scenes.disk128(n_packets=1 << 12, n=32).replace(max_orders=5, npix=32, fp64=True)
+    _say("per-order images disk32 5 orders")
+    ctx.set_scene(sc, kind=O.SOBOL)
+    ctx.set_order_images(True)
+    ctx.reset_images()
+    ctx.run(1, sc.n_packets)
+    tot = ctx.read_images(normalized=False)
+    per = np.stack([ctx.read_order_images(k, normalized=False) for k in range(1, 6)])
+    o, co, _ = O.run(sc, O.SOBOL, 1, sc.n_packets, nthreads=8, per_order=True, normalize=False)
+    for k in range(5):
+        assert_fp64_parity(per[k], o[k])
+    assert np.allclose(per.sum(axis=0), tot, rtol=1e-12, atol=1e-300)
+    with pytest.raises(Q.QRTError):
+        ctx.set_transport(4, sc.tau_min, Q.FP64)
+    with pytest.raises(Q.QRTError):
+        ctx.image_device_ptr()
+    ctx.set_order_images(False)
+    with pytest.raises(Q.QRTError):
+        ctx.read_order_images(1)
+    ctx.set_transport(4, sc.tau_min, Q.FP64)
