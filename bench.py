@@ -15,6 +15,7 @@ The JSON line carries
                 when the kernel sources are unchanged since they were taken;
   time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
                 the speed-up of each over the Monte Carlo (Philox) baseline;
+  per_order     image error per scattering order, QMC against Monte Carlo;
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload;
   surrogate     the learned peel-off on the same disk scene at 2^24 packets: pilot
                 sampling, GPU training and validation times, the share of
@@ -259,6 +260,47 @@ def sphere_star_section(qrt, stream):
     return out
 
 
+def per_order_section(qrt, sc, stream):
+    """Image error of each scattering order (disk128, 2^22 packets) for Sobol,
+    Hammersley and Monte Carlo (Philox, mean over 2 seeds), against per-order
+    images of Halton at 2^28 packets, and the Monte Carlo / QMC error ratio per
+    order: the paper's observation that the QMC gain shrinks with the order."""
+    import numpy as np
+    import torch
+
+    from paper_2406_15632_amd import metrics
+    ctx = qrt.Context(0, stream.cuda_stream)
+    grid = torch.from_numpy(sc.kappa_rho).cuda()
+    K = 6
+
+    def per_order(kind, n, seed=PHILOX_SEED):
+        ctx.set_scene(sc, kind=kind, seed=seed, n_total=n, grid=grid)
+        ctx.set_order_images(True)
+        ctx.reset_images()
+        ctx.run(1, n)
+        imgs = [ctx.read_order_images(k)[:, 0] for k in range(1, K + 1)]
+        rest = ctx.read_images()[:, 0] - sum(imgs)
+        ctx.set_order_images(False)
+        return imgs + [rest]
+
+    ref = per_order(qrt.HALTON, 1 << 28)
+    n = 1 << 22
+    out = {"orders": [str(k) for k in range(1, K + 1)] + [f">{K}"], "packets": n,
+           "reference": "halton, 2^28 packets", "share_of_light": [], "rms_error": {}}
+    tot = sum(float(r.sum()) for r in ref)
+    out["share_of_light"] = [round(float(r.sum()) / tot, 4) for r in ref]
+    for name, kind, seeds in (("sobol", qrt.SOBOL, (PHILOX_SEED,)), ("hammersley", qrt.HAMMERSLEY, (PHILOX_SEED,)),
+                              ("philox", qrt.PHILOX, (1, 2))):
+        errs = np.zeros(K + 1)
+        for sd in seeds:
+            imgs = per_order(kind, n, sd)
+            errs += np.array([metrics.rms_error(a, b) for a, b in zip(imgs, ref)])
+        out["rms_error"][name] = [round(float(e), 5) for e in errs / len(seeds)]
+    out["mc_over_sobol"] = [round(m / q, 3) for m, q in zip(out["rms_error"]["philox"], out["rms_error"]["sobol"])]
+    ctx.close()
+    return out
+
+
 def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int):
     """Image RMS error (I, all observers) against an independent high-N reference
     versus kernel time, N = 2^12 .. 2^sweep_log2; Sobol is scored against a
@@ -414,6 +456,8 @@ def main():
         result["time_to_error"] = time_to_error_sweep(ctx, qrt, sc, kinds, stream, args.ref_log2,
                                                       args.sweep_log2)
         ref = result["time_to_error"].pop("_ref_halton")
+    if not args.no_time_to_error:
+        result["per_order"] = per_order_section(qrt, sc, stream)
     if not args.no_surrogate:
         result["surrogate"] = surrogate_section(ctx, qrt, sc, stream, ref)
     if not args.no_workloads:
