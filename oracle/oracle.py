@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "qrt_oracle.c")
 LIB = os.path.join(HERE, "_build", "liboracle.so")
 
-SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX = 0, 1, 2, 3, 4
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -110,6 +110,10 @@ def seq_tables(kind: int, dims: int) -> Tuple[np.ndarray, np.ndarray]:
         mat = tables.niederreiter_columns(dims)
     elif kind in (HALTON, HAMMERSLEY):
         bases = tables.primes(dims)
+    elif kind == FAURE:
+        b, m, C = tables.faure_matrices(max(dims, 1))
+        mat = C.reshape(-1)
+        bases = np.array([b, m], dtype=np.uint32)
     return np.ascontiguousarray(mat), np.ascontiguousarray(bases)
 
 

@@ -38,7 +38,7 @@
 
 #define OG_PI 3.14159265358979323846
 
-enum { OG_SOBOL = 0, OG_HALTON = 1, OG_NIED2 = 2, OG_HAMMERSLEY = 3, OG_PHILOX = 4 };
+enum { OG_SOBOL = 0, OG_HALTON = 1, OG_NIED2 = 2, OG_HAMMERSLEY = 3, OG_PHILOX = 4, OG_FAURE = 5 };
 enum { OG_POINT = 0, OG_SPHERE = 1 };
 
 /* ------------------------------------------------------------------------- */
@@ -148,6 +148,25 @@ static uint32_t og_point(const og_seq *q, uint64_t i, int d)
            i = N gives 0, which as an azimuth is the same direction as 2 pi */
         if (d == 0) return (uint32_t)(((unsigned __int128)i << 32) / q->n_total);
         return og_radical_inverse(i, q->bases[d - 1]);
+    case OG_FAURE: {
+        /* Faure (1982): base b = bases[0], m = bases[1] digits; mat holds the
+           matrices C_d[r][k] = binom(k,r) d^(k-r) mod b, [dims][m][m].
+           y = C_d a (mod b) for the base-b digits a of i (least significant
+           first), x = sum_r y_r b^-(r+1), returned as floor(x 2^32). */
+        uint32_t b = q->bases[0], m = q->bases[1];
+        uint32_t a[64];
+        uint64_t n = i;
+        for (uint32_t k = 0; k < m; ++k) { a[k] = (uint32_t)(n % b); n /= b; }
+        const uint32_t *C = q->mat + (size_t)d * m * m;
+        unsigned __int128 Y = 0, B = 1;
+        for (uint32_t r = 0; r < m; ++r) {
+            uint64_t y = 0;
+            for (uint32_t k = r; k < m; ++k) y += (uint64_t)C[r * m + k] * a[k];
+            Y = Y * b + (y % b);
+            B *= b;
+        }
+        return (uint32_t)((Y << 32) / B);
+    }
     case OG_PHILOX: {
         uint64_t ctr[4] = {i, (uint64_t)(d >> 3), 0, 0}, key[2] = {q->seed, 0}, out[4];
         og_philox4x64(ctr, key, out);

@@ -22,6 +22,8 @@ from __future__ import annotations
 import functools
 from typing import List
 
+import math
+
 import numpy as np
 
 
@@ -187,3 +189,38 @@ def primes(count: int) -> np.ndarray:
             out.append(c)
         c += 1
     return np.array(out, dtype=np.uint32)
+
+
+# ----------------------------------------------------------------------------
+# Faure (1982): digital sequence in the prime base b >= s; coordinate d of
+# point i applies the d-th power of the Pascal matrix modulo b to the base-b
+# digits of i, then takes the radical inverse of the resulting digits.
+
+def faure_base(dims: int) -> int:
+    """Smallest prime >= dims (at least 2)."""
+    b = max(2, dims)
+    while any(b % q == 0 for q in range(2, int(b ** 0.5) + 1)):
+        b += 1
+    return b
+
+
+def faure_digits(b: int) -> int:
+    """Base-b digits that every index below 2^32 needs: smallest m with b^m >= 2^32."""
+    m, p = 0, 1
+    while p < (1 << 32):
+        p *= b
+        m += 1
+    return m
+
+
+def faure_matrices(dims: int):
+    """(b, m, C[dims][m][m]) with C_d[r][k] = binom(k, r) d^(k-r) mod b for k >= r
+    (the d-th power of the upper-triangular Pascal matrix; d = 0 is the identity)."""
+    b = faure_base(dims)
+    m = faure_digits(b)
+    C = np.zeros((dims, m, m), dtype=np.uint32)
+    for d in range(dims):
+        for r in range(m):
+            for k in range(r, m):
+                C[d, r, k] = (math.comb(k, r) * pow(d, k - r, b)) % b
+    return b, m, C

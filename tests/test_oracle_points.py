@@ -170,3 +170,88 @@ def test_philox_matches_numpy(seed):
                 w32 += [int(w) & 0xFFFFFFFF, int(w) >> 32]
             for d in range(blk * 8, min(dims, blk * 8 + 8)):
                 assert int(ours[j, d]) == w32[d & 7]
+
+
+# ---------------------------------------------------------------- Faure
+def _faure_exact(i, d, b, m):
+    """Faure coordinate from its definition with exact integers and fractions:
+    digits of i, Pascal-matrix power P^d modulo b, radical inverse."""
+    import math
+    from fractions import Fraction
+    a = []
+    n = i
+    for _ in range(m):
+        a.append(n % b)
+        n //= b
+    x = Fraction(0)
+    for r in range(m):
+        y = sum(math.comb(k, r) * d ** (k - r) * a[k] for k in range(r, m)) % b
+        x += Fraction(y, b ** (r + 1))
+    return math.floor(x * 2 ** 32)
+
+
+def test_faure_matches_its_definition():
+    from oracle import tables
+    for dims in (3, 7, 60):
+        b, m, _ = tables.faure_matrices(dims)
+        assert b == {3: 3, 7: 7, 60: 61}[dims]
+        idx = [1, 2, b - 1, b, b * b + 3, 12345, 2 ** 31 + 7, 2 ** 32 - 1]
+        pts = np.concatenate([O.points(O.FAURE, dims, i, 1) for i in idx])
+        for row, i in zip(pts, idx):
+            for d in (0, 1, dims // 2, dims - 1):
+                assert int(row[d]) == _faure_exact(i, d, b, m), (dims, i, d)
+
+
+def test_faure_first_coordinate_is_van_der_corput():
+    from fractions import Fraction
+    b = 5
+    pts = O.points(O.FAURE, 5, 1, 400)
+    for i in range(1, 401):
+        x, n, f = Fraction(0), i, Fraction(1, b)
+        while n:
+            x += (n % b) * f
+            n //= b
+            f /= b
+        assert int(pts[i - 1, 0]) == int(x * 2 ** 32)
+
+
+def _is_net_base(pts01, b, m):
+    """Every elementary interval of volume b^-m (exponents summing to m) holds
+    exactly one of the b^m points."""
+    s = pts01.shape[1]
+    import itertools
+    for ks in itertools.product(range(m + 1), repeat=s):
+        if sum(ks) != m:
+            continue
+        cells = np.zeros(len(pts01), dtype=np.int64)
+        for j, k in enumerate(ks):
+            cells = cells * (b ** k) + np.floor(pts01[:, j] * b ** k).astype(np.int64)
+        if len(np.unique(cells)) != len(pts01):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("b,s,m", [(5, 5, 3), (5, 4, 2), (7, 7, 2), (3, 3, 4)])
+def test_faure_points_form_zero_nets(b, s, m):
+    """The first b^m points (index 0, the all-zero point, included) of the
+    s-dimensional Faure sequence, whose base b is the smallest prime >= s, form
+    a (0, m, s)-net in base b."""
+    from oracle import tables
+    assert tables.faure_base(s) == b
+    pts = O.points(O.FAURE, s, 1, b ** m - 1).astype(np.float64) / 2 ** 32
+    pts = np.vstack([np.zeros((1, s)), pts])
+    # x is stored as floor(x 2^32): move it back up by one unit before binning
+    assert _is_net_base(pts + 2.0 ** -32, b, m)
+
+
+def test_faure_planted_mistake_breaks_net():
+    """Using the transposed Pascal matrices (a plausible slip) destroys the net."""
+    from oracle import tables
+    b, m, C = tables.faure_matrices(5)
+    Ct = np.ascontiguousarray(np.transpose(C, (0, 2, 1)))
+    out = np.zeros((124, 5), dtype=np.uint32)
+    lib = O.lib()
+    bases = np.array([b, m], dtype=np.uint32)
+    lib.oracle_points(O.FAURE, 5, Ct.ctypes.data, bases.ctypes.data, 0, 0, 1, 124, out.ctypes.data)
+    pts = np.vstack([np.zeros((1, 5)), out.astype(np.float64) / 2 ** 32])
+    assert not _is_net_base(pts + 2.0 ** -32, 5, 3)
