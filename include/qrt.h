@@ -53,6 +53,7 @@ extern "C" {
 #define QRT_NIEDERREITER2 2
 #define QRT_HAMMERSLEY 3
 #define QRT_PHILOX 4
+#define QRT_FAURE 5               /* Faure (1982), base = smallest prime >= the coordinates used */
 
 /* grid ownership flags for qrt_set_grid */
 #define QRT_GRID_HOST_COPY 0      /* kappa_rho is a host pointer; copied */

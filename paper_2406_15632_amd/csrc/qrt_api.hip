@@ -59,6 +59,10 @@ struct qrt_ctx {
     int peel_mode = QRT_PEEL_EXACT;
     // bookkeeping
     uint32_t *tables = nullptr;              // [sobol kMaxDims*32][nied kMaxDims*32][bases kMaxDims]
+    uint32_t *faure = nullptr;               // Faure matrices and powers for faure_dims coordinates
+    int faure_dims = 0;
+    uint32_t faure_b = 0, faure_m = 0, faure_pow = 0;
+    uint64_t faure_bm = 0;
     unsigned long long *counters = nullptr;  // [CNT_COUNT]
     TransportBuffers tb = {};                // packet and ray queues of the transport
     uint64_t tb_packets = 0;                 // packets the queues hold
@@ -130,7 +134,64 @@ SeqParams seq_params(const qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total
     s.bases = c->tables + 2 * kMaxDims * 32;
     s.seed = seed;
     s.n_total = n_total;
+    s.faure = c->faure;
+    s.fb = c->faure_b;
+    s.fm = c->faure_m;
+    s.fpow = c->faure_pow;
+    s.fbm = c->faure_bm;
     return s;
+}
+
+constexpr size_t kFaureTable = 8192;   // u32 entries: dims * m * m + m <= 128 * 25 + 5 (and 2 * 32 * 32 + 32)
+
+// Faure tables for `dims` coordinates: base b = smallest prime >= dims, m digits
+// with b^m >= 2^32, matrices P^d[r][k] = binom(k, r) d^(k-r) mod b, powers b^k
+int ensure_faure(qrt_ctx *c, int dims)
+{
+    if (c->faure && c->faure_dims == dims) return QRT_OK;
+    uint32_t b = dims < 2 ? 2u : (uint32_t)dims;
+    for (;; ++b) {
+        bool prime = true;
+        for (uint32_t q = 2; q * q <= b; ++q)
+            if (b % q == 0) { prime = false; break; }
+        if (prime) break;
+    }
+    uint32_t m = 0;
+    uint64_t p = 1;
+    while (p < (1ull << 32)) { p *= b; ++m; }
+    const size_t need = (size_t)dims * m * m + m;
+    if (need > kFaureTable) return fail(c, QRT_UNSUPPORTED, "Faure table too large for %d coordinates", dims);
+    std::vector<uint32_t> h(kFaureTable, 0);
+    // binomials modulo b from Pascal's triangle
+    std::vector<uint32_t> binom((size_t)m * m, 0);
+    for (uint32_t k = 0; k < m; ++k) {
+        binom[(size_t)k * m + 0] = 1;
+        for (uint32_t r = 1; r <= k; ++r)
+            binom[(size_t)k * m + r] = (binom[(size_t)(k - 1) * m + r - 1] + (r <= k - 1 ? binom[(size_t)(k - 1) * m + r] : 0)) % b;
+    }
+    for (int d = 0; d < dims; ++d)
+        for (uint32_t r = 0; r < m; ++r) {
+            uint64_t dp = 1;   // d^(k-r) mod b, with 0^0 = 1
+            for (uint32_t k = r; k < m; ++k) {
+                h[((size_t)d * m + r) * m + k] = (uint32_t)((binom[(size_t)k * m + r] * dp) % b);
+                dp = (dp * (uint64_t)d) % b;
+            }
+        }
+    const uint32_t pow_off = (uint32_t)((size_t)dims * m * m);
+    uint64_t pw = 1;
+    for (uint32_t k = 0; k < m; ++k) {
+        h[pow_off + k] = (uint32_t)pw;
+        pw *= b;
+    }
+    if (!c->faure) HIP_TRY(c, hipMalloc(&c->faure, kFaureTable * sizeof(uint32_t)), "Faure table");
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    HIP_TRY(c, hipMemcpy(c->faure, h.data(), kFaureTable * sizeof(uint32_t), hipMemcpyHostToDevice), "Faure table");
+    c->faure_dims = dims;
+    c->faure_b = b;
+    c->faure_m = m;
+    c->faure_pow = pow_off;
+    c->faure_bm = pw;
+    return QRT_OK;
 }
 
 int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, uint64_t count)
@@ -259,6 +320,7 @@ void qrt_destroy(qrt_ctx *c)
     if (c->grid_owned && c->grid) (void)hipFree(c->grid);
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
+    if (c->faure) (void)hipFree(c->faure);
     if (c->counters) (void)hipFree(c->counters);
     if (c->tb.packets) (void)hipFree(c->tb.packets);
     if (c->tb.peels) (void)hipFree(c->tb.peels);
@@ -413,7 +475,7 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
 int qrt_set_sequence(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total)
 {
     if (!c) return QRT_INVALID_ARG;
-    if (kind < QRT_SOBOL || kind > QRT_PHILOX) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
+    if (kind < QRT_SOBOL || kind > QRT_FAURE) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (kind == QRT_HAMMERSLEY && (n_total < 1 || n_total > 0xFFFFFFFFull))
         return fail(c, QRT_UNSUPPORTED, "Hammersley needs 1 <= N < 2^32");
     c->kind = kind;
@@ -529,9 +591,10 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     int rc = run_checks(c, c->kind, c->n_total, first, count);
     if (rc) return rc;
     if (count == 0) return QRT_OK;
+    DeviceGuard dg(c->device);
+    if (c->kind == QRT_FAURE && (rc = ensure_faure(c, point_dims(c)))) return rc;
     TransportParams P;
     transport_params(c, P);
-    DeviceGuard dg(c->device);
     rc = ensure_queues(c, count);
     if (rc) return rc;
     // chunks never exceed the queue capacity
@@ -665,7 +728,7 @@ int qrt_generate_points(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total, u
                         int dims, uint32_t *out, int out_on_device)
 {
     if (!c) return QRT_INVALID_ARG;
-    if (kind < QRT_SOBOL || kind > QRT_PHILOX) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
+    if (kind < QRT_SOBOL || kind > QRT_FAURE) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (dims < 1 || dims > kMaxDims) return fail(c, QRT_UNSUPPORTED, "dims must be in 1..%d", kMaxDims);
     if (!out && count) return fail(c, QRT_INVALID_ARG, "null output");
     if (kind == QRT_HAMMERSLEY && (n_total < 1 || n_total > 0xFFFFFFFFull))
@@ -674,6 +737,7 @@ int qrt_generate_points(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total, u
     if (rc) return rc;
     if (count == 0) return QRT_OK;
     DeviceGuard dg(c->device);
+    if (kind == QRT_FAURE && (rc = ensure_faure(c, dims))) return rc;
     SeqParams S = seq_params(c, kind, seed, n_total);
     const size_t bytes = (size_t)count * dims * sizeof(uint32_t);
     if (out_on_device) {

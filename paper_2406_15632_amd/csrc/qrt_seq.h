@@ -15,6 +15,10 @@
 //    Halton in the first primes.
 //  - Philox4x64-10 (Salmon et al., SC'11) for the Monte Carlo baseline:
 //    counter (i, d/8, 0, 0), key (seed, 0), 32-bit word d%8, low half first.
+//  - Faure (1982): base b = the smallest prime >= the number of coordinates;
+//    coordinate d takes the base-b digits a of i, y = P^d a (mod b) with the
+//    Pascal matrix power P^d[r][k] = binom(k, r) d^(k-r), and returns
+//    floor(0.y_0 y_1 ... (base b) * 2^32), exact as for Halton.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,13 +26,16 @@
 
 namespace qrt {
 
-enum SeqKind { SEQ_SOBOL = 0, SEQ_HALTON = 1, SEQ_NIED2 = 2, SEQ_HAMMERSLEY = 3, SEQ_PHILOX = 4 };
+enum SeqKind { SEQ_SOBOL = 0, SEQ_HALTON = 1, SEQ_NIED2 = 2, SEQ_HAMMERSLEY = 3, SEQ_PHILOX = 4, SEQ_FAURE = 5 };
 
 struct SeqParams {
     const uint32_t *mat;    // generator-matrix columns [dims][32] (Sobol or Niederreiter)
     const uint32_t *bases;  // Halton bases [dims]
     uint64_t seed;
     uint64_t n_total;       // Hammersley N
+    const uint32_t *faure;  // Faure: [dims][m][m] matrices P^d mod b, then b^0 .. b^(m-1) at faure + fpow
+    uint32_t fb, fm, fpow;  // Faure base, digits per index (b^m >= 2^32), offset of the powers
+    uint64_t fbm;           // b^m
 };
 
 __device__ __forceinline__ uint32_t digital_point(const uint32_t *__restrict__ cols, uint64_t i)
@@ -104,6 +111,25 @@ __device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t i, int d
     return (d & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
 }
 
+// Faure coordinate d of point i (< 2^32): digit k of i is (i / b^k) mod b,
+// taken up to the highest nonzero one
+__device__ __forceinline__ uint32_t faure_point(const SeqParams &S, uint64_t i, int d)
+{
+    const uint32_t b = S.fb, m = S.fm;
+    const uint32_t *__restrict__ C = S.faure + (size_t)d * m * m;
+    const uint32_t *__restrict__ pw = S.faure + S.fpow;
+    const uint32_t n = (uint32_t)i;
+    uint32_t top = 0;
+    while (top + 1 < m && pw[top + 1] <= n) ++top;
+    uint64_t Y = 0;
+    for (uint32_t r = 0; r < m; ++r) {
+        uint32_t y = 0;   // at most m (b-1)^2 < 2^20
+        for (uint32_t k = r; k <= top; ++k) y += C[r * m + k] * ((n / pw[k]) % b);
+        Y = Y * b + (y % b);
+    }
+    return frac_to_u32(Y, S.fbm);
+}
+
 template <int KIND>
 __device__ __forceinline__ uint32_t seq_point(const SeqParams &S, uint64_t i, int d)
 {
@@ -122,6 +148,8 @@ __device__ __forceinline__ uint32_t seq_point(const SeqParams &S, uint64_t i, in
             return (uint32_t)qi;
         }
         return radical_inverse(i, S.bases[d - 1]);
+    } else if constexpr (KIND == SEQ_FAURE) {
+        return faure_point(S, i, d);
     } else {
         return philox_word(S.seed, i, d);
     }
