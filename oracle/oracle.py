@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "qrt_oracle.c")
 LIB = os.path.join(HERE, "_build", "liboracle.so")
 
-SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE = 0, 1, 2, 3, 4, 5
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE, SOBOL_OWEN = 0, 1, 2, 3, 4, 5, 6
 
 
 def build(force: bool = True) -> str:
@@ -104,7 +104,7 @@ def seq_tables(kind: int, dims: int) -> Tuple[np.ndarray, np.ndarray]:
     """(matrix columns [dims][32], bases [dims]) for a sequence kind."""
     mat = np.zeros((max(dims, 1), 32), dtype=np.uint32)
     bases = np.zeros(max(dims, 1), dtype=np.uint32)
-    if kind == SOBOL:
+    if kind in (SOBOL, SOBOL_OWEN):
         mat = tables.sobol_columns(dims)
     elif kind == NIEDERREITER2:
         mat = tables.niederreiter_columns(dims)

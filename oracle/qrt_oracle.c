@@ -38,7 +38,7 @@
 
 #define OG_PI 3.14159265358979323846
 
-enum { OG_SOBOL = 0, OG_HALTON = 1, OG_NIED2 = 2, OG_HAMMERSLEY = 3, OG_PHILOX = 4, OG_FAURE = 5 };
+enum { OG_SOBOL = 0, OG_HALTON = 1, OG_NIED2 = 2, OG_HAMMERSLEY = 3, OG_PHILOX = 4, OG_FAURE = 5, OG_SOBOL_OWEN = 6 };
 enum { OG_POINT = 0, OG_SPHERE = 1 };
 
 /* ------------------------------------------------------------------------- */
@@ -135,12 +135,43 @@ typedef struct {
 } og_seq;
 
 /* coordinate d (0-based) of point i (i >= 1) */
+/* splitmix64 output function (Steele, Lea and Flood, OOPSLA 2014): add the
+   golden-ratio increment, then two xor-shift-multiply rounds and a final
+   xor-shift. */
+static uint64_t og_splitmix64(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Owen's nested uniform scrambling of a 0.32 fixed-point coordinate: going
+   from the most significant bit down, bit j (depth t = 31 - j) is flipped by a
+   random bit that depends on the seed, the dimension, the depth and the t
+   original bits above it, so that every elementary interval is permuted as a
+   whole.  The random bit is the top bit of splitmix64 of a key built from
+   (seed, dimension, depth, prefix). */
+static uint32_t og_owen(uint32_t x, uint64_t seed, int d)
+{
+    uint32_t out = x;
+    for (int t = 0; t < 32; ++t) {
+        uint64_t prefix = t == 0 ? 0 : (uint64_t)(x >> (32 - t));
+        uint64_t key = og_splitmix64(seed ^ og_splitmix64(((uint64_t)(uint32_t)d << 8) | (uint64_t)t)) ^ prefix;
+        uint32_t flip = (uint32_t)(og_splitmix64(key) >> 63);
+        out ^= flip << (31 - t);
+    }
+    return out;
+}
+
 static uint32_t og_point(const og_seq *q, uint64_t i, int d)
 {
     switch (q->kind) {
     case OG_SOBOL:
     case OG_NIED2:
         return og_digital(q->mat + 32 * (size_t)d, i);
+    case OG_SOBOL_OWEN:
+        return og_owen(og_digital(q->mat + 32 * (size_t)d, i), q->seed, d);
     case OG_HALTON:
         return og_radical_inverse(i, q->bases[d]);
     case OG_HAMMERSLEY:

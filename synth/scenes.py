@@ -27,9 +27,9 @@ from typing import List, Optional, Tuple
 import numpy as np
 
 # sequence kinds (shared numbering of the C-ABI and of the oracle front end)
-SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE = 0, 1, 2, 3, 4, 5
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE, SOBOL_OWEN = 0, 1, 2, 3, 4, 5, 6
 KIND_NAMES = {SOBOL: "sobol", HALTON: "halton", NIEDERREITER2: "niederreiter2",
-              HAMMERSLEY: "hammersley", PHILOX: "philox", FAURE: "faure"}
+              HAMMERSLEY: "hammersley", PHILOX: "philox", FAURE: "faure", SOBOL_OWEN: "sobol_owen"}
 KIND_BY_NAME = {v: k for k, v in KIND_NAMES.items()}
 
 POINT_SOURCE, SPHERE_SOURCE = 0, 1

@@ -61,10 +61,13 @@ def _net_counts_ok(pts, m, t, dims):
     return True
 
 
-def _first_pts(kind, dims, m):
-    # index 0 (the origin) plus indices 1 .. 2^m-1
-    body = O.points(kind, dims, 1, (1 << m) - 1)
-    return np.vstack([np.zeros((1, dims), dtype=np.uint32), body])
+def _first_pts(kind, dims, m, seed=0):
+    # index 0 (the origin, scrambled like the rest when scrambling) plus indices 1 .. 2^m-1
+    body = O.points(kind, dims, 1, (1 << m) - 1, seed=seed)
+    origin = np.zeros((1, dims), dtype=np.uint32)
+    if kind == O.SOBOL_OWEN:
+        origin[0] = [_owen_py(0, seed, d) for d in range(dims)]
+    return np.vstack([origin, body])
 
 
 @pytest.mark.parametrize("m", [4, 8, 12, 16])
@@ -255,3 +258,56 @@ def test_faure_planted_mistake_breaks_net():
     lib.oracle_points(O.FAURE, 5, Ct.ctypes.data, bases.ctypes.data, 0, 0, 1, 124, out.ctypes.data)
     pts = np.vstack([np.zeros((1, 5)), out.astype(np.float64) / 2 ** 32])
     assert not _is_net_base(pts + 2.0 ** -32, 5, 3)
+
+
+# ---------------------------------------------------------------- Owen scrambling
+def _splitmix64(z):
+    """splitmix64 output function (Steele, Lea and Flood 2014), 64-bit wrap-around."""
+    M = (1 << 64) - 1
+    z = (z + 0x9E3779B97F4A7C15) & M
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+    return z ^ (z >> 31)
+
+
+def test_splitmix64_known_values():
+    # published first outputs of the splitmix64 generator from state 0 (state
+    # advanced by the increment before mixing): 0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4
+    assert _splitmix64(0) == 0xE220A8397B1DCDAF
+    assert _splitmix64(0x9E3779B97F4A7C15) == 0x6E789E6AA1B965F4
+
+
+@pytest.mark.parametrize("m", [6, 10])
+def test_owen_scrambling_keeps_sobol_nets(m):
+    """Owen's scrambling permutes every elementary interval as a whole, so the
+    first 2^m scrambled Sobol points (index 0 included, scrambled like the
+    others) are still (0,m,1)-nets per dimension and a (0,m,2)-net in dims 0-1."""
+    for seed in (1, 99):
+        pts = _first_pts(O.SOBOL_OWEN, 4, m, seed=seed)
+        for d in range(4):
+            assert _net_counts_ok(pts, m, 0, [d])
+        assert _net_counts_ok(pts, m, 0, [0, 1])
+
+
+def _owen_py(x, seed, d):
+    """Owen scrambling of one 0.32 fixed-point coordinate, written out bit by bit."""
+    out = x
+    for t in range(32):
+        prefix = 0 if t == 0 else x >> (32 - t)
+        key = _splitmix64(seed ^ _splitmix64((d << 8) | t)) ^ prefix
+        out ^= (_splitmix64(key) >> 63) << (31 - t)
+    return out
+
+
+def test_owen_scrambling_definition():
+    """Against the definition written out here bit by bit (a key per depth,
+    dimension and seed, xored with the original higher bits)."""
+    seed = 12345
+    raw = O.points(O.SOBOL, 5, 1, 300)
+    scr = O.points(O.SOBOL_OWEN, 5, 1, 300, seed=seed)
+    for i in range(0, 300, 7):
+        for d in range(5):
+            assert int(scr[i, d]) == _owen_py(int(raw[i, d]), seed, d)
+    # different seeds give different, uniformly spread points
+    other = O.points(O.SOBOL_OWEN, 5, 1, 300, seed=seed + 1)
+    assert not np.array_equal(scr, other)
