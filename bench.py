@@ -327,7 +327,8 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
     ref_h, _ = run(qrt.HALTON, n_ref)
     floor = metrics.rms_error(ref_s, ref_h)
     names = {qrt.SOBOL: "sobol", qrt.HALTON: "halton", qrt.NIEDERREITER2: "niederreiter2",
-             qrt.HAMMERSLEY: "hammersley", qrt.PHILOX: "philox"}
+             qrt.HAMMERSLEY: "hammersley", qrt.PHILOX: "philox", qrt.FAURE: "faure"}
+    kinds = list(kinds) + [qrt.FAURE]   # the paper's fourth low-discrepancy sequence
     curves = {}
     for kind in kinds:
         ref = ref_h if kind == qrt.SOBOL else ref_s

@@ -54,6 +54,7 @@ extern "C" {
 #define QRT_HAMMERSLEY 3
 #define QRT_PHILOX 4
 #define QRT_FAURE 5               /* Faure (1982), base = smallest prime >= the coordinates used */
+#define QRT_SOBOL_OWEN 6          /* Sobol with Owen's nested uniform scrambling keyed by the seed */
 
 /* grid ownership flags for qrt_set_grid */
 #define QRT_GRID_HOST_COPY 0      /* kappa_rho is a host pointer; copied */
@@ -135,9 +136,9 @@ int qrt_set_dust(qrt_ctx *ctx, double albedo, double g, double p_lin, double p_c
 int qrt_set_observers(qrt_ctx *ctx, int n_obs, const double *theta, const double *phi, int npix,
                       double half_width);
 
-/* Point set (Sec. 3.1): kind QRT_*, seed (PRNG key; ignored by the
-   low-discrepancy kinds) and n_total (Hammersley's N, 1 <= N < 2^32;
-   ignored by the others). */
+/* Point set (Sec. 3.1): kind QRT_*, seed (PRNG key, or the scrambling key of
+   QRT_SOBOL_OWEN; ignored by the other low-discrepancy kinds) and n_total
+   (Hammersley's N, 1 <= N < 2^32; ignored by the others). */
 int qrt_set_sequence(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total);
 
 /* Transport (Sec. 3.2, 3.5): at most max_orders scatterings (1 .. 42 for a

@@ -475,7 +475,7 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
 int qrt_set_sequence(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total)
 {
     if (!c) return QRT_INVALID_ARG;
-    if (kind < QRT_SOBOL || kind > QRT_FAURE) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
+    if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (kind == QRT_HAMMERSLEY && (n_total < 1 || n_total > 0xFFFFFFFFull))
         return fail(c, QRT_UNSUPPORTED, "Hammersley needs 1 <= N < 2^32");
     c->kind = kind;
@@ -728,7 +728,7 @@ int qrt_generate_points(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total, u
                         int dims, uint32_t *out, int out_on_device)
 {
     if (!c) return QRT_INVALID_ARG;
-    if (kind < QRT_SOBOL || kind > QRT_FAURE) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
+    if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (dims < 1 || dims > kMaxDims) return fail(c, QRT_UNSUPPORTED, "dims must be in 1..%d", kMaxDims);
     if (!out && count) return fail(c, QRT_INVALID_ARG, "null output");
     if (kind == QRT_HAMMERSLEY && (n_total < 1 || n_total > 0xFFFFFFFFull))

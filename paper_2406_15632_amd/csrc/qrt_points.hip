@@ -34,6 +34,7 @@ hipError_t launch_points(const SeqParams &S, int kind, uint64_t first, uint64_t 
     case SEQ_HAMMERSLEY: hipLaunchKernelGGL(k_points<SEQ_HAMMERSLEY>, dim3(blocks), dim3(256), 0, stream, S, first, count, dims, out); break;
     case SEQ_PHILOX: hipLaunchKernelGGL(k_points<SEQ_PHILOX>, dim3(blocks), dim3(256), 0, stream, S, first, count, dims, out); break;
     case SEQ_FAURE: hipLaunchKernelGGL(k_points<SEQ_FAURE>, dim3(blocks), dim3(256), 0, stream, S, first, count, dims, out); break;
+    case SEQ_SOBOL_OWEN: hipLaunchKernelGGL(k_points<SEQ_SOBOL_OWEN>, dim3(blocks), dim3(256), 0, stream, S, first, count, dims, out); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

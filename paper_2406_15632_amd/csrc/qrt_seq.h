@@ -15,6 +15,10 @@
 //    Halton in the first primes.
 //  - Philox4x64-10 (Salmon et al., SC'11) for the Monte Carlo baseline:
 //    counter (i, d/8, 0, 0), key (seed, 0), 32-bit word d%8, low half first.
+//  - Sobol with Owen's nested uniform scrambling (randomised QMC): from the most
+//    significant bit down, bit j of a coordinate is flipped by the top bit of
+//    splitmix64 (Steele, Lea and Flood 2014) of a key made from the seed, the
+//    dimension, the depth and the original bits above j.
 //  - Faure (1982): base b = the smallest prime >= the number of coordinates;
 //    coordinate d takes the base-b digits a of i, y = P^d a (mod b) with the
 //    Pascal matrix power P^d[r][k] = binom(k, r) d^(k-r), and returns
@@ -26,7 +30,9 @@
 
 namespace qrt {
 
-enum SeqKind { SEQ_SOBOL = 0, SEQ_HALTON = 1, SEQ_NIED2 = 2, SEQ_HAMMERSLEY = 3, SEQ_PHILOX = 4, SEQ_FAURE = 5 };
+enum SeqKind {
+    SEQ_SOBOL = 0, SEQ_HALTON = 1, SEQ_NIED2 = 2, SEQ_HAMMERSLEY = 3, SEQ_PHILOX = 4, SEQ_FAURE = 5, SEQ_SOBOL_OWEN = 6
+};
 
 struct SeqParams {
     const uint32_t *mat;    // generator-matrix columns [dims][32] (Sobol or Niederreiter)
@@ -111,6 +117,25 @@ __device__ __forceinline__ uint32_t philox_word(uint64_t seed, uint64_t i, int d
     return (d & 1) ? (uint32_t)(w >> 32) : (uint32_t)w;
 }
 
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z)
+{
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint32_t owen_scramble(uint32_t x, uint64_t seed, int d)
+{
+    uint32_t out = x;
+    for (int t = 0; t < 32; ++t) {
+        const uint64_t prefix = t == 0 ? 0ull : (uint64_t)(x >> (32 - t));
+        const uint64_t key = splitmix64_mix(seed ^ splitmix64_mix(((uint64_t)(uint32_t)d << 8) | (uint64_t)t)) ^ prefix;
+        out ^= (uint32_t)(splitmix64_mix(key) >> 63) << (31 - t);
+    }
+    return out;
+}
+
 // Faure coordinate d of point i (< 2^32): digit k of i is (i / b^k) mod b,
 // taken up to the highest nonzero one
 __device__ __forceinline__ uint32_t faure_point(const SeqParams &S, uint64_t i, int d)
@@ -135,6 +160,8 @@ __device__ __forceinline__ uint32_t seq_point(const SeqParams &S, uint64_t i, in
 {
     if constexpr (KIND == SEQ_SOBOL || KIND == SEQ_NIED2) {
         return digital_point(S.mat + 32 * d, i);
+    } else if constexpr (KIND == SEQ_SOBOL_OWEN) {
+        return owen_scramble(digital_point(S.mat + 32 * d, i), S.seed, d);
     } else if constexpr (KIND == SEQ_HALTON) {
         return radical_inverse(i, S.bases[d]);
     } else if constexpr (KIND == SEQ_HAMMERSLEY) {

@@ -817,6 +817,7 @@ static hipError_t run_kind(const TransportParams &P, int kind, uint64_t first, u
     case SEQ_HAMMERSLEY: return run_src<R, SEQ_HAMMERSLEY>(P, first, count, B, st);
     case SEQ_PHILOX: return run_src<R, SEQ_PHILOX>(P, first, count, B, st);
     case SEQ_FAURE: return run_src<R, SEQ_FAURE>(P, first, count, B, st);
+    case SEQ_SOBOL_OWEN: return run_src<R, SEQ_SOBOL_OWEN>(P, first, count, B, st);
     default: return hipErrorInvalidValue;
     }
 }

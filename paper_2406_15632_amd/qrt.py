@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(PKG, "libqrt.so")
 
 QRT_OK, QRT_INVALID_ARG, QRT_BAD_STATE, QRT_HIP_ERROR = 0, -1, -2, -3
 QRT_OUT_OF_MEMORY, QRT_UNSUPPORTED, QRT_NOT_TRAINED = -4, -5, -6
-SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE = 0, 1, 2, 3, 4, 5
+SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE, SOBOL_OWEN = 0, 1, 2, 3, 4, 5, 6
 GRID_HOST_COPY, GRID_DEVICE_COPY, GRID_DEVICE_BORROW = 0, 1, 2
 FP32, FP64 = 0, 1
 PEEL_EXACT, PEEL_SURROGATE = 0, 1

@@ -88,7 +88,7 @@ def assert_counters_equal(cg, co):
 POINT_RANGES = [(1, 4096), ((1 << 16) - 3, 9), ((1 << 24) - 2, 5), ((1 << 32) - 8, 7)]
 
 
-@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX, O.FAURE])
+@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX, O.FAURE, O.SOBOL_OWEN])
 @pytest.mark.parametrize("dims", [3, 60, 128])
 def test_points_bit_exact(ctx, Q, kind, dims):
     for first, count in POINT_RANGES:
@@ -191,7 +191,7 @@ def test_envelope32_fp64_parity(ctx, Q):
     assert_counters_equal(cg, co)
 
 
-@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX, O.FAURE])
+@pytest.mark.parametrize("kind", [O.SOBOL, O.HALTON, O.NIEDERREITER2, O.HAMMERSLEY, O.PHILOX, O.FAURE, O.SOBOL_OWEN])
 def test_small_disk_multi_order_fp64_parity(ctx, Q, kind):
     sc = scenes.disk128(n=32).replace(npix=64, fp64=True, n_packets=1 << 14)
     _say(f"disk32 FP64 20 orders kind={kind}")
