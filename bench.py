@@ -16,6 +16,8 @@ The JSON line carries
   time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
                 the speed-up of each over the Monte Carlo (Philox) baseline;
   per_order     image error per scattering order, QMC against Monte Carlo;
+                (time_to_error also holds Faure's curve and the error bar of
+                8 Owen-scrambled Sobol runs against their actual error)
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload;
   surrogate     the learned peel-off on the same disk scene at 2^24 packets: pilot
                 sampling, GPU training and validation times, the share of
@@ -343,11 +345,21 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
                 ts.append(t)
             pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg))
         curves[names[kind]] = pts
+    # randomised QMC: R independent Owen scramblings give an error bar from
+    # their spread; compared here with the actual error of their mean
+    R, n_each = 8, 1 << 21
+    imgs = [run(qrt.SOBOL_OWEN, n_each, 1000 + r)[0] for r in range(R)]
+    mean = sum(imgs) / R
+    spread = float(np.sqrt(sum(float(np.sum((im - mean) ** 2)) for im in imgs) / (R * (R - 1))) /
+                   np.linalg.norm(ref_h))
+    owen = {"scramblings": R, "packets_each": n_each, "estimated_rms_error_of_mean": spread,
+            "actual_rms_error_of_mean": metrics.rms_error(mean, ref_h),
+            "unscrambled_sobol_rms_error_same_packets": metrics.rms_error(run(qrt.SOBOL, R * n_each)[0], ref_h)}
     targets = (0.05, 0.01, 0.003)
     out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor, "_ref_halton": ref_h,
            "rms_error_by_log2_packets": {k: {int(p[2]).bit_length() - 1: round(p[1], 6) for p in v}
                                          for k, v in curves.items()},
-           "time_s": {}, "speedup_vs_mc": {}}
+           "time_s": {}, "speedup_vs_mc": {}, "owen_error_bar": owen}
     for k, pts in curves.items():
         ts = [p[0] for p in pts]
         es = [p[1] for p in pts]
