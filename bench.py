@@ -27,7 +27,9 @@ The JSON line carries
                 clumpy envelope 256^3 with a spherical star);
   sphere_star   time to 5 % and 1 % image error for the spherical star in the
                 direct and the inverse order of the point coordinates against
-                Monte Carlo.
+                Monte Carlo;
+  batch         64 uneven seeded scenes in one batched launch sequence against
+                the same scenes run one after another.
 """
 from __future__ import annotations
 
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--sweep-log2", type=int, default=26, help="largest log2 packets of the error sweep")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     return ap.parse_args()
 
 
@@ -207,6 +210,63 @@ def other_workloads(qrt, stream):
                      "algorithmic_GBps": (4.0 * cnt["visits"] + 24.0 * cnt["peels"]) / t / 1e9}
         ctx.close()
     return res
+
+
+def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
+    """The batched workload: 64 uneven scenes drawn from `seed` (grids 32^3 to
+    192^3, 2^16 to 2^24 packets, tau 0.1 to 20, g 0 to 0.8, albedo 0.3 to 0.9,
+    envelope or disk, point source or sphere star, 1 to 4 observers, 1 to 20
+    orders, 128^2 images, FP32 rays with FP64 sums), Sobol points.  One batch
+    run (every scene's packets in one launch sequence) against the same scenes
+    run one after another through the single-scene calls, meshes resident in
+    HBM for both."""
+    import torch
+
+    from synth import scenes
+    bs = scenes.uneven_batch(seed, 64)
+    total = sum(sc.n_packets for sc in bs)
+    grids = [torch.from_numpy(sc.kappa_rho).cuda() for sc in bs]
+    ctx = qrt.Context(0, stream.cuda_stream)
+    ctx.batch_set(bs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)               # warm-up
+    torch.cuda.synchronize()
+    ctx.batch_reset()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_wall = (time.perf_counter() - w0) / steps
+    batch_s = e0.elapsed_time(e1) * 1e-3 / steps
+    cnt = ctx.counters()
+    # the same scenes one after another
+    seq = qrt.Context(0, stream.cuda_stream)
+    for sc, g in zip(bs[:2], grids[:2]):             # warm-up of the single-scene kernels
+        seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
+        seq.run(1, min(sc.n_packets, 1 << 16))
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for sc, g in zip(bs, grids):
+        seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
+        seq.run(1, sc.n_packets)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_wall = time.perf_counter() - w0
+    seq_s = e0.elapsed_time(e1) * 1e-3
+    ctx.close()
+    seq.close()
+    return {
+        "scenes": len(bs), "packets": total, "seed": seed,
+        "batch_packets_per_s": total / batch_s, "batch_ms": batch_s * 1e3, "batch_wall_ms": batch_wall * 1e3,
+        "sequential_packets_per_s": total / seq_s, "sequential_ms": seq_s * 1e3,
+        "sequential_wall_ms": seq_wall * 1e3,
+        "speedup": seq_s / batch_s,
+        "visits_per_packet": cnt["visits"] / cnt["packets"],
+        "algorithmic_GBps": (4.0 * cnt["visits"] + 24.0 * cnt["peels"]) / (batch_s * steps) / 1e9,
+    }
 
 
 def sphere_star_section(qrt, stream):
@@ -476,6 +536,8 @@ def main():
     if not args.no_workloads:
         result["workloads"] = other_workloads(qrt, stream)
         result["sphere_star"] = sphere_star_section(qrt, stream)
+    if not args.no_batch:
+        result["batch"] = batch_section(qrt, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()

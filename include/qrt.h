@@ -301,6 +301,65 @@ int qrt_surrogate_train(qrt_ctx *ctx, int64_t n, const float *pos_obs, const flo
 int qrt_surrogate_validate(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, double max_err,
                            double floor_frac, int64_t min_count, qrt_mask_report *rep);
 
+/* ---------------------------------------------------------------------------
+ * Batches of scenes.
+ *
+ * Many independent scenes of uneven size, each with its own mesh, source,
+ * dust, 1..QRT_BATCH_MAX_OBSERVERS observers, image and packet range, run in
+ * one launch sequence that treats all their packets as one queue of work.
+ * Every packet follows exactly the transport of a single-scene run of its
+ * scene (Sec. 3.2-3.7): the images of scene s equal those of qrt_run on that
+ * scene with the same point set, indices and precision, up to the order of
+ * the FP64 image sums.  Exact peel-off only; every point set but QRT_FAURE
+ * (whose base depends on the coordinates used, which differ between scenes).
+ * The batch's images and the context's counters are separate from those of
+ * single-scene runs; counters of batch runs add to the context counters.
+ * ------------------------------------------------------------------------- */
+
+#define QRT_BATCH_MAX_OBSERVERS 4
+#define QRT_BATCH_MAX_SCENES 1024
+
+/* source kinds of a batch scene */
+#define QRT_SOURCE_POINT 0        /* isotropic point source (Sec. 3.2) */
+#define QRT_SOURCE_SPHERE 1       /* uniform-brightness sphere star (Sec. 3.3) */
+
+typedef struct {
+    int nx, ny, nz;               /* mesh cells; kappa_rho as for qrt_set_grid, a host pointer (copied) */
+    double lo[3], hi[3];
+    const float *kappa_rho;
+    int source;                   /* QRT_SOURCE_POINT or QRT_SOURCE_SPHERE */
+    int emit_order;               /* sphere star: QRT_EMIT_DIRECT or QRT_EMIT_INVERSE */
+    double src[3];                /* source centre, inside the box (a star wholly inside) */
+    double radius;                /* star radius (> 0 for a star, ignored for a point) */
+    double albedo, g, p_lin;      /* dust as for qrt_set_dust (p_circ = 0) */
+    int n_obs;                    /* 1 .. QRT_BATCH_MAX_OBSERVERS */
+    double theta[QRT_BATCH_MAX_OBSERVERS], phi[QRT_BATCH_MAX_OBSERVERS];
+    int npix;                     /* 1 .. 8192 */
+    double half_width;
+    int max_orders;               /* >= 1, point dimension <= QRT_MAX_DIMS */
+    double tau_min;
+    uint64_t first, count;        /* point indices first .. first+count-1 (first >= 1; count may be 0) */
+    uint64_t n_total;             /* Hammersley's N of this scene (ignored by the other kinds) */
+} qrt_batch_scene;
+
+/* Set the scenes of the batch (1 <= n_scenes <= QRT_BATCH_MAX_SCENES): copies
+   every mesh to the device, allocates one FP64 image set per scene and
+   zeroes the batch images.  Replaces a previous batch.  Synchronous. */
+int qrt_batch_set(qrt_ctx *ctx, int n_scenes, const qrt_batch_scene *scenes);
+
+/* Transport every scene's packets once with point set `kind` and `seed` (as
+   for qrt_set_sequence) at `precision` (QRT_FP32 or QRT_FP64), adding to the
+   batch images.  Asynchronous on the context stream. */
+int qrt_batch_run(qrt_ctx *ctx, int kind, uint64_t seed, int precision);
+
+/* Copy the images of observer obs of scene `scene`, as qrt_read_images;
+   normalized = 1 divides by the scene's packet count times the batch runs
+   since the last reset.  Synchronises the stream. */
+int qrt_batch_read_images(qrt_ctx *ctx, int scene, int obs, double *I, double *Q, double *U, int normalized);
+
+/* Zero the batch images, the batch run count and the context counters. */
+int qrt_batch_reset(qrt_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

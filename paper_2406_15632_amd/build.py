@@ -21,12 +21,16 @@ LIB = os.path.join(PKG, "libqrt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qrt_api.hip", "qrt_transport.hip", "qrt_points.hip", "qrt_mlp.hip", "qrt_tables.cpp"]
+SOURCES = ["qrt_api.hip", "qrt_transport.hip", "qrt_batch.hip", "qrt_points.hip", "qrt_mlp.hip", "qrt_tables.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC",
     f"--offload-arch={ARCH}",
     "-munsafe-fp-atomics",
+    # multiply-adds are fused only where the source calls fma(): a packet then
+    # gets the same FP32 arithmetic in every kernel that transports it (the
+    # single-scene and the batched launch sequences)
+    "-ffp-contract=off",
     # packed FP32 instructions stay off: they are generated only from plain float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -82,6 +82,17 @@ struct qrt_ctx {
     double dom_r_in = 0, dom_r_out = 0, dom_h0 = 0, dom_beta = 0, dom_zmax = 0;
     int dom_nr = 0, dom_nz = 0;
     uint8_t *dom_valid = nullptr;            // [QRT_MAX_OBSERVERS][nr][nz] on the device
+    // batch of scenes
+    std::vector<BScene> batch;               // scene records (device addresses inside)
+    BScene *batch_dev = nullptr;             // [kMaxBatchScenes]
+    float *batch_grid = nullptr;             // all meshes, one after the other
+    size_t batch_grid_alloc = 0;             // floats
+    double *batch_img = nullptr;             // all image sets, one after the other
+    size_t batch_img_alloc = 0;              // doubles
+    size_t batch_img_used = 0;
+    uint64_t batch_total = 0;                // packets of one batch run
+    int batch_max_orders = 0;
+    uint64_t batch_runs = 0;                 // batch runs since the last reset
 };
 
 namespace {
@@ -208,15 +219,15 @@ int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, ui
     return QRT_OK;
 }
 
-// Queues for chunks of up to `packets` packets (at most kChunk) at the
-// context's precision and observer count; grown on demand, never shrunk.
-int ensure_queues(qrt_ctx *c, uint64_t count)
+// Queues for chunks of up to `count` packets (at most kChunk) at the given
+// precision and peel slots per packet; grown on demand, never shrunk.
+int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
 {
     uint64_t want = 1u << 16;
     while (want < count && want < kChunk) want <<= 1;
     if (want > kChunk) want = kChunk;
-    const size_t pb = packet_state_bytes(c->precision) * want;
-    const size_t rb = peel_ray_bytes(c->precision) * (want + 64) * (size_t)c->n_obs;
+    const size_t pb = packet_state_bytes(precision) * want;
+    const size_t rb = peel_ray_bytes(precision) * (want + 64) * (size_t)n_obs;
     if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb_packets >= want) return QRT_OK;
     HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
     if (c->tb.packet_bytes < pb || c->tb_packets < want) {
@@ -335,6 +346,9 @@ void qrt_destroy(qrt_ctx *c)
     if (c->part) (void)hipFree(c->part);
     if (c->train_x) (void)hipFree(c->train_x);
     if (c->dom_valid) (void)hipFree(c->dom_valid);
+    if (c->batch_dev) (void)hipFree(c->batch_dev);
+    if (c->batch_grid) (void)hipFree(c->batch_grid);
+    if (c->batch_img) (void)hipFree(c->batch_img);
     delete c;
 }
 
@@ -516,6 +530,20 @@ static DevGrid dev_grid(const qrt_ctx *c)
     return g;
 }
 
+// direction o of an observer at (theta, phi) and its image axes
+// e_x = (-sin phi, cos phi, 0), e_y = o x e_x (Sec. 3.6)
+static DevObserver dev_observer(double theta, double phi)
+{
+    const double st = sin(theta), ct = cos(theta), sp = sin(phi), cp = cos(phi);
+    DevObserver O;
+    O.o[0] = st * cp; O.o[1] = st * sp; O.o[2] = ct;
+    O.ex[0] = -sp; O.ex[1] = cp; O.ex[2] = 0.0;
+    O.ey[0] = O.o[1] * O.ex[2] - O.o[2] * O.ex[1];
+    O.ey[1] = O.o[2] * O.ex[0] - O.o[0] * O.ex[2];
+    O.ey[2] = O.o[0] * O.ex[1] - O.o[1] * O.ex[0];
+    return O;
+}
+
 static InputMap input_map(const qrt_ctx *c)
 {
     InputMap M;
@@ -546,15 +574,7 @@ static void transport_params(const qrt_ctx *c, TransportParams &P)
     P.n_obs = c->n_obs;
     P.npix = c->npix;
     P.half_width = c->half_width;
-    for (int i = 0; i < c->n_obs; ++i) {
-        const double st = sin(c->theta[i]), ct = cos(c->theta[i]), sp = sin(c->phi[i]), cp = cos(c->phi[i]);
-        DevObserver &O = P.obs[i];
-        O.o[0] = st * cp; O.o[1] = st * sp; O.o[2] = ct;
-        O.ex[0] = -sp; O.ex[1] = cp; O.ex[2] = 0.0;
-        O.ey[0] = O.o[1] * O.ex[2] - O.o[2] * O.ex[1];
-        O.ey[1] = O.o[2] * O.ex[0] - O.o[0] * O.ex[2];
-        O.ey[2] = O.o[0] * O.ex[1] - O.o[1] * O.ex[0];
-    }
+    for (int i = 0; i < c->n_obs; ++i) P.obs[i] = dev_observer(c->theta[i], c->phi[i]);
     P.seq = seq_params(c, c->kind, c->seed, c->n_total);
     P.max_orders = c->max_orders;
     P.tau_min = c->tau_min;
@@ -595,7 +615,7 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     if (c->kind == QRT_FAURE && (rc = ensure_faure(c, point_dims(c)))) return rc;
     TransportParams P;
     transport_params(c, P);
-    rc = ensure_queues(c, count);
+    rc = ensure_queues(c, count, c->n_obs, c->precision);
     if (rc) return rc;
     // chunks never exceed the queue capacity
     for (uint64_t done = 0; done < count;) {
@@ -971,7 +991,7 @@ int qrt_surrogate_sample(qrt_ctx *c, int64_t n, uint64_t seed, float *pos_obs, f
     uint64_t chunk = 1ull << 16;
     while (chunk > 256 && chunk * per_packet > (1ull << 24)) chunk >>= 1;
     const uint64_t capacity = chunk * per_packet;
-    rc = ensure_queues(c, chunk);
+    rc = ensure_queues(c, chunk, c->n_obs, c->precision);
     if (rc) return rc;
     float *cap = nullptr;
     uint32_t *cap_count = nullptr;
@@ -1216,6 +1236,207 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
         rep->samples_valid = samples_valid;
         rep->max_err_valid = worst;
     }
+    return QRT_OK;
+}
+
+// ---------------------------------------------------------------- batches of scenes
+
+// checks one scene description; returns its point dimension, or a status < 0
+static int batch_scene_check(qrt_ctx *c, int i, const qrt_batch_scene &S)
+{
+    if (S.nx < 1 || S.ny < 1 || S.nz < 1 || !S.kappa_rho)
+        return fail(c, QRT_INVALID_ARG, "scene %d: bad grid arguments", i);
+    if ((int64_t)S.nx * S.ny * S.nz > (int64_t)1 << 31) return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large", i);
+    for (int a = 0; a < 3; ++a)
+        if (!(S.hi[a] > S.lo[a]) || !isfinite(S.lo[a]) || !isfinite(S.hi[a]))
+            return fail(c, QRT_INVALID_ARG, "scene %d: box must satisfy lo < hi on every axis", i);
+    const size_t cells = (size_t)S.nx * S.ny * S.nz;
+    for (size_t k = 0; k < cells; ++k)
+        if (!(S.kappa_rho[k] >= 0.0f) || !isfinite(S.kappa_rho[k]))
+            return fail(c, QRT_INVALID_ARG, "scene %d: cell %zu is negative or not finite", i, k);
+    if (S.source != QRT_SOURCE_POINT && S.source != QRT_SOURCE_SPHERE)
+        return fail(c, QRT_INVALID_ARG, "scene %d: unknown source kind %d", i, S.source);
+    const double r = S.source == QRT_SOURCE_SPHERE ? S.radius : 0.0;
+    if (S.source == QRT_SOURCE_SPHERE) {
+        if (!(S.radius > 0.0) || !isfinite(S.radius)) return fail(c, QRT_INVALID_ARG, "scene %d: radius must be > 0", i);
+        if (S.emit_order != QRT_EMIT_DIRECT && S.emit_order != QRT_EMIT_INVERSE)
+            return fail(c, QRT_INVALID_ARG, "scene %d: unknown emission order %d", i, S.emit_order);
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!(S.src[a] - r >= S.lo[a] && S.src[a] + r <= S.hi[a]))
+            return fail(c, QRT_INVALID_ARG, "scene %d: the source must lie inside the box", i);
+    if (!(S.albedo >= 0.0 && S.albedo <= 1.0)) return fail(c, QRT_INVALID_ARG, "scene %d: albedo must be in [0,1]", i);
+    if (!(fabs(S.g) < 1.0)) return fail(c, QRT_INVALID_ARG, "scene %d: |g| must be < 1", i);
+    if (!(S.p_lin >= 0.0 && S.p_lin <= 1.0)) return fail(c, QRT_INVALID_ARG, "scene %d: p_lin must be in [0,1]", i);
+    if (S.n_obs < 1 || S.n_obs > QRT_BATCH_MAX_OBSERVERS)
+        return fail(c, QRT_INVALID_ARG, "scene %d: need 1..%d observers", i, QRT_BATCH_MAX_OBSERVERS);
+    for (int o = 0; o < S.n_obs; ++o)
+        if (!isfinite(S.theta[o]) || !isfinite(S.phi[o]))
+            return fail(c, QRT_INVALID_ARG, "scene %d: observer %d direction not finite", i, o);
+    if (S.npix < 1 || S.npix > 8192) return fail(c, QRT_INVALID_ARG, "scene %d: npix must be in 1..8192", i);
+    if (!(S.half_width > 0.0) || !isfinite(S.half_width))
+        return fail(c, QRT_INVALID_ARG, "scene %d: half_width must be > 0", i);
+    if (S.max_orders < 1) return fail(c, QRT_INVALID_ARG, "scene %d: max_orders must be >= 1", i);
+    const int dims = (S.source == QRT_SOURCE_SPHERE ? 5 : 3) + 3 * (S.max_orders - 1);
+    if (dims > kMaxDims)
+        return fail(c, QRT_UNSUPPORTED, "scene %d: %d point dimensions exceed the %d served", i, dims, kMaxDims);
+    if (!(S.tau_min >= 0.0) || !isfinite(S.tau_min)) return fail(c, QRT_INVALID_ARG, "scene %d: tau_min must be >= 0", i);
+    if (S.first < 1) return fail(c, QRT_INVALID_ARG, "scene %d: packet indices start at 1", i);
+    if (S.count > 0 && S.first + S.count - 1 < S.first) return fail(c, QRT_INVALID_ARG, "scene %d: index range overflows", i);
+    return dims;
+}
+
+int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (n_scenes < 1 || n_scenes > QRT_BATCH_MAX_SCENES || !scenes)
+        return fail(c, QRT_INVALID_ARG, "need 1..%d scenes", QRT_BATCH_MAX_SCENES);
+    size_t cells = 0, pixels = 0;
+    uint64_t total = 0;
+    int max_orders = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        const qrt_batch_scene &S = scenes[i];
+        const int rc = batch_scene_check(c, i, S);
+        if (rc < 0) return rc;
+        cells += (size_t)S.nx * S.ny * S.nz;
+        pixels += (size_t)S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
+        if (total + S.count < total) return fail(c, QRT_INVALID_ARG, "packet total overflows");
+        total += S.count;
+        max_orders = std::max(max_orders, S.max_orders);
+    }
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    c->batch.clear();
+    c->batch_total = 0;
+    if (!c->batch_dev) HIP_TRY(c, hipMalloc(&c->batch_dev, sizeof(BScene) * kMaxBatchScenes), "batch scenes");
+    if (c->batch_grid_alloc < cells) {
+        if (c->batch_grid) (void)hipFree(c->batch_grid);
+        c->batch_grid = nullptr;
+        c->batch_grid_alloc = 0;
+        HIP_TRY(c, hipMalloc(&c->batch_grid, cells * sizeof(float)), "batch meshes");
+        c->batch_grid_alloc = cells;
+    }
+    if (c->batch_img_alloc < pixels) {
+        if (c->batch_img) (void)hipFree(c->batch_img);
+        c->batch_img = nullptr;
+        c->batch_img_alloc = 0;
+        HIP_TRY(c, hipMalloc(&c->batch_img, pixels * sizeof(double)), "batch images");
+        c->batch_img_alloc = pixels;
+    }
+    std::vector<BScene> host((size_t)n_scenes);
+    size_t grid_off = 0, img_off = 0;
+    uint64_t begin = 0;
+    for (int i = 0; i < n_scenes; ++i) {
+        const qrt_batch_scene &S = scenes[i];
+        BScene &B = host[(size_t)i];
+        memset(&B, 0, sizeof(B));
+        const size_t nc = (size_t)S.nx * S.ny * S.nz;
+        HIP_TRY(c, hipMemcpyAsync(c->batch_grid + grid_off, S.kappa_rho, nc * sizeof(float), hipMemcpyHostToDevice,
+                                  c->stream),
+                "batch mesh copy");
+        B.kr = c->batch_grid + grid_off;
+        grid_off += nc;
+        B.n[0] = S.nx; B.n[1] = S.ny; B.n[2] = S.nz;
+        for (int a = 0; a < 3; ++a) {
+            B.lo[a] = S.lo[a];
+            B.h[a] = (S.hi[a] - S.lo[a]) / (double)B.n[a];
+            B.src[a] = S.src[a];
+        }
+        B.src_kind = S.source == QRT_SOURCE_SPHERE ? (S.emit_order == QRT_EMIT_INVERSE ? 2 : 1) : 0;
+        B.r_star = S.source == QRT_SOURCE_SPHERE ? S.radius : 0.0;
+        B.albedo = S.albedo;
+        B.g = S.g;
+        B.p_lin = S.p_lin;
+        B.n_obs = S.n_obs;
+        B.npix = S.npix;
+        B.half_width = S.half_width;
+        for (int o = 0; o < S.n_obs; ++o) B.obs[o] = dev_observer(S.theta[o], S.phi[o]);
+        B.max_orders = S.max_orders;
+        B.tau_min = S.tau_min;
+        B.img = c->batch_img + img_off;
+        img_off += (size_t)S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
+        B.first = S.first;
+        B.begin = begin;
+        B.count = S.count;
+        B.n_total = S.n_total;
+        begin += S.count;
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->batch_dev, host.data(), host.size() * sizeof(BScene), hipMemcpyHostToDevice, c->stream),
+            "batch scene copy");
+    HIP_TRY(c, hipMemsetAsync(c->batch_img, 0, pixels * sizeof(double), c->stream), "batch image reset");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "batch set sync");
+    c->batch.swap(host);
+    c->batch_img_used = pixels;
+    c->batch_total = total;
+    c->batch_max_orders = max_orders;
+    c->batch_runs = 0;
+    return QRT_OK;
+}
+
+int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (c->batch.empty()) return fail(c, QRT_BAD_STATE, "set the batch scenes first");
+    if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
+    if (kind == QRT_FAURE) return fail(c, QRT_UNSUPPORTED, "Faure points are not served in batches");
+    if (precision != QRT_FP32 && precision != QRT_FP64) return fail(c, QRT_INVALID_ARG, "unknown precision");
+    for (size_t i = 0; i < c->batch.size(); ++i) {
+        const BScene &B = c->batch[i];
+        if (kind == QRT_HAMMERSLEY && (B.n_total < 1 || B.n_total > 0xFFFFFFFFull))
+            return fail(c, QRT_UNSUPPORTED, "scene %zu: Hammersley needs 1 <= N < 2^32", i);
+        const int rc = check_index_range(c, kind, B.n_total, B.first, B.count);
+        if (rc) return rc;
+    }
+    c->batch_runs++;
+    if (c->batch_total == 0) return QRT_OK;
+    DeviceGuard dg(c->device);
+    int rc = ensure_queues(c, c->batch_total, kBatchObs, precision);
+    if (rc) return rc;
+    BatchParams P;
+    memset(&P, 0, sizeof(P));
+    P.scenes = c->batch_dev;
+    P.n_scenes = (int)c->batch.size();
+    while ((1 << P.scene_bits) < P.n_scenes) P.scene_bits++;
+    P.seq = seq_params(c, kind, seed, 0);
+    P.max_orders = c->batch_max_orders;
+    P.counters = c->counters;
+    HIP_TRY(c, launch_batch(P, precision, kind, c->batch_total, c->tb, c->tb_packets, c->stream), "batch launch");
+    return QRT_OK;
+}
+
+int qrt_batch_read_images(qrt_ctx *c, int scene, int obs, double *I, double *Q, double *U, int normalized)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (scene < 0 || scene >= (int)c->batch.size()) return fail(c, QRT_INVALID_ARG, "scene %d out of range", scene);
+    const BScene &B = c->batch[(size_t)scene];
+    if (obs < 0 || obs >= B.n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
+    DeviceGuard dg(c->device);
+    const size_t plane = (size_t)B.npix * B.npix;
+    double *dst[3] = {I, Q, U};
+    for (int s = 0; s < 3; ++s)
+        if (dst[s])
+            HIP_TRY(c, hipMemcpyAsync(dst[s], B.img + ((size_t)obs * 3 + s) * plane, plane * sizeof(double),
+                                      hipMemcpyDeviceToHost, c->stream),
+                    "batch image copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "batch image copy sync");
+    const double n = (double)B.count * (double)c->batch_runs;
+    if (normalized && n > 0) {
+        const double inv = 1.0 / n;
+        for (int s = 0; s < 3; ++s)
+            if (dst[s])
+                for (size_t i = 0; i < plane; ++i) dst[s][i] *= inv;
+    }
+    return QRT_OK;
+}
+
+int qrt_batch_reset(qrt_ctx *c)
+{
+    if (!c) return QRT_INVALID_ARG;
+    DeviceGuard dg(c->device);
+    if (c->batch_img && c->batch_img_used)
+        HIP_TRY(c, hipMemsetAsync(c->batch_img, 0, c->batch_img_used * sizeof(double), c->stream), "batch image reset");
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, CNT_COUNT * sizeof(unsigned long long), c->stream), "counter reset");
+    c->batch_runs = 0;
     return QRT_OK;
 }
 

@@ -1,0 +1,501 @@
+// Batched transport: many uneven scenes in one launch sequence.
+//
+// Every scene of a batch has its own mesh, source, dust, observers (up to 4),
+// image and packet range; the packets of all scenes share one numbering and
+// run through the same kernels as one work queue.  Each lane looks up the
+// scene of its packet (a binary search over the scenes' first batch numbers)
+// and walks that scene's mesh through a plain pointer.  The per-packet
+// physics is that of the single-scene transport (qrt_transport.hip): emission
+// (Sec. 3.2, 3.3), tau1 and the forced first scattering (Sec. 3.2), moves and
+// peel-off walks (Sec. 3.4, 3.6), Henyey-Greenstein scattering with White's
+// Mueller matrix (Sec. 2.2, 3.5), coordinates by purpose (Sec. 3.7).
+//
+// Launch sequence of a chunk of batch numbers: emission keys (scene and
+// coarse emission direction) -> counting sort -> persistent first flight
+// -> per order up to the largest order of the batch: scatter, then walk.  A
+// packet whose scene has fewer orders stops at its own last order.
+#include <hip/hip_runtime.h>
+
+#include "qrt_internal.h"
+#include "qrt_physics.h"
+#include "qrt_wave.h"
+
+namespace qrt {
+
+// scene of batch number b: the last scene whose first batch number is <= b
+__device__ __forceinline__ int batch_scene(const BatchParams &P, uint64_t b)
+{
+    int lo = 0, hi = P.n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.scenes[mid].begin <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R>
+__device__ __forceinline__ LaneGrid<R> lane_grid(const BScene &S)
+{
+    LaneGrid<R> G;
+    G.kr = S.kr;
+    for (int a = 0; a < 3; ++a) {
+        G.n[a] = S.n[a];
+        G.lo[a] = (R)S.lo[a];
+        G.h[a] = (R)S.h[a];
+    }
+    return G;
+}
+
+__device__ __forceinline__ SeqParams scene_seq(const BatchParams &P, const BScene &S)
+{
+    SeqParams q = P.seq;
+    q.n_total = S.n_total;
+    return q;
+}
+
+// first coordinate of the scattering flights and of the forced optical depth
+__device__ __forceinline__ int first_scatter_dim(const BScene &S) { return S.src_kind >= 1 ? 5 : 3; }
+__device__ __forceinline__ int forced_tau_dim(const BScene &S) { return S.src_kind == 1 ? 4 : 2; }
+
+// Emission of a packet of scene S (point source, or a sphere star in the
+// direct or the inverse order of the coordinates), as in the single-scene path.
+template <typename R, int KIND>
+__device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, uint64_t idx, R p[3], R k[3])
+{
+    uint32_t xa[3], xb[3];
+    seq_triple<KIND>(q, idx, 0, xa);
+    if (S.src_kind == 0) {
+        R sp, cp;
+        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
+        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
+        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+        for (int a = 0; a < 3; ++a) p[a] = (R)S.src[a];
+        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+        return;
+    }
+    seq_triple<KIND>(q, idx, 2, xb);
+    if (S.src_kind == 1) {
+        // direct order: point on the star (v1, v2), local direction (v3, v4)
+        R spe, cpe, spl, cpl;
+        sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
+        const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
+        const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
+        sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
+        const R ctl = sqrt(to_unit<R>(xb[1]));
+        const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
+        const R ne[3] = {ste * cpe, ste * spe, cte};
+        const R t1[3] = {cte * cpe, cte * spe, -ste};
+        const R t2[3] = {-spe, cpe, (R)0};
+        for (int a = 0; a < 3; ++a) {
+            p[a] = (R)S.src[a] + (R)S.r_star * ne[a];
+            k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
+        }
+    } else {
+        // inverse order: direction (v1, v2), emission point about it (v4, v5)
+        R sp, cp, spr, cpr;
+        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
+        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
+        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+        sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
+        const R ca = sqrt(to_unit<R>(xb[2]));
+        const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
+        const R t1[3] = {ct * cp, ct * sp, -st};
+        const R t2[3] = {-sp, cp, (R)0};
+        for (int a = 0; a < 3; ++a) p[a] = (R)S.src[a] + (R)S.r_star * (ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]));
+    }
+}
+
+// ---------------------------------------------------------------- emission sort
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_bkey(const BatchParams P, uint64_t b0, uint32_t count,
+                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ hist)
+{
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
+        const uint64_t b = b0 + j;
+        const int s = batch_scene(P, b);
+        const BScene &S = P.scenes[s];
+        R p[3], k[3];
+        batch_emit<R, KIND>(S, scene_seq(P, S), S.first + (b - S.begin), p, k);
+        const uint32_t key = ((uint32_t)s << (kSortBits - P.scene_bits)) | (direction_key(k) >> P.scene_bits);
+        keys[j] = key;
+        atomicAdd(hist + key, 1u);
+    }
+}
+
+// ---------------------------------------------------------------- first flight
+enum BatchFirstPhase : int { BF_IDLE = 0, BF_EDGE = 1, BF_FORCED = 2 };
+
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0, uint32_t count,
+                                                const uint32_t *__restrict__ order, PacketState<R> *__restrict__ pks,
+                                                uint32_t *__restrict__ live0, Queues *__restrict__ Q)
+{
+    uint64_t n_visits = 0;
+    uint32_t n_packets = 0, n_cuts = 0;
+    int phase = BF_IDLE;
+    uint32_t j = 0;
+    int s = 0;
+    R p[3] = {(R)0, (R)0, (R)0}, k[3] = {(R)0, (R)0, (R)1};
+    R S0 = (R)0;
+    LaneGrid<R> G = {};
+    Walk<R> W;
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        bool append = false;
+        if (W.done && phase == BF_EDGE) {
+            n_visits += W.visits;
+            const BScene &S = P.scenes[s];
+            const double tau1 = W.tau;
+            if (tau1 < S.tau_min) {
+                n_cuts++;
+                phase = BF_IDLE;
+            } else {
+                const double W1 = -expm1(-tau1);
+                const uint64_t idx = S.first + (b0 + j - S.begin);
+                const double u = (double)seq_point<KIND>(scene_seq(P, S), idx, forced_tau_dim(S)) * 0x1p-32;
+                S0 = (R)W1;
+                walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
+                phase = BF_FORCED;
+            }
+        } else if (W.done && phase == BF_FORCED) {
+            n_visits += W.visits;
+            const BScene &S = P.scenes[s];
+            PacketState<R> st;
+            for (int a = 0; a < 3; ++a) {
+                st.p[a] = p[a] + W.t_out * k[a];
+                st.k[a] = k[a];
+            }
+            basis_of(k, st.m);
+            st.S[0] = S0; st.S[1] = (R)0; st.S[2] = (R)0;
+            st.target = 0.0;
+            st.idx = S.first + (b0 + j - S.begin);
+            st.next_dim = (uint32_t)s;   // the batch keeps the scene here
+            st.order = 1;
+            pks[j] = st;
+            append = true;
+            phase = BF_IDLE;
+        }
+        const uint32_t pos = wave_append(append, &Q->n_live[0]);
+        if (append) live0[pos] = j;
+        uint64_t item = 0;
+        if (pool.take(phase == BF_IDLE, count, &Q->work[0], item)) {
+            j = order[item];
+            s = batch_scene(P, b0 + j);
+            const BScene &S = P.scenes[s];
+            n_packets++;
+            batch_emit<R, KIND>(S, scene_seq(P, S), S.first + (b0 + j - S.begin), p, k);
+            G = lane_grid<R>(S);
+            walk_begin(W, G, p, k, WALK_EDGE, 0.0);
+            phase = BF_EDGE;
+        }
+        if (__ballot(phase != BF_IDLE) == 0 && pool.dry) break;
+        for (;;) {
+            walk_batch<R, kWalkBatch>(W, G);
+            if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
+        }
+    }
+    flush_counter(P.counters + CNT_PACKETS, n_packets);
+    flush_counter(P.counters + CNT_TAU_CUTS, n_cuts);
+    flush_counter(P.counters + CNT_VISITS, n_visits);
+}
+
+// ---------------------------------------------------------------- scattering
+// Albedo, peel-off contributions toward the scene's observers (slots of the
+// batch's fixed width kBatchObs; the observer field holds scene * 16 + obs)
+// and, unless it was the scene's last order, the new direction and flight.
+// A packet at its scene's last order gets target -1 and does not move.
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
+                                                  const uint32_t *__restrict__ live_in, int in,
+                                                  PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Q->n_live[in ^ 1] = 0;
+        Q->work[1] = 0;
+    }
+    const uint32_t n = Q->n_live[in];
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    uint32_t n_scat = 0, n_occ = 0;
+    for (uint32_t base = wave0; base < n; base += stride) {
+        const uint32_t i = base + (uint32_t)lane;
+        const bool valid = i < n;
+        const uint32_t slot = valid ? live_in[i] : 0;
+        PacketState<R> st = {};
+        int s = 0;
+        if (valid) {
+            st = pks[slot];
+            s = (int)st.next_dim;
+            n_scat++;
+        }
+        const BScene &S = P.scenes[s];
+        if (valid) {
+            const R albedo = (R)S.albedo;
+            st.S[0] *= albedo; st.S[1] *= albedo; st.S[2] *= albedo;
+        }
+        R n_ax[3];
+        cross3(st.k, st.m, n_ax);
+        const R Rw = (R)S.half_width;
+        for (int ob = 0; ob < kBatchObs; ++ob) {
+            bool vis = false;
+            R c3[3] = {(R)0, (R)0, (R)0};
+            uint32_t pix = 0;
+            if (valid && ob < S.n_obs) {
+                const DevObserver &O = S.obs[ob];
+                const R o[3] = {(R)O.o[0], (R)O.o[1], (R)O.o[2]};
+                const R ex[3] = {(R)O.ex[0], (R)O.ex[1], (R)O.ex[2]};
+                const R ey[3] = {(R)O.ey[0], (R)O.ey[1], (R)O.ey[2]};
+                const R X = dot3(st.p, ex), Y = dot3(st.p, ey);
+                const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)S.npix);
+                const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)S.npix);
+                vis = fx >= (R)0 && fy >= (R)0 && fx < (R)S.npix && fy < (R)S.npix;
+                if (vis && S.src_kind >= 1) {
+                    R d[3] = {st.p[0] - (R)S.src[0], st.p[1] - (R)S.src[1], st.p[2] - (R)S.src[2]};
+                    const R b = dot3(d, o), cc = dot3(d, d) - (R)(S.r_star * S.r_star);
+                    if (b < (R)0 && b * b > cc) {   // the star blocks the ray
+                        n_occ++;
+                        vis = false;
+                    }
+                }
+                if (vis) {
+                    R c = dot3(st.k, o);
+                    c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
+                    const R sn = sqrt(fmax((R)0, (R)1 - c * c));
+                    R Sv[3] = {st.S[0], st.S[1], st.S[2]};
+                    R mi[3];
+                    if (sn < (R)1e-12) {
+                        mi[0] = st.m[0]; mi[1] = st.m[1]; mi[2] = st.m[2];
+                    } else {
+                        const R inv_s = (R)1 / sn;
+                        for (int a = 0; a < 3; ++a) mi[a] = (o[a] - c * st.k[a]) * inv_s;
+                        rotate_stokes(Sv, dot3(st.m, mi), dot3(n_ax, mi));
+                    }
+                    R p11, r12, r33;
+                    mueller((R)S.g, (R)S.p_lin, c, p11, r12, r33);
+                    const R w = p11 * (R)(0.25 / 3.14159265358979323846);
+                    c3[0] = w * (Sv[0] + r12 * Sv[1]);
+                    c3[1] = w * (r12 * Sv[0] + Sv[1]);
+                    c3[2] = w * (r33 * Sv[2]);
+                    R mo[3], no[3];
+                    for (int a = 0; a < 3; ++a) mo[a] = c * mi[a] - sn * st.k[a];
+                    cross3(o, mo, no);
+                    rotate_stokes(c3, dot3(mo, ex), dot3(no, ex));
+                    pix = (uint32_t)((int)fy * S.npix + (int)fx);
+                }
+            }
+            PeelRay<R> r;
+            r.p[0] = st.p[0]; r.p[1] = st.p[1]; r.p[2] = st.p[2];
+            r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
+            r.pix = (valid && vis) ? pix : kNoPixel;
+            r.obs = ((uint32_t)s << 4) | (uint32_t)ob;
+            peels[peel_slot(i, ob, kBatchObs)] = r;
+        }
+        if (valid) {
+            if (order < S.max_orders) {
+                const int dim = first_scatter_dim(S) + 3 * (order - 1);
+                uint32_t x[3];
+                seq_triple<KIND>(scene_seq(P, S), st.idx, dim, x);
+                R si, ci;
+                sincos_2pi<R>(to_unit<R>(x[0]), si, ci);
+                const R ct = hg_cos<R>((R)S.g, to_unit<R>(x[1]));
+                const R sth = sqrt(fmax((R)0, (R)1 - ct * ct));
+                R mi[3];
+                for (int a = 0; a < 3; ++a) mi[a] = ci * st.m[a] + si * n_ax[a];
+                rotate_stokes(st.S, ci, si);
+                R p11, r12, r33;
+                mueller((R)S.g, (R)S.p_lin, ct, p11, r12, r33);
+                const R I1 = st.S[0] + r12 * st.S[1], Q1 = r12 * st.S[0] + st.S[1], U1 = r33 * st.S[2];
+                st.S[0] = I1; st.S[1] = Q1; st.S[2] = U1;
+                for (int a = 0; a < 3; ++a) {
+                    const R kn = ct * st.k[a] + sth * mi[a];
+                    const R mn = ct * mi[a] - sth * st.k[a];
+                    st.k[a] = kn;
+                    st.m[a] = mn;
+                }
+                st.target = -log((double)x[2] * 0x1p-32);
+            } else {
+                st.target = -1.0;   // the scene's last scattering: no further flight
+            }
+            pks[slot] = st;
+        }
+    }
+    flush_counter(P.counters + CNT_SCATTERINGS, n_scat);
+    flush_counter(P.counters + CNT_OCCLUDED, n_occ);
+}
+
+// ---------------------------------------------------------------- walks of one order
+enum BatchWalkItem : int { BW_NONE = 0, BW_PEEL = 1, BW_MOVE = 2 };
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
+                                               const uint32_t *__restrict__ live_in, int in,
+                                               uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
+                                               Queues *__restrict__ Q)
+{
+    const uint64_t n_live = Q->n_live[in];
+    const uint64_t n_peel = (uint64_t)kBatchObs * 64 * ((n_live + 63) / 64);
+    const uint64_t n_move = order < P.max_orders ? n_live : 0;
+    const uint64_t total = n_peel + n_move;
+    uint64_t n_visits = 0;
+    uint32_t n_peels = 0, n_esc = 0;
+    int kind = BW_NONE;
+    uint32_t slot = 0, pix = 0;
+    int s = 0, obs = 0;
+    R c3[3] = {(R)0, (R)0, (R)0};
+    LaneGrid<R> G = {};
+    Walk<R> W;
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        bool append = false;
+        if (W.done && kind == BW_PEEL) {
+            n_visits += W.visits;
+            n_peels++;
+            const BScene &S = P.scenes[s];
+            const size_t plane = (size_t)S.npix * (size_t)S.npix;
+            const double att = exp(-W.tau);
+            double *dst = S.img + (size_t)obs * 3 * plane + (size_t)pix;
+            unsafeAtomicAdd(dst, att * (double)c3[0]);
+            unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
+            unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
+            kind = BW_NONE;
+        } else if (W.done && kind == BW_MOVE) {
+            n_visits += W.visits;
+            if (W.stopped) {
+                PacketState<R> *ps = pks + slot;
+                R q[3];
+                for (int a = 0; a < 3; ++a) q[a] = ps->p[a] + W.t_out * ps->k[a];
+                for (int a = 0; a < 3; ++a) ps->p[a] = q[a];
+                append = true;
+            } else {
+                n_esc++;
+            }
+            kind = BW_NONE;
+        }
+        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
+        if (append) live_out[pos] = slot;
+        uint64_t item = 0;
+        if (pool.take(kind == BW_NONE, total, &Q->work[1], item)) {
+            if (item < n_peel) {
+                const PeelRay<R> r = peels[item];
+                if (r.pix != kNoPixel) {
+                    s = (int)(r.obs >> 4);
+                    obs = (int)(r.obs & 15u);
+                    const BScene &S = P.scenes[s];
+                    const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
+                    c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                    pix = r.pix;
+                    G = lane_grid<R>(S);
+                    walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                    kind = BW_PEEL;
+                }
+            } else {
+                slot = live_in[item - n_peel];
+                const PacketState<R> *ps = pks + slot;
+                if (ps->target >= 0.0) {
+                    s = (int)ps->next_dim;
+                    const R p0[3] = {ps->p[0], ps->p[1], ps->p[2]};
+                    const R k0[3] = {ps->k[0], ps->k[1], ps->k[2]};
+                    G = lane_grid<R>(P.scenes[s]);
+                    walk_begin(W, G, p0, k0, WALK_MOVE, ps->target);
+                    kind = BW_MOVE;
+                }
+            }
+        }
+        if (__ballot(kind != BW_NONE) == 0) {
+            if (pool.dry) break;
+            continue;
+        }
+        for (;;) {
+            walk_batch<R, kWalkBatch>(W, G);
+            if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
+        }
+    }
+    flush_counter(P.counters + CNT_VISITS, n_visits);
+    flush_counter(P.counters + CNT_PEELS, n_peels);
+    flush_counter(P.counters + CNT_PEEL_RAYS, n_peels);
+    flush_counter(P.counters + CNT_ESCAPES, n_esc);
+}
+
+// ---------------------------------------------------------------- launch sequence
+template <typename F>
+static int batch_resident_blocks(F kernel)
+{
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    (void)hipGetDevice(&dev);
+    int cus = 256;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0) cus = prop.multiProcessorCount;
+    return per_cu * cus;
+}
+
+template <typename R, int KIND>
+static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count, const TransportBuffers &B,
+                              hipStream_t st)
+{
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
+    if (!nb_first) {
+        nb_first = batch_resident_blocks(k_bfirst<R, KIND>);
+        nb_scatter = batch_resident_blocks(k_bscatter<R, KIND>);
+        nb_walk = batch_resident_blocks(k_bwalk<R>);
+    }
+    PacketState<R> *pks = (PacketState<R> *)B.packets;
+    PeelRay<R> *peels = (PeelRay<R> *)B.peels;
+    const uint32_t cblocks = (count + 255) / 256;
+    const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
+    hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
+    if (e == hipSuccess) e = hipMemsetAsync(B.hist, 0, sizeof(uint32_t) << kSortBits, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys, B.hist);
+    if ((e = launch_scan_bins(B.hist, st)) != hipSuccess) return e;
+    if ((e = launch_place(B.keys, count, B.hist, B.order, b_elem, st)) != hipSuccess) return e;
+    const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
+    hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order, pks,
+                       B.live[0], B.q);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
+    for (int order = 1; order <= P.max_orders; ++order) {
+        const int in = (order - 1) & 1;
+        hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, pks,
+                           (const uint32_t *)B.live[in], in, peels, B.q);
+        hipLaunchKernelGGL((k_bwalk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks,
+                           (const uint32_t *)B.live[in], in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename R>
+static hipError_t batch_kind(const BatchParams &P, int kind, uint64_t b0, uint32_t count, const TransportBuffers &B,
+                             hipStream_t st)
+{
+    switch (kind) {
+    case SEQ_SOBOL: return batch_chunk<R, SEQ_SOBOL>(P, b0, count, B, st);
+    case SEQ_HALTON: return batch_chunk<R, SEQ_HALTON>(P, b0, count, B, st);
+    case SEQ_NIED2: return batch_chunk<R, SEQ_NIED2>(P, b0, count, B, st);
+    case SEQ_HAMMERSLEY: return batch_chunk<R, SEQ_HAMMERSLEY>(P, b0, count, B, st);
+    case SEQ_PHILOX: return batch_chunk<R, SEQ_PHILOX>(P, b0, count, B, st);
+    case SEQ_SOBOL_OWEN: return batch_chunk<R, SEQ_SOBOL_OWEN>(P, b0, count, B, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch(const BatchParams &P, int precision, int kind, uint64_t total, const TransportBuffers &B,
+                        uint64_t chunk, hipStream_t stream)
+{
+    for (uint64_t done = 0; done < total;) {
+        const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
+        hipError_t e = precision == 1 ? batch_kind<double>(P, kind, done, n, B, stream)
+                                      : batch_kind<float>(P, kind, done, n, B, stream);
+        if (e != hipSuccess) return e;
+        done += n;
+    }
+    return hipSuccess;
+}
+
+}  // namespace qrt

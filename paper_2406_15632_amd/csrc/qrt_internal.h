@@ -142,6 +142,47 @@ struct TransportBuffers {
 size_t packet_state_bytes(int precision);
 size_t peel_ray_bytes(int precision);
 
+// ---------------------------------------------------------------- batches of scenes
+constexpr int kBatchObs = 4;            // observers per scene of a batch (peel slots per packet)
+constexpr int kMaxBatchScenes = 1024;
+
+// One scene of a batch: its own mesh, source, dust, observers, image and
+// packet range.  Its packets are the batch numbers begin .. begin+count-1 and
+// use point indices first .. first+count-1 of the scene's sequence.
+struct BScene {
+    const float *kr;            // [n2][n1][n0], x fastest
+    int n[3];
+    double lo[3], h[3];
+    int src_kind;               // 0 point, 1 sphere star (direct order), 2 sphere star (inverse order)
+    double src[3], r_star;
+    double albedo, g, p_lin;
+    int n_obs, npix;
+    double half_width;
+    DevObserver obs[kBatchObs];
+    int max_orders;
+    double tau_min;
+    double *img;                // [n_obs][3][npix][npix]
+    uint64_t first, begin, count, n_total;
+};
+
+struct BatchParams {
+    const BScene *scenes;       // device array [n_scenes], ordered by begin
+    int n_scenes;
+    int scene_bits;             // sort-key bits that hold the scene (the rest: emission direction)
+    SeqParams seq;              // n_total is replaced by each scene's own
+    int max_orders;             // largest over the scenes
+    unsigned long long *counters;
+};
+
+// All `total` batch numbers of a batch, in chunks of at most `chunk`.
+hipError_t launch_batch(const BatchParams &P, int precision, int kind, uint64_t total, const TransportBuffers &B,
+                        uint64_t chunk, hipStream_t stream);
+
+// counting-sort steps shared by the transport launch sequences
+hipError_t launch_scan_bins(uint32_t *hist, hipStream_t st);
+hipError_t launch_place(const uint32_t *keys, uint32_t count, uint32_t *hist, uint32_t *out, int blocks,
+                        hipStream_t st);
+
 // One chunk of packets first .. first+count-1 (count <= kChunk) through every
 // scattering order: first flight, then per order a scatter kernel and a walk
 // kernel.  All launches go to stream.

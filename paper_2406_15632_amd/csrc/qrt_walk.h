@@ -52,6 +52,16 @@ __device__ __forceinline__ RayGrid<R> ray_grid(const DevGrid &g)
     return r;
 }
 
+// Mesh of one lane (a batch of scenes: every lane may walk its own mesh); the
+// densities are read through a plain pointer, since a buffer descriptor has
+// to be the same for the whole wave.
+template <typename R>
+struct LaneGrid {
+    const float *kr;
+    int n[3];
+    R lo[3], h[3];
+};
+
 template <typename R> __device__ __forceinline__ R r_inf();
 template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
@@ -60,6 +70,12 @@ template <typename R>
 __device__ __forceinline__ R load_kr(const RayGrid<R> &G, int cell)
 {
     return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, cell * 4, 0, 0));
+}
+
+template <typename R>
+__device__ __forceinline__ R load_kr(const LaneGrid<R> &G, int cell)
+{
+    return (R)G.kr[cell];
 }
 
 enum WalkMode { WALK_EDGE = 0, WALK_MOVE = 1 };
@@ -80,8 +96,8 @@ struct Walk {
     uint32_t visits;
 };
 
-template <typename R>
-__device__ __forceinline__ void axis_setup(const RayGrid<R> &G, int a, R p, R d, int stride, int &c, R &T0, R &D,
+template <typename R, typename GT>
+__device__ __forceinline__ void axis_setup(const GT &G, int a, R p, R d, int stride, int &c, R &T0, R &D,
                                            R &tb, int &dc)
 {
     R f = floor((p - G.lo[a]) / G.h[a]);
@@ -107,8 +123,8 @@ __device__ __forceinline__ void axis_setup(const RayGrid<R> &G, int a, R p, R d,
 
 // Start a walk from p along unit d.  Returns false (and a finished walk with
 // tau = 0) for non-finite input or a zero direction.
-template <typename R>
-__device__ __forceinline__ bool walk_begin(Walk<R> &W, const RayGrid<R> &G, const R p[3], const R d[3], int mode,
+template <typename R, typename GT>
+__device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3], const R d[3], int mode,
                                            double target)
 {
     W.mode = mode;
@@ -148,8 +164,8 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const RayGrid<R> &G, cons
 // zero length: they add nothing and are not counted as visits.  The stop
 // position of a move is computed once, after the batch, for the step that
 // reached the target.
-template <typename R, int B>
-__device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
+template <typename R, int B, typename GT>
+__device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
 {
     if (W.done) return;
     int cells[B];
@@ -217,8 +233,8 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const RayGrid<R> &G)
     }
 }
 
-template <typename R, int B>
-__device__ __forceinline__ void walk_run(Walk<R> &W, const RayGrid<R> &G)
+template <typename R, int B, typename GT>
+__device__ __forceinline__ void walk_run(Walk<R> &W, const GT &G)
 {
     while (!W.done) walk_batch<R, B>(W, G);
 }

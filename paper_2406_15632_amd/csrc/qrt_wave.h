@@ -1,0 +1,101 @@
+// Wave-level building blocks shared by the transport kernels: work pool of the
+// persistent kernels, counter flushes, peel-off slot layout and the
+// emission-direction key of the coherence sort.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qrt_physics.h"
+
+namespace qrt {
+
+constexpr int kWalkBatch = 4;
+constexpr uint32_t kNoPixel = 0xFFFFFFFFu;   // a peel ray that is off the image or blocked
+
+__host__ __device__ __forceinline__ size_t peel_slot(uint32_t i, int ob, int n_obs)
+{
+    return ((size_t)(i >> 6) * (size_t)n_obs + (size_t)ob) * 64 + (i & 63);
+}
+constexpr int kWaveRefill = 64;   // refill a wave once all its lanes are idle: keeps its rays coherent
+
+__device__ __forceinline__ void flush_counter(unsigned long long *dst, uint64_t v)
+{
+    const uint64_t s = wave_sum_u64(v);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
+}
+
+// Wave-uniform pool of work items [next, end), 64 at a time: the first block of
+// every wave is fixed by its wave index (no atomic at start-up, when every
+// wave would hit the same counter at once), later blocks come from a global
+// counter that starts after the fixed ones.
+struct WorkPool {
+    uint64_t next = 0, end = 0;
+    bool dry = false, started = false;
+
+    // returns true for a lane that received an item (in `item`)
+    __device__ __forceinline__ bool take(bool want, uint64_t total, unsigned long long *ctr, uint64_t &item)
+    {
+        bool got = false;
+        uint64_t need = __ballot(want);
+        while (need && !dry) {
+            if (next >= end) {
+                const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+                uint64_t base;
+                if (!started) {
+                    base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+                    started = true;
+                } else {
+                    unsigned long long b = 0;
+                    if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, 64ull);
+                    base = nwaves * 64 + __shfl(b, 0, 64);
+                }
+                next = base;
+                end = base + 64 < total ? base + 64 : total;
+                if (next >= total) {
+                    dry = true;
+                    break;
+                }
+            }
+            const uint64_t avail = end - next;
+            const uint64_t n = (uint64_t)__popcll(need);
+            const uint64_t take_n = n < avail ? n : avail;
+            const uint64_t rank = (uint64_t)__popcll(need & lanes_below_mask());
+            if (want && !got && rank < take_n) {
+                item = next + rank;
+                got = true;
+            }
+            next += take_n;
+            need = __ballot(want && !got);
+        }
+        return got;
+    }
+};
+
+// Octahedral map of a direction to 2 x 8 bits, interleaved (nearby directions
+// get nearby keys).
+__device__ __forceinline__ uint32_t interleave2(uint32_t qu, uint32_t qv, int bits)
+{
+    uint32_t key = 0;
+    for (int b = 0; b < bits; ++b) key |= ((qu >> b) & 1u) << (2 * b) | ((qv >> b) & 1u) << (2 * b + 1);
+    return key;
+}
+
+template <typename R>
+__device__ __forceinline__ uint32_t direction_key(const R k[3])
+{
+    const R s = fabs(k[0]) + fabs(k[1]) + fabs(k[2]);
+    R u = k[0] / s, v = k[1] / s;
+    if (k[2] < (R)0) {
+        const R uu = ((R)1 - fabs(v)) * (u >= (R)0 ? (R)1 : (R)-1);
+        const R vv = ((R)1 - fabs(u)) * (v >= (R)0 ? (R)1 : (R)-1);
+        u = uu;
+        v = vv;
+    }
+    int qu = (int)((u + (R)1) * (R)128), qv = (int)((v + (R)1) * (R)128);
+    qu = qu < 0 ? 0 : (qu > 255 ? 255 : qu);
+    qv = qv < 0 ? 0 : (qv > 255 ? 255 : qv);
+    return interleave2((uint32_t)qu, (uint32_t)qv, 8);
+}
+
+}  // namespace qrt

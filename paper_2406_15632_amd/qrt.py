@@ -26,6 +26,8 @@ PEEL_EXACT, PEEL_SURROGATE = 0, 1
 EMIT_DIRECT, EMIT_INVERSE = 0, 1
 MAX_DIMS, MAX_OBSERVERS = 128, 16
 MLP_PARAMS = 12929
+BATCH_MAX_OBSERVERS, BATCH_MAX_SCENES = 4, 1024
+SOURCE_POINT, SOURCE_SPHERE = 0, 1
 
 
 class qrt_counters(C.Structure):
@@ -49,6 +51,17 @@ class qrt_train_report(C.Structure):
 class qrt_mask_report(C.Structure):
     _fields_ = [("cells", C.c_int64), ("valid_cells", C.c_int64), ("samples", C.c_int64),
                 ("samples_valid", C.c_int64), ("max_err_valid", C.c_double)]
+
+
+class qrt_batch_scene(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("kappa_rho", C.c_void_p),
+                ("source", C.c_int), ("emit_order", C.c_int), ("src", C.c_double * 3), ("radius", C.c_double),
+                ("albedo", C.c_double), ("g", C.c_double), ("p_lin", C.c_double),
+                ("n_obs", C.c_int), ("theta", C.c_double * BATCH_MAX_OBSERVERS),
+                ("phi", C.c_double * BATCH_MAX_OBSERVERS), ("npix", C.c_int), ("half_width", C.c_double),
+                ("max_orders", C.c_int), ("tau_min", C.c_double),
+                ("first", C.c_uint64), ("count", C.c_uint64), ("n_total", C.c_uint64)]
 
 
 def _as_dict(st):
@@ -95,6 +108,10 @@ SIGNATURES = {
                                       C.POINTER(qrt_train_report)]),
     "qrt_surrogate_validate": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_double, C.c_int64,
                                          C.POINTER(qrt_mask_report)]),
+    "qrt_batch_set": (C.c_int, [_P, C.c_int, C.POINTER(qrt_batch_scene)]),
+    "qrt_batch_run": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_int]),
+    "qrt_batch_read_images": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, C.c_int]),
+    "qrt_batch_reset": (C.c_int, [_P]),
 }
 
 _lib: Optional[C.CDLL] = None
@@ -341,3 +358,55 @@ class Context:
                                                  C.c_void_p(tau.data_ptr()), max_err, floor_frac, min_count,
                                                  C.byref(rep)))
         return _as_dict(rep)
+
+    # -------- batches of scenes
+    def batch_set(self, scenes, firsts: Optional[Sequence[int]] = None, counts: Optional[Sequence[int]] = None,
+                  n_totals: Optional[Sequence[int]] = None):
+        """Set a batch from synth.Scene objects: scene i runs point indices
+        firsts[i] .. firsts[i]+counts[i]-1 (defaults: 1 and its n_packets);
+        Hammersley's N is n_totals[i] (default: its n_packets)."""
+        n = len(scenes)
+        arr = (qrt_batch_scene * n)()
+        keep = []
+        for i, sc in enumerate(scenes):
+            kr = np.ascontiguousarray(sc.kappa_rho, dtype=np.float32)
+            keep.append(kr)
+            d = arr[i]
+            d.nx, d.ny, d.nz = sc.n
+            d.lo = (C.c_double * 3)(*sc.lo)
+            d.hi = (C.c_double * 3)(*sc.hi)
+            d.kappa_rho = kr.ctypes.data
+            d.source = SOURCE_SPHERE if sc.source_kind == 1 else SOURCE_POINT
+            d.emit_order = getattr(sc, "emit_order", EMIT_DIRECT)
+            d.src = (C.c_double * 3)(*sc.source)
+            d.radius = sc.r_star
+            d.albedo, d.g, d.p_lin = sc.albedo, sc.g, sc.p_lin
+            d.n_obs = len(sc.observers)
+            if d.n_obs > BATCH_MAX_OBSERVERS:
+                raise ValueError(f"scene {i}: at most {BATCH_MAX_OBSERVERS} observers in a batch")
+            for o, (th, ph) in enumerate(sc.observers):
+                d.theta[o], d.phi[o] = th, ph
+            d.npix, d.half_width = sc.npix, sc.half_width
+            d.max_orders, d.tau_min = sc.max_orders, sc.tau_min
+            d.first = 1 if firsts is None else int(firsts[i])
+            d.count = sc.n_packets if counts is None else int(counts[i])
+            d.n_total = sc.n_packets if n_totals is None else int(n_totals[i])
+        self._ck(self.lib.qrt_batch_set(self.h, n, arr))
+        self.batch_shapes = [(len(sc.observers), sc.npix) for sc in scenes]
+
+    def batch_run(self, kind: int = SOBOL, seed: int = 0, precision: int = FP32):
+        self._ck(self.lib.qrt_batch_run(self.h, kind, seed, precision))
+
+    def batch_read_images(self, scene: int, normalized: bool = True) -> np.ndarray:
+        """[n_obs][3][npix][npix] float64 (I, Q, U) of one scene of the batch."""
+        if not 0 <= scene < len(getattr(self, "batch_shapes", [])):
+            self._ck(self.lib.qrt_batch_read_images(self.h, scene, 0, None, None, None, 0))   # the library refuses
+        n_obs, npix = self.batch_shapes[scene]
+        out = np.zeros((n_obs, 3, npix, npix), dtype=np.float64)
+        for o in range(n_obs):
+            self._ck(self.lib.qrt_batch_read_images(self.h, scene, o, out[o, 0].ctypes.data, out[o, 1].ctypes.data,
+                                                    out[o, 2].ctypes.data, int(normalized)))
+        return out
+
+    def batch_reset(self):
+        self._ck(self.lib.qrt_batch_reset(self.h))

@@ -173,6 +173,57 @@ def random_grid(shape: Tuple[int, int, int], seed: int, zero_frac: float = 0.2) 
     return g.astype(np.float32)
 
 
+def envelope_density(n: int, power: float = 2.0) -> np.ndarray:
+    """Spherical envelope rho ~ r^-power on 0.05 < r < 1."""
+    x, y, z = _mesh(n)
+    r = np.sqrt(x * x + y * y + z * z)
+    return np.where((r > 0.05) & (r < 1.0), 1.0 / np.maximum(r, 1e-30) ** power, 0.0)
+
+
+def uneven_batch(seed: int, n_scenes: int = 64, sizes: Tuple[int, int, int] = (32, 192, 16),
+                 log2_packets: Tuple[float, float] = (16.0, 24.0), npix: int = 128,
+                 orders: Tuple[int, int] = (1, 20), tau: Tuple[float, float] = (0.1, 20.0)) -> List[Scene]:
+    """A batch of uneven scenes drawn from `seed`, each independently:
+      grid n^3 with n uniform over sizes[0] .. sizes[1] in steps of sizes[2] (even n);
+      packets 2^u, u uniform in log2_packets;
+      geometry: spherical envelope (rho ~ r^-2) or flared disk (as disk128), 1:1;
+      optical depth along +x from the centre log-uniform in `tau`;
+      g uniform in [0, 0.8], albedo uniform in [0.3, 0.9], p_lin 0.5;
+      source: point source at the centre, or for an envelope with probability
+      1/2 a sphere star of radius 0.02 emitting in the direct or inverse order;
+      1 to 4 observers, inclination uniform in [0, 90] deg, azimuth uniform;
+      max_orders uniform over orders[0] .. orders[1]; npix^2 images over the box;
+      FP32 transport."""
+    rng = np.random.default_rng(seed)
+    cache = {}
+    out = []
+    lo_n, hi_n, step = sizes
+    choices = list(range(lo_n, hi_n + 1, step))
+    for i in range(n_scenes):
+        n = int(rng.choice(choices))
+        n_packets = int(2.0 ** rng.uniform(*log2_packets))
+        disk = bool(rng.integers(2))
+        t = float(math.exp(rng.uniform(math.log(tau[0]), math.log(tau[1]))))
+        g = float(rng.uniform(0.0, 0.8))
+        albedo = float(rng.uniform(0.3, 0.9))
+        star = (not disk) and bool(rng.integers(2))
+        emit_order = int(rng.integers(2)) if star else 0
+        n_obs = int(rng.integers(1, 5))
+        observers = [(float(math.radians(rng.uniform(0.0, 90.0))), float(rng.uniform(0.0, 2.0 * math.pi)))
+                     for _ in range(n_obs)]
+        max_orders = int(rng.integers(orders[0], orders[1] + 1))
+        key = (disk, n)
+        if key not in cache:
+            rho = disk_density(n) if disk else envelope_density(n)
+            cache[key] = (rho, _scale_to_x_ray(rho, 1.0))
+        kr = (cache[key][1] * t).astype(np.float32)
+        out.append(Scene(name=f"batch{seed}_{i}", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+                         source_kind=SPHERE_SOURCE if star else POINT_SOURCE, r_star=0.02 if star else 0.0,
+                         emit_order=emit_order, albedo=albedo, g=g, p_lin=0.5, observers=observers,
+                         npix=npix, half_width=1.0, max_orders=max_orders, fp64=False, n_packets=n_packets))
+    return out
+
+
 def scene_by_name(name: str, n_packets: Optional[int] = None) -> Scene:
     table = {"envelope32": envelope32, "disk128": disk128, "clumpy256": clumpy256}
     sc = table[name]()

@@ -46,3 +46,34 @@ def test_binding_refuses_a_missing_library(tmp_path):
             qrt.load(str(tmp_path / "absent.so"))
     finally:
         qrt._lib = saved
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct of the binding has the size and field offsets of the C
+    header (compiled with the host C compiler)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_2406_15632_amd import qrt
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"qrt_counters": qrt.qrt_counters, "qrt_train_cfg": qrt.qrt_train_cfg,
+               "qrt_train_report": qrt.qrt_train_report, "qrt_mask_report": qrt.qrt_mask_report,
+               "qrt_batch_scene": qrt.qrt_batch_scene}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qrt.h"', "int main(void) {"]
+    for name, st in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                           check=True).stdout.split("\n") if l)
+    for name, st in structs.items():
+        assert int(got[name]) == C.sizeof(st), name
+        for f, _ in st._fields_:
+            assert int(got[f"{name}.{f}"]) == getattr(st, f).offset, f"{name}.{f}"
