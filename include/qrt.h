@@ -343,8 +343,9 @@ typedef struct {
 } qrt_batch_scene;
 
 /* Set the scenes of the batch (1 <= n_scenes <= QRT_BATCH_MAX_SCENES): copies
-   every mesh to the device, allocates one FP64 image set per scene and
-   zeroes the batch images.  Replaces a previous batch.  Synchronous. */
+   every mesh to the device, allocates the FP64 images of every scene (eight
+   accumulators each, folded when read) and zeroes them.  Replaces a previous
+   batch.  Synchronous. */
 int qrt_batch_set(qrt_ctx *ctx, int n_scenes, const qrt_batch_scene *scenes);
 
 /* Transport every scene's packets once with point set `kind` and `seed` (as

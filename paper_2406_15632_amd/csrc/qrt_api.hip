@@ -84,10 +84,11 @@ struct qrt_ctx {
     uint8_t *dom_valid = nullptr;            // [QRT_MAX_OBSERVERS][nr][nz] on the device
     // batch of scenes
     std::vector<BScene> batch;               // scene records (device addresses inside)
+    std::vector<uint64_t> batch_begin;       // first batch number per scene
     BScene *batch_dev = nullptr;             // [kMaxBatchScenes]
     float *batch_grid = nullptr;             // all meshes, one after the other
     size_t batch_grid_alloc = 0;             // floats
-    double *batch_img = nullptr;             // all image sets, one after the other
+    double *batch_img = nullptr;             // all image sets (kImageCopies each), one after the other
     size_t batch_img_alloc = 0;              // doubles
     size_t batch_img_used = 0;
     uint64_t batch_total = 0;                // packets of one batch run
@@ -1299,7 +1300,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         const int rc = batch_scene_check(c, i, S);
         if (rc < 0) return rc;
         cells += (size_t)S.nx * S.ny * S.nz;
-        pixels += (size_t)S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
+        pixels += (size_t)kImageCopies * S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
         if (total + S.count < total) return fail(c, QRT_INVALID_ARG, "packet total overflows");
         total += S.count;
         max_orders = std::max(max_orders, S.max_orders);
@@ -1324,6 +1325,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         c->batch_img_alloc = pixels;
     }
     std::vector<BScene> host((size_t)n_scenes);
+    std::vector<uint64_t> begins((size_t)n_scenes);
     size_t grid_off = 0, img_off = 0;
     uint64_t begin = 0;
     for (int i = 0; i < n_scenes; ++i) {
@@ -1354,9 +1356,11 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         B.max_orders = S.max_orders;
         B.tau_min = S.tau_min;
         B.img = c->batch_img + img_off;
-        img_off += (size_t)S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
+        B.img_set = (uint64_t)S.n_obs * 3 * (uint64_t)S.npix * (uint64_t)S.npix;
+        img_off += (size_t)kImageCopies * B.img_set;
         B.first = S.first;
         B.begin = begin;
+        begins[(size_t)i] = begin;
         B.count = S.count;
         B.n_total = S.n_total;
         begin += S.count;
@@ -1366,6 +1370,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
     HIP_TRY(c, hipMemsetAsync(c->batch_img, 0, pixels * sizeof(double), c->stream), "batch image reset");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "batch set sync");
     c->batch.swap(host);
+    c->batch_begin.swap(begins);
     c->batch_img_used = pixels;
     c->batch_total = total;
     c->batch_max_orders = max_orders;
@@ -1396,11 +1401,12 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     memset(&P, 0, sizeof(P));
     P.scenes = c->batch_dev;
     P.n_scenes = (int)c->batch.size();
-    while ((1 << P.scene_bits) < P.n_scenes) P.scene_bits++;
     P.seq = seq_params(c, kind, seed, 0);
     P.max_orders = c->batch_max_orders;
     P.counters = c->counters;
-    HIP_TRY(c, launch_batch(P, precision, kind, c->batch_total, c->tb, c->tb_packets, c->stream), "batch launch");
+    HIP_TRY(c,
+            launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, c->tb_packets, c->stream),
+            "batch launch");
     return QRT_OK;
 }
 
@@ -1412,6 +1418,7 @@ int qrt_batch_read_images(qrt_ctx *c, int scene, int obs, double *I, double *Q, 
     if (obs < 0 || obs >= B.n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
     DeviceGuard dg(c->device);
     const size_t plane = (size_t)B.npix * B.npix;
+    HIP_TRY(c, launch_fold_images(B.img, (size_t)B.img_set, c->stream), "batch image fold");
     double *dst[3] = {I, Q, U};
     for (int s = 0; s < 3; ++s)
         if (dst[s])

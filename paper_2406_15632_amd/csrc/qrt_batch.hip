@@ -118,7 +118,8 @@ __global__ void __launch_bounds__(256) k_bkey(const BatchParams P, uint64_t b0, 
         const BScene &S = P.scenes[s];
         R p[3], k[3];
         batch_emit<R, KIND>(S, scene_seq(P, S), S.first + (b - S.begin), p, k);
-        const uint32_t key = ((uint32_t)s << (kSortBits - P.scene_bits)) | (direction_key(k) >> P.scene_bits);
+        const uint32_t key = ((uint32_t)(s - P.scene_base) << (kSortBits - P.scene_bits)) |
+                             (direction_key(k) >> P.scene_bits);
         keys[j] = key;
         atomicAdd(hist + key, 1u);
     }
@@ -203,10 +204,14 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
 }
 
 // ---------------------------------------------------------------- scattering
-// Albedo, peel-off contributions toward the scene's observers (slots of the
-// batch's fixed width kBatchObs; the observer field holds scene * 16 + obs)
-// and, unless it was the scene's last order, the new direction and flight.
-// A packet at its scene's last order gets target -1 and does not move.
+// Albedo, peel-off contributions toward the scene's observers and, unless it
+// was the scene's last order, the new direction and flight.  A packet at its
+// scene's last order gets target -1 and does not move.  Scenes have 1 to
+// kBatchObs observers, so instead of fixed slots the visible peel rays are
+// appended: each wave reserves room for all its rays with one atomic and lays
+// them out observer by observer, so a wave's rays toward one observer stay
+// contiguous and no slot is empty.  The observer field holds
+// scene * 16 + observer.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
                                                   const uint32_t *__restrict__ live_in, int in,
@@ -216,6 +221,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         Q->n_live[in ^ 1] = 0;
         Q->work[1] = 0;
     }
+    uint32_t *n_peel = &Q->n_peel[order & 1];   // cleared by the walk of the previous order
     const uint32_t n = Q->n_live[in];
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
@@ -240,6 +246,10 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         R n_ax[3];
         cross3(st.k, st.m, n_ax);
         const R Rw = (R)S.half_width;
+        bool visv[kBatchObs];
+        R cv[kBatchObs][3];
+        uint32_t pixv[kBatchObs];
+#pragma unroll
         for (int ob = 0; ob < kBatchObs; ++ob) {
             bool vis = false;
             R c3[3] = {(R)0, (R)0, (R)0};
@@ -287,12 +297,34 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
                     pix = (uint32_t)((int)fy * S.npix + (int)fx);
                 }
             }
-            PeelRay<R> r;
-            r.p[0] = st.p[0]; r.p[1] = st.p[1]; r.p[2] = st.p[2];
-            r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
-            r.pix = (valid && vis) ? pix : kNoPixel;
-            r.obs = ((uint32_t)s << 4) | (uint32_t)ob;
-            peels[peel_slot(i, ob, kBatchObs)] = r;
+            visv[ob] = valid && vis;
+            cv[ob][0] = c3[0]; cv[ob][1] = c3[1]; cv[ob][2] = c3[2];
+            pixv[ob] = pix;
+        }
+        // one reservation for the wave's rays toward all observers
+        uint64_t mv[kBatchObs];
+        uint32_t total = 0;
+#pragma unroll
+        for (int ob = 0; ob < kBatchObs; ++ob) {
+            mv[ob] = __ballot(visv[ob]);
+            total += (uint32_t)__popcll(mv[ob]);
+        }
+        uint32_t at = 0;
+        if (total) {
+            if (lane == 0) at = atomicAdd(n_peel, total);
+            at = __shfl(at, 0, 64);
+        }
+#pragma unroll
+        for (int ob = 0; ob < kBatchObs; ++ob) {
+            if (visv[ob]) {
+                PeelRay<R> r;
+                r.p[0] = st.p[0]; r.p[1] = st.p[1]; r.p[2] = st.p[2];
+                r.c[0] = cv[ob][0]; r.c[1] = cv[ob][1]; r.c[2] = cv[ob][2];
+                r.pix = pixv[ob];
+                r.obs = ((uint32_t)s << 4) | (uint32_t)ob;
+                peels[at + (uint32_t)__popcll(mv[ob] & lanes_below_mask())] = r;
+            }
+            at += (uint32_t)__popcll(mv[ob]);
         }
         if (valid) {
             if (order < S.max_orders) {
@@ -336,8 +368,9 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
                                                uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
                                                Queues *__restrict__ Q)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) Q->n_peel[(order + 1) & 1] = 0;   // for the next scatter
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_peel = (uint64_t)kBatchObs * 64 * ((n_live + 63) / 64);
+    const uint64_t n_peel = Q->n_peel[order & 1];
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     uint64_t n_visits = 0;
@@ -358,7 +391,8 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
             const BScene &S = P.scenes[s];
             const size_t plane = (size_t)S.npix * (size_t)S.npix;
             const double att = exp(-W.tau);
-            double *dst = S.img + (size_t)obs * 3 * plane + (size_t)pix;
+            // image copy of this block: blocks go round-robin to the XCDs
+            double *dst = S.img + (size_t)(blockIdx.x % kImageCopies) * S.img_set + (size_t)obs * 3 * plane + (size_t)pix;
             unsafeAtomicAdd(dst, att * (double)c3[0]);
             unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
             unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
@@ -382,17 +416,15 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
         if (pool.take(kind == BW_NONE, total, &Q->work[1], item)) {
             if (item < n_peel) {
                 const PeelRay<R> r = peels[item];
-                if (r.pix != kNoPixel) {
-                    s = (int)(r.obs >> 4);
-                    obs = (int)(r.obs & 15u);
-                    const BScene &S = P.scenes[s];
-                    const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
-                    c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
-                    pix = r.pix;
-                    G = lane_grid<R>(S);
-                    walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
-                    kind = BW_PEEL;
-                }
+                s = (int)(r.obs >> 4);
+                obs = (int)(r.obs & 15u);
+                const BScene &S = P.scenes[s];
+                const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
+                c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                pix = r.pix;
+                G = lane_grid<R>(S);
+                walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                kind = BW_PEEL;
             } else {
                 slot = live_in[item - n_peel];
                 const PacketState<R> *ps = pks + slot;
@@ -438,6 +470,7 @@ template <typename R, int KIND>
 static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count, const TransportBuffers &B,
                               hipStream_t st)
 {
+    // P.scene_base and P.scene_bits are set per chunk by launch_batch
     static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
     if (!nb_first) {
         nb_first = batch_resident_blocks(k_bfirst<R, KIND>);
@@ -485,11 +518,29 @@ static hipError_t batch_kind(const BatchParams &P, int kind, uint64_t b0, uint32
     }
 }
 
-hipError_t launch_batch(const BatchParams &P, int precision, int kind, uint64_t total, const TransportBuffers &B,
-                        uint64_t chunk, hipStream_t stream)
+// last scene whose first batch number is <= b (host copy of the search in batch_scene)
+static int host_scene_of(const uint64_t *begin, int n_scenes, uint64_t b)
+{
+    int lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precision, int kind, uint64_t total,
+                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream)
 {
     for (uint64_t done = 0; done < total;) {
         const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
+        // the sort key spends only the bits that the chunk's scenes need on the scene
+        BatchParams P = P0;
+        P.scene_base = host_scene_of(begin, P.n_scenes, done);
+        const int span = host_scene_of(begin, P.n_scenes, done + n - 1) - P.scene_base + 1;
+        P.scene_bits = 0;
+        while ((1 << P.scene_bits) < span) P.scene_bits++;
         hipError_t e = precision == 1 ? batch_kind<double>(P, kind, done, n, B, stream)
                                       : batch_kind<float>(P, kind, done, n, B, stream);
         if (e != hipSuccess) return e;

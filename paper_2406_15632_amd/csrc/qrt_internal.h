@@ -123,6 +123,7 @@ struct alignas(16) PeelRay {
 struct Queues {
     uint32_t n_live[2];   // live packets per ping-pong list
     unsigned long long work[4];   // work counters of the persistent kernels
+    uint32_t n_peel[2];   // appended peel rays per order parity (batched launches)
 };
 
 constexpr int kSortBits = 16;                 // bins of the coherence sorts: 2^kSortBits
@@ -161,22 +162,25 @@ struct BScene {
     DevObserver obs[kBatchObs];
     int max_orders;
     double tau_min;
-    double *img;                // [n_obs][3][npix][npix]
+    double *img;                // [kImageCopies][n_obs][3][npix][npix]
+    uint64_t img_set;           // doubles of one copy: n_obs * 3 * npix^2
     uint64_t first, begin, count, n_total;
 };
 
 struct BatchParams {
     const BScene *scenes;       // device array [n_scenes], ordered by begin
     int n_scenes;
-    int scene_bits;             // sort-key bits that hold the scene (the rest: emission direction)
+    int scene_base;             // first scene of the chunk being launched
+    int scene_bits;             // sort-key bits that hold scene - scene_base (the rest: emission direction)
     SeqParams seq;              // n_total is replaced by each scene's own
     int max_orders;             // largest over the scenes
     unsigned long long *counters;
 };
 
-// All `total` batch numbers of a batch, in chunks of at most `chunk`.
-hipError_t launch_batch(const BatchParams &P, int precision, int kind, uint64_t total, const TransportBuffers &B,
-                        uint64_t chunk, hipStream_t stream);
+// All `total` batch numbers of a batch, in chunks of at most `chunk`; begin[s]
+// (host) is the first batch number of scene s.
+hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precision, int kind, uint64_t total,
+                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream);
 
 // counting-sort steps shared by the transport launch sequences
 hipError_t launch_scan_bins(uint32_t *hist, hipStream_t st);
