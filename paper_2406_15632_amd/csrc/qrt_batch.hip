@@ -130,8 +130,9 @@ enum BatchFirstPhase : int { BF_IDLE = 0, BF_EDGE = 1, BF_FORCED = 2 };
 
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0, uint32_t count,
-                                                const uint32_t *__restrict__ order, PacketState<R> *__restrict__ pks,
-                                                uint32_t *__restrict__ live0, Queues *__restrict__ Q)
+                                                const uint32_t *__restrict__ order, const uint32_t *__restrict__ keys,
+                                                PacketState<R> *__restrict__ pks, uint32_t *__restrict__ live0,
+                                                Queues *__restrict__ Q)
 {
     uint64_t n_visits = 0;
     uint32_t n_packets = 0, n_cuts = 0;
@@ -184,7 +185,8 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
         uint64_t item = 0;
         if (pool.take(phase == BF_IDLE, count, &Q->work[0], item)) {
             j = order[item];
-            s = batch_scene(P, b0 + j);
+            // the sort key holds the scene relative to the chunk's first
+            s = P.scene_base + (int)(keys[j] >> (kSortBits - P.scene_bits));
             const BScene &S = P.scenes[s];
             n_packets++;
             batch_emit<R, KIND>(S, scene_seq(P, S), S.first + (b0 + j - S.begin), p, k);
@@ -210,8 +212,11 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
 // kBatchObs observers, so instead of fixed slots the visible peel rays are
 // appended: each wave reserves room for all its rays with one atomic and lays
 // them out observer by observer, so a wave's rays toward one observer stay
-// contiguous and no slot is empty.  The observer field holds
-// scene * 16 + observer.
+// contiguous and no slot is empty.  The 64-packet block b of the live list
+// appends to group b % kPeelGroups, which has its own counter and region:
+// a group receives at most ceil(blocks / kPeelGroups) blocks of at most
+// 64 kBatchObs rays, which the host sizes group_cap for.  The observer field
+// holds scene * 16 + observer.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
                                                   const uint32_t *__restrict__ live_in, int in,
@@ -221,7 +226,6 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         Q->n_live[in ^ 1] = 0;
         Q->work[1] = 0;
     }
-    uint32_t *n_peel = &Q->n_peel[order & 1];   // cleared by the walk of the previous order
     const uint32_t n = Q->n_live[in];
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
@@ -309,11 +313,14 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
             mv[ob] = __ballot(visv[ob]);
             total += (uint32_t)__popcll(mv[ob]);
         }
+        const uint32_t group = (base >> 6) % kPeelGroups;
         uint32_t at = 0;
         if (total) {
-            if (lane == 0) at = atomicAdd(n_peel, total);
+            // counters cleared by the walk of the previous order (or with the queues)
+            if (lane == 0) at = atomicAdd(&Q->n_peel[order & 1][group][0], total);
             at = __shfl(at, 0, 64);
         }
+        at += group * P.group_cap;
 #pragma unroll
         for (int ob = 0; ob < kBatchObs; ++ob) {
             if (visv[ob]) {
@@ -368,9 +375,16 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
                                                uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
                                                Queues *__restrict__ Q)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) Q->n_peel[(order + 1) & 1] = 0;   // for the next scatter
+    if (blockIdx.x == 0 && threadIdx.x < kPeelGroups) Q->n_peel[(order + 1) & 1][threadIdx.x][0] = 0;   // next scatter
+    // peel rays of the groups, numbered one group after the other
+    uint32_t g_count[kPeelGroups];
+    uint64_t n_peel = 0;
+#pragma unroll
+    for (int g = 0; g < kPeelGroups; ++g) {
+        g_count[g] = Q->n_peel[order & 1][g][0];
+        n_peel += g_count[g];
+    }
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_peel = Q->n_peel[order & 1];
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     uint64_t n_visits = 0;
@@ -415,7 +429,15 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
         uint64_t item = 0;
         if (pool.take(kind == BW_NONE, total, &Q->work[1], item)) {
             if (item < n_peel) {
-                const PeelRay<R> r = peels[item];
+                uint64_t at = item;
+                int g = 0;
+#pragma unroll
+                for (int q = 0; q < kPeelGroups - 1; ++q) {
+                    const bool past = g == q && at >= g_count[q];
+                    at -= past ? g_count[q] : 0;
+                    g += past ? 1 : 0;
+                }
+                const PeelRay<R> r = peels[(uint64_t)g * P.group_cap + at];
                 s = (int)(r.obs >> 4);
                 obs = (int)(r.obs & 15u);
                 const BScene &S = P.scenes[s];
@@ -488,8 +510,8 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     if ((e = launch_scan_bins(B.hist, st)) != hipSuccess) return e;
     if ((e = launch_place(B.keys, count, B.hist, B.order, b_elem, st)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
-    hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order, pks,
-                       B.live[0], B.q);
+    hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order,
+                       (const uint32_t *)B.keys, pks, B.live[0], B.q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     for (int order = 1; order <= P.max_orders; ++order) {
@@ -537,6 +559,8 @@ hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precis
         const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
         // the sort key spends only the bits that the chunk's scenes need on the scene
         BatchParams P = P0;
+        // group g of the peel rays: at most ceil(chunk / 64 / kPeelGroups) blocks of 64 kBatchObs rays
+        P.group_cap = (uint32_t)(((chunk / 64 + kPeelGroups - 1) / kPeelGroups) * 64 * kBatchObs);
         P.scene_base = host_scene_of(begin, P.n_scenes, done);
         const int span = host_scene_of(begin, P.n_scenes, done + n - 1) - P.scene_base + 1;
         P.scene_bits = 0;

@@ -120,10 +120,14 @@ struct alignas(16) PeelRay {
 };
 
 // Device-side queue counters of one chunk.
+constexpr int kPeelGroups = 8;     // peel-ray append counters of the batched launches
+
 struct Queues {
     uint32_t n_live[2];   // live packets per ping-pong list
     unsigned long long work[4];   // work counters of the persistent kernels
-    uint32_t n_peel[2];   // appended peel rays per order parity (batched launches)
+    // appended peel rays per order parity and group (batched launches), one
+    // counter per 128-byte line so that the groups' atomics do not share one
+    uint32_t n_peel[2][kPeelGroups][32];
 };
 
 constexpr int kSortBits = 16;                 // bins of the coherence sorts: 2^kSortBits
@@ -174,6 +178,7 @@ struct BatchParams {
     int scene_bits;             // sort-key bits that hold scene - scene_base (the rest: emission direction)
     SeqParams seq;              // n_total is replaced by each scene's own
     int max_orders;             // largest over the scenes
+    uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap)
     unsigned long long *counters;
 };
 
