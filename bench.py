@@ -76,6 +76,8 @@ def transport_source_hash() -> str:
         if f.endswith((".hip", ".h", ".cpp")):
             h.update(f.encode())
             h.update(open(os.path.join(csrc, f), "rb").read())
+    # the compiler flags are part of the kernels too
+    h.update(open(os.path.join(ROOT, "paper_2406_15632_amd", "build.py"), "rb").read())
     return h.hexdigest()[:16]
 
 

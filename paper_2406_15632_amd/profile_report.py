@@ -11,7 +11,17 @@
     python -m paper_2406_15632_amd.profile_report traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR
         COPY_WRITE_DIR COPY_MIB LAUNCHES OUT.txt "COMMANDS"
         HBM bytes per transport launch from FETCH_SIZE and WRITE_SIZE, each
-        scaled by the factor the same counter shows for the copy probe.
+        scaled by the factor the same counter shows for the copy probe;
+
+    python -m paper_2406_15632_amd.profile_report counters OUT.md "COMMANDS" DIR...
+        L2 hit rate, VALU busy, VALU lane utilization and the share of wave
+        time spent waiting, per transport kernel, from --pmc runs of
+        TCC_HIT_sum TCC_MISS_sum and of SQ_ACTIVE_INST_VALU
+        SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_ANY SQ_WAVE_CYCLES GRBM_GUI_ACTIVE;
+
+    python -m paper_2406_15632_amd.profile_report trace-batch DIR RUNS OUT.md "COMMAND"
+        per-kernel durations of the batched kernels (k_b*, sort steps of the
+        batch) per batch run.
 """
 from __future__ import annotations
 
@@ -46,22 +56,57 @@ def copy_probe(mib: int = 1024):
     print(f"copied {mib} MiB")
 
 
-def trace_summary(d: str, launches: int, out: str, command: str):
+def _batch_kernel(name: str) -> bool:
+    return "qrt::k_b" in name
+
+
+def trace_summary(d: str, launches: int, out: str, command: str, select=_transport,
+                  title: str = "transport kernels", unit: str = "transport launch (qrt_run calls)"):
     db = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)[0]
     c = sqlite3.connect(db)
     rows = list(c.execute("select name, total_calls, total_duration, average from top_kernels"))
-    lines = [f"# rocprofv3 kernel trace: transport kernels", "", "Command:", "", "```", command, "```", "",
-             f"Transport launches (qrt_run calls) in the run: {launches}", "",
-             "| kernel | calls | total ms | avg us | ms per transport launch |", "|---|---|---|---|---|"]
+    lines = [f"# rocprofv3 kernel trace: {title}", "", "Command:", "", "```", command, "```", "",
+             f"Units of work ({unit}) in the run: {launches}", "",
+             "| kernel | calls | total ms | avg us | ms per unit |", "|---|---|---|---|---|"]
     per_launch = 0.0
     for name, calls, total, avg in rows:   # the view reports microseconds
-        if not _transport(name):
+        if not select(name):
             continue
         short = name.split("(")[0].replace("void ", "")
         per = total / 1e3 / launches
         per_launch += per
         lines.append(f"| `{short}` | {calls} | {total / 1e3:.3f} | {avg:.2f} | {per:.3f} |")
-    lines += ["", f"Sum of transport kernel time per launch: {per_launch:.3f} ms", ""]
+    lines += ["", f"Sum of kernel time per unit: {per_launch:.3f} ms", ""]
+    open(out, "w").write("\n".join(lines))
+    print("\n".join(lines))
+
+
+def counters(out: str, commands: str, *dirs):
+    """Per transport kernel: L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS); VALU
+    busy 100 SQ_ACTIVE_INST_VALU / (CUs GRBM_GUI_ACTIVE), summed over the
+    kernel's dispatches (the rocprofv3 VALUBusy definition); VALU lane
+    utilization 100 SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU); the share
+    of wave cycles spent waiting on an instruction's inputs,
+    SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES."""
+    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    for d in dirs:
+        for k, v in _pmc_totals(d).items():
+            for n, x in v.items():
+                tot[k][n] += x
+    cus = 256
+    lines = ["# rocprofv3 counters of the transport kernels (disk128)", "", "Commands:", "", "```", commands, "```",
+             "", "| kernel | L2 hit % | VALU busy % | VALU lanes active % | wave cycles waiting % |",
+             "|---|---|---|---|---|"]
+    for k in sorted(tot):
+        if not _transport(k):
+            continue
+        v = tot[k]
+        hit = v["TCC_HIT_sum"] / max(1.0, v["TCC_HIT_sum"] + v["TCC_MISS_sum"]) * 100
+        busy = 100 * v["SQ_ACTIVE_INST_VALU"] / cus / max(1.0, v["GRBM_GUI_ACTIVE"])
+        lanes = 100 * v["SQ_THREAD_CYCLES_VALU"] / max(1.0, 64 * v["SQ_ACTIVE_INST_VALU"])
+        wait = 100 * v["SQ_WAIT_INST_ANY"] / max(1.0, v["SQ_WAVE_CYCLES"])
+        lines.append(f"| `{k.replace('void ', '')}` | {hit:.1f} | {busy:.1f} | {lanes:.1f} | {wait:.1f} |")
+    lines.append("")
     open(out, "w").write("\n".join(lines))
     print("\n".join(lines))
 
@@ -126,3 +171,8 @@ if __name__ == "__main__":
         trace_summary(sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5])
     elif cmd == "traffic":
         traffic(*sys.argv[2:6], float(sys.argv[6]), int(sys.argv[7]), sys.argv[8], sys.argv[9])
+    elif cmd == "counters":
+        counters(sys.argv[2], sys.argv[3], *sys.argv[4:])
+    elif cmd == "trace-batch":
+        trace_summary(sys.argv[2], int(sys.argv[3]), sys.argv[4], sys.argv[5], select=_batch_kernel,
+                      title="batched transport kernels (64 uneven scenes)", unit="batch runs (qrt_batch_run calls)")
