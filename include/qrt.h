@@ -18,7 +18,7 @@
  *  - No C++ exception crosses this interface.
  *  - Host pointers are owned by the caller and only read or written during
  *    the call.  Device pointers are HIP device addresses on the context's
- *    device; a borrowed device grid must outlive every run that uses it.
+ *    device.
  *  - All GPU work goes to the context's HIP stream, in order.  Calls that
  *    return host data synchronise that stream; the others only enqueue work.
  *  - One context per host thread; a context is not thread safe.
@@ -58,8 +58,8 @@ extern "C" {
 
 /* grid ownership flags for qrt_set_grid */
 #define QRT_GRID_HOST_COPY 0      /* kappa_rho is a host pointer; copied */
-#define QRT_GRID_DEVICE_COPY 1    /* kappa_rho is a device pointer; copied */
-#define QRT_GRID_DEVICE_BORROW 2  /* kappa_rho is a device pointer; used in place */
+#define QRT_GRID_DEVICE_COPY 1    /* kappa_rho is a device pointer; copied on the device */
+#define QRT_GRID_DEVICE_BORROW 2  /* as QRT_GRID_DEVICE_COPY (the library keeps the mesh in its own cell order) */
 
 /* arithmetic of the transport */
 #define QRT_FP32 0                /* FP32 positions/directions/weights, FP64 optical depth and image sums */
@@ -107,7 +107,10 @@ int qrt_set_stream(qrt_ctx *ctx, void *hip_stream);
 
 /* Density mesh (Sec. 2.1, 3.4): nx*ny*nz cells over the box [lo, hi]; each cell
    holds the constant extinction kappa*rho (FP32), laid out [nz][ny][nx] with x
-   fastest.  flags is one of QRT_GRID_*.  Cells must be finite and >= 0. */
+   fastest.  flags is one of QRT_GRID_*.  Cells must be finite and >= 0 (checked
+   for host input).  The library copies the mesh into its own order (bricks of
+   4x4x4 cells, at most 2^29 cells after rounding each axis up to a multiple
+   of 4); the caller's buffer is not used after the call returns. */
 int qrt_set_grid(qrt_ctx *ctx, int nx, int ny, int nz, const double lo[3], const double hi[3],
                  const float *kappa_rho, int flags);
 

@@ -28,12 +28,12 @@ struct qrt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
-    // mesh
+    // mesh (the library's bricked copy)
     bool has_grid = false;
     int n[3] = {0, 0, 0};
     double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float *grid = nullptr;
-    bool grid_owned = false;
+    size_t grid_alloc = 0;                   // floats
     // source
     bool has_source = false;
     int src_kind = 0;
@@ -329,7 +329,7 @@ void qrt_destroy(qrt_ctx *c)
     DeviceGuard dg(c->device);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
-    if (c->grid_owned && c->grid) (void)hipFree(c->grid);
+    if (c->grid) (void)hipFree(c->grid);
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
     if (c->faure) (void)hipFree(c->faure);
@@ -372,7 +372,8 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
     if (!c) return QRT_INVALID_ARG;
     if (nx < 1 || ny < 1 || nz < 1 || !lo || !hi || !kappa_rho)
         return fail(c, QRT_INVALID_ARG, "bad grid arguments");
-    if ((int64_t)nx * ny * nz > (int64_t)1 << 31) return fail(c, QRT_UNSUPPORTED, "grid too large");
+    const int64_t bricked = (int64_t)bricks_of(nx) * bricks_of(ny) * bricks_of(nz) * (kBrick * kBrick * kBrick);
+    if (bricked > (int64_t)1 << 29) return fail(c, QRT_UNSUPPORTED, "grid too large (at most 2^29 cells)");
     for (int a = 0; a < 3; ++a)
         if (!(hi[a] > lo[a]) || !isfinite(lo[a]) || !isfinite(hi[a]))
             return fail(c, QRT_INVALID_ARG, "box must satisfy lo < hi on every axis");
@@ -384,23 +385,27 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
             if (!(kappa_rho[i] >= 0.0f) || !isfinite(kappa_rho[i]))
                 return fail(c, QRT_INVALID_ARG, "cell %zu is negative or not finite", i);
     DeviceGuard dg(c->device);
-    if (c->grid_owned && c->grid) {
-        HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
-        (void)hipFree(c->grid);
-    }
-    c->grid = nullptr;
-    c->grid_owned = false;
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
     c->has_grid = false;
-    if (flags == QRT_GRID_DEVICE_BORROW) {
-        c->grid = const_cast<float *>(kappa_rho);
-    } else {
-        HIP_TRY(c, hipMalloc(&c->grid, cells * sizeof(float)), "grid allocation");
-        c->grid_owned = true;
-        HIP_TRY(c,
-                hipMemcpyAsync(c->grid, kappa_rho, cells * sizeof(float),
-                               flags == QRT_GRID_HOST_COPY ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
-                               c->stream),
+    if (c->grid_alloc < (size_t)bricked) {
+        if (c->grid) (void)hipFree(c->grid);
+        c->grid = nullptr;
+        c->grid_alloc = 0;
+        HIP_TRY(c, hipMalloc(&c->grid, (size_t)bricked * sizeof(float)), "grid allocation");
+        c->grid_alloc = (size_t)bricked;
+    }
+    const int nbx = bricks_of(nx), nby = bricks_of(ny);
+    if (flags == QRT_GRID_HOST_COPY) {
+        std::vector<float> b((size_t)bricked, 0.0f);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    b[(size_t)brick_index(x, y, z, nbx, nby)] = kappa_rho[((size_t)z * ny + y) * nx + x];
+        HIP_TRY(c, hipMemcpy(c->grid, b.data(), (size_t)bricked * sizeof(float), hipMemcpyHostToDevice),
                 "grid copy");
+    } else {
+        HIP_TRY(c, hipMemsetAsync(c->grid, 0, (size_t)bricked * sizeof(float), c->stream), "grid clear");
+        HIP_TRY(c, launch_to_bricks(kappa_rho, c->grid, nx, ny, nz, c->stream), "grid layout");
         HIP_TRY(c, hipStreamSynchronize(c->stream), "grid copy sync");
     }
     c->n[0] = nx; c->n[1] = ny; c->n[2] = nz;
@@ -523,6 +528,7 @@ static DevGrid dev_grid(const qrt_ctx *c)
     DevGrid g;
     g.kr = c->grid;
     g.nx = c->n[0]; g.ny = c->n[1]; g.nz = c->n[2];
+    for (int a = 0; a < 3; ++a) g.nb[a] = bricks_of(c->n[a]);
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = c->lo[a];
         g.hi[a] = c->hi[a];
@@ -1247,7 +1253,8 @@ static int batch_scene_check(qrt_ctx *c, int i, const qrt_batch_scene &S)
 {
     if (S.nx < 1 || S.ny < 1 || S.nz < 1 || !S.kappa_rho)
         return fail(c, QRT_INVALID_ARG, "scene %d: bad grid arguments", i);
-    if ((int64_t)S.nx * S.ny * S.nz > (int64_t)1 << 31) return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large", i);
+    if ((int64_t)bricks_of(S.nx) * bricks_of(S.ny) * bricks_of(S.nz) * (kBrick * kBrick * kBrick) > (int64_t)1 << 29)
+        return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large (at most 2^29 cells)", i);
     for (int a = 0; a < 3; ++a)
         if (!(S.hi[a] > S.lo[a]) || !isfinite(S.lo[a]) || !isfinite(S.hi[a]))
             return fail(c, QRT_INVALID_ARG, "scene %d: box must satisfy lo < hi on every axis", i);
@@ -1299,7 +1306,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         const qrt_batch_scene &S = scenes[i];
         const int rc = batch_scene_check(c, i, S);
         if (rc < 0) return rc;
-        cells += (size_t)S.nx * S.ny * S.nz;
+        cells += (size_t)bricks_of(S.nx) * bricks_of(S.ny) * bricks_of(S.nz) * (kBrick * kBrick * kBrick);
         pixels += (size_t)kImageCopies * S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
         if (total + S.count < total) return fail(c, QRT_INVALID_ARG, "packet total overflows");
         total += S.count;
@@ -1332,13 +1339,19 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         const qrt_batch_scene &S = scenes[i];
         BScene &B = host[(size_t)i];
         memset(&B, 0, sizeof(B));
-        const size_t nc = (size_t)S.nx * S.ny * S.nz;
-        HIP_TRY(c, hipMemcpyAsync(c->batch_grid + grid_off, S.kappa_rho, nc * sizeof(float), hipMemcpyHostToDevice,
-                                  c->stream),
+        B.n[0] = S.nx; B.n[1] = S.ny; B.n[2] = S.nz;
+        for (int a = 0; a < 3; ++a) B.nb[a] = bricks_of(B.n[a]);
+        const size_t nc = (size_t)B.nb[0] * B.nb[1] * B.nb[2] * (kBrick * kBrick * kBrick);
+        std::vector<float> bricked(nc, 0.0f);
+        for (int z = 0; z < S.nz; ++z)
+            for (int y = 0; y < S.ny; ++y)
+                for (int x = 0; x < S.nx; ++x)
+                    bricked[(size_t)brick_index(x, y, z, B.nb[0], B.nb[1])] =
+                        S.kappa_rho[((size_t)z * S.ny + y) * S.nx + x];
+        HIP_TRY(c, hipMemcpy(c->batch_grid + grid_off, bricked.data(), nc * sizeof(float), hipMemcpyHostToDevice),
                 "batch mesh copy");
         B.kr = c->batch_grid + grid_off;
         grid_off += nc;
-        B.n[0] = S.nx; B.n[1] = S.ny; B.n[2] = S.nz;
         for (int a = 0; a < 3; ++a) {
             B.lo[a] = S.lo[a];
             B.h[a] = (S.hi[a] - S.lo[a]) / (double)B.n[a];

@@ -39,6 +39,8 @@ __device__ __forceinline__ LaneGrid<R> lane_grid(const BScene &S)
 {
     LaneGrid<R> G;
     G.kr = S.kr;
+    G.nbx = S.nb[0];
+    G.nby = S.nb[1];
     for (int a = 0; a < 3; ++a) {
         G.n[a] = S.n[a];
         G.lo[a] = (R)S.lo[a];

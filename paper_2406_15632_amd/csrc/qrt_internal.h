@@ -155,8 +155,9 @@ constexpr int kMaxBatchScenes = 1024;
 // packet range.  Its packets are the batch numbers begin .. begin+count-1 and
 // use point indices first .. first+count-1 of the scene's sequence.
 struct BScene {
-    const float *kr;            // [n2][n1][n0], x fastest
+    const float *kr;            // bricked as the single-scene mesh
     int n[3];
+    int nb[3];                  // bricks per axis
     double lo[3], h[3];
     int src_kind;               // 0 point, 1 sphere star (direct order), 2 sphere star (inverse order)
     double src[3], r_star;
@@ -197,6 +198,9 @@ hipError_t launch_place(const uint32_t *keys, uint32_t count, uint32_t *hist, ui
 // kernel.  All launches go to stream.
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first,
                             uint64_t count, const TransportBuffers &B, hipStream_t stream);
+
+// the x-fastest mesh src[nz][ny][nx] into the bricked order of dst (cleared beforehand)
+hipError_t launch_to_bricks(const float *src, float *dst, int nx, int ny, int nz, hipStream_t stream);
 
 // img[0 .. n) += img[c n .. (c+1) n) for every further copy c, which is cleared
 hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream);

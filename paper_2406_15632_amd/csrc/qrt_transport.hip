@@ -786,6 +786,33 @@ hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- mesh layout
+// x-fastest cells [nz][ny][nx] into 4x4x4 bricks (the destination is cleared
+// beforehand: cells past the mesh edge stay 0)
+__global__ void __launch_bounds__(256) k_to_bricks(const float *__restrict__ src, float *__restrict__ dst, int nx,
+                                                   int ny, int nz, int nbx, int nby)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(i % (size_t)nx);
+        const size_t r = i / (size_t)nx;
+        const int y = (int)(r % (size_t)ny);
+        const int z = (int)(r / (size_t)ny);
+        dst[brick_index(x, y, z, nbx, nby)] = src[i];
+    }
+}
+
+hipError_t launch_to_bricks(const float *src, float *dst, int nx, int ny, int nz, hipStream_t stream)
+{
+    const size_t n = (size_t)nx * ny * nz;
+    if (n == 0) return hipSuccess;
+    const size_t need = (n + 255) / 256;
+    const int blocks = (int)(need < 8192 ? need : 8192);
+    hipLaunchKernelGGL(k_to_bricks, dim3(blocks), dim3(256), 0, stream, src, dst, nx, ny, nz, bricks_of(nx),
+                       bricks_of(ny));
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- optical depth of given rays
 template <typename R>
 __global__ void __launch_bounds__(256) k_trace_tau(const DevGrid g, int64_t n, const double *__restrict__ p,

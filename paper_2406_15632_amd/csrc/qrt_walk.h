@@ -21,6 +21,12 @@
 //    stop test of a move done per step.
 // Loads go through a buffer resource whose range is the mesh, so an address
 // outside the mesh could only read zero.
+//
+// Cell order in memory: every mesh is stored in bricks of 4x4x4
+// cells (bricks x fastest, then y, then z; inside a brick x fastest), so that
+// one 128-byte line holds a 4x4x2 block and a ray crossing a brick stays on
+// few lines whatever its direction.  The walk keeps the cell's coordinates
+// and asks the grid type for the element index.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,9 +34,21 @@
 
 namespace qrt {
 
+constexpr int kBrick = 4;   // cells per brick edge
+
+__host__ __device__ inline int bricks_of(int n) { return (n + kBrick - 1) / kBrick; }
+
+// element index of cell (x, y, z) in the bricked order; nbx, nby bricks along x, y
+__host__ __device__ inline int brick_index(int x, int y, int z, int nbx, int nby)
+{
+    const int brick = ((z >> 2) * nby + (y >> 2)) * nbx + (x >> 2);
+    return (brick << 6) | ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
+}
+
 struct DevGrid {
-    const float *kr;      // [nz][ny][nx], x fastest
+    const float *kr;      // bricked: [nbz][nby][nbx][4][4][4], cells outside the mesh 0
     int nx, ny, nz;
+    int nb[3];            // bricks per axis
     double lo[3], hi[3], h[3];
 };
 
@@ -38,6 +56,7 @@ template <typename R>
 struct RayGrid {
     __amdgpu_buffer_rsrc_t rsrc;
     int n[3];
+    int nbx, nby;
     R lo[3], h[3];
 };
 
@@ -45,9 +64,11 @@ template <typename R>
 __device__ __forceinline__ RayGrid<R> ray_grid(const DevGrid &g)
 {
     RayGrid<R> r;
-    const int bytes = g.nx * g.ny * g.nz * 4;
+    const int bytes = g.nb[0] * g.nb[1] * g.nb[2] * (kBrick * kBrick * kBrick * 4);
     r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.kr, (short)0, bytes, 0x00020000);
     r.n[0] = g.nx; r.n[1] = g.ny; r.n[2] = g.nz;
+    r.nbx = g.nb[0];
+    r.nby = g.nb[1];
     for (int a = 0; a < 3; ++a) { r.lo[a] = (R)g.lo[a]; r.h[a] = (R)g.h[a]; }
     return r;
 }
@@ -59,6 +80,7 @@ template <typename R>
 struct LaneGrid {
     const float *kr;
     int n[3];
+    int nbx, nby;
     R lo[3], h[3];
 };
 
@@ -67,9 +89,21 @@ template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_h
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
 
 template <typename R>
+__device__ __forceinline__ int cell_index(const RayGrid<R> &G, int x, int y, int z)
+{
+    return brick_index(x, y, z, G.nbx, G.nby);
+}
+
+template <typename R>
 __device__ __forceinline__ R load_kr(const RayGrid<R> &G, int cell)
 {
     return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, cell * 4, 0, 0));
+}
+
+template <typename R>
+__device__ __forceinline__ int cell_index(const LaneGrid<R> &G, int x, int y, int z)
+{
+    return brick_index(x, y, z, G.nbx, G.nby);
 }
 
 template <typename R>
@@ -88,7 +122,8 @@ struct Walk {
     R jx, jy, jz;                  // faces crossed per axis
     R tx, ty, tz;                  // next face distance per axis
     R t, t_exit;
-    int cell, dx, dy, dz;          // linear cell index and its step per axis
+    int cx, cy, cz;                // cell coordinates
+    int sx, sy, sz;                // step per axis: -1, 0 or +1
     double tau, target;
     int mode;
     bool done, stopped;
@@ -97,19 +132,18 @@ struct Walk {
 };
 
 template <typename R, typename GT>
-__device__ __forceinline__ void axis_setup(const GT &G, int a, R p, R d, int stride, int &c, R &T0, R &D,
-                                           R &tb, int &dc)
+__device__ __forceinline__ void axis_setup(const GT &G, int a, R p, R d, int &c, R &T0, R &D, R &tb, int &sgn)
 {
     R f = floor((p - G.lo[a]) / G.h[a]);
     f = f < (R)0 ? (R)0 : f;
     f = f > (R)(G.n[a] - 1) ? (R)(G.n[a] - 1) : f;
     c = (int)f;
     const int s = d > (R)1e-30 ? 1 : (d < (R)-1e-30 ? -1 : 0);
+    sgn = s;
     if (s == 0) {
         T0 = r_inf<R>();
         D = (R)0;
         tb = r_inf<R>();
-        dc = 0;
     } else {
         const R inv = (R)1 / d;
         const R face0 = G.lo[a] + (R)(c + (s > 0 ? 1 : 0)) * G.h[a];
@@ -117,7 +151,6 @@ __device__ __forceinline__ void axis_setup(const GT &G, int a, R p, R d, int str
         D = G.h[a] * fabs(inv);
         const int J = s > 0 ? G.n[a] - 1 - c : c;
         tb = fma((R)J, D, T0);
-        dc = s * stride;
     }
 }
 
@@ -139,22 +172,20 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
                     isfinite(d[2]) && (fabs(d[0]) > (R)1e-30 || fabs(d[1]) > (R)1e-30 || fabs(d[2]) > (R)1e-30);
     if (!ok) {
         W.done = true;
-        W.cell = 0;
-        W.dx = W.dy = W.dz = 0;
+        W.cx = W.cy = W.cz = 0;
+        W.sx = W.sy = W.sz = 0;
         W.t_exit = (R)0;
         W.T0x = W.T0y = W.T0z = W.tx = W.ty = W.tz = r_inf<R>();
         W.Dx = W.Dy = W.Dz = (R)0;
         return false;
     }
     W.done = false;
-    int cx, cy, cz;
     R bx, by, bz;
-    axis_setup(G, 0, p[0], d[0], 1, cx, W.T0x, W.Dx, bx, W.dx);
-    axis_setup(G, 1, p[1], d[1], G.n[0], cy, W.T0y, W.Dy, by, W.dy);
-    axis_setup(G, 2, p[2], d[2], G.n[0] * G.n[1], cz, W.T0z, W.Dz, bz, W.dz);
+    axis_setup(G, 0, p[0], d[0], W.cx, W.T0x, W.Dx, bx, W.sx);
+    axis_setup(G, 1, p[1], d[1], W.cy, W.T0y, W.Dy, by, W.sy);
+    axis_setup(G, 2, p[2], d[2], W.cz, W.T0z, W.Dz, bz, W.sz);
     W.tx = W.T0x; W.ty = W.T0y; W.tz = W.T0z;
     W.t_exit = fmin(bx, fmin(by, bz));
-    W.cell = (cz * G.n[1] + cy) * G.n[0] + cx;
     return true;
 }
 
@@ -179,17 +210,18 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         const bool mz = !mx && !my;
         const R tn = fmin(W.tx, fmin(W.ty, W.tz));
         nv += alive ? 1u : 0u;
-        cells[b] = W.cell;
+        cells[b] = cell_index(G, W.cx, W.cy, W.cz);
         t0s[b] = W.t;
         const R seg = tn - W.t;
         segs[b] = seg > (R)0 ? seg : (R)0;
         W.t = tn > W.t ? tn : W.t;
         // the face about to be crossed is a boundary face: the walk ends in this cell
         const bool adv = tn < W.t_exit;
-        // cell step of the chosen axis as mask arithmetic (a select between
-        // struct fields would become a load from a selected address)
-        const int dc = (W.dx & -(int)mx) | (W.dy & -(int)my) | (W.dz & -(int)mz);
-        W.cell += dc & -(int)adv;
+        // coordinate step of the chosen axis as mask arithmetic (a select
+        // between struct fields would become a load from a selected address)
+        W.cx += W.sx & -(int)(adv && mx);
+        W.cy += W.sy & -(int)(adv && my);
+        W.cz += W.sz & -(int)(adv && mz);
         W.jx += (adv && mx) ? (R)1 : (R)0;
         W.jy += (adv && my) ? (R)1 : (R)0;
         W.jz += (adv && mz) ? (R)1 : (R)0;

@@ -164,7 +164,6 @@ class Context:
         if rc != QRT_OK:
             raise QRTError(rc, "qrt_create failed")
         self.h = h
-        self._keep = []
 
     def _ck(self, rc: int):
         if rc != QRT_OK:
@@ -192,7 +191,7 @@ class Context:
         self._ck(self.lib.qrt_set_stream(self.h, C.c_void_p(stream)))
 
     def set_grid(self, kappa_rho, lo=(-1.0, -1.0, -1.0), hi=(1.0, 1.0, 1.0)):
-        """kappa_rho: float32 [nz][ny][nx], a numpy array (copied) or a CUDA torch tensor (borrowed)."""
+        """kappa_rho: float32 [nz][ny][nx], a numpy array or a CUDA torch tensor (copied into the library's order)."""
         nz, ny, nx = kappa_rho.shape
         if isinstance(kappa_rho, np.ndarray):
             a = np.ascontiguousarray(kappa_rho, dtype=np.float32)
@@ -202,9 +201,8 @@ class Context:
             t = kappa_rho
             if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError("device grid must be a contiguous float32 CUDA tensor")
-            self._keep = [t]
             self._ck(self.lib.qrt_set_grid(self.h, nx, ny, nz, _d3(lo), _d3(hi), C.c_void_p(t.data_ptr()),
-                                           GRID_DEVICE_BORROW))
+                                           GRID_DEVICE_COPY))
 
     def set_point_source(self, x=0.0, y=0.0, z=0.0):
         self._ck(self.lib.qrt_set_point_source(self.h, x, y, z))
@@ -230,7 +228,7 @@ class Context:
 
     def set_scene(self, sc, kind: int = SOBOL, seed: int = 0, n_total: Optional[int] = None, grid=None,
                   precision: Optional[int] = None):
-        """Configure everything from a synth.Scene (grid may be a device tensor to borrow)."""
+        """Configure everything from a synth.Scene (grid may be a device tensor holding its mesh)."""
         self.set_grid(sc.kappa_rho if grid is None else grid, sc.lo, sc.hi)
         if sc.source_kind == 1:
             self.set_sphere_source(*sc.source, sc.r_star, getattr(sc, "emit_order", EMIT_DIRECT))
