@@ -304,6 +304,15 @@ int qrt_surrogate_train(qrt_ctx *ctx, int64_t n, const float *pos_obs, const flo
 int qrt_surrogate_validate(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, double max_err,
                            double floor_frac, int64_t min_count, qrt_mask_report *rep);
 
+/* The trained surrogate as one blob: parameters, domain, mask, and the
+   observer directions the mask was validated for.  get: blob NULL returns the
+   size in *nbytes; otherwise *nbytes is the blob's capacity (too small:
+   QRT_INVALID_ARG, *nbytes set to the size).  set: the context's observers
+   must be the blob's (else QRT_BAD_STATE); resets the Adam moments.
+   Synchronous. */
+int qrt_surrogate_get_state(qrt_ctx *ctx, void *blob, size_t *nbytes);
+int qrt_surrogate_set_state(qrt_ctx *ctx, const void *blob, size_t nbytes);
+
 /* ---------------------------------------------------------------------------
  * Batches of scenes.
  *

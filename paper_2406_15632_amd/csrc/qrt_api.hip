@@ -1246,6 +1246,100 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
     return QRT_OK;
 }
 
+// ---------------------------------------------------------------- surrogate state
+
+// Blob of a trained surrogate: this header, then theta[n_obs] and phi[n_obs]
+// (FP64, the observers the mask was validated for), the FP32 parameters and
+// the mask [n_obs][n_r][n_z].
+struct SurrogateStateHeader {
+    char magic[8];              // "QRTSUR01"
+    uint32_t n_params, n_obs;
+    int32_t n_r, n_z;
+    double center[3];
+    double r_in, r_out, h0, beta, zmax;
+};
+static const char kStateMagic[8] = {'Q', 'R', 'T', 'S', 'U', 'R', '0', '1'};
+
+static size_t state_bytes(uint32_t n_obs, int n_r, int n_z)
+{
+    return sizeof(SurrogateStateHeader) + 2 * sizeof(double) * n_obs + sizeof(float) * kMlpParams +
+           (size_t)n_obs * n_r * n_z;
+}
+
+int qrt_surrogate_get_state(qrt_ctx *c, void *blob, size_t *nbytes)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!nbytes) return fail(c, QRT_INVALID_ARG, "null size");
+    if (!c->has_mlp || !c->has_domain || !c->has_obs)
+        return fail(c, QRT_NOT_TRAINED, "the surrogate needs network parameters, a domain and observers");
+    const size_t need = state_bytes((uint32_t)c->n_obs, c->dom_nr, c->dom_nz);
+    if (!blob) {
+        *nbytes = need;
+        return QRT_OK;
+    }
+    if (*nbytes < need) {
+        *nbytes = need;
+        return fail(c, QRT_INVALID_ARG, "the state needs %zu bytes", need);
+    }
+    SurrogateStateHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, kStateMagic, sizeof(h.magic));
+    h.n_params = kMlpParams;
+    h.n_obs = (uint32_t)c->n_obs;
+    h.n_r = c->dom_nr;
+    h.n_z = c->dom_nz;
+    for (int a = 0; a < 3; ++a) h.center[a] = c->dom_center[a];
+    h.r_in = c->dom_r_in; h.r_out = c->dom_r_out; h.h0 = c->dom_h0; h.beta = c->dom_beta; h.zmax = c->dom_zmax;
+    char *out = (char *)blob;
+    memcpy(out, &h, sizeof(h));
+    out += sizeof(h);
+    memcpy(out, c->theta, sizeof(double) * c->n_obs);
+    out += sizeof(double) * c->n_obs;
+    memcpy(out, c->phi, sizeof(double) * c->n_obs);
+    out += sizeof(double) * c->n_obs;
+    int rc = qrt_mlp_get_params(c, (float *)out, kMlpParams);
+    if (rc) return rc;
+    out += sizeof(float) * kMlpParams;
+    rc = qrt_surrogate_get_mask(c, (uint8_t *)out);
+    if (rc) return rc;
+    *nbytes = need;
+    return QRT_OK;
+}
+
+int qrt_surrogate_set_state(qrt_ctx *c, const void *blob, size_t nbytes)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (!blob || nbytes < sizeof(SurrogateStateHeader)) return fail(c, QRT_INVALID_ARG, "state too short");
+    if (!c->has_obs) return fail(c, QRT_BAD_STATE, "set the observers first");
+    SurrogateStateHeader h;
+    memcpy(&h, blob, sizeof(h));
+    if (memcmp(h.magic, kStateMagic, sizeof(h.magic)) != 0) return fail(c, QRT_INVALID_ARG, "not a surrogate state");
+    if (h.n_params != (uint32_t)kMlpParams || h.n_obs < 1 || h.n_obs > QRT_MAX_OBSERVERS || h.n_r < 1 ||
+        h.n_z < 1 || h.n_r > 1024 || h.n_z > 1024)
+        return fail(c, QRT_INVALID_ARG, "inconsistent surrogate state");
+    if (nbytes != state_bytes(h.n_obs, h.n_r, h.n_z)) return fail(c, QRT_INVALID_ARG, "state size mismatch");
+    const char *in = (const char *)blob + sizeof(h);
+    const double *th = (const double *)(const void *)in;
+    const double *ph = th + h.n_obs;
+    if ((int)h.n_obs != c->n_obs) return fail(c, QRT_BAD_STATE, "the state is for %u observers", h.n_obs);
+    for (int o = 0; o < c->n_obs; ++o) {
+        double t, p;
+        memcpy(&t, th + o, sizeof(double));
+        memcpy(&p, ph + o, sizeof(double));
+        if (t != c->theta[o] || p != c->phi[o])
+            return fail(c, QRT_BAD_STATE, "observer %d differs from the one the mask was validated for", o);
+    }
+    in += 2 * sizeof(double) * h.n_obs;
+    std::vector<float> params(kMlpParams);
+    memcpy(params.data(), in, sizeof(float) * kMlpParams);
+    in += sizeof(float) * kMlpParams;
+    int rc = qrt_surrogate_set_domain(c, h.center, h.r_in, h.r_out, h.h0, h.beta, h.zmax, h.n_r, h.n_z);
+    if (rc) return rc;
+    rc = qrt_mlp_set_params(c, params.data(), kMlpParams);
+    if (rc) return rc;
+    return qrt_surrogate_set_mask(c, (const uint8_t *)in);
+}
+
 // ---------------------------------------------------------------- batches of scenes
 
 // checks one scene description; returns its point dimension, or a status < 0

@@ -108,6 +108,8 @@ SIGNATURES = {
                                       C.POINTER(qrt_train_report)]),
     "qrt_surrogate_validate": (C.c_int, [_P, C.c_int64, _P, _P, C.c_double, C.c_double, C.c_int64,
                                          C.POINTER(qrt_mask_report)]),
+    "qrt_surrogate_get_state": (C.c_int, [_P, _P, C.POINTER(C.c_size_t)]),
+    "qrt_surrogate_set_state": (C.c_int, [_P, _P, C.c_size_t]),
     "qrt_batch_set": (C.c_int, [_P, C.c_int, C.POINTER(qrt_batch_scene)]),
     "qrt_batch_run": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_int]),
     "qrt_batch_read_images": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, C.c_int]),
@@ -356,6 +358,18 @@ class Context:
                                                  C.c_void_p(tau.data_ptr()), max_err, floor_frac, min_count,
                                                  C.byref(rep)))
         return _as_dict(rep)
+
+    def surrogate_get_state(self) -> bytes:
+        n = C.c_size_t(0)
+        self._ck(self.lib.qrt_surrogate_get_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._ck(self.lib.qrt_surrogate_get_state(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def surrogate_set_state(self, blob: bytes):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._ck(self.lib.qrt_surrogate_set_state(self.h, buf, len(blob)))
+        self.dom_shape = tuple(np.frombuffer(bytes(blob)[16:24], dtype=np.int32))   # header: n_r, n_z
 
     # -------- batches of scenes
     def batch_set(self, scenes, firsts: Optional[Sequence[int]] = None, counts: Optional[Sequence[int]] = None,

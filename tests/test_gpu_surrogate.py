@@ -265,3 +265,40 @@ def test_surrogate_requires_parameters_and_domain(ctx, Q):
     ctx.set_transport(3, 1e-8, Q.FP64, Q.PEEL_SURROGATE)
     with pytest.raises(Q.QRTError):
         ctx.mlp_set_params(np.zeros(10, np.float32))
+
+
+def test_surrogate_state_round_trip(Q):
+    """A trained surrogate saved from one context and restored into another
+    gives the same parameters, mask and transport; observers that differ from
+    the ones the mask was validated for, and damaged blobs, are refused."""
+    sc = _small_disk()
+    th = _params(51, out_bias=1.2)
+    valid = (np.random.default_rng(52).random((3, 16, 12)) < 0.5).astype(np.uint8)
+    count = 1 << 11
+    a, b = Q.Context(0), Q.Context(0)
+    try:
+        _say("surrogate state round trip")
+        ga, ca = _sur_run_gpu(a, Q, sc, th, valid, count)
+        blob = a.surrogate_get_state()
+        b.set_scene(sc)
+        b.surrogate_set_state(blob)
+        assert np.array_equal(b.mlp_get_params(), th)
+        assert np.array_equal(b.surrogate_get_mask(), valid)
+        b.set_transport(sc.max_orders, sc.tau_min, Q.FP64, Q.PEEL_SURROGATE)
+        b.reset_images()
+        b.run(1, count)
+        gb = b.read_images(normalized=False) / count
+        assert np.allclose(ga, gb, rtol=1e-12, atol=1e-300)
+        assert b.counters() == ca
+        b.set_observers([(0.1, 0.0), (0.5, 0.0), (1.5, 0.0)], sc.npix, sc.half_width)
+        with pytest.raises(Q.QRTError):
+            b.surrogate_set_state(blob)
+        b.set_observers(sc.observers, sc.npix, sc.half_width)
+        with pytest.raises(Q.QRTError):
+            b.surrogate_set_state(b"XXXXXXXX" + blob[8:])
+        with pytest.raises(Q.QRTError):
+            b.surrogate_set_state(blob[:-1])
+    finally:
+        a.close()
+        b.close()
+
