@@ -1511,8 +1511,14 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     P.seq = seq_params(c, kind, seed, 0);
     P.max_orders = c->batch_max_orders;
     P.counters = c->counters;
-    HIP_TRY(c,
-            launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, c->tb_packets, c->stream),
+    // the peel-ray buffer split into equal append regions (launch_batch checks that every chunk fits)
+    const size_t peel_capacity = c->tb.peel_bytes / peel_ray_bytes(precision);
+    P.group_cap = (uint32_t)std::min<size_t>(peel_capacity / kPeelGroups, 0xFFFFFFFFu);
+    // chunks of a multiple of 64 kPeelGroups packets put 64 kBatchObs rays per block in each group
+    const uint64_t unit = 64 * kPeelGroups, per_unit = 64 * kBatchObs;
+    const uint64_t chunk = std::min<uint64_t>(c->tb_packets, (P.group_cap / per_unit) * unit);
+    if (chunk == 0) return fail(c, QRT_HIP_ERROR, "peel-ray buffer too small for a batch");
+    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, chunk, c->stream),
             "batch launch");
     return QRT_OK;
 }

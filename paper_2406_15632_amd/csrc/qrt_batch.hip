@@ -561,8 +561,10 @@ hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precis
         const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
         // the sort key spends only the bits that the chunk's scenes need on the scene
         BatchParams P = P0;
-        // group g of the peel rays: at most ceil(chunk / 64 / kPeelGroups) blocks of 64 kBatchObs rays
-        P.group_cap = (uint32_t)(((chunk / 64 + kPeelGroups - 1) / kPeelGroups) * 64 * kBatchObs);
+        // a group of peel rays receives at most ceil(blocks / kPeelGroups) of the chunk's
+        // 64-packet blocks, each with at most 64 kBatchObs rays: it must fit its region
+        const uint64_t blocks = ((uint64_t)n + 63) / 64;
+        if (((blocks + kPeelGroups - 1) / kPeelGroups) * 64 * kBatchObs > P.group_cap) return hipErrorInvalidValue;
         P.scene_base = host_scene_of(begin, P.n_scenes, done);
         const int span = host_scene_of(begin, P.n_scenes, done + n - 1) - P.scene_base + 1;
         P.scene_bits = 0;

@@ -179,7 +179,8 @@ struct BatchParams {
     int scene_bits;             // sort-key bits that hold scene - scene_base (the rest: emission direction)
     SeqParams seq;              // n_total is replaced by each scene's own
     int max_orders;             // largest over the scenes
-    uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap)
+    uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap),
+                                // kPeelGroups group_cap rays at most the peel buffer's capacity
     unsigned long long *counters;
 };
 

@@ -173,6 +173,25 @@ def test_batch_fp32_equals_single_runs(ctx, Q, kind):
     assert cb == sum_counters(cs)
 
 
+def test_batch_after_a_larger_single_scene_run(ctx, Q):
+    """Queues grown by a larger single-scene run with one observer (packet
+    lists for 2^22 packets, one peel slot each) and then a small batch with up
+    to four observers per scene: the batch's peel regions are sized from the
+    peel buffer it actually has, and every scene still equals its oracle run."""
+    big = scenes.disk128(n_packets=1 << 22, n=32).replace(observers=[(0.4, 0.0)], max_orders=2, npix=16)
+    _say("single-scene run of 2^22 packets, one observer")
+    ctx.set_scene(big, precision=Q.FP32)
+    ctx.run(1, 1 << 22)
+    bs = small_batch(seed=12, n_scenes=5)
+    _say(f"then a small fp64 batch, packets={[sc.n_packets for sc in bs]}")
+    ctx.batch_set(bs)
+    ctx.batch_reset()
+    ctx.batch_run(Q.SOBOL, 0, Q.FP64)
+    for i, sc in enumerate(bs):
+        o, _, _ = O.run(sc, O.SOBOL, 1, sc.n_packets)
+        assert_fp64_parity(ctx.batch_read_images(i), o, f"scene {i}")
+
+
 def test_batch_runs_add_and_reset(ctx, Q):
     bs = small_batch(seed=3, n_scenes=3)
     ctx.batch_set(bs)
