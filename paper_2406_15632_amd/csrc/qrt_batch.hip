@@ -16,6 +16,8 @@
 // packet whose scene has fewer orders stops at its own last order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qrt_internal.h"
 #include "qrt_physics.h"
 #include "qrt_wave.h"
@@ -467,7 +469,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
             continue;
         }
         for (;;) {
-            walk_batch<R, kWalkBatch>(W, G);
+            walk_batch<R, kFlightBatch>(W, G);
             if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
         }
     }
@@ -503,6 +505,7 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     }
     PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
+    const int walk_blocks = std::min(nb_walk, walk_blocks_per_cu(P.mesh_bytes) * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
@@ -520,7 +523,8 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
         const int in = (order - 1) & 1;
         hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, pks,
                            (const uint32_t *)B.live[in], in, peels, B.q);
-        hipLaunchKernelGGL((k_bwalk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks,
+        const int wb = order < P.max_orders ? walk_blocks : nb_walk;   // the last order walks peel rays only
+        hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order, pks,
                            (const uint32_t *)B.live[in], in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

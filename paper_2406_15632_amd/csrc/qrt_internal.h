@@ -179,6 +179,7 @@ struct BatchParams {
     int scene_bits;             // sort-key bits that hold scene - scene_base (the rest: emission direction)
     SeqParams seq;              // n_total is replaced by each scene's own
     int max_orders;             // largest over the scenes
+    size_t mesh_bytes;          // all meshes of the batch (they share the caches)
     uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap),
                                 // kPeelGroups group_cap rays at most the peel buffer's capacity
     unsigned long long *counters;

@@ -41,6 +41,8 @@
 // sums, optical-depth targets and image sums) or double throughout.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "qrt_internal.h"
 #include "qrt_mlp.h"
 #include "qrt_physics.h"
@@ -498,7 +500,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
             continue;   // every item just taken was an invisible peel ray
         }
         for (;;) {
-            walk_batch<R, kWalkBatch>(W, G);
+            walk_batch<R, kFlightBatch>(W, G);
             if (__popcll(__ballot(W.done || kind == WI_NONE)) >= kWaveRefill) break;
         }
     }
@@ -693,6 +695,8 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const size_t hist_bytes = sizeof(uint32_t) << kSortBits;
+    const size_t mesh_bytes = (size_t)P.grid.nb[0] * P.grid.nb[1] * P.grid.nb[2] * (kBrick * kBrick * kBrick) * 4;
+    const int walk_blocks = std::min(nb_walk, walk_blocks_per_cu(mesh_bytes) * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
@@ -718,7 +722,9 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         if (P.peel_mode == 1)
             hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, order, peels, (const Queues *)B.q,
                                in);
-        hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
+        // the last order walks peel rays only (no flights): those want every resident wave
+        const int wb = order < P.max_orders ? walk_blocks : nb_walk;
+        hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
                            in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

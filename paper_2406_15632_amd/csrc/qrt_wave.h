@@ -10,7 +10,32 @@
 
 namespace qrt {
 
-constexpr int kWalkBatch = 4;
+constexpr int kWalkBatch = 4;    // steps per load batch of the first flights
+constexpr int kFlightBatch = 6;  // steps per load batch of the per-order walks (which run at low occupancy)
+
+// Blocks per CU of the per-order walk kernels (measured).  With fewer waves
+// the CU's vector L1 cache keeps more of each lane's current lines between
+// steps: on meshes that the L2 caches and the MALL mostly hold, two blocks
+// (two waves per SIMD) beat the four or five that the registers allow; larger
+// meshes, whose misses go further, want a third block to hide the latency.
+// Only orders that walk flights are limited: the peel rays of the last order
+// run side by side and want every wave.
+inline int walk_blocks_per_cu(size_t mesh_bytes) { return mesh_bytes <= (16u << 20) ? 2 : 3; }
+
+// compute units of the current device (read once)
+inline int device_cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        (void)hipGetDevice(&dev);
+        cus = (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+                  ? prop.multiProcessorCount : 256;
+    }
+    return cus;
+}
+
 constexpr uint32_t kNoPixel = 0xFFFFFFFFu;   // a peel ray that is off the image or blocked
 
 __host__ __device__ __forceinline__ size_t peel_slot(uint32_t i, int ob, int n_obs)
