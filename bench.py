@@ -67,17 +67,28 @@ def parse():
     return ap.parse_args()
 
 
-def transport_source_hash() -> str:
-    """Hash of the sources that define the transport kernels (traffic counters
-    taken on other sources do not describe this build)."""
+def _code_only(text: str, hash_comments: bool) -> str:
+    """Source text without comments and blank space (they do not change the kernels)."""
+    import re
+    if hash_comments:
+        text = re.sub(r"#[^\n]*", "", text)
+    else:
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+    return " ".join(text.split())
+
+
+def transport_source_hash(root: str = ROOT) -> str:
+    """Hash of the code that defines the transport kernels, comments left out
+    (traffic counters taken on other code do not describe this build)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2406_15632_amd", "csrc")
+    csrc = os.path.join(root, "paper_2406_15632_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".h", ".cpp")):
             h.update(f.encode())
-            h.update(open(os.path.join(csrc, f), "rb").read())
+            h.update(_code_only(open(os.path.join(csrc, f)).read(), False).encode())
     # the compiler flags are part of the kernels too
-    h.update(open(os.path.join(ROOT, "paper_2406_15632_amd", "build.py"), "rb").read())
+    h.update(_code_only(open(os.path.join(root, "paper_2406_15632_amd", "build.py")).read(), True).encode())
     return h.hexdigest()[:16]
 
 

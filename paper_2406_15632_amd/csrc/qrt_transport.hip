@@ -21,10 +21,13 @@
 //              contribution to the image) and every flight (survivors go to the
 //              next live list).
 // Only the two persistent kernels walk the mesh; their per-ray events are a
-// few loads and stores, so they keep a small register footprint and high
-// occupancy.  All physics runs in k_first's events and in k_scatter, which is
-// convergent.  Waves of the persistent kernels take work 64 items at a time
-// from a global counter and refill lanes once a quarter of the wave is idle.
+// few loads and stores, so they keep a small register footprint.  All physics
+// runs in k_first's events and in k_scatter, which is convergent.  Waves of
+// the persistent kernels take work 64 items at a time from a global counter
+// and refill once every lane of the wave is idle, which keeps a wave's rays
+// together.  The per-order walks run at two or three blocks per CU (see
+// walk_blocks_per_cu): their flights are incoherent gathers, and fewer waves
+// leave more of each lane's lines in the L1 cache.
 //
 // Point coordinates are generated from the packet index: flight k uses
 // coordinates 3(k-1) .. 3(k-1)+2 (sphere star: 0..4 for the first flight, then
