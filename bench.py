@@ -368,16 +368,19 @@ def per_order_section(qrt, sc, stream):
     ref = per_order(qrt.HALTON, 1 << 28)
     n = 1 << 22
     out = {"orders": [str(k) for k in range(1, K + 1)] + [f">{K}"], "packets": n,
-           "reference": "halton, 2^28 packets", "share_of_light": [], "rms_error": {}}
+           "reference": "halton, 2^28 packets", "share_of_light": [], "rms_error": {}, "image_norm": {}}
     tot = sum(float(r.sum()) for r in ref)
     out["share_of_light"] = [round(float(r.sum()) / tot, 4) for r in ref]
     for name, kind, seeds in (("sobol", qrt.SOBOL, (PHILOX_SEED,)), ("hammersley", qrt.HAMMERSLEY, (PHILOX_SEED,)),
                               ("philox", qrt.PHILOX, (1, 2))):
         errs = np.zeros(K + 1)
+        norms = np.zeros(K + 1)
         for sd in seeds:
             imgs = per_order(kind, n, sd)
             errs += np.array([metrics.rms_error(a, b) for a, b in zip(imgs, ref)])
+            norms += np.array([metrics.image_norm(a, b) for a, b in zip(imgs, ref)])
         out["rms_error"][name] = [round(float(e), 5) for e in errs / len(seeds)]
+        out["image_norm"][name] = [round(float(e), 5) for e in norms / len(seeds)]
     out["mc_over_sobol"] = [round(m / q, 3) for m, q in zip(out["rms_error"]["philox"], out["rms_error"]["sobol"])]
     ctx.close()
     return out
@@ -418,12 +421,14 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
         top = sweep_log2 + (2 if kind == qrt.PHILOX else 0)   # MC needs ~4x the packets
         for lg in range(12, top + 1):
             seeds = ((1, 2, 3, 4) if lg < 24 else (1, 2)) if kind == qrt.PHILOX else (PHILOX_SEED,)
-            errs, ts = [], []
+            errs, ts, dis, ins = [], [], [], []
             for sd in seeds:
                 img, t = run(kind, 1 << lg, sd)
                 errs.append(metrics.rms_error(img, ref))
+                dis.append(abs(metrics.integral_norm(img, ref)))
+                ins.append(metrics.image_norm(img, ref))
                 ts.append(t)
-            pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg))
+            pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg, float(np.mean(dis)), float(np.mean(ins))))
         curves[names[kind]] = pts
     # randomised QMC: R independent Owen scramblings give an error bar from
     # their spread; compared here with the actual error of their mean
@@ -436,17 +441,42 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
             "actual_rms_error_of_mean": metrics.rms_error(mean, ref_h),
             "unscrambled_sobol_rms_error_same_packets": metrics.rms_error(run(qrt.SOBOL, R * n_each)[0], ref_h)}
     targets = (0.05, 0.01, 0.003)
+    floor_in = metrics.image_norm(ref_s, ref_h)
+    by_lg = lambda v, j: {int(p[2]).bit_length() - 1: round(p[j], 6) for p in v}
     out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor, "_ref_halton": ref_h,
-           "rms_error_by_log2_packets": {k: {int(p[2]).bit_length() - 1: round(p[1], 6) for p in v}
-                                         for k, v in curves.items()},
-           "time_s": {}, "speedup_vs_mc": {}, "owen_error_bar": owen}
+           "rms_error_by_log2_packets": {k: by_lg(v, 1) for k, v in curves.items()},
+           "time_s": {}, "speedup_vs_mc": {}, "owen_error_bar": owen,
+           # the paper's norms (Sec. 4): |dI| of the total intensity and Delta I / I over
+           # the pixels of all observers, the times to Delta I / I targets, and the
+           # power laws a t^-0.5 and a t^-b of |dI| (Sec. 5; t in seconds)
+           "ref_floor_image_norm": floor_in,
+           "ref_floor_integral_norm": abs(metrics.integral_norm(ref_s, ref_h)),
+           "integral_norm_by_log2_packets": {k: by_lg(v, 3) for k, v in curves.items()},
+           "image_norm_by_log2_packets": {k: by_lg(v, 4) for k, v in curves.items()},
+           "time_s_image_norm": {}, "speedup_vs_mc_image_norm": {}, "integral_norm_fits": {}}
     for k, pts in curves.items():
         ts = [p[0] for p in pts]
         es = [p[1] for p in pts]
         out["time_s"][k] = [metrics.time_to_error(ts, es, tg) if tg >= 3 * floor else None for tg in targets]
-    mc = out["time_s"]["philox"]
-    for k, tt in out["time_s"].items():
-        out["speedup_vs_mc"][k] = [(m / t if (m is not None and t) else None) for m, t in zip(mc, tt)]
+        ins = [p[4] for p in pts]
+        out["time_s_image_norm"][k] = [metrics.time_to_error(ts, ins, tg) if tg >= 3 * floor_in else None
+                                       for tg in targets]
+        dis = [p[3] for p in pts]
+        half = len(pts) // 2
+        a05 = metrics.power_fit(ts, dis, b=0.5)
+        ab = metrics.power_fit(ts, dis)
+        ab_long = metrics.power_fit(ts[half:], dis[half:])
+        out["integral_norm_fits"][k] = {"a_for_b_0.5": a05[0] if a05 else None,
+                                        "a_b_all": list(ab) if ab else None,
+                                        "a_b_longest_half": list(ab_long) if ab_long else None}
+    # the paper's comparison of the a t^-0.5 fits: how many times smaller |dI| is than Monte Carlo's
+    a_mc = out["integral_norm_fits"]["philox"]["a_for_b_0.5"]
+    for k, f in out["integral_norm_fits"].items():
+        f["mc_a_over_a"] = (a_mc / f["a_for_b_0.5"]) if (a_mc and f["a_for_b_0.5"]) else None
+    for key, dst in (("time_s", "speedup_vs_mc"), ("time_s_image_norm", "speedup_vs_mc_image_norm")):
+        mc = out[key]["philox"]
+        for k, tt in out[key].items():
+            out[dst][k] = [(m / t if (m is not None and t) else None) for m, t in zip(mc, tt)]
     return out
 
 

@@ -7,7 +7,8 @@
   error the time-to-error comparisons use;
 * time to reach a target error, read off a (time, error) curve by log-log
   interpolation between the two bracketing measurements (Sec. 5, the
-  time-to-error tables).
+  time-to-error tables);
+* least-squares power laws a t^-b of an error against time (Sec. 5).
 """
 from __future__ import annotations
 
@@ -50,6 +51,22 @@ def time_to_error(times: Sequence[float], errors: Sequence[float], target: float
             f = (math.log(target) - math.log(e0)) / (math.log(e) - math.log(e0))
             return float(math.exp(math.log(t0) + f * (math.log(t) - math.log(t0))))
     return None
+
+
+def power_fit(times: Sequence[float], errors: Sequence[float], b: Optional[float] = None):
+    """Least-squares fit of error = a t^-b on log-log axes (the paper's error
+    approximations of Sec. 5: a t^-0.5 with b fixed, or a t^-b with both
+    fitted).  Points with a non-positive time or error are left out.
+    Returns (a, b), or None with fewer than two points (one when b is given)."""
+    pts = [(math.log(t), math.log(e)) for t, e in zip(times, errors) if t > 0 and e > 0]
+    if len(pts) < (1 if b is not None else 2):
+        return None
+    x = np.array([p[0] for p in pts])
+    y = np.array([p[1] for p in pts])
+    if b is None:
+        slope, icpt = np.polyfit(x, y, 1)
+        return float(math.exp(icpt)), float(-slope)
+    return float(math.exp(np.mean(y + b * x))), float(b)
 
 
 def central_mask(npix: int, half_width: float, radius: float) -> np.ndarray:

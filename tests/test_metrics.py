@@ -28,3 +28,18 @@ def test_central_mask():
     m = M.central_mask(8, 1.0, 0.3)
     assert not m[3, 3] and not m[4, 4] and m[0, 0]
     assert m.sum() == 64 - 4
+
+
+def test_power_fit_recovers_exact_power_laws():
+    t = np.array([1e-3, 4e-3, 2e-2, 0.1, 0.7])
+    a, b = M.power_fit(t, 0.3 * t ** -0.7)
+    assert a == pytest.approx(0.3, rel=1e-12) and b == pytest.approx(0.7, rel=1e-12)
+    a, b = M.power_fit(t, 2.0 * t ** -0.5, b=0.5)
+    assert a == pytest.approx(2.0, rel=1e-12) and b == 0.5
+    # with b fixed, a is the geometric mean of e t^b
+    e = np.array([1.0, 3.0, 2.0, 0.5, 0.1])
+    a, _ = M.power_fit(t, e, b=0.5)
+    assert a == pytest.approx(float(np.exp(np.mean(np.log(e * t ** 0.5)))), rel=1e-12)
+    assert M.power_fit([1.0], [0.1]) is None
+    assert M.power_fit([1.0, 2.0], [0.0, -1.0]) is None
+
