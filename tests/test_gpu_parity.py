@@ -250,6 +250,19 @@ def test_clumpy256_sphere_star_fp64_parity(ctx, Q, emit_order):
     assert_counters_equal(cg, co)
 
 
+def test_large_mesh_multi_order_fp64_parity(ctx, Q):
+    """A 64 MiB mesh with three scattering orders: the per-order walks of a
+    mesh this large run at three blocks per CU (two for smaller meshes, all
+    resident waves for the last order); the images do not depend on it."""
+    sc = scenes.clumpy256().replace(fp64=True, n_packets=1 << 14, max_orders=3)
+    _say("clumpy256 FP64, 3 orders, sobol 2^14")
+    g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, sc.n_packets)
+    o, co, _ = O.run(sc, O.SOBOL, count=sc.n_packets, nthreads=8)
+    assert co["scatterings"] > co["packets"] - co["tau_cuts"]   # packets do scatter more than once
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
 @pytest.mark.parametrize("kind", [O.SOBOL, O.PHILOX])
 def test_sphere_star_inverse_order_multi_order_fp64_parity(ctx, Q, kind):
     """Inverse emission order with scatterings beyond the first: the point
