@@ -50,10 +50,19 @@ __device__ __forceinline__ void flush_counter(unsigned long long *dst, uint64_t 
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
 }
 
-// Wave-uniform pool of work items [next, end), 64 at a time: the first block of
-// every wave is fixed by its wave index (no atomic at start-up, when every
-// wave would hit the same counter at once), later blocks come from a global
-// counter that starts after the fixed ones.
+// Wave-uniform pool of work items [next, end), taken a block at a time: the
+// first block of every wave is fixed by its wave index (no atomic at start-up,
+// when every wave would hit the same counter at once), later blocks come from
+// a global counter that starts after the fixed ones.  The counter is shared by
+// every wave of the device, so its atomics are a serial point: large launches
+// take bigger blocks (fewer atomics), small ones keep 64-item blocks so that
+// the few items still spread over many waves.
+__device__ __forceinline__ uint64_t pool_block(uint64_t total, uint64_t nwaves)
+{
+    const uint64_t per_wave = total / nwaves;
+    return per_wave >= 4096 ? 512 : (per_wave >= 1024 ? 256 : (per_wave >= 256 ? 128 : 64));
+}
+
 struct WorkPool {
     uint64_t next = 0, end = 0;
     bool dry = false, started = false;
@@ -66,17 +75,18 @@ struct WorkPool {
         while (need && !dry) {
             if (next >= end) {
                 const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+                const uint64_t blk = pool_block(total, nwaves);
                 uint64_t base;
                 if (!started) {
-                    base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64;
+                    base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * blk;
                     started = true;
                 } else {
                     unsigned long long b = 0;
-                    if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, 64ull);
-                    base = nwaves * 64 + __shfl(b, 0, 64);
+                    if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, (unsigned long long)blk);
+                    base = nwaves * blk + __shfl(b, 0, 64);
                 }
                 next = base;
-                end = base + 64 < total ? base + 64 : total;
+                end = base + blk < total ? base + blk : total;
                 if (next >= total) {
                     dry = true;
                     break;
