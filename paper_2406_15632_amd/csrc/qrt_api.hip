@@ -88,7 +88,6 @@ struct qrt_ctx {
     BScene *batch_dev = nullptr;             // [kMaxBatchScenes]
     float *batch_grid = nullptr;             // all meshes, one after the other
     size_t batch_grid_alloc = 0;             // floats
-    size_t batch_mesh_bytes = 0;             // bytes of the current batch's meshes
     double *batch_img = nullptr;             // all image sets (kImageCopies each), one after the other
     size_t batch_img_alloc = 0;              // doubles
     size_t batch_img_used = 0;
@@ -1480,7 +1479,6 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
     c->batch.swap(host);
     c->batch_begin.swap(begins);
     c->batch_img_used = pixels;
-    c->batch_mesh_bytes = cells * sizeof(float);
     c->batch_total = total;
     c->batch_max_orders = max_orders;
     c->batch_runs = 0;
@@ -1513,7 +1511,6 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     P.seq = seq_params(c, kind, seed, 0);
     P.max_orders = c->batch_max_orders;
     P.counters = c->counters;
-    P.mesh_bytes = c->batch_mesh_bytes;
     // the peel-ray buffer split into equal append regions (launch_batch checks that every chunk fits)
     const size_t peel_capacity = c->tb.peel_bytes / peel_ray_bytes(precision);
     P.group_cap = (uint32_t)std::min<size_t>(peel_capacity / kPeelGroups, 0xFFFFFFFFu);

@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
         const uint32_t pos = wave_append(append, &Q->n_live[0]);
         if (append) live0[pos] = j;
         uint64_t item = 0;
-        if (pool.take(phase == BF_IDLE, count, &Q->work[0], item)) {
+        if (pool.take(phase == BF_IDLE, count, &Q->work[0][0][0], item)) {
             j = order[item];
             // the sort key holds the scene relative to the chunk's first
             s = P.scene_base + (int)(keys[j] >> (kSortBits - P.scene_bits));
@@ -226,9 +226,9 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
                                                   const uint32_t *__restrict__ live_in, int in,
                                                   PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        Q->n_live[in ^ 1] = 0;
-        Q->work[1] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) {
+        if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
+        Q->work[1][threadIdx.x][0] = 0;
     }
     const uint32_t n = Q->n_live[in];
     const int lane = threadIdx.x & 63;
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
         const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
         if (append) live_out[pos] = slot;
         uint64_t item = 0;
-        if (pool.take(kind == BW_NONE, total, &Q->work[1], item)) {
+        if (pool.take(kind == BW_NONE, total, &Q->work[1][0][0], item)) {
             if (item < n_peel) {
                 uint64_t at = item;
                 int g = 0;
@@ -505,7 +505,7 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     }
     PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
-    const int walk_blocks = std::min(nb_walk, walk_blocks_per_cu(P.mesh_bytes) * device_cu_count());
+    const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);

@@ -124,7 +124,9 @@ constexpr int kPeelGroups = 8;     // peel-ray append counters of the batched la
 
 struct Queues {
     uint32_t n_live[2];   // live packets per ping-pong list
-    unsigned long long work[4];   // work counters of the persistent kernels
+    // work counters of the persistent kernels: per pool, kPoolParts counters
+    // (one per XCD) of which each owns a 128-byte line
+    unsigned long long work[4][8][16];
     // appended peel rays per order parity and group (batched launches), one
     // counter per 128-byte line so that the groups' atomics do not share one
     uint32_t n_peel[2][kPeelGroups][32];
@@ -179,7 +181,6 @@ struct BatchParams {
     int scene_bits;             // sort-key bits that hold scene - scene_base (the rest: emission direction)
     SeqParams seq;              // n_total is replaced by each scene's own
     int max_orders;             // largest over the scenes
-    size_t mesh_bytes;          // all meshes of the batch (they share the caches)
     uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap),
                                 // kPeelGroups group_cap rays at most the peel buffer's capacity
     unsigned long long *counters;

@@ -23,10 +23,10 @@
 // Only the two persistent kernels walk the mesh; their per-ray events are a
 // few loads and stores, so they keep a small register footprint.  All physics
 // runs in k_first's events and in k_scatter, which is convergent.  Waves of
-// the persistent kernels take work 64 items at a time from a global counter
-// and refill once every lane of the wave is idle, which keeps a wave's rays
-// together.  The per-order walks run at two or three blocks per CU (see
-// walk_blocks_per_cu): their flights are incoherent gathers, and fewer waves
+// the persistent kernels take work in blocks of 64 to 512 items from counters
+// of their XCD (WorkPool) and refill once every lane of the wave is idle, which
+// keeps a wave's rays together.  The per-order walks run at three blocks per CU
+// (kWalkBlocksPerCu): their flights are incoherent gathers, and fewer waves
 // leave more of each lane's lines in the L1 cache.
 //
 // Point coordinates are generated from the packet index: flight k uses
@@ -50,6 +50,10 @@
 #include "qrt_mlp.h"
 #include "qrt_physics.h"
 #include "qrt_wave.h"
+
+static_assert(sizeof(((qrt::Queues *)nullptr)->work[0]) ==
+                  sizeof(unsigned long long) * qrt::kPoolParts * qrt::kPoolStride,
+              "a pool's counters: kPoolParts lines of kPoolStride counters");
 
 namespace qrt {
 
@@ -250,7 +254,7 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
         const uint32_t pos = wave_append(append, &Q->n_live[0]);
         if (append) live0[pos] = j;
         uint64_t item = 0;
-        if (pool.take(phase == FF_IDLE, count, &Q->work[0], item)) {
+        if (pool.take(phase == FF_IDLE, count, &Q->work[0][0][0], item)) {
             j = order[item];
             n_packets++;
             emit<R, KIND, SRC>(P, first + j, p, k);
@@ -295,10 +299,10 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) {
         // counters of the walk that follows
-        Q->n_live[in ^ 1] = 0;
-        Q->work[1] = 0;
+        if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
+        Q->work[1][threadIdx.x][0] = 0;
     }
     const uint32_t n = Q->n_live[in];
     const int lane = threadIdx.x & 63;
@@ -478,7 +482,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
         const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
         if (append) live_out[pos] = slot;
         uint64_t item = 0;
-        if (pool.take(kind == WI_NONE, total, &Q->work[1], item)) {
+        if (pool.take(kind == WI_NONE, total, &Q->work[1][0][0], item)) {
             if (item < n_peel) {
                 const PeelRay<R> r = peels[item];
                 if (r.pix != kNoPixel) {
@@ -698,8 +702,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const size_t hist_bytes = sizeof(uint32_t) << kSortBits;
-    const size_t mesh_bytes = (size_t)P.grid.nb[0] * P.grid.nb[1] * P.grid.nb[2] * (kBrick * kBrick * kBrick) * 4;
-    const int walk_blocks = std::min(nb_walk, walk_blocks_per_cu(mesh_bytes) * device_cu_count());
+    const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);

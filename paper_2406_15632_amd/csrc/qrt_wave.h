@@ -13,14 +13,12 @@ namespace qrt {
 constexpr int kWalkBatch = 4;    // steps per load batch of the first flights
 constexpr int kFlightBatch = 6;  // steps per load batch of the per-order walks (which run at low occupancy)
 
-// Blocks per CU of the per-order walk kernels (measured).  With fewer waves
-// the CU's vector L1 cache keeps more of each lane's current lines between
-// steps: on meshes that the L2 caches and the MALL mostly hold, two blocks
-// (two waves per SIMD) beat the four or five that the registers allow; larger
-// meshes, whose misses go further, want a third block to hide the latency.
-// Only orders that walk flights are limited: the peel rays of the last order
-// run side by side and want every wave.
-inline int walk_blocks_per_cu(size_t mesh_bytes) { return mesh_bytes <= (16u << 20) ? 2 : 3; }
+// Blocks per CU of the per-order walk kernels (measured): three of the four
+// or five that the registers allow.  With fewer waves the CU's vector L1 cache
+// keeps more of each lane's current lines between steps; with two, the misses'
+// latency shows.  Only orders that walk flights are limited: the peel rays of
+// the last order run side by side and want every wave.
+constexpr int kWalkBlocksPerCu = 3;
 
 // compute units of the current device (read once)
 inline int device_cu_count()
@@ -52,11 +50,16 @@ __device__ __forceinline__ void flush_counter(unsigned long long *dst, uint64_t 
 
 // Wave-uniform pool of work items [next, end), taken a block at a time: the
 // first block of every wave is fixed by its wave index (no atomic at start-up,
-// when every wave would hit the same counter at once), later blocks come from
-// a global counter that starts after the fixed ones.  The counter is shared by
-// every wave of the device, so its atomics are a serial point: large launches
-// take bigger blocks (fewer atomics), small ones keep 64-item blocks so that
-// the few items still spread over many waves.
+// when every wave would hit the same counter at once).  The items after the
+// fixed blocks are split into kPoolParts equal parts, each with its own counter
+// on its own 128-byte line: a wave draws from the part of its block index
+// modulo kPoolParts (workgroups go to the XCDs in turn, so that each XCD has a
+// part of its own) and, once that part is spent, from the next ones.  Atomics
+// on one counter are a serial point; parts divide them by kPoolParts, and large
+// launches take bigger blocks still.
+constexpr int kPoolParts = 8;
+constexpr int kPoolStride = 16;   // counters per 128-byte line
+
 __device__ __forceinline__ uint64_t pool_block(uint64_t total, uint64_t nwaves)
 {
     const uint64_t per_wave = total / nwaves;
@@ -66,31 +69,53 @@ __device__ __forceinline__ uint64_t pool_block(uint64_t total, uint64_t nwaves)
 struct WorkPool {
     uint64_t next = 0, end = 0;
     bool dry = false, started = false;
+    int part = 0, tried = 0;
 
-    // returns true for a lane that received an item (in `item`)
+    // next block of this wave; false once every part is spent
+    __device__ __forceinline__ bool refill(uint64_t total, unsigned long long *ctr)
+    {
+        const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
+        const uint64_t blk = pool_block(total, nwaves);
+        const uint64_t fixed = nwaves * blk;
+        if (!started) {
+            started = true;
+            part = (int)(blockIdx.x % kPoolParts);
+            const uint64_t base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * blk;
+            if (base < total) {
+                next = base;
+                end = base + blk < total ? base + blk : total;
+                return true;
+            }
+        }
+        const uint64_t rest = total > fixed ? total - fixed : 0;
+        const uint64_t len = (rest + kPoolParts - 1) / kPoolParts;
+        while (tried < kPoolParts) {
+            const uint64_t lo = fixed + (uint64_t)part * len;
+            const uint64_t hi = lo + len < total ? lo + len : total;
+            unsigned long long b = 0;
+            if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr + part * kPoolStride, (unsigned long long)blk);
+            const uint64_t base = lo + __shfl(b, 0, 64);
+            if (base < hi) {
+                next = base;
+                end = base + blk < hi ? base + blk : hi;
+                return true;
+            }
+            part = part + 1 == kPoolParts ? 0 : part + 1;
+            ++tried;
+        }
+        return false;
+    }
+
+    // returns true for a lane that received an item (in `item`); ctr points at
+    // the pool's kPoolParts counters, kPoolStride apart
     __device__ __forceinline__ bool take(bool want, uint64_t total, unsigned long long *ctr, uint64_t &item)
     {
         bool got = false;
         uint64_t need = __ballot(want);
         while (need && !dry) {
-            if (next >= end) {
-                const uint64_t nwaves = (uint64_t)gridDim.x * (blockDim.x >> 6);
-                const uint64_t blk = pool_block(total, nwaves);
-                uint64_t base;
-                if (!started) {
-                    base = ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * blk;
-                    started = true;
-                } else {
-                    unsigned long long b = 0;
-                    if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr, (unsigned long long)blk);
-                    base = nwaves * blk + __shfl(b, 0, 64);
-                }
-                next = base;
-                end = base + blk < total ? base + blk : total;
-                if (next >= total) {
-                    dry = true;
-                    break;
-                }
+            if (next >= end && !refill(total, ctr)) {
+                dry = true;
+                break;
             }
             const uint64_t avail = end - next;
             const uint64_t n = (uint64_t)__popcll(need);
