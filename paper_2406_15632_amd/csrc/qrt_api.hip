@@ -63,7 +63,7 @@ struct qrt_ctx {
     int faure_dims = 0;
     uint32_t faure_b = 0, faure_m = 0, faure_pow = 0;
     uint64_t faure_bm = 0;
-    unsigned long long *counters = nullptr;  // [CNT_COUNT]
+    unsigned long long *counters = nullptr;  // [kCounterCopies][kCounterLine], summed on read
     TransportBuffers tb = {};                // packet and ray queues of the transport
     uint64_t tb_packets = 0;                 // packets the queues hold
     uint64_t packets_run = 0;
@@ -154,6 +154,7 @@ SeqParams seq_params(const qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total
     return s;
 }
 
+constexpr size_t kCounterBytes = sizeof(unsigned long long) * kCounterCopies * kCounterLine;
 constexpr size_t kFaureTable = 8192;   // u32 entries: dims * m * m + m <= 128 * 25 + 5 (and 2 * 32 * 32 + 32)
 
 // Faure tables for `dims` coordinates: base b = smallest prime >= dims, m digits
@@ -311,8 +312,8 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     hipError_t e = hipMalloc(&c->tables, nt * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemcpy(c->tables, host, nt * sizeof(uint32_t), hipMemcpyHostToDevice);
     delete[] host;
-    if (e == hipSuccess) e = hipMalloc(&c->counters, CNT_COUNT * sizeof(unsigned long long));
-    if (e == hipSuccess) e = hipMemset(c->counters, 0, CNT_COUNT * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMalloc(&c->counters, kCounterBytes);
+    if (e == hipSuccess) e = hipMemset(c->counters, 0, kCounterBytes);
     if (e == hipSuccess) e = hipMalloc(&c->tb.q, sizeof(Queues));
     if (e == hipSuccess) e = hipMalloc(&c->tb.hist, sizeof(uint32_t) << kSortBits);
     if (e != hipSuccess) {
@@ -726,7 +727,7 @@ int qrt_reset_images(qrt_ctx *c)
     DeviceGuard dg(c->device);
     if (c->img)
         HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_alloc * sizeof(double), c->stream), "image reset");
-    HIP_TRY(c, hipMemsetAsync(c->counters, 0, CNT_COUNT * sizeof(unsigned long long), c->stream), "counter reset");
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, kCounterBytes, c->stream), "counter reset");
     c->packets_run = 0;
     return QRT_OK;
 }
@@ -735,9 +736,12 @@ int qrt_get_counters(qrt_ctx *c, qrt_counters *out)
 {
     if (!c || !out) return QRT_INVALID_ARG;
     DeviceGuard dg(c->device);
-    unsigned long long h[CNT_COUNT];
-    HIP_TRY(c, hipMemcpyAsync(h, c->counters, sizeof(h), hipMemcpyDeviceToHost, c->stream), "counter copy");
+    unsigned long long copies[kCounterCopies][kCounterLine];
+    HIP_TRY(c, hipMemcpyAsync(copies, c->counters, sizeof(copies), hipMemcpyDeviceToHost, c->stream), "counter copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "counter copy sync");
+    unsigned long long h[CNT_COUNT] = {};
+    for (int k = 0; k < kCounterCopies; ++k)
+        for (int i = 0; i < CNT_COUNT; ++i) h[i] += copies[k][i];
     out->packets = (int64_t)h[CNT_PACKETS];
     out->visits = (int64_t)h[CNT_VISITS];
     out->peels = (int64_t)h[CNT_PEELS];
@@ -1555,7 +1559,7 @@ int qrt_batch_reset(qrt_ctx *c)
     DeviceGuard dg(c->device);
     if (c->batch_img && c->batch_img_used)
         HIP_TRY(c, hipMemsetAsync(c->batch_img, 0, c->batch_img_used * sizeof(double), c->stream), "batch image reset");
-    HIP_TRY(c, hipMemsetAsync(c->counters, 0, CNT_COUNT * sizeof(unsigned long long), c->stream), "counter reset");
+    HIP_TRY(c, hipMemsetAsync(c->counters, 0, kCounterBytes, c->stream), "counter reset");
     c->batch_runs = 0;
     return QRT_OK;
 }

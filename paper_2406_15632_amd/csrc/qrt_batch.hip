@@ -204,9 +204,7 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
         }
     }
-    flush_counter(P.counters + CNT_PACKETS, n_packets);
-    flush_counter(P.counters + CNT_TAU_CUTS, n_cuts);
-    flush_counter(P.counters + CNT_VISITS, n_visits);
+    flush_counters<3>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS}, {n_packets, n_cuts, n_visits});
 }
 
 // ---------------------------------------------------------------- scattering
@@ -366,8 +364,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
             pks[slot] = st;
         }
     }
-    flush_counter(P.counters + CNT_SCATTERINGS, n_scat);
-    flush_counter(P.counters + CNT_OCCLUDED, n_occ);
+    flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
 }
 
 // ---------------------------------------------------------------- walks of one order
@@ -473,10 +470,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
             if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
         }
     }
-    flush_counter(P.counters + CNT_VISITS, n_visits);
-    flush_counter(P.counters + CNT_PEELS, n_peels);
-    flush_counter(P.counters + CNT_PEEL_RAYS, n_peels);
-    flush_counter(P.counters + CNT_ESCAPES, n_esc);
+    flush_counters<4>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES}, {n_visits, n_peels, n_peels, n_esc});
 }
 
 // ---------------------------------------------------------------- launch sequence

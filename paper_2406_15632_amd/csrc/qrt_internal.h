@@ -19,6 +19,12 @@ enum CounterSlot {
     CNT_PACKETS = 0, CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES, CNT_TAU_CUTS,
     CNT_SCATTERINGS, CNT_OCCLUDED, CNT_SURROGATE, CNT_FALLBACKS, CNT_COUNT
 };
+// The device counter array holds kCounterCopies copies of the slots, each on
+// its own 128-byte line: a block adds into copy blockIdx % kCounterCopies
+// (one per XCD), and a read sums the copies.
+constexpr int kCounterCopies = 8;
+constexpr int kCounterLine = 16;
+static_assert(CNT_COUNT <= kCounterLine, "the counter slots fit one line");
 
 struct DevObserver {
     double o[3], ex[3], ey[3];
@@ -81,7 +87,7 @@ struct TransportParams {
     double tau_min;
     double *img;                   // [sets][kImageCopies][n_obs][3][npix][npix]
     int order_images;              // 0: one set; K: one set per scattering order 1..K
-    unsigned long long *counters;  // [CNT_COUNT]
+    unsigned long long *counters;  // [kCounterCopies][kCounterLine]
     int peel_mode;                 // 0 exact traversal, 1 surrogate inside its valid cells
     SurrogateParams sur;
 };
@@ -183,7 +189,7 @@ struct BatchParams {
     int max_orders;             // largest over the scenes
     uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap),
                                 // kPeelGroups group_cap rays at most the peel buffer's capacity
-    unsigned long long *counters;
+    unsigned long long *counters;  // [kCounterCopies][kCounterLine]
 };
 
 // All `total` batch numbers of a batch, in chunks of at most `chunk`; begin[s]

@@ -267,9 +267,7 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
             if (__popcll(__ballot(W.done || phase == FF_IDLE)) >= kWaveRefill) break;
         }
     }
-    flush_counter(P.counters + CNT_PACKETS, n_packets);
-    flush_counter(P.counters + CNT_TAU_CUTS, n_cuts);
-    flush_counter(P.counters + CNT_VISITS, n_visits);
+    flush_counters<3>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS}, {n_packets, n_cuts, n_visits});
 }
 
 // --------------------------------------------------------------------------
@@ -412,8 +410,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
             pks[slot] = s;
         }
     }
-    flush_counter(P.counters + CNT_SCATTERINGS, n_scat);
-    flush_counter(P.counters + CNT_OCCLUDED, n_occ);
+    flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
 }
 
 // --------------------------------------------------------------------------
@@ -511,10 +508,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
             if (__popcll(__ballot(W.done || kind == WI_NONE)) >= kWaveRefill) break;
         }
     }
-    flush_counter(P.counters + CNT_VISITS, n_visits);
-    flush_counter(P.counters + CNT_PEELS, n_peels);
-    flush_counter(P.counters + CNT_PEEL_RAYS, n_peels);
-    flush_counter(P.counters + CNT_ESCAPES, n_esc);
+    flush_counters<4>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES}, {n_visits, n_peels, n_peels, n_esc});
 }
 
 // --------------------------------------------------------------------------
@@ -639,9 +633,7 @@ __global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, int o
         }
     }
     if (count > 0) peel_mlp_batch<R>(P, L, w, lane, count, peels, img_copy, plane);
-    flush_counter(P.counters + CNT_SURROGATE, n_sur);
-    flush_counter(P.counters + CNT_FALLBACKS, n_fb);
-    flush_counter(P.counters + CNT_PEELS, n_sur);
+    flush_counters<3>(P.counters, {CNT_SURROGATE, CNT_FALLBACKS, CNT_PEELS}, {n_sur, n_fb, n_sur});
 }
 
 // Pilot capture: (position, observer) of every visible peel ray inside the

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qrt_internal.h"
 #include "qrt_physics.h"
 
 namespace qrt {
@@ -42,10 +43,26 @@ __host__ __device__ __forceinline__ size_t peel_slot(uint32_t i, int ob, int n_o
 }
 constexpr int kWaveRefill = 64;   // refill a wave once all its lanes are idle: keeps its rays coherent
 
-__device__ __forceinline__ void flush_counter(unsigned long long *dst, uint64_t v)
+// Adds the per-lane values v[i] to counter slots slot[i]: summed over the
+// wave, then over the block in LDS, then one atomic per block and slot into
+// the block's copy of the counters.  A device-wide atomic per wave would put
+// thousands of read-modify-writes on one line at the end of every launch.
+// Every thread of the block calls it.
+template <int N>
+__device__ __forceinline__ void flush_counters(unsigned long long *counters, const int (&slot)[N],
+                                               const uint64_t (&v)[N])
 {
-    const uint64_t s = wave_sum_u64(v);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(dst, (unsigned long long)s);
+    __shared__ unsigned long long s_sum[N];
+    if (threadIdx.x < N) s_sum[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint64_t s = wave_sum_u64(v[i]);
+        if ((threadIdx.x & 63) == 0 && s) atomicAdd(&s_sum[i], (unsigned long long)s);
+    }
+    __syncthreads();
+    if (threadIdx.x < N && s_sum[threadIdx.x])
+        atomicAdd(counters + (blockIdx.x % kCounterCopies) * kCounterLine + slot[threadIdx.x], s_sum[threadIdx.x]);
 }
 
 // Wave-uniform pool of work items [next, end), taken a block at a time: the
@@ -92,13 +109,15 @@ struct WorkPool {
         while (tried < kPoolParts) {
             const uint64_t lo = fixed + (uint64_t)part * len;
             const uint64_t hi = lo + len < total ? lo + len : total;
-            unsigned long long b = 0;
-            if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr + part * kPoolStride, (unsigned long long)blk);
-            const uint64_t base = lo + __shfl(b, 0, 64);
-            if (base < hi) {
-                next = base;
-                end = base + blk < hi ? base + blk : hi;
-                return true;
+            if (lo < hi) {
+                unsigned long long b = 0;
+                if ((threadIdx.x & 63) == 0) b = atomicAdd(ctr + part * kPoolStride, (unsigned long long)blk);
+                const uint64_t base = lo + __shfl(b, 0, 64);
+                if (base < hi) {
+                    next = base;
+                    end = base + blk < hi ? base + blk : hi;
+                    return true;
+                }
             }
             part = part + 1 == kPoolParts ? 0 : part + 1;
             ++tried;
