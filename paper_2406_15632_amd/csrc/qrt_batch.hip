@@ -64,10 +64,15 @@ __device__ __forceinline__ int forced_tau_dim(const BScene &S) { return S.src_ki
 
 // Emission of a packet of scene S (point source, or a sphere star in the
 // direct or the inverse order of the coordinates), as in the single-scene path.
+// Each branch computes into local arrays and p, k are assigned once at the
+// end: assignments to p and k on several paths would keep them in private
+// memory.
 template <typename R, int KIND>
-__device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, uint64_t idx, R p[3], R k[3])
+__device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, uint64_t idx, R p_out[3],
+                                           R k_out[3])
 {
     uint32_t xa[3], xb[3];
+    R p[3], k[3];
     seq_triple<KIND>(q, idx, 0, xa);
     if (S.src_kind == 0) {
         R sp, cp;
@@ -76,38 +81,43 @@ __device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, 
         const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
         for (int a = 0; a < 3; ++a) p[a] = (R)S.src[a];
         k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-        return;
-    }
-    seq_triple<KIND>(q, idx, 2, xb);
-    if (S.src_kind == 1) {
-        // direct order: point on the star (v1, v2), local direction (v3, v4)
-        R spe, cpe, spl, cpl;
-        sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
-        const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
-        const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
-        sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
-        const R ctl = sqrt(to_unit<R>(xb[1]));
-        const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
-        const R ne[3] = {ste * cpe, ste * spe, cte};
-        const R t1[3] = {cte * cpe, cte * spe, -ste};
-        const R t2[3] = {-spe, cpe, (R)0};
-        for (int a = 0; a < 3; ++a) {
-            p[a] = (R)S.src[a] + (R)S.r_star * ne[a];
-            k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
-        }
     } else {
-        // inverse order: direction (v1, v2), emission point about it (v4, v5)
-        R sp, cp, spr, cpr;
-        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
-        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
-        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-        sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
-        const R ca = sqrt(to_unit<R>(xb[2]));
-        const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
-        const R t1[3] = {ct * cp, ct * sp, -st};
-        const R t2[3] = {-sp, cp, (R)0};
-        for (int a = 0; a < 3; ++a) p[a] = (R)S.src[a] + (R)S.r_star * (ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]));
+        seq_triple<KIND>(q, idx, 2, xb);
+        if (S.src_kind == 1) {
+            // direct order: point on the star (v1, v2), local direction (v3, v4)
+            R spe, cpe, spl, cpl;
+            sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
+            const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
+            const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
+            sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
+            const R ctl = sqrt(to_unit<R>(xb[1]));
+            const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
+            const R ne[3] = {ste * cpe, ste * spe, cte};
+            const R t1[3] = {cte * cpe, cte * spe, -ste};
+            const R t2[3] = {-spe, cpe, (R)0};
+            for (int a = 0; a < 3; ++a) {
+                p[a] = (R)S.src[a] + (R)S.r_star * ne[a];
+                k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
+            }
+        } else {
+            // inverse order: direction (v1, v2), emission point about it (v4, v5)
+            R sp, cp, spr, cpr;
+            sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
+            const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
+            const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
+            k[0] = st * cp; k[1] = st * sp; k[2] = ct;
+            sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
+            const R ca = sqrt(to_unit<R>(xb[2]));
+            const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
+            const R t1[3] = {ct * cp, ct * sp, -st};
+            const R t2[3] = {-sp, cp, (R)0};
+            for (int a = 0; a < 3; ++a)
+                p[a] = (R)S.src[a] + (R)S.r_star * (ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]));
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        p_out[a] = p[a];
+        k_out[a] = k[a];
     }
 }
 

@@ -155,7 +155,10 @@ __device__ __forceinline__ void axis_setup(const GT &G, int a, R p, R d, int &c,
 }
 
 // Start a walk from p along unit d.  Returns false (and a finished walk with
-// tau = 0) for non-finite input or a zero direction.
+// tau = 0) for non-finite input or a zero direction.  Such input is set up
+// like a ray from the mesh corner along +x, so that every field of the state
+// is assigned on one path (separate assignments on a second path lead the
+// compiler to keep the face spacings in private memory).
 template <typename R, typename GT>
 __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3], const R d[3], int mode,
                                            double target)
@@ -170,23 +173,14 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
     W.jx = W.jy = W.jz = (R)0;
     const bool ok = isfinite(p[0]) && isfinite(p[1]) && isfinite(p[2]) && isfinite(d[0]) && isfinite(d[1]) &&
                     isfinite(d[2]) && (fabs(d[0]) > (R)1e-30 || fabs(d[1]) > (R)1e-30 || fabs(d[2]) > (R)1e-30);
-    if (!ok) {
-        W.done = true;
-        W.cx = W.cy = W.cz = 0;
-        W.sx = W.sy = W.sz = 0;
-        W.t_exit = (R)0;
-        W.T0x = W.T0y = W.T0z = W.tx = W.ty = W.tz = r_inf<R>();
-        W.Dx = W.Dy = W.Dz = (R)0;
-        return false;
-    }
-    W.done = false;
+    W.done = !ok;
     R bx, by, bz;
-    axis_setup(G, 0, p[0], d[0], W.cx, W.T0x, W.Dx, bx, W.sx);
-    axis_setup(G, 1, p[1], d[1], W.cy, W.T0y, W.Dy, by, W.sy);
-    axis_setup(G, 2, p[2], d[2], W.cz, W.T0z, W.Dz, bz, W.sz);
+    axis_setup(G, 0, ok ? p[0] : G.lo[0], ok ? d[0] : (R)1, W.cx, W.T0x, W.Dx, bx, W.sx);
+    axis_setup(G, 1, ok ? p[1] : G.lo[1], ok ? d[1] : (R)0, W.cy, W.T0y, W.Dy, by, W.sy);
+    axis_setup(G, 2, ok ? p[2] : G.lo[2], ok ? d[2] : (R)0, W.cz, W.T0z, W.Dz, bz, W.sz);
     W.tx = W.T0x; W.ty = W.T0y; W.tz = W.T0z;
     W.t_exit = fmin(bx, fmin(by, bz));
-    return true;
+    return ok;
 }
 
 // B steps of a walk (no effect once done).  The cell sequence does not depend
