@@ -14,10 +14,12 @@
         scaled by the factor the same counter shows for the copy probe;
 
     python -m paper_2406_15632_amd.profile_report counters OUT.md "COMMANDS" DIR...
-        L2 hit rate, VALU busy, VALU lane utilization and the share of wave
-        time spent waiting, per transport kernel, from --pmc runs of
-        TCC_HIT_sum TCC_MISS_sum and of SQ_ACTIVE_INST_VALU
-        SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_ANY SQ_WAVE_CYCLES GRBM_GUI_ACTIVE;
+        L2 hit rate, VALU busy, VALU lane utilization, the share of wave
+        time spent waiting and texture address / data busy, per transport
+        kernel, from --pmc runs of TCC_HIT_sum TCC_MISS_sum, of
+        SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_WAIT_INST_ANY
+        SQ_WAVE_CYCLES GRBM_GUI_ACTIVE and of TA_TA_BUSY_sum TD_TD_BUSY_sum
+        GRBM_GUI_ACTIVE;
 
     python -m paper_2406_15632_amd.profile_report trace-batch DIR RUNS OUT.md "COMMAND"
         per-kernel durations of the batched kernels (k_b*, sort steps of the
@@ -81,31 +83,54 @@ def trace_summary(d: str, launches: int, out: str, command: str, select=_transpo
     print("\n".join(lines))
 
 
+def _agent(d):
+    """(XCDs, CUs) of the profiled GPU, from rocprofv3's agent table."""
+    for f in glob.glob(os.path.join(d, "**", "*agent_info.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r.get("Name", "").startswith("gfx") and int(r.get("Cu_Count") or 0) > 0:
+                return int(r["Num_Xcc"]), int(r["Cu_Count"])
+    raise RuntimeError(f"no GPU agent in {d}")
+
+
 def counters(out: str, commands: str, *dirs):
-    """Per transport kernel: L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS); VALU
-    busy 100 SQ_ACTIVE_INST_VALU / (CUs GRBM_GUI_ACTIVE), summed over the
-    kernel's dispatches (the rocprofv3 VALUBusy definition); VALU lane
-    utilization 100 SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU); the share
-    of wave cycles spent waiting on an instruction's inputs,
-    SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES."""
-    tot = collections.defaultdict(lambda: collections.defaultdict(float))
+    """Per transport kernel, summed over its dispatches: L2 hit rate
+    TCC_HIT / (TCC_HIT + TCC_MISS); VALU busy 100 SQ_ACTIVE_INST_VALU / (CUs
+    cycles), the rocprofv3 VALUBusy definition; VALU lane utilization
+    100 SQ_THREAD_CYCLES_VALU / (64 SQ_ACTIVE_INST_VALU); the share of wave
+    cycles spent waiting on an instruction's inputs, SQ_WAIT_INST_ANY /
+    SQ_WAVE_CYCLES; texture address (TA) and texture data (TD) busy,
+    100 TA_TA_BUSY / (CUs cycles) and the same for TD_TD_BUSY.  The cycles of a
+    dispatch are GRBM_GUI_ACTIVE of one XCD: the counter is reported summed
+    over the XCDs, each of which counts the whole dispatch, so it is divided by
+    their number.  Each ratio uses the cycles of the run that took its
+    counters."""
+    metrics = collections.defaultdict(dict)
     for d in dirs:
+        n_xcc, cus = _agent(d)
         for k, v in _pmc_totals(d).items():
-            for n, x in v.items():
-                tot[k][n] += x
-    cus = 256
+            if not _transport(k):
+                continue
+            cycles = max(1.0, v.get("GRBM_GUI_ACTIVE", 0.0) / n_xcc)
+            m = metrics[k]
+            if "TCC_HIT_sum" in v:
+                m["hit"] = 100 * v["TCC_HIT_sum"] / max(1.0, v["TCC_HIT_sum"] + v["TCC_MISS_sum"])
+            if "SQ_ACTIVE_INST_VALU" in v:
+                m["busy"] = 100 * v["SQ_ACTIVE_INST_VALU"] / cus / cycles
+                m["lanes"] = 100 * v["SQ_THREAD_CYCLES_VALU"] / max(1.0, 64 * v["SQ_ACTIVE_INST_VALU"])
+                m["wait"] = 100 * v["SQ_WAIT_INST_ANY"] / max(1.0, v["SQ_WAVE_CYCLES"])
+            if "TA_TA_BUSY_sum" in v:
+                m["ta"] = 100 * v["TA_TA_BUSY_sum"] / cus / cycles
+                m["td"] = 100 * v["TD_TD_BUSY_sum"] / cus / cycles
     lines = ["# rocprofv3 counters of the transport kernels (disk128)", "", "Commands:", "", "```", commands, "```",
-             "", "| kernel | L2 hit % | VALU busy % | VALU lanes active % | wave cycles waiting % |",
-             "|---|---|---|---|---|"]
-    for k in sorted(tot):
-        if not _transport(k):
-            continue
-        v = tot[k]
-        hit = v["TCC_HIT_sum"] / max(1.0, v["TCC_HIT_sum"] + v["TCC_MISS_sum"]) * 100
-        busy = 100 * v["SQ_ACTIVE_INST_VALU"] / cus / max(1.0, v["GRBM_GUI_ACTIVE"])
-        lanes = 100 * v["SQ_THREAD_CYCLES_VALU"] / max(1.0, 64 * v["SQ_ACTIVE_INST_VALU"])
-        wait = 100 * v["SQ_WAIT_INST_ANY"] / max(1.0, v["SQ_WAVE_CYCLES"])
-        lines.append(f"| `{k.replace('void ', '')}` | {hit:.1f} | {busy:.1f} | {lanes:.1f} | {wait:.1f} |")
+             "", "| kernel | L2 hit % | VALU busy % | VALU lanes active % | wave cycles waiting % | TA busy % "
+             "| TD busy % |", "|---|---|---|---|---|---|---|"]
+
+    def f(m, key):
+        return f"{m[key]:.1f}" if key in m else "-"
+    for k in sorted(metrics):
+        m = metrics[k]
+        lines.append(f"| `{k.replace('void ', '')}` | {f(m, 'hit')} | {f(m, 'busy')} | {f(m, 'lanes')} | "
+                     f"{f(m, 'wait')} | {f(m, 'ta')} | {f(m, 'td')} |")
     lines.append("")
     open(out, "w").write("\n".join(lines))
     print("\n".join(lines))
