@@ -109,8 +109,9 @@ int qrt_set_stream(qrt_ctx *ctx, void *hip_stream);
    holds the constant extinction kappa*rho (FP32), laid out [nz][ny][nx] with x
    fastest.  flags is one of QRT_GRID_*.  Cells must be finite and >= 0 (checked
    for host input).  The library copies the mesh into its own order (bricks of
-   4x4x4 cells, at most 2^29 cells after rounding each axis up to a multiple
-   of 4); the caller's buffer is not used after the call returns. */
+   4x4x4 cells, the brick counts along x and y rounded up to powers of two; at
+   most 2^29 stored cells, else QRT_UNSUPPORTED); the caller's buffer is not
+   used after the call returns. */
 int qrt_set_grid(qrt_ctx *ctx, int nx, int ny, int nz, const double lo[3], const double hi[3],
                  const float *kappa_rho, int flags);
 

@@ -373,8 +373,8 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
     if (!c) return QRT_INVALID_ARG;
     if (nx < 1 || ny < 1 || nz < 1 || !lo || !hi || !kappa_rho)
         return fail(c, QRT_INVALID_ARG, "bad grid arguments");
-    const int64_t bricked = (int64_t)bricks_of(nx) * bricks_of(ny) * bricks_of(nz) * (kBrick * kBrick * kBrick);
-    if (bricked > (int64_t)1 << 29) return fail(c, QRT_UNSUPPORTED, "grid too large (at most 2^29 cells)");
+    const int64_t bricked = mesh_cells(nx, ny, nz);
+    if (bricked > (int64_t)1 << 29) return fail(c, QRT_UNSUPPORTED, "grid too large (at most 2^29 stored cells)");
     for (int a = 0; a < 3; ++a)
         if (!(hi[a] > lo[a]) || !isfinite(lo[a]) || !isfinite(hi[a]))
             return fail(c, QRT_INVALID_ARG, "box must satisfy lo < hi on every axis");
@@ -395,7 +395,9 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
         HIP_TRY(c, hipMalloc(&c->grid, (size_t)bricked * sizeof(float)), "grid allocation");
         c->grid_alloc = (size_t)bricked;
     }
-    const int nbx = bricks_of(nx), nby = bricks_of(ny);
+    int nb[3];
+    mesh_bricks(nx, ny, nz, nb);
+    const int nbx = nb[0], nby = nb[1];
     if (flags == QRT_GRID_HOST_COPY) {
         std::vector<float> b((size_t)bricked, 0.0f);
         for (int z = 0; z < nz; ++z)
@@ -529,7 +531,7 @@ static DevGrid dev_grid(const qrt_ctx *c)
     DevGrid g;
     g.kr = c->grid;
     g.nx = c->n[0]; g.ny = c->n[1]; g.nz = c->n[2];
-    for (int a = 0; a < 3; ++a) g.nb[a] = bricks_of(c->n[a]);
+    mesh_bricks(c->n[0], c->n[1], c->n[2], g.nb);
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = c->lo[a];
         g.hi[a] = c->hi[a];
@@ -1351,8 +1353,8 @@ static int batch_scene_check(qrt_ctx *c, int i, const qrt_batch_scene &S)
 {
     if (S.nx < 1 || S.ny < 1 || S.nz < 1 || !S.kappa_rho)
         return fail(c, QRT_INVALID_ARG, "scene %d: bad grid arguments", i);
-    if ((int64_t)bricks_of(S.nx) * bricks_of(S.ny) * bricks_of(S.nz) * (kBrick * kBrick * kBrick) > (int64_t)1 << 29)
-        return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large (at most 2^29 cells)", i);
+    if (mesh_cells(S.nx, S.ny, S.nz) > (int64_t)1 << 29)
+        return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large (at most 2^29 stored cells)", i);
     for (int a = 0; a < 3; ++a)
         if (!(S.hi[a] > S.lo[a]) || !isfinite(S.lo[a]) || !isfinite(S.hi[a]))
             return fail(c, QRT_INVALID_ARG, "scene %d: box must satisfy lo < hi on every axis", i);
@@ -1404,7 +1406,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         const qrt_batch_scene &S = scenes[i];
         const int rc = batch_scene_check(c, i, S);
         if (rc < 0) return rc;
-        cells += (size_t)bricks_of(S.nx) * bricks_of(S.ny) * bricks_of(S.nz) * (kBrick * kBrick * kBrick);
+        cells += (size_t)mesh_cells(S.nx, S.ny, S.nz);
         pixels += (size_t)kImageCopies * S.n_obs * 3 * (size_t)S.npix * (size_t)S.npix;
         if (total + S.count < total) return fail(c, QRT_INVALID_ARG, "packet total overflows");
         total += S.count;
@@ -1438,7 +1440,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
         BScene &B = host[(size_t)i];
         memset(&B, 0, sizeof(B));
         B.n[0] = S.nx; B.n[1] = S.ny; B.n[2] = S.nz;
-        for (int a = 0; a < 3; ++a) B.nb[a] = bricks_of(B.n[a]);
+        mesh_bricks(B.n[0], B.n[1], B.n[2], B.nb);
         const size_t nc = (size_t)B.nb[0] * B.nb[1] * B.nb[2] * (kBrick * kBrick * kBrick);
         std::vector<float> bricked(nc, 0.0f);
         for (int z = 0; z < S.nz; ++z)

@@ -43,6 +43,7 @@ __device__ __forceinline__ LaneGrid<R> lane_grid(const BScene &S)
     G.kr = S.kr;
     G.nbx = S.nb[0];
     G.nby = S.nb[1];
+    axis_masks(S.nb[0], S.nb[1], G.m);
     for (int a = 0; a < 3; ++a) {
         G.n[a] = S.n[a];
         G.lo[a] = (R)S.lo[a];

@@ -812,8 +812,9 @@ hipError_t launch_to_bricks(const float *src, float *dst, int nx, int ny, int nz
     if (n == 0) return hipSuccess;
     const size_t need = (n + 255) / 256;
     const int blocks = (int)(need < 8192 ? need : 8192);
-    hipLaunchKernelGGL(k_to_bricks, dim3(blocks), dim3(256), 0, stream, src, dst, nx, ny, nz, bricks_of(nx),
-                       bricks_of(ny));
+    int nb[3];
+    mesh_bricks(nx, ny, nz, nb);
+    hipLaunchKernelGGL(k_to_bricks, dim3(blocks), dim3(256), 0, stream, src, dst, nx, ny, nz, nb[0], nb[1]);
     return hipGetLastError();
 }
 

@@ -25,8 +25,11 @@
 // Cell order in memory: every mesh is stored in bricks of 4x4x4
 // cells (bricks x fastest, then y, then z; inside a brick x fastest), so that
 // one 128-byte line holds a 4x4x2 block and a ray crossing a brick stays on
-// few lines whatever its direction.  The walk keeps the cell's coordinates
-// and asks the grid type for the element index.
+// few lines whatever its direction.  The brick counts along x and y are
+// padded to powers of two: an element index is then the OR of one part per
+// axis, each in bit fields of its own, and the walk moves the part of the
+// axis it steps along by one with an add whose carry runs across the other
+// axes' bits (a dilated-integer increment).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +41,25 @@ constexpr int kBrick = 4;   // cells per brick edge
 
 __host__ __device__ inline int bricks_of(int n) { return (n + kBrick - 1) / kBrick; }
 
+// Stored bricks per axis of an nx x ny x nz mesh: a power of two along x and
+// y, bricks_of(nz) along z.
+__host__ __device__ inline void mesh_bricks(int nx, int ny, int nz, int nb[3])
+{
+    nb[0] = 1;
+    while (nb[0] < bricks_of(nx)) nb[0] <<= 1;
+    nb[1] = 1;
+    while (nb[1] < bricks_of(ny)) nb[1] <<= 1;
+    nb[2] = bricks_of(nz);
+}
+
+// stored cells of a mesh (the cells past its edge hold 0)
+__host__ __device__ inline int64_t mesh_cells(int nx, int ny, int nz)
+{
+    int nb[3];
+    mesh_bricks(nx, ny, nz, nb);
+    return (int64_t)nb[0] * nb[1] * nb[2] * (kBrick * kBrick * kBrick);
+}
+
 // element index of cell (x, y, z) in the bricked order; nbx, nby bricks along x, y
 __host__ __device__ inline int brick_index(int x, int y, int z, int nbx, int nby)
 {
@@ -45,10 +67,24 @@ __host__ __device__ inline int brick_index(int x, int y, int z, int nbx, int nby
     return (brick << 6) | ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
 }
 
+// Bit fields of each axis' part of an element index, for nbx = 2^lx and
+// nby = 2^ly bricks: x in bits 0-1 and 6 .. 5+lx, y in bits 2-3 and
+// 6+lx .. 5+lx+ly, z in bits 4-5 and from 6+lx+ly up.  The index of
+// (x, y, z) is brick_index(x, 0, 0) | brick_index(0, y, 0) | brick_index(0, 0, z).
+__host__ __device__ inline void axis_masks(int nbx, int nby, uint32_t m[3])
+{
+    int lx = 0, ly = 0;
+    while ((1 << lx) < nbx) ++lx;
+    while ((1 << ly) < nby) ++ly;
+    m[0] = 0x03u | (((1u << lx) - 1u) << 6);
+    m[1] = 0x0Cu | (((1u << ly) - 1u) << (6 + lx));
+    m[2] = 0x30u | (~0u << (6 + lx + ly));
+}
+
 struct DevGrid {
     const float *kr;      // bricked: [nbz][nby][nbx][4][4][4], cells outside the mesh 0
     int nx, ny, nz;
-    int nb[3];            // bricks per axis
+    int nb[3];            // stored bricks per axis (mesh_bricks)
     double lo[3], hi[3], h[3];
 };
 
@@ -57,6 +93,7 @@ struct RayGrid {
     __amdgpu_buffer_rsrc_t rsrc;
     int n[3];
     int nbx, nby;
+    uint32_t m[3];        // axis_masks
     R lo[3], h[3];
 };
 
@@ -69,6 +106,7 @@ __device__ __forceinline__ RayGrid<R> ray_grid(const DevGrid &g)
     r.n[0] = g.nx; r.n[1] = g.ny; r.n[2] = g.nz;
     r.nbx = g.nb[0];
     r.nby = g.nb[1];
+    axis_masks(g.nb[0], g.nb[1], r.m);
     for (int a = 0; a < 3; ++a) { r.lo[a] = (R)g.lo[a]; r.h[a] = (R)g.h[a]; }
     return r;
 }
@@ -81,6 +119,7 @@ struct LaneGrid {
     const float *kr;
     int n[3];
     int nbx, nby;
+    uint32_t m[3];        // axis_masks
     R lo[3], h[3];
 };
 
@@ -89,21 +128,9 @@ template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_h
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
 
 template <typename R>
-__device__ __forceinline__ int cell_index(const RayGrid<R> &G, int x, int y, int z)
-{
-    return brick_index(x, y, z, G.nbx, G.nby);
-}
-
-template <typename R>
 __device__ __forceinline__ R load_kr(const RayGrid<R> &G, int cell)
 {
     return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, cell * 4, 0, 0));
-}
-
-template <typename R>
-__device__ __forceinline__ int cell_index(const LaneGrid<R> &G, int x, int y, int z)
-{
-    return brick_index(x, y, z, G.nbx, G.nby);
 }
 
 template <typename R>
@@ -122,7 +149,8 @@ struct Walk {
     R jx, jy, jz;                  // faces crossed per axis
     R tx, ty, tz;                  // next face distance per axis
     R t, t_exit;
-    int cx, cy, cz;                // cell coordinates
+    uint32_t ox, oy, oz;           // each axis' part of the cell's element index
+    uint32_t ux, uy, uz;           // per axis: the bits outside its part for a step up, 0 for a step down
     int sx, sy, sz;                // step per axis: -1, 0 or +1
     double tau, target;
     int mode;
@@ -175,11 +203,18 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
                     isfinite(d[2]) && (fabs(d[0]) > (R)1e-30 || fabs(d[1]) > (R)1e-30 || fabs(d[2]) > (R)1e-30);
     W.done = !ok;
     R bx, by, bz;
-    axis_setup(G, 0, ok ? p[0] : G.lo[0], ok ? d[0] : (R)1, W.cx, W.T0x, W.Dx, bx, W.sx);
-    axis_setup(G, 1, ok ? p[1] : G.lo[1], ok ? d[1] : (R)0, W.cy, W.T0y, W.Dy, by, W.sy);
-    axis_setup(G, 2, ok ? p[2] : G.lo[2], ok ? d[2] : (R)0, W.cz, W.T0z, W.Dz, bz, W.sz);
+    int cx, cy, cz;
+    axis_setup(G, 0, ok ? p[0] : G.lo[0], ok ? d[0] : (R)1, cx, W.T0x, W.Dx, bx, W.sx);
+    axis_setup(G, 1, ok ? p[1] : G.lo[1], ok ? d[1] : (R)0, cy, W.T0y, W.Dy, by, W.sy);
+    axis_setup(G, 2, ok ? p[2] : G.lo[2], ok ? d[2] : (R)0, cz, W.T0z, W.Dz, bz, W.sz);
     W.tx = W.T0x; W.ty = W.T0y; W.tz = W.T0z;
     W.t_exit = fmin(bx, fmin(by, bz));
+    W.ox = (uint32_t)brick_index(cx, 0, 0, G.nbx, G.nby);
+    W.oy = (uint32_t)brick_index(0, cy, 0, G.nbx, G.nby);
+    W.oz = (uint32_t)brick_index(0, 0, cz, G.nbx, G.nby);
+    W.ux = W.sx > 0 ? ~G.m[0] : 0u;
+    W.uy = W.sy > 0 ? ~G.m[1] : 0u;
+    W.uz = W.sz > 0 ? ~G.m[2] : 0u;
     return ok;
 }
 
@@ -204,18 +239,22 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         const bool mz = !mx && !my;
         const R tn = fmin(W.tx, fmin(W.ty, W.tz));
         nv += alive ? 1u : 0u;
-        cells[b] = cell_index(G, W.cx, W.cy, W.cz);
+        cells[b] = (int)(W.ox | W.oy | W.oz);
         t0s[b] = W.t;
         const R seg = tn - W.t;
         segs[b] = seg > (R)0 ? seg : (R)0;
         W.t = tn > W.t ? tn : W.t;
         // the face about to be crossed is a boundary face: the walk ends in this cell
         const bool adv = tn < W.t_exit;
-        // coordinate step of the chosen axis as mask arithmetic (a select
-        // between struct fields would become a load from a selected address)
-        W.cx += W.sx & -(int)(adv && mx);
-        W.cy += W.sy & -(int)(adv && my);
-        W.cz += W.sz & -(int)(adv && mz);
+        // the chosen axis' part moves by one: the carry (or borrow) runs
+        // through the other axes' bits, set beforehand for a step up, and the
+        // mask clears them again
+        const uint32_t nox = ((W.ox | W.ux) + (uint32_t)W.sx) & G.m[0];
+        const uint32_t noy = ((W.oy | W.uy) + (uint32_t)W.sy) & G.m[1];
+        const uint32_t noz = ((W.oz | W.uz) + (uint32_t)W.sz) & G.m[2];
+        W.ox = (adv && mx) ? nox : W.ox;
+        W.oy = (adv && my) ? noy : W.oy;
+        W.oz = (adv && mz) ? noz : W.oz;
         W.jx += (adv && mx) ? (R)1 : (R)0;
         W.jy += (adv && my) ? (R)1 : (R)0;
         W.jz += (adv && mz) ? (R)1 : (R)0;
