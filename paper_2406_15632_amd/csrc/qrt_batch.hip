@@ -210,9 +210,17 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             phase = BF_EDGE;
         }
         if (__ballot(phase != BF_IDLE) == 0 && pool.dry) break;
-        for (;;) {
-            walk_batch<R, kWalkBatch>(W, G);
-            if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
+        if (__ballot(phase == BF_FORCED) == 0) {
+            // no lane moves to a target: walks to the edge only
+            for (;;) {
+                walk_batch_edge<R, kWalkBatch>(W, G);
+                if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
+            }
+        } else {
+            for (;;) {
+                walk_batch<R, kWalkBatch>(W, G);
+                if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
+            }
         }
     }
     flush_counters<3>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS}, {n_packets, n_cuts, n_visits});
@@ -476,9 +484,17 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
             if (pool.dry) break;
             continue;
         }
-        for (;;) {
-            walk_batch<R, kFlightBatch>(W, G);
-            if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
+        if (__ballot(kind == BW_MOVE) == 0) {
+            // no lane moves to a target: walks to the edge only
+            for (;;) {
+                walk_batch_edge<R, kFlightBatch>(W, G);
+                if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
+            }
+        } else {
+            for (;;) {
+                walk_batch<R, kFlightBatch>(W, G);
+                if (__popcll(__ballot(W.done || kind == BW_NONE)) >= kWaveRefill) break;
+            }
         }
     }
     flush_counters<4>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES}, {n_visits, n_peels, n_peels, n_esc});

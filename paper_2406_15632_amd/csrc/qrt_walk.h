@@ -67,18 +67,19 @@ __host__ __device__ inline int brick_index(int x, int y, int z, int nbx, int nby
     return (brick << 6) | ((z & 3) << 4) | ((y & 3) << 2) | (x & 3);
 }
 
-// Bit fields of each axis' part of an element index, for nbx = 2^lx and
-// nby = 2^ly bricks: x in bits 0-1 and 6 .. 5+lx, y in bits 2-3 and
-// 6+lx .. 5+lx+ly, z in bits 4-5 and from 6+lx+ly up.  The index of
-// (x, y, z) is brick_index(x, 0, 0) | brick_index(0, y, 0) | brick_index(0, 0, z).
+// Bit fields of each axis' part of an element's byte offset (4 times its
+// index), for nbx = 2^lx and nby = 2^ly bricks: x in bits 2-3 and 8 .. 7+lx,
+// y in bits 4-5 and 8+lx .. 7+lx+ly, z in bits 6-7 and from 8+lx+ly up.  The
+// index of (x, y, z) is brick_index(x, 0, 0) | brick_index(0, y, 0) |
+// brick_index(0, 0, z).
 __host__ __device__ inline void axis_masks(int nbx, int nby, uint32_t m[3])
 {
     int lx = 0, ly = 0;
     while ((1 << lx) < nbx) ++lx;
     while ((1 << ly) < nby) ++ly;
-    m[0] = 0x03u | (((1u << lx) - 1u) << 6);
-    m[1] = 0x0Cu | (((1u << ly) - 1u) << (6 + lx));
-    m[2] = 0x30u | (~0u << (6 + lx + ly));
+    m[0] = 0x0Cu | (((1u << lx) - 1u) << 8);
+    m[1] = 0x30u | (((1u << ly) - 1u) << (8 + lx));
+    m[2] = 0xC0u | (~0u << (8 + lx + ly));
 }
 
 struct DevGrid {
@@ -127,16 +128,17 @@ template <typename R> __device__ __forceinline__ R r_inf();
 template <> __device__ __forceinline__ float r_inf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double r_inf<double>() { return __builtin_huge_val(); }
 
+// kappa*rho of the cell at byte offset `at`
 template <typename R>
-__device__ __forceinline__ R load_kr(const RayGrid<R> &G, int cell)
+__device__ __forceinline__ R load_kr(const RayGrid<R> &G, uint32_t at)
 {
-    return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, cell * 4, 0, 0));
+    return (R)__uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(G.rsrc, (int)at, 0, 0));
 }
 
 template <typename R>
-__device__ __forceinline__ R load_kr(const LaneGrid<R> &G, int cell)
+__device__ __forceinline__ R load_kr(const LaneGrid<R> &G, uint32_t at)
 {
-    return (R)G.kr[cell];
+    return (R)*(const float *)((const char *)G.kr + at);
 }
 
 enum WalkMode { WALK_EDGE = 0, WALK_MOVE = 1 };
@@ -149,9 +151,9 @@ struct Walk {
     R jx, jy, jz;                  // faces crossed per axis
     R tx, ty, tz;                  // next face distance per axis
     R t, t_exit;
-    uint32_t ox, oy, oz;           // each axis' part of the cell's element index
+    uint32_t ox, oy, oz;           // each axis' part of the cell's byte offset
     uint32_t ux, uy, uz;           // per axis: the bits outside its part for a step up, 0 for a step down
-    int sx, sy, sz;                // step per axis: -1, 0 or +1
+    int sx, sy, sz;                // step of the part per axis: -4, 0 or +4 (one cell)
     double tau, target;
     int mode;
     bool done, stopped;
@@ -203,35 +205,32 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
                     isfinite(d[2]) && (fabs(d[0]) > (R)1e-30 || fabs(d[1]) > (R)1e-30 || fabs(d[2]) > (R)1e-30);
     W.done = !ok;
     R bx, by, bz;
-    int cx, cy, cz;
-    axis_setup(G, 0, ok ? p[0] : G.lo[0], ok ? d[0] : (R)1, cx, W.T0x, W.Dx, bx, W.sx);
-    axis_setup(G, 1, ok ? p[1] : G.lo[1], ok ? d[1] : (R)0, cy, W.T0y, W.Dy, by, W.sy);
-    axis_setup(G, 2, ok ? p[2] : G.lo[2], ok ? d[2] : (R)0, cz, W.T0z, W.Dz, bz, W.sz);
+    int cx, cy, cz, sx, sy, sz;
+    axis_setup(G, 0, ok ? p[0] : G.lo[0], ok ? d[0] : (R)1, cx, W.T0x, W.Dx, bx, sx);
+    axis_setup(G, 1, ok ? p[1] : G.lo[1], ok ? d[1] : (R)0, cy, W.T0y, W.Dy, by, sy);
+    axis_setup(G, 2, ok ? p[2] : G.lo[2], ok ? d[2] : (R)0, cz, W.T0z, W.Dz, bz, sz);
     W.tx = W.T0x; W.ty = W.T0y; W.tz = W.T0z;
     W.t_exit = fmin(bx, fmin(by, bz));
-    W.ox = (uint32_t)brick_index(cx, 0, 0, G.nbx, G.nby);
-    W.oy = (uint32_t)brick_index(0, cy, 0, G.nbx, G.nby);
-    W.oz = (uint32_t)brick_index(0, 0, cz, G.nbx, G.nby);
-    W.ux = W.sx > 0 ? ~G.m[0] : 0u;
-    W.uy = W.sy > 0 ? ~G.m[1] : 0u;
-    W.uz = W.sz > 0 ? ~G.m[2] : 0u;
+    W.ox = (uint32_t)brick_index(cx, 0, 0, G.nbx, G.nby) << 2;
+    W.oy = (uint32_t)brick_index(0, cy, 0, G.nbx, G.nby) << 2;
+    W.oz = (uint32_t)brick_index(0, 0, cz, G.nbx, G.nby) << 2;
+    W.ux = sx > 0 ? ~G.m[0] : 0u;
+    W.uy = sy > 0 ? ~G.m[1] : 0u;
+    W.uz = sz > 0 ? ~G.m[2] : 0u;
+    W.sx = 4 * sx;
+    W.sy = 4 * sy;
+    W.sz = 4 * sz;
     return ok;
 }
 
-// B steps of a walk (no effect once done).  The cell sequence does not depend
-// on the densities, so the B cells are computed first and loaded together.
-// After the exit step the remaining steps of a batch repeat the last cell with
-// zero length: they add nothing and are not counted as visits.  The stop
-// position of a move is computed once, after the batch, for the step that
-// reached the target.
+// The cells (byte offsets), start distances and lengths of the next B steps
+// of a walk, which do not depend on the densities.  After the exit step the
+// remaining steps repeat the last cell with zero length: they add nothing and
+// are not counted as visits (nv).  alive turns false at the exit step.
 template <typename R, int B, typename GT>
-__device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
+__device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&cells)[B], R (&t0s)[B],
+                                           R (&segs)[B], uint32_t &nv, bool &alive)
 {
-    if (W.done) return;
-    int cells[B];
-    R t0s[B], segs[B];
-    uint32_t nv = 0;
-    bool alive = true;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const bool mx = W.tx <= W.ty && W.tx <= W.tz;
@@ -239,14 +238,15 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         const bool mz = !mx && !my;
         const R tn = fmin(W.tx, fmin(W.ty, W.tz));
         nv += alive ? 1u : 0u;
-        cells[b] = (int)(W.ox | W.oy | W.oz);
+        cells[b] = W.ox | W.oy | W.oz;
         t0s[b] = W.t;
-        const R seg = tn - W.t;
-        segs[b] = seg > (R)0 ? seg : (R)0;
-        W.t = tn > W.t ? tn : W.t;
+        // length max(tn - t, 0), and t never decreases
+        const R t1 = fmax(tn, W.t);
+        segs[b] = t1 - W.t;
+        W.t = t1;
         // the face about to be crossed is a boundary face: the walk ends in this cell
         const bool adv = tn < W.t_exit;
-        // the chosen axis' part moves by one: the carry (or borrow) runs
+        // the chosen axis' part moves by one cell: the carry (or borrow) runs
         // through the other axes' bits, set beforehand for a step up, and the
         // mask clears them again
         const uint32_t nox = ((W.ox | W.ux) + (uint32_t)W.sx) & G.m[0];
@@ -263,6 +263,22 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         W.tz = fma(W.jz, W.Dz, W.T0z);
         alive = alive && adv;
     }
+}
+
+// B steps of a walk in either mode (no effect once done).  The B cells are
+// computed first and loaded together; the optical depth is then accumulated
+// in order, in FP64, with the stop test of a move per step.  The stop position
+// of a move is computed once, after the batch, for the step that reached the
+// target.
+template <typename R, int B, typename GT>
+__device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
+{
+    if (W.done) return;
+    uint32_t cells[B];
+    R t0s[B], segs[B];
+    uint32_t nv = 0;
+    bool alive = true;
+    walk_steps<R, B>(W, G, cells, t0s, segs, nv, alive);
     R kr[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
@@ -290,6 +306,32 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         W.visits += nv_hit < nv ? nv_hit : nv;
         return;
     }
+    W.tau = tau;
+    W.visits += nv;
+    if (!alive) {
+        W.done = true;
+        W.t_out = W.t;
+    }
+}
+
+// B steps of a walk to the mesh edge (WALK_EDGE), as walk_batch computes
+// them, without the stop test: kernels call it when no lane of the wave moves
+// to a target.
+template <typename R, int B, typename GT>
+__device__ __forceinline__ void walk_batch_edge(Walk<R> &W, const GT &G)
+{
+    if (W.done) return;
+    uint32_t cells[B];
+    R t0s[B], segs[B];
+    uint32_t nv = 0;
+    bool alive = true;
+    walk_steps<R, B>(W, G, cells, t0s, segs, nv, alive);
+    R kr[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
+    double tau = W.tau;
+#pragma unroll
+    for (int b = 0; b < B; ++b) tau += (double)(kr[b] * segs[b]);
     W.tau = tau;
     W.visits += nv;
     if (!alive) {
