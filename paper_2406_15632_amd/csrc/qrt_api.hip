@@ -228,15 +228,17 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
     uint64_t want = 1u << 16;
     while (want < count && want < kChunk) want <<= 1;
     if (want > kChunk) want = kChunk;
-    const size_t pb = packet_state_bytes(precision) * want;
+    // the state lists hold as many packets as the other lists (which never shrink)
+    const uint64_t cap = std::max<uint64_t>(want, c->tb_packets);
+    const size_t pb = packet_state_bytes(precision) * cap * 2;   // two state lists
     const size_t rb = peel_ray_bytes(precision) * (want + 64) * (size_t)n_obs;
     if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb_packets >= want) return QRT_OK;
     HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
-    if (c->tb.packet_bytes < pb || c->tb_packets < want) {
+    if (c->tb.packet_bytes < pb) {
         if (c->tb.packets) (void)hipFree(c->tb.packets);
         c->tb.packets = nullptr;
         c->tb.packet_bytes = 0;
-        HIP_TRY(c, hipMalloc(&c->tb.packets, pb), "packet queue");
+        HIP_TRY(c, hipMalloc(&c->tb.packets, pb), "packet states");
         c->tb.packet_bytes = pb;
     }
     if (c->tb.peel_bytes < rb) {
@@ -247,15 +249,17 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
         c->tb.peel_bytes = rb;
     }
     if (c->tb_packets < want) {
-        uint32_t **lists[4] = {&c->tb.live[0], &c->tb.live[1], &c->tb.order, &c->tb.keys};
+        uint32_t **lists[2] = {&c->tb.order, &c->tb.keys};
         for (uint32_t **l : lists) {
             if (*l) (void)hipFree(*l);
             *l = nullptr;
         }
         c->tb_packets = 0;
+        c->tb.cap = 0;
         for (uint32_t **l : lists) HIP_TRY(c, hipMalloc(l, want * sizeof(uint32_t)), "packet lists");
         c->tb_packets = want;
     }
+    c->tb.cap = c->tb_packets;
     return QRT_OK;
 }
 
@@ -337,8 +341,6 @@ void qrt_destroy(qrt_ctx *c)
     if (c->counters) (void)hipFree(c->counters);
     if (c->tb.packets) (void)hipFree(c->tb.packets);
     if (c->tb.peels) (void)hipFree(c->tb.peels);
-    for (int i = 0; i < 2; ++i)
-        if (c->tb.live[i]) (void)hipFree(c->tb.live[i]);
     if (c->tb.q) (void)hipFree(c->tb.q);
     if (c->tb.order) (void)hipFree(c->tb.order);
     if (c->tb.keys) (void)hipFree(c->tb.keys);

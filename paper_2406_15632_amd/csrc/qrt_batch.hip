@@ -146,8 +146,7 @@ enum BatchFirstPhase : int { BF_IDLE = 0, BF_EDGE = 1, BF_FORCED = 2 };
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0, uint32_t count,
                                                 const uint32_t *__restrict__ order, const uint32_t *__restrict__ keys,
-                                                PacketState<R> *__restrict__ pks, uint32_t *__restrict__ live0,
-                                                Queues *__restrict__ Q)
+                                                PacketState<R> *__restrict__ out, Queues *__restrict__ Q)
 {
     uint64_t n_visits = 0;
     uint32_t n_packets = 0, n_cuts = 0;
@@ -161,7 +160,9 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
     W.done = true;
     WorkPool pool;
     for (;;) {
-        bool append = false;
+        // packets whose forced flight ended go to the first live list, in place pos
+        const bool append = W.done && phase == BF_FORCED;
+        const uint32_t pos = wave_append(append, &Q->n_live[0]);
         if (W.done && phase == BF_EDGE) {
             n_visits += W.visits;
             const BScene &S = P.scenes[s];
@@ -177,7 +178,7 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
                 walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
                 phase = BF_FORCED;
             }
-        } else if (W.done && phase == BF_FORCED) {
+        } else if (append) {
             n_visits += W.visits;
             const BScene &S = P.scenes[s];
             PacketState<R> st;
@@ -191,12 +192,9 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             st.idx = S.first + (b0 + j - S.begin);
             st.next_dim = (uint32_t)s;   // the batch keeps the scene here
             st.order = 1;
-            pks[j] = st;
-            append = true;
+            out[pos] = st;
             phase = BF_IDLE;
         }
-        const uint32_t pos = wave_append(append, &Q->n_live[0]);
-        if (append) live0[pos] = j;
         uint64_t item = 0;
         if (pool.take(phase == BF_IDLE, count, &Q->work[0][0][0], item)) {
             j = order[item];
@@ -240,8 +238,7 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
 // holds scene * 16 + observer.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
-                                                  const uint32_t *__restrict__ live_in, int in,
-                                                  PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+                                                  int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
 {
     if (blockIdx.x == 0 && threadIdx.x < kPoolParts) {
         if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
@@ -255,11 +252,10 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
         const bool valid = i < n;
-        const uint32_t slot = valid ? live_in[i] : 0;
         PacketState<R> st = {};
         int s = 0;
         if (valid) {
-            st = pks[slot];
+            st = pks[i];
             s = (int)st.next_dim;
             n_scat++;
         }
@@ -380,7 +376,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
             } else {
                 st.target = -1.0;   // the scene's last scattering: no further flight
             }
-            pks[slot] = st;
+            pks[i] = st;
         }
     }
     flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
@@ -390,9 +386,9 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
 enum BatchWalkItem : int { BW_NONE = 0, BW_PEEL = 1, BW_MOVE = 2 };
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
-                                               const uint32_t *__restrict__ live_in, int in,
-                                               uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
+__global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
+                                               const PacketState<R> *__restrict__ pks, int in,
+                                               PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
                                                Queues *__restrict__ Q)
 {
     if (blockIdx.x == 0 && threadIdx.x < kPeelGroups) Q->n_peel[(order + 1) & 1][threadIdx.x][0] = 0;   // next scatter
@@ -418,7 +414,9 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
     W.done = true;
     WorkPool pool;
     for (;;) {
-        bool append = false;
+        // packets whose flight stopped inside their mesh go to the next live list, in place pos
+        const bool append = W.done && kind == BW_MOVE && W.stopped;
+        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
         if (W.done && kind == BW_PEEL) {
             n_visits += W.visits;
             n_peels++;
@@ -433,19 +431,15 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
             kind = BW_NONE;
         } else if (W.done && kind == BW_MOVE) {
             n_visits += W.visits;
-            if (W.stopped) {
-                PacketState<R> *ps = pks + slot;
-                R q[3];
-                for (int a = 0; a < 3; ++a) q[a] = ps->p[a] + W.t_out * ps->k[a];
-                for (int a = 0; a < 3; ++a) ps->p[a] = q[a];
-                append = true;
+            if (append) {
+                PacketState<R> st = pks[slot];
+                for (int a = 0; a < 3; ++a) st.p[a] = st.p[a] + W.t_out * st.k[a];
+                out[pos] = st;
             } else {
                 n_esc++;
             }
             kind = BW_NONE;
         }
-        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
-        if (append) live_out[pos] = slot;
         uint64_t item = 0;
         if (pool.take(kind == BW_NONE, total, &Q->work[1][0][0], item)) {
             if (item < n_peel) {
@@ -468,7 +462,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order, P
                 walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
                 kind = BW_PEEL;
             } else {
-                slot = live_in[item - n_peel];
+                slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
                 if (ps->target >= 0.0) {
                     s = (int)ps->next_dim;
@@ -524,7 +518,6 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
         nb_scatter = batch_resident_blocks(k_bscatter<R, KIND>);
         nb_walk = batch_resident_blocks(k_bwalk<R>);
     }
-    PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
@@ -537,16 +530,17 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     if ((e = launch_place(B.keys, count, B.hist, B.order, b_elem, st)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
     hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order,
-                       (const uint32_t *)B.keys, pks, B.live[0], B.q);
+                       (const uint32_t *)B.keys, state_list<R>(B, 0), B.q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     for (int order = 1; order <= P.max_orders; ++order) {
         const int in = (order - 1) & 1;
-        hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, pks,
-                           (const uint32_t *)B.live[in], in, peels, B.q);
+        hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, state_list<R>(B, in), in,
+                           peels, B.q);
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;   // the last order walks peel rays only
-        hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order, pks,
-                           (const uint32_t *)B.live[in], in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
+        hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                           (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                           (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

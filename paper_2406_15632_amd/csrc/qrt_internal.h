@@ -142,15 +142,23 @@ constexpr int kSortBits = 16;                 // bins of the coherence sorts: 2^
 
 // Device buffers of the transport (owned by the context).
 struct TransportBuffers {
-    void *packets;        // PacketState<R>[chunk]
+    void *packets;        // PacketState<R>[2][cap]: the live packets of a scattering order, dense and in
+                          // the order they were appended, ping-pong by order (list in, then list in ^ 1)
     void *peels;          // PeelRay<R>[n_obs * (chunk + 64)], blocks of 64 per observer
-    uint32_t *live[2];    // slot lists (ping-pong by scattering order)
-    uint32_t *order;      // [chunk] packets or live slots in coherence order
+    uint32_t *order;      // [chunk] packets in coherence order
     uint32_t *keys;       // [chunk] sort keys
     uint32_t *hist;       // [2^kSortBits] sort histogram / placement cursors
     Queues *q;
     size_t packet_bytes, peel_bytes;
+    uint64_t cap;         // packets per state list
 };
+
+// live packet list `in` (0 or 1) of the buffers
+template <typename R>
+inline PacketState<R> *state_list(const TransportBuffers &B, int in)
+{
+    return (PacketState<R> *)B.packets + (size_t)in * B.cap;
+}
 
 size_t packet_state_bytes(int precision);
 size_t peel_ray_bytes(int precision);

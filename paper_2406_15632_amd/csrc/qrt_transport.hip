@@ -204,8 +204,7 @@ enum FirstPhase : int { FF_IDLE = 0, FF_EDGE = 1, FF_FORCED = 2 };
 template <typename R, int KIND, int SRC>
 __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t first, uint32_t count,
                                                const uint32_t *__restrict__ order,
-                                               PacketState<R> *__restrict__ pks, uint32_t *__restrict__ live0,
-                                               Queues *__restrict__ Q)
+                                               PacketState<R> *__restrict__ out, Queues *__restrict__ Q)
 {
     const RayGrid<R> G = ray_grid<R>(P.grid);
     uint64_t n_visits = 0;
@@ -218,7 +217,9 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
     W.done = true;
     WorkPool pool;
     for (;;) {
-        bool append = false;
+        // packets whose forced flight ended go to the first live list, in place pos
+        const bool append = W.done && phase == FF_FORCED;
+        const uint32_t pos = wave_append(append, &Q->n_live[0]);
         if (W.done && phase == FF_EDGE) {
             n_visits += W.visits;
             const double tau1 = W.tau;
@@ -233,7 +234,7 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
                 walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
                 phase = FF_FORCED;
             }
-        } else if (W.done && phase == FF_FORCED) {
+        } else if (append) {
             n_visits += W.visits;
             // if rounding lets the walk reach the edge first, scatter at the exit point
             PacketState<R> s;
@@ -247,12 +248,9 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
             s.idx = first + j;
             s.next_dim = 0;
             s.order = 1;
-            pks[j] = s;
-            append = true;
+            out[pos] = s;
             phase = FF_IDLE;
         }
-        const uint32_t pos = wave_append(append, &Q->n_live[0]);
-        if (append) live0[pos] = j;
         uint64_t item = 0;
         if (pool.take(phase == FF_IDLE, count, &Q->work[0][0][0], item)) {
             j = order[item];
@@ -300,8 +298,7 @@ __device__ __forceinline__ void load_obs(const TransportParams &P, ObsTable<R> &
 
 template <typename R, int KIND, int SRC>
 __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
-                                                 const uint32_t *__restrict__ live_in, int in,
-                                                 PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+                                                 int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
@@ -319,10 +316,9 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
         const bool valid = i < n;
-        const uint32_t slot = valid ? live_in[i] : 0;
         PacketState<R> s = {};
         if (valid) {
-            s = pks[slot];
+            s = pks[i];
             n_scat++;
             const R albedo = (R)P.albedo;
             s.S[0] *= albedo; s.S[1] *= albedo; s.S[2] *= albedo;
@@ -415,7 +411,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
             }
             // free flight tau2 = -ln w, all 32 bits of w in FP64
             s.target = -log((double)x[2] * 0x1p-32);
-            pks[slot] = s;
+            pks[i] = s;
         }
     }
     flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
@@ -434,9 +430,9 @@ __device__ __forceinline__ double *image_copy(const TransportParams &P, int orde
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
-                                              const uint32_t *__restrict__ live_in, int in,
-                                              uint32_t *__restrict__ live_out, const PeelRay<R> *__restrict__ peels,
+__global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order,
+                                              const PacketState<R> *__restrict__ pks, int in,
+                                              PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
                                               Queues *__restrict__ Q)
 {
     __shared__ R s_o[kMaxObs][3];
@@ -461,7 +457,9 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     W.done = true;
     WorkPool pool;
     for (;;) {
-        bool append = false;
+        // packets whose flight stopped inside the mesh go to the next live list, in place pos
+        const bool append = W.done && kind == WI_MOVE && W.stopped;
+        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
         if (W.done && kind == WI_PEEL) {
             n_visits += W.visits;
             n_peels++;
@@ -473,19 +471,15 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
             kind = WI_NONE;
         } else if (W.done && kind == WI_MOVE) {
             n_visits += W.visits;
-            if (W.stopped) {
-                PacketState<R> *ps = pks + slot;
-                R q[3];
-                for (int a = 0; a < 3; ++a) q[a] = ps->p[a] + W.t_out * ps->k[a];
-                for (int a = 0; a < 3; ++a) ps->p[a] = q[a];
-                append = true;
+            if (append) {
+                PacketState<R> s = pks[slot];
+                for (int a = 0; a < 3; ++a) s.p[a] = s.p[a] + W.t_out * s.k[a];
+                out[pos] = s;
             } else {
                 n_esc++;
             }
             kind = WI_NONE;
         }
-        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
-        if (append) live_out[pos] = slot;
         uint64_t item = 0;
         if (pool.take(kind == WI_NONE, total, &Q->work[1][0][0], item)) {
             if (item < n_peel) {
@@ -499,7 +493,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
                     kind = WI_PEEL;
                 }
             } else {
-                slot = live_in[item - n_peel];
+                slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
                 const R p0[3] = {ps->p[0], ps->p[1], ps->p[2]};
                 const R k0[3] = {ps->k[0], ps->k[1], ps->k[2]};
@@ -707,7 +701,6 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         nb_walk = resident_blocks_of(k_walk<R>);
         nb_mlp = resident_blocks_of(k_peel_mlp<R>);
     }
-    PacketState<R> *pks = (PacketState<R> *)B.packets;
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const size_t hist_bytes = sizeof(uint32_t) << kSortBits;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
@@ -723,13 +716,13 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
                        (const uint32_t *)nullptr, B.hist, B.order);
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
     hipLaunchKernelGGL((k_first<R, KIND, SRC>), dim3(bf), dim3(256), 0, st, P, first, count,
-                       (const uint32_t *)B.order, pks, B.live[0], B.q);
+                       (const uint32_t *)B.order, state_list<R>(B, 0), B.q);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     for (int order = 1; order <= P.max_orders; ++order) {
         const int in = (order - 1) & 1;
-        hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order, pks,
-                           (const uint32_t *)B.live[in], in, peels, B.q);
+        hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order,
+                           state_list<R>(B, in), in, peels, B.q);
         if (P.sur.cap)
             hipLaunchKernelGGL((k_capture<R>), dim3(bs), dim3(256), 0, st, P, (const PeelRay<R> *)peels,
                                (const Queues *)B.q, in);
@@ -738,8 +731,9 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
                                in);
         // the last order walks peel rays only (no flights): those want every resident wave
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;
-        hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order, pks, (const uint32_t *)B.live[in],
-                           in, B.live[in ^ 1], (const PeelRay<R> *)peels, B.q);
+        hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                           (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                           (const PeelRay<R> *)peels, B.q);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
