@@ -249,14 +249,16 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
         c->tb.peel_bytes = rb;
     }
     if (c->tb_packets < want) {
-        uint32_t **lists[2] = {&c->tb.order, &c->tb.keys};
+        uint32_t **lists[3] = {&c->tb.order, &c->tb.keys, &c->tb.sort_tmp};
         for (uint32_t **l : lists) {
             if (*l) (void)hipFree(*l);
             *l = nullptr;
         }
         c->tb_packets = 0;
         c->tb.cap = 0;
-        for (uint32_t **l : lists) HIP_TRY(c, hipMalloc(l, want * sizeof(uint32_t)), "packet lists");
+        HIP_TRY(c, hipMalloc(&c->tb.order, want * sizeof(uint32_t)), "packet lists");
+        HIP_TRY(c, hipMalloc(&c->tb.keys, want * sizeof(uint32_t)), "packet lists");
+        HIP_TRY(c, hipMalloc(&c->tb.sort_tmp, 2 * want * sizeof(uint32_t)), "packet lists");
         c->tb_packets = want;
     }
     c->tb.cap = c->tb_packets;
@@ -319,7 +321,7 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     if (e == hipSuccess) e = hipMalloc(&c->counters, kCounterBytes);
     if (e == hipSuccess) e = hipMemset(c->counters, 0, kCounterBytes);
     if (e == hipSuccess) e = hipMalloc(&c->tb.q, sizeof(Queues));
-    if (e == hipSuccess) e = hipMalloc(&c->tb.hist, sizeof(uint32_t) << kSortBits);
+    if (e == hipSuccess) e = hipMalloc(&c->tb.hist, sizeof(uint32_t) * kSortHist);
     if (e != hipSuccess) {
         qrt_destroy(c);
         return e == hipErrorOutOfMemory ? QRT_OUT_OF_MEMORY : QRT_HIP_ERROR;
@@ -344,6 +346,7 @@ void qrt_destroy(qrt_ctx *c)
     if (c->tb.q) (void)hipFree(c->tb.q);
     if (c->tb.order) (void)hipFree(c->tb.order);
     if (c->tb.keys) (void)hipFree(c->tb.keys);
+    if (c->tb.sort_tmp) (void)hipFree(c->tb.sort_tmp);
     if (c->tb.hist) (void)hipFree(c->tb.hist);
     if (c->mlp) (void)hipFree(c->mlp);
     if (c->tiles) (void)hipFree(c->tiles);

@@ -11,7 +11,7 @@
 // Mueller matrix (Sec. 2.2, 3.5), coordinates by purpose (Sec. 3.7).
 //
 // Launch sequence of a chunk of batch numbers: emission keys (scene and
-// coarse emission direction) -> counting sort -> persistent first flight
+// coarse emission direction) -> radix sort -> persistent first flight
 // -> per order up to the largest order of the batch: scatter, then walk.  A
 // packet whose scene has fewer orders stops at its own last order.
 #include <hip/hip_runtime.h>
@@ -125,7 +125,7 @@ __device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, 
 // ---------------------------------------------------------------- emission sort
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bkey(const BatchParams P, uint64_t b0, uint32_t count,
-                                              uint32_t *__restrict__ keys, uint32_t *__restrict__ hist)
+                                              uint32_t *__restrict__ keys)
 {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
         const uint64_t b = b0 + j;
@@ -136,7 +136,6 @@ __global__ void __launch_bounds__(256) k_bkey(const BatchParams P, uint64_t b0, 
         const uint32_t key = ((uint32_t)(s - P.scene_base) << (kSortBits - P.scene_bits)) |
                              (direction_key(k) >> P.scene_bits);
         keys[j] = key;
-        atomicAdd(hist + key, 1u);
     }
 }
 
@@ -523,11 +522,9 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
-    if (e == hipSuccess) e = hipMemsetAsync(B.hist, 0, sizeof(uint32_t) << kSortBits, st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys, B.hist);
-    if ((e = launch_scan_bins(B.hist, st)) != hipSuccess) return e;
-    if ((e = launch_place(B.keys, count, B.hist, B.order, b_elem, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys);
+    if ((e = launch_sort_keys(B, count, st)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
     hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order,
                        (const uint32_t *)B.keys, state_list<R>(B, 0), B.q);

@@ -138,7 +138,11 @@ struct Queues {
     uint32_t n_peel[2][kPeelGroups][32];
 };
 
-constexpr int kSortBits = 16;                 // bins of the coherence sorts: 2^kSortBits
+constexpr int kSortBits = 16;                 // bits of the coherence sort keys
+constexpr int kSortItems = 4096;              // items per block of the radix-sort passes
+constexpr int kSortDigit = 256;               // values of an 8-bit digit
+// histogram entries of a pass: [kSortDigit][blocks] block counts, then kSortDigit digit totals
+constexpr size_t kSortHist = (size_t)kSortDigit * (kChunk / kSortItems) + kSortDigit;
 
 // Device buffers of the transport (owned by the context).
 struct TransportBuffers {
@@ -147,7 +151,8 @@ struct TransportBuffers {
     void *peels;          // PeelRay<R>[n_obs * (chunk + 64)], blocks of 64 per observer
     uint32_t *order;      // [chunk] packets in coherence order
     uint32_t *keys;       // [chunk] sort keys
-    uint32_t *hist;       // [2^kSortBits] sort histogram / placement cursors
+    uint32_t *sort_tmp;   // [2 chunk] keys and packets after the first sort pass
+    uint32_t *hist;       // [kSortHist] histograms of a sort pass
     Queues *q;
     size_t packet_bytes, peel_bytes;
     uint64_t cap;         // packets per state list
@@ -205,10 +210,9 @@ struct BatchParams {
 hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precision, int kind, uint64_t total,
                         const TransportBuffers &B, uint64_t chunk, hipStream_t stream);
 
-// counting-sort steps shared by the transport launch sequences
-hipError_t launch_scan_bins(uint32_t *hist, hipStream_t st);
-hipError_t launch_place(const uint32_t *keys, uint32_t count, uint32_t *hist, uint32_t *out, int blocks,
-                        hipStream_t st);
+// order[0 .. count) = the packets 0 .. count-1 sorted by keys[j] (kSortBits bits), stably; count <= kChunk.
+// Two radix passes of 8 bits through B.sort_tmp, histograms in B.hist.
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st);
 
 // One chunk of packets first .. first+count-1 (count <= kChunk) through every
 // scattering order: first flight, then per order a scatter kernel and a walk

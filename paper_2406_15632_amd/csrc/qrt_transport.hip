@@ -68,7 +68,7 @@ size_t peel_ray_bytes(int precision) { return precision == 1 ? sizeof(PeelRay<do
 // --------------------------------------------------------------------------
 // Mesh walks are bound by the rate of distinct cache lines that a wave's
 // loads touch.  Lanes of a wave that walk nearly the same cells share lines,
-// so the packets of a chunk are counting-sorted by emission direction
+// so the packets of a chunk are sorted by emission direction
 // (octahedral map, 2 x 8 bits) before their first flights: a wave then walks
 // 64 nearly parallel rays from the source.  The order only changes which lanes
 // run which packets; every packet is computed as before.
@@ -78,63 +78,156 @@ __device__ __forceinline__ void emit(const TransportParams &P, uint64_t idx, R p
 
 template <typename R, int KIND, int SRC>
 __global__ void __launch_bounds__(256) k_key_emit(const TransportParams P, uint64_t first, uint32_t count,
-                                                  uint32_t *__restrict__ keys, uint32_t *__restrict__ hist)
+                                                  uint32_t *__restrict__ keys)
 {
     for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < count; j += gridDim.x * blockDim.x) {
         R p[3], k[3];
         emit<R, KIND, SRC>(P, first + j, p, k);
-        const uint32_t key = direction_key(k);
-        keys[j] = key;
-        atomicAdd(hist + key, 1u);
+        keys[j] = direction_key(k);
     }
 }
 
-// exclusive prefix sum of the 2^kSortBits bins, one block of 1024 lanes
-__global__ void __launch_bounds__(1024) k_scan_bins(uint32_t *__restrict__ hist)
+// The sort: a stable least-significant-digit radix sort of the packets by
+// their 16-bit keys, in two passes of 8 bits.  Each pass splits the items into
+// blocks of kSortItems, counts the digits per block (k_digit_hist), turns the
+// counts into each block's start inside each digit (k_digit_scan), and places
+// every item at the start of its digit, plus the items of that digit in
+// earlier blocks, plus the earlier items of that digit in its own block
+// (k_digit_scatter).  No device-wide atomics: every position is computed.
+
+// hist[d * nb + b] = items of block b whose digit (key >> shift) & 255 is d
+__global__ void __launch_bounds__(kSortDigit) k_digit_hist(const uint32_t *__restrict__ keys, uint32_t count, int shift,
+                                                           uint32_t *__restrict__ hist)
 {
-    constexpr int nb = 1 << kSortBits, per = nb / 1024;
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    uint32_t sum = 0;
-    for (int i = 0; i < per; ++i) sum += hist[t * per + i];
-    part[t] = sum;
+    __shared__ uint32_t h[kSortDigit];
+    h[threadIdx.x] = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = t >= off ? part[t - off] : 0u;
+    const uint32_t b0 = blockIdx.x * (uint32_t)kSortItems;
+    for (int r = 0; r < kSortItems / kSortDigit; ++r) {
+        const uint32_t i = b0 + (uint32_t)(r * kSortDigit) + threadIdx.x;
+        if (i < count) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// exclusive prefix of an LDS array of kSortDigit entries (the block has kSortDigit threads)
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t *a)
+{
+    const int t = threadIdx.x;
+    const uint32_t own = a[t];
+    for (int off = 1; off < kSortDigit; off <<= 1) {
+        const uint32_t v = t >= off ? a[t - off] : 0u;
         __syncthreads();
-        part[t] += v;
+        a[t] += v;
         __syncthreads();
     }
-    uint32_t run = part[t] - sum;
-    for (int i = 0; i < per; ++i) {
-        const uint32_t h = hist[t * per + i];
-        hist[t * per + i] = run;
-        run += h;
+    return a[t] - own;
+}
+
+// One block per digit d: hist[d * nb + b] becomes the sum over the blocks
+// before b (nb <= 4 kSortDigit), and tot[d] the digit's total.
+__global__ void __launch_bounds__(kSortDigit) k_digit_scan(uint32_t *__restrict__ hist, int nb,
+                                                           uint32_t *__restrict__ tot)
+{
+    __shared__ uint32_t part[kSortDigit];
+    uint32_t *row = hist + (size_t)blockIdx.x * nb;
+    const int per = (nb + kSortDigit - 1) / kSortDigit;
+    uint32_t v[4];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = (int)threadIdx.x * per + k;
+        v[k] = (k < per && i < nb) ? row[i] : 0u;
+        sum += v[k];
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    uint32_t run = block_exclusive_scan(part);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = (int)threadIdx.x * per + k;
+        if (k < per && i < nb) row[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == kSortDigit - 1) tot[blockIdx.x] = run;
+}
+
+// Stable placement of the items of one block by digit.  The block takes its
+// items in rounds of kSortDigit, in order; inside a round, the lanes of a wave
+// with the same digit are found with one ballot per digit bit, and the waves'
+// counts per digit give each wave its start.  keys_out may be null (last
+// pass); vals_in null stands for the item numbers.
+__global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__restrict__ keys_in,
+                                                              const uint32_t *__restrict__ vals_in, uint32_t count,
+                                                              int shift, const uint32_t *__restrict__ hist,
+                                                              const uint32_t *__restrict__ tot,
+                                                              uint32_t *__restrict__ keys_out,
+                                                              uint32_t *__restrict__ vals_out)
+{
+    constexpr int kWaves = kSortDigit / 64;
+    __shared__ uint32_t base[kSortDigit];
+    __shared__ uint32_t wc[kWaves][kSortDigit];
+    const int t = threadIdx.x, w = t >> 6;
+    base[t] = tot[t];
+    __syncthreads();
+    const uint32_t start = block_exclusive_scan(base);
+    __syncthreads();
+    base[t] = start + hist[t * gridDim.x + blockIdx.x];
+    for (int v = 0; v < kWaves; ++v) wc[v][t] = 0;
+    __syncthreads();
+    const uint32_t b0 = blockIdx.x * (uint32_t)kSortItems;
+    for (int r = 0; r < kSortItems / kSortDigit; ++r) {
+        const uint32_t i = b0 + (uint32_t)(r * kSortDigit) + (uint32_t)t;
+        const bool valid = i < count;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool one = (d >> bit) & 1u;
+            const uint64_t m = __ballot(valid && one);
+            peers &= one ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanes_below_mask());
+        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = base[d] + rank;
+            for (int v = 0; v < w; ++v) pos += wc[v][d];
+            if (keys_out) keys_out[pos] = key;
+            vals_out[pos] = vals_in ? vals_in[i] : i;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int v = 0; v < kWaves; ++v) {
+            add += wc[v][t];
+            wc[v][t] = 0;
+        }
+        base[t] += add;
+        __syncthreads();
     }
 }
 
-// place item i (or items[i]) at the next free position of its bin
-__global__ void __launch_bounds__(256) k_place(const uint32_t *__restrict__ keys, uint32_t count,
-                                               const uint32_t *__restrict__ items, uint32_t *__restrict__ hist,
-                                               uint32_t *__restrict__ out)
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st)
 {
-    const uint32_t n = count;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint32_t pos = atomicAdd(hist + keys[i], 1u);
-        out[pos] = items ? items[i] : i;
-    }
-}
-
-hipError_t launch_scan_bins(uint32_t *hist, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, st, hist);
-    return hipGetLastError();
-}
-
-hipError_t launch_place(const uint32_t *keys, uint32_t count, uint32_t *hist, uint32_t *out, int blocks,
-                        hipStream_t st)
-{
-    hipLaunchKernelGGL(k_place, dim3(blocks), dim3(256), 0, st, keys, count, (const uint32_t *)nullptr, hist, out);
+    if (count == 0) return hipSuccess;
+    if (count > kChunk) return hipErrorInvalidValue;
+    const int nb = (int)((count + kSortItems - 1) / kSortItems);
+    uint32_t *tot = B.hist + (size_t)kSortDigit * (kChunk / kSortItems);
+    uint32_t *tmp_keys = B.sort_tmp, *tmp_vals = B.sort_tmp + B.cap;
+    // low digit: keys and packet numbers into the scratch lists
+    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys, count, 0, B.hist);
+    hipLaunchKernelGGL(k_digit_scan, dim3(kSortDigit), dim3(kSortDigit), 0, st, B.hist, nb, tot);
+    hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys,
+                       (const uint32_t *)nullptr, count, 0, (const uint32_t *)B.hist, (const uint32_t *)tot,
+                       tmp_keys, tmp_vals);
+    // high digit: the packet numbers into order
+    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys, count, 8, B.hist);
+    hipLaunchKernelGGL(k_digit_scan, dim3(kSortDigit), dim3(kSortDigit), 0, st, B.hist, nb, tot);
+    hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys,
+                       (const uint32_t *)tmp_vals, count, 8, (const uint32_t *)B.hist, (const uint32_t *)tot,
+                       (uint32_t *)nullptr, B.order);
     return hipGetLastError();
 }
 
@@ -702,18 +795,14 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         nb_mlp = resident_blocks_of(k_peel_mlp<R>);
     }
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
-    const size_t hist_bytes = sizeof(uint32_t) << kSortBits;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
     hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
-    if (e == hipSuccess) e = hipMemsetAsync(B.hist, 0, hist_bytes, st);
     if (e != hipSuccess) return e;
     // first flights in emission-direction order
-    hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys, B.hist);
-    hipLaunchKernelGGL(k_scan_bins, dim3(1), dim3(1024), 0, st, B.hist);
-    hipLaunchKernelGGL(k_place, dim3(b_elem), dim3(256), 0, st, (const uint32_t *)B.keys, count,
-                       (const uint32_t *)nullptr, B.hist, B.order);
+    hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys);
+    if ((e = launch_sort_keys(B, count, st)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
     hipLaunchKernelGGL((k_first<R, KIND, SRC>), dim3(bf), dim3(256), 0, st, P, first, count,
                        (const uint32_t *)B.order, state_list<R>(B, 0), B.q);
