@@ -11,8 +11,8 @@
 
 namespace qrt {
 
-constexpr int kWalkBatch = 4;    // steps per load batch of the first flights
-constexpr int kFlightBatch = 6;  // steps per load batch of the per-order walks (which run at low occupancy)
+constexpr int kWalkBatch = 6;     // steps per load batch of the first flights
+constexpr int kFlightBatch = 10;  // steps per load batch of the per-order walks (which run at low occupancy)
 
 // Blocks per CU of the per-order walk kernels (measured): three of the four
 // or five that the registers allow.  With fewer waves the CU's vector L1 cache
