@@ -58,7 +58,7 @@ struct qrt_ctx {
     int precision = QRT_FP32;
     int peel_mode = QRT_PEEL_EXACT;
     // bookkeeping
-    uint32_t *tables = nullptr;              // [sobol kMaxDims*32][nied kMaxDims*32][bases kMaxDims]
+    uint32_t *tables = nullptr;              // [sobol kMaxDims*1024][nied kMaxDims*1024][bases kMaxDims]
     uint32_t *faure = nullptr;               // Faure matrices and powers for faure_dims coordinates
     int faure_dims = 0;
     uint32_t faure_b = 0, faure_m = 0, faure_pow = 0;
@@ -142,8 +142,8 @@ int point_dims(const qrt_ctx *c)
 SeqParams seq_params(const qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total)
 {
     SeqParams s;
-    s.mat = c->tables + (kind == QRT_NIEDERREITER2 ? kMaxDims * 32 : 0);
-    s.bases = c->tables + 2 * kMaxDims * 32;
+    s.mat = c->tables + (kind == QRT_NIEDERREITER2 ? kMaxDims * 1024 : 0);
+    s.bases = c->tables + 2 * kMaxDims * 1024;
     s.seed = seed;
     s.n_total = n_total;
     s.faure = c->faure;
@@ -308,16 +308,26 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     DeviceGuard dg(device);
-    // generator tables
-    const size_t nt = 2 * (size_t)kMaxDims * 32 + kMaxDims;
-    uint32_t *host = new uint32_t[nt];
-    memset(host, 0, nt * sizeof(uint32_t));
-    sobol_columns(sobol_table_dims() < kMaxDims ? sobol_table_dims() : kMaxDims, host);
-    niederreiter2_columns(kMaxDims, host + kMaxDims * 32);
-    first_primes(kMaxDims, host + 2 * kMaxDims * 32);
+    // generator tables: per digital sequence and dimension, the byte tables of
+    // its 32 columns ([4][256]: the XOR of the columns that each byte value of
+    // the Gray-code index selects), then the Halton bases
+    const size_t nbytes = (size_t)kMaxDims * 1024;
+    const size_t nt = 2 * nbytes + kMaxDims;
+    std::vector<uint32_t> cols(2 * (size_t)kMaxDims * 32, 0u), host(nt, 0u);
+    sobol_columns(sobol_table_dims() < kMaxDims ? sobol_table_dims() : kMaxDims, cols.data());
+    niederreiter2_columns(kMaxDims, cols.data() + kMaxDims * 32);
+    for (int k = 0; k < 2; ++k)
+        for (int d = 0; d < kMaxDims; ++d)
+            for (int q = 0; q < 4; ++q)
+                for (int v = 0; v < 256; ++v) {
+                    uint32_t x = 0;
+                    for (int b = 0; b < 8; ++b)
+                        if ((v >> b) & 1) x ^= cols[((size_t)k * kMaxDims + d) * 32 + 8 * q + b];
+                    host[k * nbytes + ((size_t)d * 4 + q) * 256 + v] = x;
+                }
+    first_primes(kMaxDims, host.data() + 2 * nbytes);
     hipError_t e = hipMalloc(&c->tables, nt * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemcpy(c->tables, host, nt * sizeof(uint32_t), hipMemcpyHostToDevice);
-    delete[] host;
+    if (e == hipSuccess) e = hipMemcpy(c->tables, host.data(), nt * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&c->counters, kCounterBytes);
     if (e == hipSuccess) e = hipMemset(c->counters, 0, kCounterBytes);
     if (e == hipSuccess) e = hipMalloc(&c->tb.q, sizeof(Queues));

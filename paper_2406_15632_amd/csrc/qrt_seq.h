@@ -35,7 +35,8 @@ enum SeqKind {
 };
 
 struct SeqParams {
-    const uint32_t *mat;    // generator-matrix columns [dims][32] (Sobol or Niederreiter)
+    const uint32_t *mat;    // generator-matrix byte tables [dims][4][256] (Sobol or Niederreiter): entry
+                            // [d][q][v] is the XOR of the columns 8q .. 8q+7 of d that the bits of v select
     const uint32_t *bases;  // Halton bases [dims]
     uint64_t seed;
     uint64_t n_total;       // Hammersley N
@@ -44,16 +45,13 @@ struct SeqParams {
     uint64_t fbm;           // b^m
 };
 
-__device__ __forceinline__ uint32_t digital_point(const uint32_t *__restrict__ cols, uint64_t i)
+// The XOR of the generator columns that the bits of the Gray-code index
+// select, one index byte at a time: four independent lookups in the
+// dimension's byte tables t[4][256].
+__device__ __forceinline__ uint32_t digital_point(const uint32_t *__restrict__ t, uint64_t i)
 {
-    uint32_t g = (uint32_t)(i ^ (i >> 1));   // indices are < 2^32 for the 32-bit digital sequences
-    uint32_t x = 0;
-    while (g) {
-        int b = __builtin_ctz(g);
-        x ^= cols[b];
-        g &= g - 1u;
-    }
-    return x;
+    const uint32_t g = (uint32_t)(i ^ (i >> 1));   // indices are < 2^32 for the 32-bit digital sequences
+    return t[g & 255u] ^ t[256 + ((g >> 8) & 255u)] ^ t[512 + ((g >> 16) & 255u)] ^ t[768 + (g >> 24)];
 }
 
 // floor(num * 2^32 / den) for num < den < 2^53: double quotient, exact integer fix-up
@@ -159,9 +157,9 @@ template <int KIND>
 __device__ __forceinline__ uint32_t seq_point(const SeqParams &S, uint64_t i, int d)
 {
     if constexpr (KIND == SEQ_SOBOL || KIND == SEQ_NIED2) {
-        return digital_point(S.mat + 32 * d, i);
+        return digital_point(S.mat + 1024 * d, i);
     } else if constexpr (KIND == SEQ_SOBOL_OWEN) {
-        return owen_scramble(digital_point(S.mat + 32 * d, i), S.seed, d);
+        return owen_scramble(digital_point(S.mat + 1024 * d, i), S.seed, d);
     } else if constexpr (KIND == SEQ_HALTON) {
         return radical_inverse(i, S.bases[d]);
     } else if constexpr (KIND == SEQ_HAMMERSLEY) {
