@@ -48,6 +48,7 @@ HBM_PEAK_GBS = 8000.0
 KIND_ORDER = ("sobol", "halton", "niederreiter2", "hammersley", "philox")
 PHILOX_SEED = 12345
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_disk128.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_disk128.md")
 
 
 def parse():
@@ -106,6 +107,29 @@ def committed_traffic():
         return float(d["bytes_per_step_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def committed_walk_counters():
+    """The walk kernel's VALU, TA and TD busy and VALU lane share (fractions) from the committed
+    counter summary, when it was taken with the committed traffic counters on the current kernel
+    sources (both come from one measurement run), else None."""
+    if committed_traffic() is None:
+        return None
+    try:
+        lines = open(COUNTERS_FILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("| `qrt::k_walk<float>`"):
+            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+            try:
+                _, _hit, busy, lanes, _wait, ta, td = cells[:7]
+                return {"valu_busy": float(busy) / 100, "valu_lanes_active": float(lanes) / 100,
+                        "ta_busy": float(ta) / 100, "td_busy": float(td) / 100,
+                        "source": "profiles/counters_disk128.md"}
+            except ValueError:
+                return None
+    return None
 
 
 def cpu_baseline(sc, n_sample: int):
@@ -568,8 +592,9 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "transport step qrt_run: k_key_emit, k_scan_bins, k_place, k_first, "
-                      "then per scattering order k_scatter and k_walk",
+            "kernel": "transport step qrt_run: k_key_emit, the two-pass radix sort (k_digit_hist, "
+                      "k_digit_scan, k_digit_scatter), k_first, then per scattering order k_scatter and k_walk",
+            "walk_counters": committed_walk_counters(),
             "alg_bytes_per_launch": alg_bytes / n_launch,
             "avg_launch_ms": transport_ms / n_launch,
         },
