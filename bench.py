@@ -45,6 +45,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix-core peak
+MLP_FWD_FLOP = 25344              # algorithmic FLOP of one forward pass of the surrogate network
 KIND_ORDER = ("sobol", "halton", "niederreiter2", "hammersley", "philox")
 PHILOX_SEED = 12345
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_disk128.txt")
@@ -132,6 +134,24 @@ def committed_walk_counters():
     return None
 
 
+def measured_copy_gbps(mib: int = 1024, reps: int = 5) -> float:
+    """Bytes read plus written per second by a plain device-to-device copy of mib MiB (best of reps)."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    return 2.0 * mib * (1 << 20) / best / 1e9
+
+
 def cpu_baseline(sc, n_sample: int):
     """The FP64 oracle on the host cores, on the first n_sample packets of each point set."""
     from oracle import oracle as O
@@ -207,6 +227,11 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
                      "Sobol packets, FP32 transport",
            "pilot_packets": pilot, "sample_s": t_sample, "train_s": t_train, "validate_s": t_val,
            "train_loss": [rep["loss_first"], rep["loss_final"]], "mask": mrep}
+    # training throughput: forward plus backward (input and weight gradients) = 3 forward passes per sample
+    train_tflops = steps * 8192 * 3 * MLP_FWD_FLOP / t_train / 1e12
+    out["train_mfma"] = {"tflops": train_tflops, "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
+                         "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS,
+                         "flop_per_sample": 3 * MLP_FWD_FLOP}
     curves = {}
     for mode, name in ((qrt.PEEL_EXACT, "plain"), (qrt.PEEL_SURROGATE, "surrogate")):
         ctx.set_sequence(qrt.SOBOL, PHILOX_SEED, N)
@@ -561,6 +586,7 @@ def main():
     n_launch = args.steps * len(kinds)
     alg_bytes = 4.0 * cnt["visits"] + 24.0 * cnt["peels"]
     achieved = alg_bytes / (transport_ms * 1e-3) / 1e9
+    copy_gbps = measured_copy_gbps()   # after the timed region
     packets = args.steps * len(kinds) * N
     traffic = committed_traffic() if N == 1 << 22 else None
     result = {
@@ -595,6 +621,8 @@ def main():
             "kernel": "transport step qrt_run: k_key_emit, the two-pass radix sort (k_digit_hist, "
                       "k_digit_scan, k_digit_scatter), k_first, then per scattering order k_scatter and k_walk",
             "walk_counters": committed_walk_counters(),
+            "measured_copy_GBps": copy_gbps,
+            "frac_of_measured_copy": achieved / copy_gbps,
             "alg_bytes_per_launch": alg_bytes / n_launch,
             "avg_launch_ms": transport_ms / n_launch,
         },
