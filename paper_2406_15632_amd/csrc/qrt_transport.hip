@@ -11,15 +11,18 @@
 // free flight tau2 = -ln w; end when the packet leaves the mesh.
 //
 // How the GPU runs a chunk of packets:
+//   k_key_emit and the radix sort: the packets in emission-direction order.
 //   k_first    persistent; per packet: emission, walk to the edge (tau1), the
-//              forced-flight walk; survivors are appended to a live list.
+//              forced-flight walk; the states of the packets that scatter are
+//              appended to the first live list (dense, ping-pong by order).
 //   per scattering order:
-//   k_scatter  one lane per live packet: albedo, the peel-off contribution and
-//              pixel for every observer (appended as peel rays), then the new
-//              direction, Stokes vector and flight depth.
+//   k_scatter  one lane per live packet, in place: albedo, the peel-off
+//              contribution and pixel for every observer (written as peel
+//              rays in fixed slots), then the new direction, Stokes vector and
+//              flight depth.
 //   k_walk     persistent; walks every peel ray (adding e^-tau times its
-//              contribution to the image) and every flight (survivors go to the
-//              next live list).
+//              contribution to the image) and every flight (the states of the
+//              packets that stop inside the mesh go to the other live list).
 // Only the two persistent kernels walk the mesh; their per-ray events are a
 // few loads and stores, so they keep a small register footprint.  All physics
 // runs in k_first's events and in k_scatter, which is convergent.  Waves of

@@ -102,8 +102,9 @@ template <typename R>
 __device__ __forceinline__ RayGrid<R> ray_grid(const DevGrid &g)
 {
     RayGrid<R> r;
-    const int bytes = g.nb[0] * g.nb[1] * g.nb[2] * (kBrick * kBrick * kBrick * 4);
-    r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.kr, (short)0, bytes, 0x00020000);
+    // up to 2^29 cells: the byte count (at most 2^31) is the descriptor's unsigned 32-bit record count
+    const uint32_t bytes = (uint32_t)g.nb[0] * (uint32_t)g.nb[1] * (uint32_t)g.nb[2] * (kBrick * kBrick * kBrick * 4);
+    r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)g.kr, (short)0, (int)bytes, 0x00020000);
     r.n[0] = g.nx; r.n[1] = g.ny; r.n[2] = g.nz;
     r.nbx = g.nb[0];
     r.nby = g.nb[1];
