@@ -532,8 +532,8 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(DESIGN.md describes how the path would shard)"}))
+        print(json.dumps({"error": "the transport runs on one GPU; --gpus must be 1 (no multi-GPU "
+                                   "sharding is implemented)"}))
         sys.exit(2)
     import torch
 
