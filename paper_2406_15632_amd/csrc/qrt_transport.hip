@@ -540,6 +540,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
+    const uint64_t stride = block_stride(total >> 6);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
     // image copy of this block (blocks go round-robin to the XCDs), in the
     // set of this scattering order when orders are kept apart
@@ -578,6 +579,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
         }
         uint64_t item = 0;
         if (pool.take(kind == WI_NONE, total, &Q->work[1][0][0], item)) {
+            item = scatter_block(item, total, stride);
             if (item < n_peel) {
                 const PeelRay<R> r = peels[item];
                 if (r.pix != kNoPixel) {
