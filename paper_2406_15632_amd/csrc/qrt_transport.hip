@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
-    const uint64_t stride = block_stride(total >> 6);
+    const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
     // image copy of this block (blocks go round-robin to the XCDs), in the
     // set of this scattering order when orders are kept apart

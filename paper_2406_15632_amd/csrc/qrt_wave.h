@@ -151,13 +151,17 @@ struct WorkPool {
     }
 };
 
-// The pool's items in 64-item blocks, block b of the nfull whole blocks handed
-// out as block (b * stride) mod nfull, stride = p mod nfull with p = 2^31 - 1:
-// p is prime and larger than any block count, so the map is a bijection.
-// Neighbouring list entries come from neighbouring emission directions, so
-// waves that take consecutive blocks at the same time would work in one part
-// of the mesh; strided blocks spread them over it.  A block's 64 items stay
-// together, as do the items of a partial last block.
+// The pool's items in blocks of kOrderBlock, block b of the nfull whole blocks
+// handed out as block (b * stride) mod nfull, stride = p mod nfull with
+// p = 2^31 - 1: p is prime and larger than any block count, so the map is a
+// bijection.  Neighbouring list entries come from neighbouring emission
+// directions, so waves that take consecutive blocks at the same time would
+// work in one part of the mesh; strided blocks spread them over it.  A block's
+// items stay together, as do the items of a partial last block: a wave's
+// successive rounds inside one block keep to one region.
+constexpr int kOrderBlockLog2 = 9;
+constexpr uint64_t kOrderBlock = 1ull << kOrderBlockLog2;
+
 __host__ __device__ inline uint64_t block_stride(uint64_t nfull)
 {
     return nfull ? 2147483647ull % nfull : 1;
@@ -165,9 +169,9 @@ __host__ __device__ inline uint64_t block_stride(uint64_t nfull)
 
 __host__ __device__ inline uint64_t scatter_block(uint64_t item, uint64_t total, uint64_t stride)
 {
-    const uint64_t nfull = total >> 6, b = item >> 6;
+    const uint64_t nfull = total >> kOrderBlockLog2, b = item >> kOrderBlockLog2;
     if (b >= nfull) return item;
-    return (((b * stride) % nfull) << 6) | (item & 63);
+    return (((b * stride) % nfull) << kOrderBlockLog2) | (item & (kOrderBlock - 1));
 }
 
 // Octahedral map of a direction to 2 x 8 bits, interleaved (nearby directions
