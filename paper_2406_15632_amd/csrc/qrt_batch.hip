@@ -402,6 +402,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
     const uint64_t n_live = Q->n_live[in];
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
+    const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     uint64_t n_visits = 0;
     uint32_t n_peels = 0, n_esc = 0;
     int kind = BW_NONE;
@@ -441,6 +442,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
         }
         uint64_t item = 0;
         if (pool.take(kind == BW_NONE, total, &Q->work[1][0][0], item)) {
+            item = scatter_block(item, total, stride);
             if (item < n_peel) {
                 uint64_t at = item;
                 int g = 0;

@@ -151,12 +151,13 @@ struct WorkPool {
     }
 };
 
-// The pool's items in blocks of kOrderBlock, block b of the nfull whole blocks
-// handed out as block (b * stride) mod nfull, stride = p mod nfull with
-// p = 2^31 - 1: p is prime and larger than any block count, so the map is a
-// bijection.  Neighbouring list entries come from neighbouring emission
-// directions, so waves that take consecutive blocks at the same time would
-// work in one part of the mesh; strided blocks spread them over it.  A block's
+// The per-order walks' items in blocks of kOrderBlock, block b of the nfull
+// whole blocks handed out as block (b * stride) mod nfull, stride = p mod nfull
+// with p = 2^31 - 1: p is prime and larger than any block count, so the map is
+// a bijection.  Neighbouring list entries come from neighbouring emission
+// directions (and, in a batch, from one scene), so waves that take consecutive
+// blocks at the same time would work in one part of one mesh; strided blocks
+// spread them over it.  A block's
 // items stay together, as do the items of a partial last block: a wave's
 // successive rounds inside one block keep to one region.
 constexpr int kOrderBlockLog2 = 9;
