@@ -14,11 +14,12 @@ namespace qrt {
 constexpr int kWalkBatch = 6;     // steps per load batch of the first flights
 constexpr int kFlightBatch = 10;  // steps per load batch of the per-order walks (which run at low occupancy)
 
-// Blocks per CU of the per-order walk kernels (measured): three of the four
-// or five that the registers allow.  With fewer waves the CU's vector L1 cache
-// keeps more of each lane's current lines between steps; with two, the misses'
-// latency shows.  Only orders that walk flights are limited: the peel rays of
-// the last order run side by side and want every wave.
+// Blocks per CU of the per-order walk kernels (measured): at most three.  With
+// fewer waves the CU's vector L1 cache keeps more of each lane's current lines
+// between steps; with two, the misses' latency shows.  Only orders that walk
+// flights are limited: the peel rays of the last order run side by side and
+// want every wave.  The FP32 walk's registers allow three blocks per CU
+// themselves, so the limit binds only for a leaner build of the kernel.
 constexpr int kWalkBlocksPerCu = 3;
 
 // compute units of the current device (read once)
