@@ -12,7 +12,7 @@
 namespace qrt {
 
 constexpr int kWalkBatch = 6;     // steps per load batch of the first flights
-constexpr int kFlightBatch = 10;  // steps per load batch of the per-order walks (which run at low occupancy)
+constexpr int kFlightBatch = 12;  // steps per load batch of the per-order walks (which run at low occupancy)
 
 // Blocks per CU of the per-order walk kernels (measured): at most three.  With
 // fewer waves the CU's vector L1 cache keeps more of each lane's current lines
