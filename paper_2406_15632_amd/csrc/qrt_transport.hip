@@ -28,7 +28,9 @@
 // runs in k_first's events and in k_scatter, which is convergent.  Waves of
 // the persistent kernels take work in blocks of 64 to 512 items from counters
 // of their XCD (WorkPool) and refill once every lane of the wave is idle, which
-// keeps a wave's rays together.  The per-order walks run at three blocks per CU
+// keeps a wave's rays together; the per-order walks hand out their items in
+// 512-item blocks in a strided order (scatter_block), so that concurrent waves
+// do not all walk rays of one part of the mesh.  The per-order walks run at three blocks per CU
 // (kWalkBlocksPerCu): their flights are incoherent gathers, and fewer waves
 // leave more of each lane's lines in the L1 cache.
 //
@@ -514,7 +516,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 }
 
 // --------------------------------------------------------------------------
-// walks of one order: peel-off rays, then flights
+// walks of one order: peel-off rays and flights
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
