@@ -230,6 +230,20 @@ def test_small_disk_multi_order_fp64_parity(ctx, Q, kind):
     assert_counters_equal(cg, co)
 
 
+@pytest.mark.parametrize("kind", [O.SOBOL, O.PHILOX])
+def test_large_chunk_multi_order_fp64_parity(ctx, Q, kind):
+    """One chunk of 2^20 packets through 20 orders: the work pools of every
+    order hand out their blocks in the strided order at full size, and the
+    live lists grow past a million entries."""
+    sc = scenes.disk128(n=32).replace(npix=64, fp64=True, n_packets=1 << 20)
+    _say(f"disk32 FP64 20 orders 2^20 packets kind={kind}")
+    g, cg = gpu_images(ctx, Q, sc, kind, 1, sc.n_packets, seed=2406)
+    o, co, _ = O.run(sc, kind, count=sc.n_packets, seed=2406, nthreads=8)
+    assert co["scatterings"] > 2 * (co["packets"] - co["tau_cuts"])   # packets scatter more than twice on average
+    assert_fp64_parity(g, o)
+    assert_counters_equal(cg, co)
+
+
 def test_disk128_fp64_parity(ctx, Q):
     sc = scenes.disk128().replace(fp64=True, n_packets=1 << 16)
     _say("disk128 FP64 sobol 2^16")
@@ -251,9 +265,9 @@ def test_clumpy256_sphere_star_fp64_parity(ctx, Q, emit_order):
 
 
 def test_large_mesh_multi_order_fp64_parity(ctx, Q):
-    """A 64 MiB mesh with three scattering orders: the per-order walks of a
-    mesh this large run at three blocks per CU (two for smaller meshes, all
-    resident waves for the last order); the images do not depend on it."""
+    """A 64 MiB mesh with three scattering orders: the per-order walks run at
+    three blocks per CU, and with all resident waves for the last order; the
+    images do not depend on it."""
     sc = scenes.clumpy256().replace(fp64=True, n_packets=1 << 14, max_orders=3)
     _say("clumpy256 FP64, 3 orders, sobol 2^14")
     g, cg = gpu_images(ctx, Q, sc, O.SOBOL, 1, sc.n_packets)
