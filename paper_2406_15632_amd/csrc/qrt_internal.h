@@ -12,7 +12,7 @@ namespace qrt {
 constexpr int kMaxDims = 128;
 constexpr int kMaxObs = 16;
 constexpr uint64_t kChunk = 1ull << 22;   // packets per transport chunk (queue capacity)
-constexpr int kImageCopies = 8;           // image accumulators written by different XCDs, folded on read
+constexpr int kImageCopies = 16;          // image accumulators (two per XCD: blocks go to the XCDs in turn), folded on read
 
 // counter slots in the device counter array
 enum CounterSlot {
