@@ -81,7 +81,7 @@ constexpr int kPoolStride = 16;   // counters per 128-byte line
 __device__ __forceinline__ uint64_t pool_block(uint64_t total, uint64_t nwaves)
 {
     const uint64_t per_wave = total / nwaves;
-    return per_wave >= 4096 ? 512 : (per_wave >= 1024 ? 256 : (per_wave >= 256 ? 128 : 64));
+    return per_wave >= 8192 ? 512 : (per_wave >= 2048 ? 256 : (per_wave >= 512 ? 128 : 64));
 }
 
 struct WorkPool {
