@@ -62,12 +62,27 @@ def _net_counts_ok(pts, m, t, dims):
 
 
 def _first_pts(kind, dims, m, seed=0):
-    # index 0 (the origin, scrambled like the rest when scrambling) plus indices 1 .. 2^m-1
+    # index 0 (the origin) plus indices 1 .. 2^m-1
     body = O.points(kind, dims, 1, (1 << m) - 1, seed=seed)
     origin = np.zeros((1, dims), dtype=np.uint32)
-    if kind == O.SOBOL_OWEN:
-        origin[0] = [_owen_py(0, seed, d) for d in range(dims)]
     return np.vstack([origin, body])
+
+
+def _net_counts_one_short(pts, m, dims):
+    """The 2^m - 1 points of indices 1 .. 2^m-1 of a (0,m,s)-net whose point of
+    index 0 is left out: every elementary box of volume 2^-m holds one point,
+    except exactly one box, which is empty."""
+    s = len(dims)
+    for comp in itertools.product(range(m + 1), repeat=s):
+        if sum(comp) != m:
+            continue
+        key = np.zeros(len(pts), dtype=np.int64)
+        for dd, di in zip(dims, comp):
+            key = (key << di) | (pts[:, dd].astype(np.int64) >> (32 - di) if di else 0)
+        counts = np.bincount(key, minlength=1 << m)
+        if not (np.count_nonzero(counts == 1) == (1 << m) - 1 and np.count_nonzero(counts == 0) == 1):
+            return False
+    return True
 
 
 @pytest.mark.parametrize("m", [4, 8, 12, 16])
@@ -280,34 +295,88 @@ def test_splitmix64_known_values():
 @pytest.mark.parametrize("m", [6, 10])
 def test_owen_scrambling_keeps_sobol_nets(m):
     """Owen's scrambling permutes every elementary interval as a whole, so the
-    first 2^m scrambled Sobol points (index 0 included, scrambled like the
-    others) are still (0,m,1)-nets per dimension and a (0,m,2)-net in dims 0-1."""
+    first 2^m scrambled Sobol points are still (0,m,1)-nets per dimension and a
+    (0,m,2)-net in dims 0-1.  Index 0 is not generated (Sec. 3.7), so the
+    points of indices 1 .. 2^m-1 fill every elementary box but one."""
     for seed in (1, 99):
-        pts = _first_pts(O.SOBOL_OWEN, 4, m, seed=seed)
+        pts = O.points(O.SOBOL_OWEN, 4, 1, (1 << m) - 1, seed=seed)
         for d in range(4):
-            assert _net_counts_ok(pts, m, 0, [d])
-        assert _net_counts_ok(pts, m, 0, [0, 1])
+            assert _net_counts_one_short(pts, m, [d])
+        assert _net_counts_one_short(pts, m, [0, 1])
 
 
-def _owen_py(x, seed, d):
-    """Owen scrambling of one 0.32 fixed-point coordinate, written out bit by bit."""
-    out = x
-    for t in range(32):
-        prefix = 0 if t == 0 else x >> (32 - t)
-        key = _splitmix64(seed ^ _splitmix64((d << 8) | t)) ^ prefix
-        out ^= (_splitmix64(key) >> 63) << (31 - t)
-    return out
+def _divergence_pairs(raw, d, depths):
+    """Pairs (i, j) of points whose coordinate d agrees in its top t bits and
+    differs in bit t (depth t, counted from the most significant bit), for each t
+    in depths: the first such pair found in the list."""
+    x = raw[:, d].astype(np.uint64)
+    pairs = {}
+    for t in depths:
+        top = x >> np.uint64(31 - t)          # the top t+1 bits
+        seen = {}
+        for i, v in enumerate(top.tolist()):
+            mate = seen.get(v ^ 1)            # same top t bits, other bit t
+            if mate is not None:
+                pairs[t] = (mate, i)
+                break
+            seen.setdefault(v, i)
+    return pairs
 
 
-def test_owen_scrambling_definition():
-    """Against the definition written out here bit by bit (a key per depth,
-    dimension and seed, xored with the original higher bits)."""
-    seed = 12345
-    raw = O.points(O.SOBOL, 5, 1, 300)
-    scr = O.points(O.SOBOL_OWEN, 5, 1, 300, seed=seed)
-    for i in range(0, 300, 7):
-        for d in range(5):
-            assert int(scr[i, d]) == _owen_py(int(raw[i, d]), seed, d)
-    # different seeds give different, uniformly spread points
-    other = O.points(O.SOBOL_OWEN, 5, 1, 300, seed=seed + 1)
-    assert not np.array_equal(scr, other)
+def test_owen_scrambling_is_nested():
+    """The defining property of nested uniform scrambling (Owen 1995), checked on
+    the scrambled points alone.  Two coordinates that first differ at depth t keep
+    their common top t bits after scrambling and still differ at depth t (the flips
+    of those bits depend only on the common prefix); the flips of their lower bits
+    depend on the bit where they part, so the XOR of their scrambled lower bits
+    changes with the seed, and it is uniformly distributed.  A plain random digital
+    shift (flips independent of the prefix) keeps that XOR equal to the XOR of the
+    unscrambled bits for every seed, and fails here."""
+    n = 1 << 12
+    raw = O.points(O.SOBOL, 4, 1, n)
+    seeds = list(range(1, 25))
+    scr = [O.points(O.SOBOL_OWEN, 4, 1, n, seed=s) for s in seeds]
+    depths = list(range(0, 12))
+    low_bits_same = 0
+    trials = 0
+    bit_below = []
+    for d in range(4):
+        for t, (i, j) in _divergence_pairs(raw, d, depths).items():
+            hi_mask = ((1 << t) - 1) << (32 - t) if t else 0
+            bit_t = 1 << (31 - t)
+            low_mask = bit_t - 1
+            xr = int(raw[i, d]) ^ int(raw[j, d])
+            assert xr & hi_mask == 0 and xr & bit_t
+            lows = set()
+            for sp in scr:
+                a, b = int(sp[i, d]), int(sp[j, d])
+                assert (a ^ b) & hi_mask == 0, (d, t)      # common prefix kept
+                assert (a ^ b) & bit_t, (d, t)             # still part at depth t
+                lows.add((a ^ b) & low_mask)
+                low_bits_same += ((a ^ b) & low_mask) == (xr & low_mask)
+                trials += 1
+                bit_below.append(((a ^ b) >> (30 - t)) & 1)
+            assert len(lows) > len(seeds) // 2, (d, t)     # the lower flips follow the parting bit
+    # for a nested scrambling the scrambled lower bits of a pair match the raw ones
+    # with probability 2^-(31-t) <= 2^-20 per seed; a digital shift matches always
+    assert low_bits_same == 0
+    # the first bit below the parting one is a fair coin over pairs and seeds
+    frac = float(np.mean(bit_below))
+    assert abs(frac - 0.5) < 5 * 0.5 / np.sqrt(len(bit_below)), frac
+
+
+def test_owen_scrambling_top_flip_is_shared():
+    """The flip of the top bit has no prefix to depend on: for one seed and
+    dimension it is the same for every point, so the scrambled top bit is the raw
+    top bit XOR a constant; over seeds that constant is a fair coin."""
+    raw = O.points(O.SOBOL, 3, 1, 512)
+    flips = []
+    for seed in range(1, 41):
+        scr = O.points(O.SOBOL_OWEN, 3, 1, 512, seed=seed)
+        for d in range(3):
+            f = (scr[:, d] >> 31) ^ (raw[:, d] >> 31)
+            assert np.all(f == f[0])
+            flips.append(int(f[0]))
+    assert 0.25 < np.mean(flips) < 0.75
+    # different seeds give different points
+    assert not np.array_equal(O.points(O.SOBOL_OWEN, 3, 1, 64, seed=1), O.points(O.SOBOL_OWEN, 3, 1, 64, seed=2))
