@@ -22,15 +22,36 @@ LIB = os.path.join(HERE, "_build", "liboracle.so")
 SOBOL, HALTON, NIEDERREITER2, HAMMERSLEY, PHILOX, FAURE, SOBOL_OWEN = 0, 1, 2, 3, 4, 5, 6
 
 
-def build(force: bool = True) -> str:
-    os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=gnu11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+# Sanitizer builds of the same source (the checker checked): "asan" adds
+# AddressSanitizer and UndefinedBehaviorSanitizer (every UB report aborts), "tsan"
+# ThreadSanitizer for the OpenMP packet loop.  The TSan build uses LLVM's clang
+# and OpenMP runtime, whose Archer tool tells TSan about OpenMP's barriers (GCC's
+# libgomp is not instrumented, so TSan would report its joins as races).
+# QRT_ORACLE_VARIANT selects which build lib() loads; the process must then
+# preload the matching sanitizer runtime.
+LLVM_BIN = "/opt/rocm/llvm/bin"
+VARIANT_FLAGS = {
+    "": ["gcc", "-O2"],
+    "asan": ["gcc", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"],
+    "tsan": [os.path.join(LLVM_BIN, "clang"), "-O1", "-g", "-fsanitize=thread"],
+}
+
+
+def lib_path(variant: str = "") -> str:
+    return LIB if not variant else os.path.join(HERE, "_build", f"liboracle_{variant}.so")
+
+
+def build(force: bool = True, variant: str = "") -> str:
+    path = lib_path(variant)
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(SRC):
+        tmp = path + ".tmp"
+        cmd = [*VARIANT_FLAGS[variant], "-std=gnu11", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
                "-fPIC", "-shared", SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, path)
+    return path
 
 
 class _Scene(C.Structure):
@@ -74,7 +95,7 @@ _lib: Optional[C.CDLL] = None
 def lib() -> C.CDLL:
     global _lib
     if _lib is None:
-        path = build(force=False)
+        path = build(force=False, variant=os.environ.get("QRT_ORACLE_VARIANT", ""))
         L = C.CDLL(path)
         L.oracle_points.argtypes = [C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, C.c_uint64,
                                     C.c_uint64, C.c_uint64, C.c_uint64, C.c_void_p]

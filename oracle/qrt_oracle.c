@@ -715,10 +715,10 @@ int oracle_run(const og_scene *S, uint64_t first, uint64_t count, double *img, o
                int64_t nthreads, double *events, int64_t max_events, int64_t *n_events)
 {
     if (first < 1 || S->n_obs < 1 || S->npix < 1) return -1;
+    if (S->order_images > 0 && S->order_images < S->max_orders) return -1;
     og_seq q = {S->seq_kind, S->dims, S->mat, S->bases, S->seed, S->n_total};
     og_obs *obs = (og_obs *)malloc(sizeof(og_obs) * (size_t)S->n_obs);
     for (int o = 0; o < S->n_obs; ++o) og_make_obs(S->obs_theta[o], S->obs_phi[o], &obs[o]);
-    if (S->order_images > 0 && S->order_images < S->max_orders) return -1;
     size_t img_n = (size_t)S->n_obs * 3 * (size_t)S->npix * (size_t)S->npix *
                    (size_t)(S->order_images > 0 ? S->order_images : 1);
     int64_t zero = 0;
