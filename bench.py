@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--packets", type=int, default=1 << 22, help="packets per point set per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="oracle packets per point set")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 21, help="oracle packets per point set")
     ap.add_argument("--no-time-to-error", action="store_true")
     ap.add_argument("--ref-log2", type=int, default=30, help="log2 packets of the reference images")
     ap.add_argument("--sweep-log2", type=int, default=26, help="largest log2 packets of the error sweep")
@@ -152,29 +152,67 @@ def measured_copy_gbps(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * mib * (1 << 20) / best / 1e9
 
 
-def cpu_baseline(sc, n_sample: int):
-    """The FP64 oracle on the host cores, on the first n_sample packets of each point set."""
+def host_cpus():
+    """The host's CPU model, nproc, the CPUs this process may run on, and the CPU
+    quota of its cgroup (None when unlimited); the oracle uses min(affinity, quota)
+    threads, so that a quota is not oversubscribed."""
+    import math
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = max(1, math.floor(int(q) / int(period)))
+    except (OSError, ValueError):
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": affinity, "cgroup_quota": quota,
+            "threads": min(affinity, quota) if quota else affinity}
+
+
+def cpu_baseline(sc, n_sample: int, n_single: int = 1 << 17, repeats: int = 3):
+    """The FP64 oracle on the host cores, on the first n_sample packets of each
+    point set (OpenMP over packet ranges, every usable core), and on the first
+    n_single Sobol packets on one thread (the paper's single-core timing); the
+    median of `repeats` runs for each."""
     from oracle import oracle as O
     from synth import scenes
-    threads = max(1, min(16, os.cpu_count() or 1))
+    host = host_cpus()
+    threads = host["threads"]
     for name in KIND_ORDER:   # build the generator tables outside the timing
         O.seq_tables(scenes.KIND_BY_NAME[name], sc.dims)
-    t0 = time.perf_counter()
-    for name in KIND_ORDER:
-        kind = scenes.KIND_BY_NAME[name]
-        O.run(sc, kind, first=1, count=n_sample, seed=PHILOX_SEED, n_total=sc.n_packets, nthreads=threads)
-    dt = time.perf_counter() - t0
+
+    def all_sets():
+        t0 = time.perf_counter()
+        for name in KIND_ORDER:
+            kind = scenes.KIND_BY_NAME[name]
+            O.run(sc, kind, first=1, count=n_sample, seed=PHILOX_SEED, n_total=sc.n_packets, nthreads=threads)
+        return time.perf_counter() - t0
+
+    def single():
+        t0 = time.perf_counter()
+        O.run(sc, scenes.SOBOL, first=1, count=n_single, nthreads=1)
+        return time.perf_counter() - t0
+
+    runs = sorted(all_sets() for _ in range(repeats))
+    runs1 = sorted(single() for _ in range(repeats))
+    dt, dt1 = runs[len(runs) // 2], runs1[len(runs1) // 2]
     total = n_sample * len(KIND_ORDER)
-    # one thread, the way the paper times its runs: the first 2^18 Sobol packets
-    n1 = 1 << 18
-    t1 = time.perf_counter()
-    O.run(sc, scenes.SOBOL, first=1, count=n1, nthreads=1)
-    dt1 = time.perf_counter() - t1
     return {"value": total / dt, "unit": "packets/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n_sample} packets of each of the 5 point sets of the disk128 workload "
-                      f"(FP64 oracle, OpenMP over packet ranges, {threads} threads), {dt:.1f} s",
-            "single_thread": {"value": n1 / dt1, "unit": "packets/s",
-                              "sample": f"first {n1} Sobol packets of disk128 on 1 thread, {dt1:.1f} s"}}
+                      f"(FP64 oracle, OpenMP over packet ranges, {threads} threads), median of {repeats} "
+                      f"runs of {dt:.1f} s",
+            "host": host, "runs_s": runs,
+            "single_thread": {"value": n_single / dt1, "unit": "packets/s", "runs_s": runs1,
+                              "sample": f"first {n_single} Sobol packets of disk128 on 1 thread, median of "
+                                        f"{repeats} runs of {dt1:.2f} s"}}
 
 
 DISK_DOMAIN = dict(center=(0.0, 0.0, 0.0), r_in=0.05, r_out=1.0, h0=0.1, beta=1.125, zmax_over_h=3.0)

@@ -136,7 +136,9 @@ int qrt_set_dust(qrt_ctx *ctx, double albedo, double g, double p_lin, double p_c
 /* Observers at infinity in directions (theta[i], phi[i]) (radians, Sec. 3.6),
    1 <= n_obs <= QRT_MAX_OBSERVERS.  Each image is npix x npix pixels covering
    [-half_width, half_width]^2 in image axes e_x = (-sin phi, cos phi, 0),
-   e_y = o x e_x.  Resets the images. */
+   e_y = o x e_x.  Resets the images.  If the image memory cannot be
+   allocated (QRT_OUT_OF_MEMORY), the context is left with no observers: runs
+   and image reads return QRT_BAD_STATE until a later call succeeds. */
 int qrt_set_observers(qrt_ctx *ctx, int n_obs, const double *theta, const double *phi, int npix,
                       double half_width);
 
@@ -170,7 +172,9 @@ int qrt_image_device_ptr(qrt_ctx *ctx, double **dev_ptr);
    summed set (enable = 0, the default).  Allocates max_orders times the image
    memory and resets the images.  While it is on, max_orders cannot change,
    qrt_read_images returns the sum over the orders, and qrt_image_device_ptr
-   is refused. */
+   is refused.  If the memory cannot be allocated (QRT_OUT_OF_MEMORY), the
+   context is left with no observers and no per-order images, as after a
+   failed qrt_set_observers. */
 int qrt_set_order_images(qrt_ctx *ctx, int enable);
 
 /* Copy the images of scattering order `order` (1-based) of observer obs, as

@@ -267,7 +267,11 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
 
 size_t image_sets(const qrt_ctx *c) { return c->order_images > 0 ? (size_t)c->order_images : 1; }
 
-// image buffer for the current observers and image sets
+// Image buffer for the current observers and image sets.  The old buffer is
+// freed first (two large image sets need not fit together).  If the new one
+// cannot be allocated, the context is left without observers and without
+// per-order images, so that no kernel can be launched on a missing buffer
+// until qrt_set_observers succeeds again.
 int ensure_images(qrt_ctx *c)
 {
     const size_t want = c->img_elems * kImageCopies * image_sets(c);
@@ -278,7 +282,15 @@ int ensure_images(qrt_ctx *c)
         c->img = nullptr;
         c->img_alloc = 0;
     }
-    HIP_TRY(c, hipMalloc(&c->img, want * sizeof(double)), "image allocation");
+    const hipError_t e = hipMalloc(&c->img, want * sizeof(double));
+    if (e != hipSuccess) {
+        c->img = nullptr;
+        c->has_obs = false;
+        c->order_images = 0;
+        c->img_elems = 0;
+        (void)hipGetLastError();   // the failed allocation is reported here, not by a later call
+        return hip_fail(c, e, "image allocation");
+    }
     c->img_alloc = want;
     return QRT_OK;
 }
@@ -286,6 +298,7 @@ int ensure_images(qrt_ctx *c)
 // fold the copies of every image set into its first copy
 int fold_images(qrt_ctx *c)
 {
+    if (!c->img || !c->has_obs) return fail(c, QRT_BAD_STATE, "no image buffer (set the observers)");
     for (size_t s = 0; s < image_sets(c); ++s)
         HIP_TRY(c, launch_fold_images(c->img + s * kImageCopies * c->img_elems, c->img_elems, c->stream),
                 "image fold");
@@ -621,7 +634,7 @@ static void transport_params(const qrt_ctx *c, TransportParams &P)
 
 static int run_checks(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, uint64_t count)
 {
-    if (!c->has_grid || !c->has_source || !c->has_obs)
+    if (!c->has_grid || !c->has_source || !c->has_obs || !c->img)
         return fail(c, QRT_BAD_STATE, "set grid, source and observers before running");
     if (point_dims(c) > kMaxDims)
         return fail(c, QRT_UNSUPPORTED, "%d point dimensions exceed the %d served", point_dims(c), kMaxDims);

@@ -218,8 +218,8 @@ class Context:
     def set_observers(self, observers: Sequence[Tuple[float, float]], npix: int, half_width: float):
         th = (C.c_double * len(observers))(*[o[0] for o in observers])
         ph = (C.c_double * len(observers))(*[o[1] for o in observers])
-        self.n_obs, self.npix = len(observers), npix
         self._ck(self.lib.qrt_set_observers(self.h, len(observers), th, ph, npix, half_width))
+        self.n_obs, self.npix = len(observers), npix
 
     def set_sequence(self, kind: int, seed: int = 0, n_total: int = 0):
         self._ck(self.lib.qrt_set_sequence(self.h, kind, seed, n_total))

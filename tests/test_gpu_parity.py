@@ -398,6 +398,47 @@ def test_errors_are_reported(ctx, Q):
         ctx.set_point_source(2.0, 0.0, 0.0)
 
 
+def test_failed_image_allocation_leaves_no_observers(ctx, Q):
+    """An image set too large for the device (16 observers of 8192^2 pixels, in
+    every image copy: hundreds of GB) is refused with QRT_OUT_OF_MEMORY, and the
+    context is then left without observers: runs and image reads are refused
+    before any kernel is launched, until the observers are set again; so is a
+    per-order image set too large to allocate."""
+    from paper_2406_15632_amd.qrt import QRTError
+    sc = scenes.envelope32(n_packets=1 << 10)
+    ctx.set_scene(sc)
+    ctx.run(1, sc.n_packets)
+    ref = ctx.read_images()
+    _say("image allocation too large")
+    with pytest.raises(QRTError) as e:
+        ctx.set_observers([(0.3, 0.1)] * 16, 8192, 1.0)
+    assert e.value.code == Q.QRT_OUT_OF_MEMORY
+    for call in (lambda: ctx.run(1, 10), ctx.read_images, ctx.image_device_ptr):
+        with pytest.raises(QRTError) as e:
+            call()
+        assert e.value.code == Q.QRT_BAD_STATE
+    # the observers set again: the context works as before
+    ctx.set_observers(sc.observers, sc.npix, sc.half_width)
+    ctx.reset_images()
+    ctx.run(1, sc.n_packets)
+    assert np.array_equal(ctx.read_images(), ref)
+    # per-order images of 40 orders of 16 observers at 2048^2: about 1 TB
+    ctx.set_observers([(0.3, 0.1)] * 16, 2048, 1.0)
+    ctx.set_transport(40, sc.tau_min, Q.FP64)
+    _say("per-order image allocation too large")
+    with pytest.raises(QRTError) as e:
+        ctx.set_order_images(True)
+    assert e.value.code == Q.QRT_OUT_OF_MEMORY
+    for call in (lambda: ctx.run(1, 10), lambda: ctx.read_order_images(1), ctx.read_images):
+        with pytest.raises(QRTError) as e:
+            call()
+        assert e.value.code == Q.QRT_BAD_STATE
+    ctx.set_scene(sc)
+    ctx.reset_images()
+    ctx.run(1, sc.n_packets)
+    assert np.array_equal(ctx.read_images(), ref)
+
+
 # ------------------------------------------------------------------ full benchmark size
 def test_disk128_full_size_properties(ctx, Q):
     """The benchmark configuration (2^22 packets per sequence, FP32): the run
