@@ -523,7 +523,7 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
-    hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
+    hipError_t e = launch_clear_queues(B.q, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys);
     if ((e = launch_sort_keys(B, count, st)) != hipSuccess) return e;

@@ -223,6 +223,9 @@ hipError_t launch_transport(const TransportParams &P, int precision, int kind, u
 // the x-fastest mesh src[nz][ny][nx] into the bricked order of dst (cleared beforehand)
 hipError_t launch_to_bricks(const float *src, float *dst, int nx, int ny, int nz, hipStream_t stream);
 
+// zero the queue counters of a chunk (a kernel, not a memset node)
+hipError_t launch_clear_queues(Queues *q, hipStream_t stream);
+
 // img[0 .. n) += img[c n .. (c+1) n) for every further copy c, which is cleared
 hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream);
 

@@ -805,7 +805,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
-    hipError_t e = hipMemsetAsync(B.q, 0, sizeof(Queues), st);
+    hipError_t e = launch_clear_queues(B.q, st);
     if (e != hipSuccess) return e;
     // first flights in emission-direction order
     hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys);
@@ -871,6 +871,23 @@ hipError_t launch_transport(const TransportParams &P, int precision, int kind, u
         done += n;
     }
     return hipSuccess;
+}
+
+// ---------------------------------------------------------------- queue counters
+// The queue counters of a chunk start at zero.  A kernel clears them rather
+// than a memset node, so that a launch sequence captured into a graph replays
+// the clear like its other kernels.
+static_assert(sizeof(Queues) % 4 == 0, "the queue counters are whole words");
+
+__global__ void __launch_bounds__(256) k_clear_words(uint32_t *__restrict__ p, uint32_t n)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
+hipError_t launch_clear_queues(Queues *q, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, stream, (uint32_t *)q, (uint32_t)(sizeof(Queues) / 4));
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- image copies

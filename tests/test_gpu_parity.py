@@ -421,7 +421,8 @@ def test_failed_image_allocation_leaves_no_observers(ctx, Q):
     ctx.set_observers(sc.observers, sc.npix, sc.half_width)
     ctx.reset_images()
     ctx.run(1, sc.n_packets)
-    assert np.array_equal(ctx.read_images(), ref)
+    # equal up to the order of the FP64 atomic sums
+    assert np.allclose(ctx.read_images(), ref, rtol=1e-12, atol=1e-15 * ref.max())
     # per-order images of 40 orders of 16 observers at 2048^2: about 1 TB
     ctx.set_observers([(0.3, 0.1)] * 16, 2048, 1.0)
     ctx.set_transport(40, sc.tau_min, Q.FP64)
@@ -436,7 +437,7 @@ def test_failed_image_allocation_leaves_no_observers(ctx, Q):
     ctx.set_scene(sc)
     ctx.reset_images()
     ctx.run(1, sc.n_packets)
-    assert np.array_equal(ctx.read_images(), ref)
+    assert np.allclose(ctx.read_images(), ref, rtol=1e-12, atol=1e-15 * ref.max())
 
 
 # ------------------------------------------------------------------ full benchmark size
