@@ -157,6 +157,23 @@ int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precisio
    add their contributions to the images.  Asynchronous on the context stream. */
 int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
 
+/* qrt_run for callers that cannot allocate device memory: code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc.  It transports
+   the same packets with the same kernels and adds the same contributions to
+   the images, but takes every transport buffer (packet states, peel-off slots,
+   sort lists, queue counters) from a static scratch array of 36 MiB that each
+   device holds from the library's load to the end of the process, in chunks
+   of 2^16 packets; it calls no hipMalloc, hipFree or other allocating routine.
+   The grid, images, counters and tables are the context's, allocated by the
+   set-up calls.  Limits: QRT_UNSUPPORTED when a chunk's buffers exceed the
+   scratch (more than 4 observers in FP64, more than 11 in FP32);
+   QRT_BAD_STATE for Faure points whose tables no earlier qrt_run or
+   qrt_generate_points built for this many coordinates.  All contexts on one
+   device share its scratch: calls that overlap on one device (other streams,
+   other host threads) race and must be serialised by the caller.  Asynchronous
+   on the context stream, like qrt_run. */
+int qrt_run_static(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
+
 /* Copy image obs (npix*npix doubles each, [iy][ix]) of Stokes I, Q, U to host
    buffers (any may be NULL).  normalized = 1 divides by the number of packets
    run since the last reset.  Synchronises the stream. */

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,11 @@ void sobol_columns(int dims, uint32_t *out);
 }  // namespace qrt
 
 using namespace qrt;
+
+// Transport scratch of the allocation-free runs (qrt_run_static), one copy per
+// device; see static_buffers below for its layout.
+constexpr size_t kStaticScratchBytes = 36ull << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct qrt_ctx {
     int device = 0;
@@ -94,6 +100,8 @@ struct qrt_ctx {
     uint64_t batch_total = 0;                // packets of one batch run
     int batch_max_orders = 0;
     uint64_t batch_runs = 0;                 // batch runs since the last reset
+    // device address of this device's static transport scratch (allocation-free runs)
+    unsigned char *scratch = nullptr;
 };
 
 namespace {
@@ -305,6 +313,65 @@ int fold_images(qrt_ctx *c)
     return QRT_OK;
 }
 
+// ---------------------------------------------------------------- allocation-free transport
+// qrt_run_static takes every transport buffer (state lists, peel slots, sort
+// lists and histograms, queue counters) from one file-scope device array
+// instead of context allocations, in chunks of kStaticChunk packets.  Each
+// device holds its own copy of the array from the load of the library to the
+// end of the process.  In host code `scratch` is only a stand-in for the
+// symbol: its device address comes from hipGetSymbolAddress, once per device,
+// and only that address is ever handed to kernels.
+constexpr uint64_t kStaticChunk = 1ull << 16;
+constexpr int kStaticMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kStaticMaxDevices] = {};
+
+// device address of the scratch array on `device` (the current device)
+hipError_t scratch_address(int device, unsigned char **out)
+{
+    if (device < 0 || device >= kStaticMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[device] = (unsigned char *)ptr;
+    }
+    *out = g_scratch_dev[device];
+    return hipSuccess;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// The transport buffers of one kStaticChunk-packet chunk carved from the
+// scratch at base (null: only the size); returns the bytes they take.
+size_t static_buffers(unsigned char *base, int precision, int n_obs, TransportBuffers &B)
+{
+    const uint64_t cap = kStaticChunk;
+    const size_t pb = packet_state_bytes(precision) * cap * 2;
+    const size_t rb = peel_ray_bytes(precision) * (cap + 64) * (size_t)n_obs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        unsigned char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    B = TransportBuffers{};
+    B.packets = take(pb);
+    B.peels = take(rb);
+    B.order = (uint32_t *)take(cap * sizeof(uint32_t));
+    B.keys = (uint32_t *)take(cap * sizeof(uint32_t));
+    B.sort_tmp = (uint32_t *)take(2 * cap * sizeof(uint32_t));
+    B.hist = (uint32_t *)take(kSortHist * sizeof(uint32_t));
+    B.q = (Queues *)take(sizeof(Queues));
+    B.packet_bytes = pb;
+    B.peel_bytes = rb;
+    B.cap = cap;
+    return off;
+}
+
 }  // namespace
 
 extern "C" {
@@ -345,6 +412,8 @@ int qrt_create(qrt_ctx **out, int device, void *hip_stream)
     if (e == hipSuccess) e = hipMemset(c->counters, 0, kCounterBytes);
     if (e == hipSuccess) e = hipMalloc(&c->tb.q, sizeof(Queues));
     if (e == hipSuccess) e = hipMalloc(&c->tb.hist, sizeof(uint32_t) * kSortHist);
+    // this device's static scratch (looked up once per device, with the device current)
+    if (e == hipSuccess) e = scratch_address(device, &c->scratch);
     if (e != hipSuccess) {
         qrt_destroy(c);
         return e == hipErrorOutOfMemory ? QRT_OUT_OF_MEMORY : QRT_HIP_ERROR;
@@ -659,6 +728,38 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = count - done < c->tb_packets ? count - done : c->tb_packets;
         HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream), "transport launch");
+        done += n;
+    }
+    c->packets_run += count;
+    return QRT_OK;
+}
+
+int qrt_run_static(qrt_ctx *c, uint64_t first, uint64_t count)
+{
+    if (!c) return QRT_INVALID_ARG;
+    int rc = run_checks(c, c->kind, c->n_total, first, count);
+    if (rc) return rc;
+    if (!c->scratch) return fail(c, QRT_HIP_ERROR, "no static scratch on device %d", c->device);
+    if (c->kind == QRT_FAURE && !(c->faure && c->faure_dims == point_dims(c)))
+        return fail(c, QRT_BAD_STATE,
+                    "the Faure tables for %d coordinates are built by qrt_run or qrt_generate_points; "
+                    "the allocation-free run does not build them", point_dims(c));
+    TransportBuffers B;
+    const size_t need = static_buffers(nullptr, c->precision, c->n_obs, B);
+    if (need > kStaticScratchBytes)
+        return fail(c, QRT_UNSUPPORTED,
+                    "%d observers at %s need %zu bytes of scratch per chunk of %llu packets; the static "
+                    "scratch holds %zu (at most 4 observers in FP64, 11 in FP32)",
+                    c->n_obs, c->precision == QRT_FP64 ? "FP64" : "FP32", need,
+                    (unsigned long long)kStaticChunk, kStaticScratchBytes);
+    if (count == 0) return QRT_OK;
+    DeviceGuard dg(c->device);
+    static_buffers(c->scratch, c->precision, c->n_obs, B);
+    TransportParams P;
+    transport_params(c, P);
+    for (uint64_t done = 0; done < count;) {
+        const uint64_t n = count - done < kStaticChunk ? count - done : kStaticChunk;
+        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, B, c->stream), "transport launch");
         done += n;
     }
     c->packets_run += count;

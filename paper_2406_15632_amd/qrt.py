@@ -84,6 +84,7 @@ SIGNATURES = {
     "qrt_set_sequence": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64]),
     "qrt_set_transport": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.c_int]),
     "qrt_run": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
+    "qrt_run_static": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
     "qrt_read_images": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_image_device_ptr": (C.c_int, [_P, C.POINTER(C.c_void_p)]),
     "qrt_reset_images": (C.c_int, [_P]),
@@ -245,6 +246,10 @@ class Context:
     # -------- work
     def run(self, first: int, count: int):
         self._ck(self.lib.qrt_run(self.h, first, count))
+
+    def run_static(self, first: int, count: int):
+        """qrt_run on the device's static scratch (no allocation)."""
+        self._ck(self.lib.qrt_run_static(self.h, first, count))
 
     def reset_images(self):
         self._ck(self.lib.qrt_reset_images(self.h))
