@@ -16,6 +16,9 @@ The JSON line carries
   time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
                 the speed-up of each over the Monte Carlo (Philox) baseline;
   per_order     image error per scattering order, QMC against Monte Carlo;
+  envelope_time_to_error  the same sweep for the single-scattering dust
+                envelope (32^3, FP64), with the paper's single-scattering
+                speed-ups quoted as context;
                 (time_to_error also holds Faure's curve and the error bar of
                 8 Owen-scrambled Sobol runs against their actual error)
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload;
@@ -215,9 +218,6 @@ def cpu_baseline(sc, n_sample: int, n_single: int = 1 << 17, repeats: int = 3):
                                         f"{repeats} runs of {dt1:.2f} s"}}
 
 
-DISK_DOMAIN = dict(center=(0.0, 0.0, 0.0), r_in=0.05, r_out=1.0, h0=0.1, beta=1.125, zmax_over_h=3.0)
-
-
 def _timed_run(ctx, stream, n):
     import torch
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -246,18 +246,10 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    n_train, n_val = 1 << 20, 1 << 17
-    ctx.surrogate_set_domain(n_r=16, n_z=12, **DISK_DOMAIN)
-    pos = torch.zeros((n_train, 4), dtype=torch.float32, device="cuda")
-    tau = torch.zeros(n_train, dtype=torch.float32, device="cuda")
-    pilot, t_sample = sync_time(lambda: ctx.surrogate_sample(pos, tau, seed=101))
-    vpos = torch.zeros((n_val, 4), dtype=torch.float32, device="cuda")
-    vtau = torch.zeros(n_val, dtype=torch.float32, device="cuda")
-    ctx.surrogate_sample(vpos, vtau, seed=202)
-    steps = 20000
-    rep, t_train = sync_time(lambda: ctx.surrogate_train(pos, tau, steps=steps, batch=8192, lr=2e-3, lr_final=5e-5,
-                                                         seed=7, tau_cap=12.0, weight_floor=0.02))
-    mrep, t_val = sync_time(lambda: ctx.surrogate_validate(vpos, vtau, max_err=0.02, floor_frac=0.3, min_count=16))
+    from paper_2406_15632_amd import surrogate_recipe as SR
+    pilot, rep, mrep, times = SR.train_disk_surrogate(ctx, timer=sync_time)
+    t_sample, t_train, t_val = times["sample_s"], times["train_s"], times["validate_s"]
+    steps, batch = SR.TRAIN["steps"], SR.TRAIN["batch"]
     N = 1 << 24
     out = {"config": "disk128 scene, cylindrical domain R in [0.05, 1), |z| < 3 h(R), 16 x 12 cells per observer; "
                      "2^20 pilot samples (Philox), 2^17 validation samples, 20000 Adam steps of 8192, "
@@ -266,7 +258,7 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
            "pilot_packets": pilot, "sample_s": t_sample, "train_s": t_train, "validate_s": t_val,
            "train_loss": [rep["loss_first"], rep["loss_final"]], "mask": mrep}
     # training throughput: forward plus backward (input and weight gradients) = 3 forward passes per sample
-    train_tflops = steps * 8192 * 3 * MLP_FWD_FLOP / t_train / 1e12
+    train_tflops = steps * batch * 3 * MLP_FWD_FLOP / t_train / 1e12
     out["train_mfma"] = {"tflops": train_tflops, "peak_tflops": MFMA_BF16_PEAK_TFLOPS,
                          "frac": train_tflops / MFMA_BF16_PEAK_TFLOPS,
                          "flop_per_sample": 3 * MLP_FWD_FLOP}
@@ -473,12 +465,14 @@ def per_order_section(qrt, sc, stream):
     return out
 
 
-def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int):
+def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: int, faure: bool = True,
+                        owen: bool = True):
     """Image RMS error (I, all observers) against an independent high-N reference
     versus kernel time, N = 2^12 .. 2^sweep_log2; Sobol is scored against a
     Halton reference and every other set against a Sobol reference; the PRNG
     errors are averaged over seeds (4 below 2^24 packets, 2 above) and run to
-    4x the largest quasi-random size, since they converge more slowly."""
+    4x the largest quasi-random size, since they converge more slowly.  Faure's
+    curve and the error bar of Owen-scrambled Sobol runs are optional."""
     import numpy as np
     import torch
 
@@ -500,7 +494,7 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
     floor = metrics.rms_error(ref_s, ref_h)
     names = {qrt.SOBOL: "sobol", qrt.HALTON: "halton", qrt.NIEDERREITER2: "niederreiter2",
              qrt.HAMMERSLEY: "hammersley", qrt.PHILOX: "philox", qrt.FAURE: "faure"}
-    kinds = list(kinds) + [qrt.FAURE]   # the paper's fourth low-discrepancy sequence
+    kinds = list(kinds) + ([qrt.FAURE] if faure else [])   # the paper's fourth low-discrepancy sequence
     curves = {}
     for kind in kinds:
         ref = ref_h if kind == qrt.SOBOL else ref_s
@@ -517,22 +511,25 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
                 ts.append(t)
             pts.append((float(np.mean(ts)), float(np.mean(errs)), 1 << lg, float(np.mean(dis)), float(np.mean(ins))))
         curves[names[kind]] = pts
-    # randomised QMC: R independent Owen scramblings give an error bar from
-    # their spread; compared here with the actual error of their mean
-    R, n_each = 8, 1 << 21
-    imgs = [run(qrt.SOBOL_OWEN, n_each, 1000 + r)[0] for r in range(R)]
-    mean = sum(imgs) / R
-    spread = float(np.sqrt(sum(float(np.sum((im - mean) ** 2)) for im in imgs) / (R * (R - 1))) /
-                   np.linalg.norm(ref_h))
-    owen = {"scramblings": R, "packets_each": n_each, "estimated_rms_error_of_mean": spread,
-            "actual_rms_error_of_mean": metrics.rms_error(mean, ref_h),
-            "unscrambled_sobol_rms_error_same_packets": metrics.rms_error(run(qrt.SOBOL, R * n_each)[0], ref_h)}
+    owen_bar = None
+    if owen:
+        # randomised QMC: R independent Owen scramblings give an error bar from
+        # their spread; compared here with the actual error of their mean
+        R, n_each = 8, 1 << 21
+        imgs = [run(qrt.SOBOL_OWEN, n_each, 1000 + r)[0] for r in range(R)]
+        mean = sum(imgs) / R
+        spread = float(np.sqrt(sum(float(np.sum((im - mean) ** 2)) for im in imgs) / (R * (R - 1))) /
+                       np.linalg.norm(ref_h))
+        owen_bar = {"scramblings": R, "packets_each": n_each, "estimated_rms_error_of_mean": spread,
+                    "actual_rms_error_of_mean": metrics.rms_error(mean, ref_h),
+                    "unscrambled_sobol_rms_error_same_packets":
+                        metrics.rms_error(run(qrt.SOBOL, R * n_each)[0], ref_h)}
     targets = (0.05, 0.01, 0.003)
     floor_in = metrics.image_norm(ref_s, ref_h)
     by_lg = lambda v, j: {int(p[2]).bit_length() - 1: round(p[j], 6) for p in v}
     out = {"targets": list(targets), "ref_packets": n_ref, "ref_floor_rms": floor, "_ref_halton": ref_h,
            "rms_error_by_log2_packets": {k: by_lg(v, 1) for k, v in curves.items()},
-           "time_s": {}, "speedup_vs_mc": {}, "owen_error_bar": owen,
+           "time_s": {}, "speedup_vs_mc": {}, "owen_error_bar": owen_bar,
            # the paper's norms (Sec. 4): |dI| of the total intensity and Delta I / I over
            # the pixels of all observers, the times to Delta I / I targets, and the
            # power laws a t^-0.5 and a t^-b of |dI| (Sec. 5; t in seconds)
@@ -540,11 +537,17 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
            "ref_floor_integral_norm": abs(metrics.integral_norm(ref_s, ref_h)),
            "integral_norm_by_log2_packets": {k: by_lg(v, 3) for k, v in curves.items()},
            "image_norm_by_log2_packets": {k: by_lg(v, 4) for k, v in curves.items()},
-           "time_s_image_norm": {}, "speedup_vs_mc_image_norm": {}, "integral_norm_fits": {}}
+           "time_s_image_norm": {}, "speedup_vs_mc_image_norm": {}, "integral_norm_fits": {},
+           # packets to the RMS targets: the ratio the paper's CPU times measure (its time is
+           # proportional to the packets), free of the GPU's fixed launch cost at small N
+           "packets_to_error": {}, "speedup_vs_mc_in_packets": {}}
     for k, pts in curves.items():
         ts = [p[0] for p in pts]
         es = [p[1] for p in pts]
+        ns = [float(p[2]) for p in pts]
         out["time_s"][k] = [metrics.time_to_error(ts, es, tg) if tg >= 3 * floor else None for tg in targets]
+        out["packets_to_error"][k] = [metrics.time_to_error(ns, es, tg) if tg >= 3 * floor else None
+                                      for tg in targets]
         ins = [p[4] for p in pts]
         out["time_s_image_norm"][k] = [metrics.time_to_error(ts, ins, tg) if tg >= 3 * floor_in else None
                                        for tg in targets]
@@ -560,10 +563,44 @@ def time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2: int, sweep_log2: 
     a_mc = out["integral_norm_fits"]["philox"]["a_for_b_0.5"]
     for k, f in out["integral_norm_fits"].items():
         f["mc_a_over_a"] = (a_mc / f["a_for_b_0.5"]) if (a_mc and f["a_for_b_0.5"]) else None
-    for key, dst in (("time_s", "speedup_vs_mc"), ("time_s_image_norm", "speedup_vs_mc_image_norm")):
+    for key, dst in (("time_s", "speedup_vs_mc"), ("time_s_image_norm", "speedup_vs_mc_image_norm"),
+                     ("packets_to_error", "speedup_vs_mc_in_packets")):
         mc = out[key]["philox"]
         for k, tt in out[key].items():
             out[dst][k] = [(m / t if (m is not None and t) else None) for m, t in zip(mc, tt)]
+    return out
+
+
+# The paper's single-scattering time table (Sec. 5), dust sphere envelope with a
+# point source: CPU seconds to reach Delta I / I = 5 %, 1 %, 0.3 % on one core of
+# an Intel Core i5-10400F at 4.1 GHz ("quasi MC" = the mean over Sobol,
+# Niederreiter, Faure and Halton).  Context only: other scene, other hardware.
+PAPER_ENVELOPE_SECONDS = {"monte_carlo": [77.0, 1.7e3, 2.0e4], "quasi_mc": [19.0, 1.9e2, 9.4e2],
+                          "hammersley": [8.0, 80.0, 5.0e2]}
+
+
+def envelope_time_to_error(qrt, stream, ref_log2: int = 30, sweep_log2: int = 26):
+    """Time to a fixed image error for the single-scattering dust envelope
+    (envelope32: 32^3 mesh, point source, one 64^2 view at 45 deg, FP64
+    transport), every point set against Monte Carlo, with the paper's
+    single-scattering speed-ups for its dust-sphere envelope beside them."""
+    import torch
+
+    from synth import scenes
+    sc = scenes.envelope32()
+    ctx = qrt.Context(0, stream.cuda_stream)
+    ctx.set_scene(sc, kind=qrt.SOBOL, grid=torch.from_numpy(sc.kappa_rho).cuda())
+    kinds = [scenes.KIND_BY_NAME[k] for k in KIND_ORDER]
+    out = time_to_error_sweep(ctx, qrt, sc, kinds, stream, ref_log2, sweep_log2, faure=True, owen=False)
+    out.pop("_ref_halton")
+    ctx.close()
+    P = PAPER_ENVELOPE_SECONDS
+    out["paper_context"] = {
+        "scene": "the paper's dust sphere envelope, single scattering, point source (Sec. 5 time table)",
+        "hardware": "one core of an Intel Core i5-10400F at 4.1 GHz",
+        "error": "Delta I / I at 5 %, 1 %, 0.3 %",
+        "speedup_vs_mc": {k: [m / t for m, t in zip(P["monte_carlo"], P[k])] for k in ("quasi_mc", "hammersley")},
+    }
     return out
 
 
@@ -676,6 +713,7 @@ def main():
         ref = result["time_to_error"].pop("_ref_halton")
     if not args.no_time_to_error:
         result["per_order"] = per_order_section(qrt, sc, stream)
+        result["envelope_time_to_error"] = envelope_time_to_error(qrt, stream)
     if not args.no_surrogate:
         result["surrogate"] = surrogate_section(ctx, qrt, sc, stream, ref)
     if not args.no_workloads:

@@ -238,6 +238,50 @@ def test_surrogate_transport_matches_oracle(ctx, Q, fill):
             assert np.all(np.abs(g[ob, s] - o[ob, s]) <= 2e-3 * Io + 1e-11 * mx)
 
 
+def test_trained_surrogate_on_the_benchmark_scene_matches_oracle(ctx, Q):
+    """The benchmarked surrogate configuration: the full disk128 scene (128^3
+    mesh, 20 orders, three 256^2 views), the network trained and validated on
+    the GPU with the benchmark's recipe (2^20 Philox pilot samples with exact
+    labels, 20000 Adam steps of 8192, a validity mask from 2^17 validation
+    samples), then FP64 transport with that network and mask against the
+    oracle's surrogate transport with the same parameters and mask, 2^15 Sobol
+    packets: images per pixel within 2e-3 (bfloat16 activations rounded after
+    FP32 instead of FP64 sums), surrogate, fallback and peel counts equal up to
+    the near-tie flips of the other counters."""
+    from paper_2406_15632_amd import surrogate_recipe as SR
+    sc = scenes.disk128()
+    ctx.set_scene(sc)
+    _say("train the disk128 surrogate with the benchmark recipe")
+    pilot, rep, mrep, _ = SR.train_disk_surrogate(ctx)
+    assert pilot > 0 and rep["loss_final"] < 0.1 * rep["loss_first"]
+    assert mrep["valid_cells"] > 0
+    th = ctx.mlp_get_params()
+    valid = ctx.surrogate_get_mask()
+    count = 1 << 15
+    ctx.set_sequence(Q.SOBOL, 0, count)
+    ctx.set_transport(sc.max_orders, sc.tau_min, Q.FP64, Q.PEEL_SURROGATE)
+    ctx.reset_images()
+    _say("disk128 FP64 surrogate transport, 2^15 packets")
+    ctx.run(1, count)
+    g = ctx.read_images(normalized=False) / count
+    cg = ctx.counters()
+    sg = O.Surrogate(th, valid=valid, **SR.DISK_DOMAIN)
+    _say("oracle surrogate transport disk128")
+    o, co, _ = O.run(sc, O.SOBOL, 1, count, nthreads=8, surrogate=sg)
+    assert co["surrogate"] > 0.05 * co["peels"]
+    assert cg["packets"] == co["packets"] == count
+    for k in ("surrogate", "fallbacks", "peels", "peel_rays", "scatterings", "escapes"):
+        assert abs(cg[k] - co[k]) <= 4 + 1e-5 * co[k], f"{k}: gpu {cg[k]} oracle {co[k]}"
+    for ob in range(3):
+        Io = o[ob, 0]
+        mx = Io.max()
+        assert abs(g[ob, 0].sum() - Io.sum()) <= 1e-4 * Io.sum()
+        d = np.abs(g[ob, 0] - Io)
+        assert np.all(d <= 2e-3 * Io + 1e-11 * mx), f"obs {ob}: max rel {np.max(d / np.maximum(Io, 1e-300)):.3e}"
+        for s in (1, 2):
+            assert np.all(np.abs(g[ob, s] - o[ob, s]) <= 2e-3 * Io + 1e-11 * mx)
+
+
 def test_zero_mask_is_the_exact_transport(ctx, Q):
     _say("surrogate zero mask vs exact")
     sc = _small_disk()
