@@ -8,11 +8,15 @@ FP64 optical-depth and image sums.  The mesh is resident in HBM before timing.
 
 The JSON line carries
   value         photon packets/s over the timed steps (HIP events);
-  roofline      of the transport step: algorithmic bytes (4 B per voxel visit +
-                24 B per peel-off contribution, exact counts from the kernels'
-                counters) over the transport time measured with HIP events on
-                the launch stream; HBM traffic from committed rocprofv3 counters
-                when the kernel sources are unchanged since they were taken;
+  roofline      of the dominant kernel, k_walk (the peel-off rays and free
+                flights of every order): its algorithmic bytes (4 B per voxel
+                visit + 24 B per peel-off contribution, exact counts from the
+                kernels' counters) over its time, measured with HIP events that
+                the library records on its launch stream around every kernel in
+                a timing pass after the timed region; the same figure for the
+                whole transport step under "step"; HBM traffic from committed
+                rocprofv3 counters when the kernel sources are unchanged since
+                they were taken;
   time_to_error time to reach 5 %, 1 %, 0.3 % image RMS error per point set and
                 the speed-up of each over the Monte Carlo (Philox) baseline;
   per_order     image error per scattering order, QMC against Monte Carlo;
@@ -61,6 +65,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--timing-steps", type=int, default=3,
+                    help="steps of the per-kernel timing pass (HIP events around every kernel)")
     ap.add_argument("--packets", type=int, default=1 << 22, help="packets per point set per step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 21, help="oracle packets per point set")
@@ -98,9 +104,10 @@ def transport_source_hash(root: str = ROOT) -> str:
     return h.hexdigest()[:16]
 
 
-def committed_traffic():
-    """HBM bytes per transport launch from the committed counter summary, or
-    None when it is missing or was taken on other kernel sources."""
+def committed_traffic(key: str = "bytes_per_step_launch"):
+    """HBM bytes per transport launch (of the whole step, or of the walk
+    kernel with key "walk_bytes_per_launch") from the committed counter summary,
+    or None when it is missing or was taken on other kernel sources."""
     from paper_2406_15632_amd.profile_report import read_traffic
     try:
         d = read_traffic(TRAFFIC_FILE)
@@ -109,7 +116,7 @@ def committed_traffic():
     if d.get("source_hash") != transport_source_hash():
         return None
     try:
-        return float(d["bytes_per_step_launch"])
+        return float(d[key])
     except (KeyError, ValueError):
         return None
 
@@ -661,9 +668,27 @@ def main():
     n_launch = args.steps * len(kinds)
     alg_bytes = 4.0 * cnt["visits"] + 24.0 * cnt["peels"]
     achieved = alg_bytes / (transport_ms * 1e-3) / 1e9
+    # per-kernel timing pass over the same workload: the library records HIP events
+    # on its launch stream around every kernel, by class
+    ctx.set_timing(True)
+    ctx.timing(reset=True)
+    ctx.reset_images()
+    for _ in range(args.timing_steps):
+        step()
+    tm = ctx.timing(reset=True)
+    cnt_t = ctx.counters()
+    ctx.set_timing(False)
+    n_t = args.timing_steps * len(kinds)
+    timed_ms = sum(v[0] for v in tm.values()) / n_t
+    walk_ms = tm["walk"][0] / n_t
+    walk_bytes = (4.0 * (cnt_t["visits"] - cnt_t["visits_first"]) + 24.0 * cnt_t["peels"]) / n_t
+    walk_gbps = walk_bytes / (walk_ms * 1e-3) / 1e9
+    first_ms = tm["first"][0] / n_t
+    first_bytes = 4.0 * cnt_t["visits_first"] / n_t
     copy_gbps = measured_copy_gbps()   # after the timed region
     packets = args.steps * len(kinds) * N
     traffic = committed_traffic() if N == 1 << 22 else None
+    walk_traffic = committed_traffic("walk_bytes_per_launch") if N == 1 << 22 else None
     result = {
         "metric": "photon packets/s (QMC radiative transfer, disk128 workload)",
         "value": packets / (elapsed_ms * 1e-3),
@@ -688,18 +713,33 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "achieved": achieved,
+            "achieved": walk_gbps,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "kernel": "transport step qrt_run: k_key_emit, the two-pass radix sort (k_digit_hist, "
-                      "k_digit_scan, k_digit_scatter), k_first, then per scattering order k_scatter and k_walk",
+            "frac": walk_gbps / HBM_PEAK_GBS,
+            "traffic": walk_traffic,
+            "kernel": "k_walk, the dominant kernel: the peel-off rays and free flights of every scattering "
+                      "order (its 20 dispatches of one transport launch together)",
+            "alg_bytes_per_launch": walk_bytes,
+            "alg_bytes": "4 B per cell visit of the walk (all visits but those of the first flights) + 24 B "
+                         "per binned peel-off contribution, exact counts from the kernels' counters",
+            "avg_launch_ms": walk_ms,
+            "avg_dispatch_us": 1e3 * tm["walk"][0] / max(1, tm["walk"][1]),
+            "share_of_launch": walk_ms / timed_ms if timed_ms else None,
+            "timing": f"HIP events on the launch stream around every kernel, {args.timing_steps} steps "
+                      f"({n_t} launches) after the timed region",
             "walk_counters": committed_walk_counters(),
             "measured_copy_GBps": copy_gbps,
-            "frac_of_measured_copy": achieved / copy_gbps,
-            "alg_bytes_per_launch": alg_bytes / n_launch,
-            "avg_launch_ms": transport_ms / n_launch,
+            "frac_of_measured_copy": walk_gbps / copy_gbps,
+            "step": {
+                "kernel": "the whole transport step qrt_run: k_key_emit, the two-pass radix sort, k_first, "
+                          "then per scattering order k_scatter and k_walk",
+                "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "alg_bytes_per_launch": alg_bytes / n_launch, "avg_launch_ms": transport_ms / n_launch,
+            },
+            "first_flights": {"kernel": "k_first", "avg_launch_ms": first_ms, "alg_bytes_per_launch": first_bytes,
+                              "achieved": first_bytes / (first_ms * 1e-3) / 1e9 if first_ms else None},
+            "kernel_ms_per_launch": {k: v[0] / n_t for k, v in tm.items()},
         },
         "per_sequence_packets_per_s": {k: N / (v * 1e-3) for k, v in per_kind_ms.items()},
         "counters_per_packet": {k: cnt[k] / cnt["packets"] for k in ("visits", "peels", "scatterings",

@@ -90,6 +90,9 @@ typedef struct {
     int64_t occluded;     /* peel-off rays blocked by a sphere star */
     int64_t surrogate;    /* peel-off optical depths taken from the network */
     int64_t fallbacks;    /* surrogate requests answered by exact traversal */
+    int64_t visits_first; /* the part of visits made by the first flights: the walk to the mesh edge
+                             for tau1 and the forced flight (Sec. 3.2); the rest are the per-order
+                             peel-off rays and free flights */
 } qrt_counters;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
@@ -203,6 +206,25 @@ int qrt_reset_images(qrt_ctx *ctx);
 
 /* Counters accumulated since the last reset.  Synchronises the stream. */
 int qrt_get_counters(qrt_ctx *ctx, qrt_counters *out);
+
+/* Kernel timing (a measurement aid, off by default).  While enabled, qrt_run
+   and qrt_batch_run record a pair of HIP events on the context stream around
+   every kernel launch, by class: QRT_T_SORT (emission keys and the radix sort),
+   QRT_T_FIRST (first flights), QRT_T_SCATTER (scattering, peel-off
+   contributions, new directions), QRT_T_WALK (peel-off rays and free flights of
+   one order), QRT_T_PEEL_MLP (surrogate peel-off), QRT_T_OTHER (queue clears,
+   pilot capture).  qrt_get_timing synchronises the stream and returns, per
+   class, the summed milliseconds between each pair and the number of launches
+   since the last reset (reset = 1 clears them afterwards).  The events cost a
+   few microseconds per launch; qrt_run_static records none. */
+enum { QRT_T_SORT = 0, QRT_T_FIRST = 1, QRT_T_SCATTER = 2, QRT_T_WALK = 3, QRT_T_PEEL_MLP = 4, QRT_T_OTHER = 5,
+       QRT_T_CLASSES = 6 };
+typedef struct {
+    double ms[QRT_T_CLASSES];
+    int64_t launches[QRT_T_CLASSES];
+} qrt_timing;
+int qrt_set_timing(qrt_ctx *ctx, int enable);
+int qrt_get_timing(qrt_ctx *ctx, qrt_timing *out, int reset);
 
 /* Coordinates of points first .. first+count-1, dims each, as unsigned 0.32
    fixed point, row-major [count][dims] (Sec. 3.1).  out is a device pointer

@@ -83,7 +83,7 @@ class Counters(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("packets", "visits", "peels", "peel_rays", "escapes",
                                          "tau_cuts", "scatterings", "occluded")] + \
                [(f, C.c_double) for f in ("e_direct", "e_absorbed", "e_escaped", "e_remaining")] + \
-               [(f, C.c_int64) for f in ("surrogate", "fallbacks")]
+               [(f, C.c_int64) for f in ("surrogate", "fallbacks", "visits_first")]
 
     def as_dict(self) -> Dict[str, float]:
         return {f: getattr(self, f) for f, _ in self._fields_}

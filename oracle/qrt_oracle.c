@@ -77,6 +77,7 @@ typedef struct {
     int64_t packets, visits, peels, peel_rays, escapes, tau_cuts, scatterings, occluded;
     double e_direct, e_absorbed, e_escaped, e_remaining;
     int64_t surrogate, fallbacks;
+    int64_t visits_first;   /* visits of the two first-flight walks (to the edge, then the forced flight) */
 } og_counters;
 
 /* ------------------------------------------------------------------------- */
@@ -631,6 +632,7 @@ static void og_packet(const og_scene *S, const og_seq *q, const og_obs *obs, uin
     int64_t vis = 0;
     double tau1 = og_walk(S, p, k, 0, 0.0, NULL, NULL, &vis);
     C->visits += vis;
+    C->visits_first += vis;
     if (tau1 < S->tau_min) {
         C->tau_cuts++;
         C->e_direct += 1.0;
@@ -645,6 +647,7 @@ static void og_packet(const og_scene *S, const og_seq *q, const og_obs *obs, uin
         vis = 0;
         og_walk(S, p, k, 1, tau, &t, &stopped, &vis);
         C->visits += vis;
+        C->visits_first += vis;
         /* if rounding lets the walk reach the edge first, scatter at the exit point */
         for (int a = 0; a < 3; ++a) p[a] += t * k[a];
     }
@@ -706,6 +709,7 @@ static void og_add_counters(og_counters *a, const og_counters *b)
     a->e_direct += b->e_direct; a->e_absorbed += b->e_absorbed;
     a->e_escaped += b->e_escaped; a->e_remaining += b->e_remaining;
     a->surrogate += b->surrogate; a->fallbacks += b->fallbacks;
+    a->visits_first += b->visits_first;
 }
 
 /* Run packets first .. first+count-1 and ADD their (unnormalised) Stokes sums to

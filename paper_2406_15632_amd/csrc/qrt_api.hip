@@ -102,6 +102,9 @@ struct qrt_ctx {
     uint64_t batch_runs = 0;                 // batch runs since the last reset
     // device address of this device's static transport scratch (allocation-free runs)
     unsigned char *scratch = nullptr;
+    // kernel timing (qrt_set_timing)
+    bool timing = false;
+    KernelTimer timer;
 };
 
 namespace {
@@ -448,6 +451,7 @@ void qrt_destroy(qrt_ctx *c)
     if (c->batch_dev) (void)hipFree(c->batch_dev);
     if (c->batch_grid) (void)hipFree(c->batch_grid);
     if (c->batch_img) (void)hipFree(c->batch_img);
+    c->timer.destroy();
     delete c;
 }
 
@@ -727,7 +731,9 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     // chunks never exceed the queue capacity
     for (uint64_t done = 0; done < count;) {
         const uint64_t n = count - done < c->tb_packets ? count - done : c->tb_packets;
-        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream), "transport launch");
+        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream,
+                                    c->timing ? &c->timer : nullptr),
+                "transport launch");
         done += n;
     }
     c->packets_run += count;
@@ -883,6 +889,33 @@ int qrt_get_counters(qrt_ctx *c, qrt_counters *out)
     out->occluded = (int64_t)h[CNT_OCCLUDED];
     out->surrogate = (int64_t)h[CNT_SURROGATE];
     out->fallbacks = (int64_t)h[CNT_FALLBACKS];
+    out->visits_first = (int64_t)h[CNT_VISITS_FIRST];
+    return QRT_OK;
+}
+
+int qrt_set_timing(qrt_ctx *c, int enable)
+{
+    if (!c) return QRT_INVALID_ARG;
+    c->timing = enable != 0;
+    return QRT_OK;
+}
+
+int qrt_get_timing(qrt_ctx *c, qrt_timing *out, int reset)
+{
+    if (!c || !out) return QRT_INVALID_ARG;
+    static_assert(QRT_T_CLASSES == TC_COUNT, "timing classes of the ABI and the library agree");
+    DeviceGuard dg(c->device);
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "timing sync");
+    HIP_TRY(c, c->timer.collect(), "timing events");
+    for (int k = 0; k < QRT_T_CLASSES; ++k) {
+        out->ms[k] = c->timer.ms[k];
+        out->launches[k] = c->timer.launches[k];
+    }
+    if (reset)
+        for (int k = 0; k < QRT_T_CLASSES; ++k) {
+            c->timer.ms[k] = 0.0;
+            c->timer.launches[k] = 0;
+        }
     return QRT_OK;
 }
 
@@ -1653,7 +1686,8 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     const uint64_t unit = 64 * kPeelGroups, per_unit = 64 * kBatchObs;
     const uint64_t chunk = std::min<uint64_t>(c->tb_packets, (P.group_cap / per_unit) * unit);
     if (chunk == 0) return fail(c, QRT_HIP_ERROR, "peel-ray buffer too small for a batch");
-    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, chunk, c->stream),
+    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, chunk, c->stream,
+                            c->timing ? &c->timer : nullptr),
             "batch launch");
     return QRT_OK;
 }

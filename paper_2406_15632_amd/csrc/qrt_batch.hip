@@ -220,7 +220,8 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             }
         }
     }
-    flush_counters<3>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS}, {n_packets, n_cuts, n_visits});
+    flush_counters<4>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS, CNT_VISITS_FIRST},
+                      {n_packets, n_cuts, n_visits, n_visits});
 }
 
 // ---------------------------------------------------------------- scattering
@@ -510,7 +511,7 @@ static int batch_resident_blocks(F kernel)
 
 template <typename R, int KIND>
 static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count, const TransportBuffers &B,
-                              hipStream_t st)
+                              hipStream_t st, KernelTimer *T)
 {
     // P.scene_base and P.scene_bits are set per chunk by launch_batch
     static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
@@ -523,23 +524,35 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
-    hipError_t e = launch_clear_queues(B.q, st);
+    hipError_t e = launch_clear_queues(B.q, st, T);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys);
-    if ((e = launch_sort_keys(B, count, st)) != hipSuccess) return e;
+    {
+        TimedLaunch tl(T, st, TC_SORT);
+        hipLaunchKernelGGL((k_bkey<R, KIND>), dim3(b_elem), dim3(256), 0, st, P, b0, count, B.keys);
+    }
+    if ((e = launch_sort_keys(B, count, st, T)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
-    hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order,
-                       (const uint32_t *)B.keys, state_list<R>(B, 0), B.q);
+    {
+        TimedLaunch tl(T, st, TC_FIRST);
+        hipLaunchKernelGGL((k_bfirst<R, KIND>), dim3(bf), dim3(256), 0, st, P, b0, count, (const uint32_t *)B.order,
+                           (const uint32_t *)B.keys, state_list<R>(B, 0), B.q);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     for (int order = 1; order <= P.max_orders; ++order) {
         const int in = (order - 1) & 1;
-        hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, state_list<R>(B, in), in,
-                           peels, B.q);
+        {
+            TimedLaunch tl(T, st, TC_SCATTER);
+            hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, state_list<R>(B, in), in,
+                               peels, B.q);
+        }
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;   // the last order walks peel rays only
-        hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order,
-                           (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                           (const PeelRay<R> *)peels, B.q);
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                               (const PeelRay<R> *)peels, B.q);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -547,15 +560,15 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
 
 template <typename R>
 static hipError_t batch_kind(const BatchParams &P, int kind, uint64_t b0, uint32_t count, const TransportBuffers &B,
-                             hipStream_t st)
+                             hipStream_t st, KernelTimer *T)
 {
     switch (kind) {
-    case SEQ_SOBOL: return batch_chunk<R, SEQ_SOBOL>(P, b0, count, B, st);
-    case SEQ_HALTON: return batch_chunk<R, SEQ_HALTON>(P, b0, count, B, st);
-    case SEQ_NIED2: return batch_chunk<R, SEQ_NIED2>(P, b0, count, B, st);
-    case SEQ_HAMMERSLEY: return batch_chunk<R, SEQ_HAMMERSLEY>(P, b0, count, B, st);
-    case SEQ_PHILOX: return batch_chunk<R, SEQ_PHILOX>(P, b0, count, B, st);
-    case SEQ_SOBOL_OWEN: return batch_chunk<R, SEQ_SOBOL_OWEN>(P, b0, count, B, st);
+    case SEQ_SOBOL: return batch_chunk<R, SEQ_SOBOL>(P, b0, count, B, st, T);
+    case SEQ_HALTON: return batch_chunk<R, SEQ_HALTON>(P, b0, count, B, st, T);
+    case SEQ_NIED2: return batch_chunk<R, SEQ_NIED2>(P, b0, count, B, st, T);
+    case SEQ_HAMMERSLEY: return batch_chunk<R, SEQ_HAMMERSLEY>(P, b0, count, B, st, T);
+    case SEQ_PHILOX: return batch_chunk<R, SEQ_PHILOX>(P, b0, count, B, st, T);
+    case SEQ_SOBOL_OWEN: return batch_chunk<R, SEQ_SOBOL_OWEN>(P, b0, count, B, st, T);
     default: return hipErrorInvalidValue;
     }
 }
@@ -573,7 +586,7 @@ static int host_scene_of(const uint64_t *begin, int n_scenes, uint64_t b)
 }
 
 hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precision, int kind, uint64_t total,
-                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream)
+                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream, KernelTimer *timer)
 {
     for (uint64_t done = 0; done < total;) {
         const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
@@ -587,8 +600,8 @@ hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precis
         const int span = host_scene_of(begin, P.n_scenes, done + n - 1) - P.scene_base + 1;
         P.scene_bits = 0;
         while ((1 << P.scene_bits) < span) P.scene_bits++;
-        hipError_t e = precision == 1 ? batch_kind<double>(P, kind, done, n, B, stream)
-                                      : batch_kind<float>(P, kind, done, n, B, stream);
+        hipError_t e = precision == 1 ? batch_kind<double>(P, kind, done, n, B, stream, timer)
+                                      : batch_kind<float>(P, kind, done, n, B, stream, timer);
         if (e != hipSuccess) return e;
         done += n;
     }

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "qrt_seq.h"
 #include "qrt_walk.h"
 
@@ -17,7 +19,7 @@ constexpr int kImageCopies = 16;          // image accumulators (two per XCD: bl
 // counter slots in the device counter array
 enum CounterSlot {
     CNT_PACKETS = 0, CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES, CNT_TAU_CUTS,
-    CNT_SCATTERINGS, CNT_OCCLUDED, CNT_SURROGATE, CNT_FALLBACKS, CNT_COUNT
+    CNT_SCATTERINGS, CNT_OCCLUDED, CNT_SURROGATE, CNT_FALLBACKS, CNT_VISITS_FIRST, CNT_COUNT
 };
 // The device counter array holds kCounterCopies copies of the slots, each on
 // its own 128-byte line: a block adds into copy blockIdx % kCounterCopies
@@ -25,6 +27,91 @@ enum CounterSlot {
 constexpr int kCounterCopies = 8;
 constexpr int kCounterLine = 16;
 static_assert(CNT_COUNT <= kCounterLine, "the counter slots fit one line");
+
+// Optional kernel timing: a pair of HIP events on the launch stream around each
+// kernel launch, by class (the QRT_T_* classes of the C ABI).  Events are reused
+// from a free list; pairs wait in `pending` until collect() sums them.
+struct KernelTimer {
+    struct Pair {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> free_events;
+    std::vector<Pair> pending;
+    double ms[8] = {};
+    int64_t launches[8] = {};
+    hipEvent_t open = nullptr;
+    int open_cls = 0;
+
+    hipEvent_t take()
+    {
+        if (!free_events.empty()) {
+            hipEvent_t e = free_events.back();
+            free_events.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+    }
+    void begin(hipStream_t st, int cls)
+    {
+        open = take();
+        open_cls = cls;
+        if (open) (void)hipEventRecord(open, st);
+    }
+    void end(hipStream_t st)
+    {
+        hipEvent_t b = take();
+        if (open && b) {
+            (void)hipEventRecord(b, st);
+            pending.push_back({open_cls, open, b});
+        } else {
+            if (open) free_events.push_back(open);
+            if (b) free_events.push_back(b);
+        }
+        open = nullptr;
+    }
+    // sums the pairs recorded so far (their stream must have been synchronised)
+    hipError_t collect()
+    {
+        for (const Pair &p : pending) {
+            float t = 0.0f;
+            const hipError_t e = hipEventElapsedTime(&t, p.a, p.b);
+            if (e != hipSuccess) return e;
+            ms[p.cls] += (double)t;
+            launches[p.cls] += 1;
+            free_events.push_back(p.a);
+            free_events.push_back(p.b);
+        }
+        pending.clear();
+        return hipSuccess;
+    }
+    void destroy()
+    {
+        for (const Pair &p : pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+        pending.clear();
+        free_events.clear();
+    }
+};
+enum TimingClass { TC_SORT = 0, TC_FIRST, TC_SCATTER, TC_WALK, TC_PEEL_MLP, TC_OTHER, TC_COUNT };
+
+// times one launch when a timer is given
+struct TimedLaunch {
+    KernelTimer *t;
+    hipStream_t st;
+    TimedLaunch(KernelTimer *timer, hipStream_t stream, int cls) : t(timer), st(stream)
+    {
+        if (t) t->begin(st, cls);
+    }
+    ~TimedLaunch()
+    {
+        if (t) t->end(st);
+    }
+};
 
 struct DevObserver {
     double o[3], ex[3], ey[3];
@@ -208,23 +295,24 @@ struct BatchParams {
 // All `total` batch numbers of a batch, in chunks of at most `chunk`; begin[s]
 // (host) is the first batch number of scene s.
 hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precision, int kind, uint64_t total,
-                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream);
+                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream, KernelTimer *timer = nullptr);
 
 // order[0 .. count) = the packets 0 .. count-1 sorted by keys[j] (kSortBits bits), stably; count <= kChunk.
 // Two radix passes of 8 bits through B.sort_tmp, histograms in B.hist.
-hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st);
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer = nullptr);
 
 // One chunk of packets first .. first+count-1 (count <= kChunk) through every
 // scattering order: first flight, then per order a scatter kernel and a walk
 // kernel.  All launches go to stream.
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first,
-                            uint64_t count, const TransportBuffers &B, hipStream_t stream);
+                            uint64_t count, const TransportBuffers &B, hipStream_t stream,
+                            KernelTimer *timer = nullptr);
 
 // the x-fastest mesh src[nz][ny][nx] into the bricked order of dst (cleared beforehand)
 hipError_t launch_to_bricks(const float *src, float *dst, int nx, int ny, int nz, hipStream_t stream);
 
 // zero the queue counters of a chunk (a kernel, not a memset node)
-hipError_t launch_clear_queues(Queues *q, hipStream_t stream);
+hipError_t launch_clear_queues(Queues *q, hipStream_t stream, KernelTimer *timer = nullptr);
 
 // img[0 .. n) += img[c n .. (c+1) n) for every further copy c, which is cleared
 hipError_t launch_fold_images(double *img, size_t n, hipStream_t stream);

@@ -214,10 +214,11 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
     }
 }
 
-hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st)
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer)
 {
     if (count == 0) return hipSuccess;
     if (count > kChunk) return hipErrorInvalidValue;
+    TimedLaunch tl(timer, st, TC_SORT);
     const int nb = (int)((count + kSortItems - 1) / kSortItems);
     uint32_t *tot = B.hist + (size_t)kSortDigit * (kChunk / kSortItems);
     uint32_t *tmp_keys = B.sort_tmp, *tmp_vals = B.sort_tmp + B.cap;
@@ -371,7 +372,8 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
             }
         }
     }
-    flush_counters<3>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS}, {n_packets, n_cuts, n_visits});
+    flush_counters<4>(P.counters, {CNT_PACKETS, CNT_TAU_CUTS, CNT_VISITS, CNT_VISITS_FIRST},
+                      {n_packets, n_cuts, n_visits, n_visits});
 }
 
 // --------------------------------------------------------------------------
@@ -792,7 +794,7 @@ static int resident_blocks_of(F kernel)
 
 template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
-                            hipStream_t st)
+                            hipStream_t st, KernelTimer *T)
 {
     static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_mlp = 0;
     if (!nb_first) {
@@ -805,31 +807,47 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
     const uint32_t cblocks = (count + 255) / 256;
     const int b_elem = (int)(cblocks < 2048u ? cblocks : 2048u);
-    hipError_t e = launch_clear_queues(B.q, st);
+    hipError_t e = launch_clear_queues(B.q, st, T);
     if (e != hipSuccess) return e;
     // first flights in emission-direction order
-    hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys);
-    if ((e = launch_sort_keys(B, count, st)) != hipSuccess) return e;
+    {
+        TimedLaunch tl(T, st, TC_SORT);
+        hipLaunchKernelGGL((k_key_emit<R, KIND, SRC>), dim3(b_elem), dim3(256), 0, st, P, first, count, B.keys);
+    }
+    if ((e = launch_sort_keys(B, count, st, T)) != hipSuccess) return e;
     const int bf = (int)(cblocks < (uint32_t)nb_first ? cblocks : (uint32_t)nb_first);
-    hipLaunchKernelGGL((k_first<R, KIND, SRC>), dim3(bf), dim3(256), 0, st, P, first, count,
-                       (const uint32_t *)B.order, state_list<R>(B, 0), B.q);
+    {
+        TimedLaunch tl(T, st, TC_FIRST);
+        hipLaunchKernelGGL((k_first<R, KIND, SRC>), dim3(bf), dim3(256), 0, st, P, first, count,
+                           (const uint32_t *)B.order, state_list<R>(B, 0), B.q);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     for (int order = 1; order <= P.max_orders; ++order) {
         const int in = (order - 1) & 1;
-        hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order,
-                           state_list<R>(B, in), in, peels, B.q);
-        if (P.sur.cap)
+        {
+            TimedLaunch tl(T, st, TC_SCATTER);
+            hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order,
+                               state_list<R>(B, in), in, peels, B.q);
+        }
+        if (P.sur.cap) {
+            TimedLaunch tl(T, st, TC_OTHER);
             hipLaunchKernelGGL((k_capture<R>), dim3(bs), dim3(256), 0, st, P, (const PeelRay<R> *)peels,
                                (const Queues *)B.q, in);
-        if (P.peel_mode == 1)
+        }
+        if (P.peel_mode == 1) {
+            TimedLaunch tl(T, st, TC_PEEL_MLP);
             hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, order, peels, (const Queues *)B.q,
                                in);
+        }
         // the last order walks peel rays only (no flights): those want every resident wave
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;
-        hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
-                           (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                           (const PeelRay<R> *)peels, B.q);
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                               (const PeelRay<R> *)peels, B.q);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
@@ -837,36 +855,36 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
 
 template <typename R, int KIND>
 static hipError_t run_src(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
-                          hipStream_t st)
+                          hipStream_t st, KernelTimer *T)
 {
-    if (P.src_kind == 1) return run_chunk<R, KIND, 1>(P, first, count, B, st);
-    if (P.src_kind == 2) return run_chunk<R, KIND, 2>(P, first, count, B, st);
-    return run_chunk<R, KIND, 0>(P, first, count, B, st);
+    if (P.src_kind == 1) return run_chunk<R, KIND, 1>(P, first, count, B, st, T);
+    if (P.src_kind == 2) return run_chunk<R, KIND, 2>(P, first, count, B, st, T);
+    return run_chunk<R, KIND, 0>(P, first, count, B, st, T);
 }
 
 template <typename R>
 static hipError_t run_kind(const TransportParams &P, int kind, uint64_t first, uint32_t count,
-                           const TransportBuffers &B, hipStream_t st)
+                           const TransportBuffers &B, hipStream_t st, KernelTimer *T)
 {
     switch (kind) {
-    case SEQ_SOBOL: return run_src<R, SEQ_SOBOL>(P, first, count, B, st);
-    case SEQ_HALTON: return run_src<R, SEQ_HALTON>(P, first, count, B, st);
-    case SEQ_NIED2: return run_src<R, SEQ_NIED2>(P, first, count, B, st);
-    case SEQ_HAMMERSLEY: return run_src<R, SEQ_HAMMERSLEY>(P, first, count, B, st);
-    case SEQ_PHILOX: return run_src<R, SEQ_PHILOX>(P, first, count, B, st);
-    case SEQ_FAURE: return run_src<R, SEQ_FAURE>(P, first, count, B, st);
-    case SEQ_SOBOL_OWEN: return run_src<R, SEQ_SOBOL_OWEN>(P, first, count, B, st);
+    case SEQ_SOBOL: return run_src<R, SEQ_SOBOL>(P, first, count, B, st, T);
+    case SEQ_HALTON: return run_src<R, SEQ_HALTON>(P, first, count, B, st, T);
+    case SEQ_NIED2: return run_src<R, SEQ_NIED2>(P, first, count, B, st, T);
+    case SEQ_HAMMERSLEY: return run_src<R, SEQ_HAMMERSLEY>(P, first, count, B, st, T);
+    case SEQ_PHILOX: return run_src<R, SEQ_PHILOX>(P, first, count, B, st, T);
+    case SEQ_FAURE: return run_src<R, SEQ_FAURE>(P, first, count, B, st, T);
+    case SEQ_SOBOL_OWEN: return run_src<R, SEQ_SOBOL_OWEN>(P, first, count, B, st, T);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_transport(const TransportParams &P, int precision, int kind, uint64_t first, uint64_t count,
-                            const TransportBuffers &B, hipStream_t stream)
+                            const TransportBuffers &B, hipStream_t stream, KernelTimer *timer)
 {
     for (uint64_t done = 0; done < count;) {
         const uint32_t n = (uint32_t)(count - done < kChunk ? count - done : kChunk);
-        hipError_t e = precision == 1 ? run_kind<double>(P, kind, first + done, n, B, stream)
-                                      : run_kind<float>(P, kind, first + done, n, B, stream);
+        hipError_t e = precision == 1 ? run_kind<double>(P, kind, first + done, n, B, stream, timer)
+                                      : run_kind<float>(P, kind, first + done, n, B, stream, timer);
         if (e != hipSuccess) return e;
         done += n;
     }
@@ -884,8 +902,9 @@ __global__ void __launch_bounds__(256) k_clear_words(uint32_t *__restrict__ p, u
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
 }
 
-hipError_t launch_clear_queues(Queues *q, hipStream_t stream)
+hipError_t launch_clear_queues(Queues *q, hipStream_t stream, KernelTimer *timer)
 {
+    TimedLaunch tl(timer, stream, TC_OTHER);
     hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, stream, (uint32_t *)q, (uint32_t)(sizeof(Queues) / 4));
     return hipGetLastError();
 }

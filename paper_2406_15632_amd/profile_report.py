@@ -156,6 +156,10 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, launches, ou
     w_raw = sum(v["WRITE_SIZE"] for k, v in write.items() if _transport(k))
     fetch_b = f_raw * f_scale / launches
     write_b = w_raw * w_scale / launches
+    # the dominant kernel on its own: the per-order walks (every k_walk dispatch of a launch)
+    walk = lambda k: "qrt::k_walk<" in k   # noqa: E731
+    wf = sum(v["FETCH_SIZE"] for k, v in fetch.items() if walk(k)) * f_scale / launches
+    ww = sum(v["WRITE_SIZE"] for k, v in write.items() if walk(k)) * w_scale / launches
     lines = ["# HBM traffic of the transport step (disk128, 2^22 packets per launch)", "",
              "Commands:", "", "```", commands, "```", "",
              f"source_hash: {transport_source_hash()}",
@@ -169,7 +173,10 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, launches, ou
              f"transport_WRITE_SIZE_total: {w_raw:.6g}",
              f"fetch_bytes_per_launch: {fetch_b:.6g}",
              f"write_bytes_per_launch: {write_b:.6g}",
-             f"bytes_per_step_launch: {fetch_b + write_b:.6g}", ""]
+             f"bytes_per_step_launch: {fetch_b + write_b:.6g}",
+             f"walk_fetch_bytes_per_launch: {wf:.6g}",
+             f"walk_write_bytes_per_launch: {ww:.6g}",
+             f"walk_bytes_per_launch: {wf + ww:.6g}", ""]
     lines += ["Per kernel (FETCH_SIZE, WRITE_SIZE raw totals):", ""]
     for k in sorted(set(fetch) | set(write)):
         if _transport(k):

@@ -32,10 +32,17 @@ SOURCE_POINT, SOURCE_SPHERE = 0, 1
 
 class qrt_counters(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("packets", "visits", "peels", "peel_rays", "escapes", "tau_cuts",
-                                         "scatterings", "occluded", "surrogate", "fallbacks")]
+                                         "scatterings", "occluded", "surrogate", "fallbacks", "visits_first")]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+TIMING_CLASSES = ("sort", "first", "scatter", "walk", "peel_mlp", "other")
+
+
+class qrt_timing(C.Structure):
+    _fields_ = [("ms", C.c_double * len(TIMING_CLASSES)), ("launches", C.c_int64 * len(TIMING_CLASSES))]
 
 
 class qrt_train_cfg(C.Structure):
@@ -91,6 +98,8 @@ SIGNATURES = {
     "qrt_set_order_images": (C.c_int, [_P, C.c_int]),
     "qrt_read_order_images": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_get_counters": (C.c_int, [_P, C.POINTER(qrt_counters)]),
+    "qrt_set_timing": (C.c_int, [_P, C.c_int]),
+    "qrt_get_timing": (C.c_int, [_P, C.POINTER(qrt_timing), C.c_int]),
     "qrt_generate_points": (C.c_int, [_P, C.c_int, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
                                       _P, C.c_int]),
     "qrt_trace_tau": (C.c_int, [_P, C.c_int64, _P, _P, _P, _P]),
@@ -282,6 +291,15 @@ class Context:
         c = qrt_counters()
         self._ck(self.lib.qrt_get_counters(self.h, C.byref(c)))
         return c.as_dict()
+
+    def set_timing(self, enable: bool):
+        self._ck(self.lib.qrt_set_timing(self.h, int(enable)))
+
+    def timing(self, reset: bool = True) -> dict:
+        """{class: (summed ms, launches)} of the kernels timed since the last reset."""
+        t = qrt_timing()
+        self._ck(self.lib.qrt_get_timing(self.h, C.byref(t), int(reset)))
+        return {k: (float(t.ms[i]), int(t.launches[i])) for i, k in enumerate(TIMING_CLASSES)}
 
     def generate_points(self, kind: int, first: int, count: int, dims: int, seed: int = 0,
                         n_total: int = 0) -> np.ndarray:

@@ -60,7 +60,7 @@ def test_binding_structs_match_the_header(tmp_path):
         pytest.skip("no host C compiler")
     structs = {"qrt_counters": qrt.qrt_counters, "qrt_train_cfg": qrt.qrt_train_cfg,
                "qrt_train_report": qrt.qrt_train_report, "qrt_mask_report": qrt.qrt_mask_report,
-               "qrt_batch_scene": qrt.qrt_batch_scene}
+               "qrt_batch_scene": qrt.qrt_batch_scene, "qrt_timing": qrt.qrt_timing}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qrt.h"', "int main(void) {"]
     for name, st in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')

@@ -80,7 +80,7 @@ def assert_counters_equal(cg, co):
     stop may land on the other side of a face.  Each flip changes a count by
     about one; allow a few plus 1e-5 relative."""
     assert cg["packets"] == co["packets"]
-    for k in ("visits", "peels", "peel_rays", "escapes", "tau_cuts", "scatterings", "occluded"):
+    for k in ("visits", "visits_first", "peels", "peel_rays", "escapes", "tau_cuts", "scatterings", "occluded"):
         assert abs(cg[k] - co[k]) <= 4 + 1e-5 * co[k], f"{k}: gpu {cg[k]} oracle {co[k]}"
 
 
