@@ -623,6 +623,113 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     flush_counters<4>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES}, {n_visits, n_peels, n_peels, n_esc});
 }
 
+// Peel-off rays of a walk launch without flights (the last scattering order),
+// when the image set of the order fits in LDS: each block accumulates its rays'
+// contributions into an FP64 image tile in LDS (LDS atomics), then adds the
+// tile into its image copy once, with coalesced atomics.  Every contribution
+// that k_walk would add to the global image is added to the tile instead, so
+// the images differ only in the order of the FP64 sums.  Global atomics per
+// launch fall from three per visible ray to three per pixel and block; for a
+// 64^2 image these scattered atomics were most of the walk's time.  One block
+// per CU (the tile takes most of the LDS) of 16 waves; peel rays walk to the
+// edge only, so the kernel needs no stop test and few registers.
+constexpr int kPeelLdsThreads = 1024;
+
+template <typename R>
+__global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const TransportParams P, int order, int in,
+                                                                  const PeelRay<R> *__restrict__ peels,
+                                                                  Queues *__restrict__ Q)
+{
+    extern __shared__ double tile[];   // [n_obs][3][npix][npix]
+    __shared__ R s_o[kMaxObs][3];
+    const size_t plane = (size_t)P.npix * (size_t)P.npix;
+    const size_t n_tile = (size_t)P.n_obs * 3 * plane;
+    for (size_t i = threadIdx.x; i < n_tile; i += blockDim.x) tile[i] = 0.0;
+    for (int i = threadIdx.x; i < P.n_obs; i += blockDim.x)
+        for (int a = 0; a < 3; ++a) s_o[i][a] = (R)P.obs[i].o[a];
+    __syncthreads();
+    const RayGrid<R> G = ray_grid<R>(P.grid);
+    const uint64_t n_live = Q->n_live[in];
+    const uint64_t total = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t stride = block_stride(total >> kOrderBlockLog2);
+    uint64_t n_visits = 0;
+    uint32_t n_peels = 0;
+    bool busy = false;
+    uint32_t pix = 0, obs = 0;
+    R c3[3] = {(R)0, (R)0, (R)0};
+    Walk<R> W;
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        if (W.done && busy) {
+            n_visits += W.visits;
+            n_peels++;
+            const double att = exp(-W.tau);
+            double *dst = tile + (size_t)obs * 3 * plane + (size_t)pix;
+            atomicAdd(dst, att * (double)c3[0]);
+            atomicAdd(dst + plane, att * (double)c3[1]);
+            atomicAdd(dst + 2 * plane, att * (double)c3[2]);
+            busy = false;
+        }
+        uint64_t item = 0;
+        if (pool.take(!busy, total, &Q->work[1][0][0], item)) {
+            item = scatter_block(item, total, stride);
+            const PeelRay<R> r = peels[item];
+            if (r.pix != kNoPixel) {
+                const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
+                c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                pix = r.pix;
+                obs = r.obs;
+                walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                busy = true;
+            }
+        }
+        if (__ballot(busy) == 0) {
+            if (pool.dry) break;
+            continue;   // every item just taken was an invisible peel ray
+        }
+        for (;;) {
+            // FP64 steps take twice the registers: four steps per load batch keep 16 waves per CU
+            // within 128 registers without spilling
+            walk_batch_edge<R, sizeof(R) == 8 ? 4 : kFlightBatch>(W, G);
+            if (__popcll(__ballot(W.done || !busy)) >= kWaveRefill) break;
+        }
+    }
+    __syncthreads();
+    double *img_copy = image_copy(P, order, plane);
+    for (size_t i = threadIdx.x; i < n_tile; i += blockDim.x) {
+        const double v = tile[i];
+        if (v != 0.0) unsafeAtomicAdd(img_copy + i, v);
+    }
+    flush_counters<3>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS}, {n_visits, n_peels, n_peels});
+}
+
+// Blocks and dynamic LDS bytes of k_walk_peel_lds for an image set of `bytes`,
+// or 0 blocks when the set does not fit one block's LDS on this device.
+template <typename R>
+static int peel_lds_blocks(size_t bytes)
+{
+    static int max_lds = -1, attr_set = 0;
+    if (max_lds < 0) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        max_lds = hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess ? v : 0;
+    }
+    // static LDS of the kernel: observer directions and the counter sums
+    const size_t reserve = 1024;
+    if (bytes + reserve > (size_t)max_lds) return 0;
+    if (!attr_set) {
+        attr_set = hipFuncSetAttribute((const void *)k_walk_peel_lds<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       max_lds - (int)reserve) == hipSuccess ? 1 : -1;
+    }
+    if (attr_set < 0) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_walk_peel_lds<R>, kPeelLdsThreads, bytes) !=
+            hipSuccess || per_cu < 1)
+        return 0;
+    return per_cu * device_cu_count();
+}
+
 // --------------------------------------------------------------------------
 // surrogate peel-off (an addition to the method): inside the validated
 // domain the network gives tau to the observer; the ray is then binned here
@@ -823,6 +930,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
+    const size_t tile_bytes = (size_t)P.n_obs * 3 * (size_t)P.npix * (size_t)P.npix * sizeof(double);
     for (int order = 1; order <= P.max_orders; ++order) {
         const int in = (order - 1) & 1;
         {
@@ -840,13 +948,19 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, order, peels, (const Queues *)B.q,
                                in);
         }
-        // the last order walks peel rays only (no flights): those want every resident wave
+        // the last order walks peel rays only (no flights): those want every resident
+        // wave, and an image set that fits in LDS is summed there first
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;
+        const int lds_blocks = order == P.max_orders ? peel_lds_blocks<R>(tile_bytes) : 0;
         {
             TimedLaunch tl(T, st, TC_WALK);
-            hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
-                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                               (const PeelRay<R> *)peels, B.q);
+            if (lds_blocks > 0)
+                hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
+                                   order, in, (const PeelRay<R> *)peels, B.q);
+            else
+                hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                                   (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                                   (const PeelRay<R> *)peels, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
