@@ -536,6 +536,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
                                               Queues *__restrict__ Q)
 {
     __shared__ R s_o[kMaxObs][3];
+    __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
     for (int i = threadIdx.x; i < P.n_obs; i += blockDim.x)
         for (int a = 0; a < 3; ++a) s_o[i][a] = (R)P.obs[i].o[a];
     __syncthreads();
@@ -549,6 +550,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     // image copy of this block (blocks go round-robin to the XCDs), in the
     // set of this scattering order when orders are kept apart
     double *img_copy = image_copy(P, order, plane);
+    const int key_bits = bits_for((uint64_t)P.n_obs * 3 * plane);
     uint64_t n_visits = 0;
     uint32_t n_peels = 0, n_esc = 0;
     int kind = WI_NONE;
@@ -561,16 +563,23 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
         // packets whose flight stopped inside the mesh go to the next live list, in place pos
         const bool append = W.done && kind == WI_MOVE && W.stopped;
         const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
-        if (W.done && kind == WI_PEEL) {
-            n_visits += W.visits;
-            n_peels++;
-            const double att = exp(-W.tau);
-            double *dst = img_copy + (size_t)obs * 3 * plane + (size_t)pix;
-            unsafeAtomicAdd(dst, att * (double)c3[0]);
-            unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
-            unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
-            kind = WI_NONE;
-        } else if (W.done && kind == WI_MOVE) {
+        const bool peel_done = W.done && kind == WI_PEEL;
+        if (__ballot(peel_done) != 0) {
+            double v[3] = {0.0, 0.0, 0.0};
+            if (peel_done) {
+                n_visits += W.visits;
+                n_peels++;
+                const double att = exp(-W.tau);
+                v[0] = att * (double)c3[0];
+                v[1] = att * (double)c3[1];
+                v[2] = att * (double)c3[2];
+                kind = WI_NONE;
+            }
+            // the key is the offset of the pixel's I value in the image set [obs][3][plane]
+            const uint32_t key = peel_done ? obs * 3u * (uint32_t)plane + pix : 0u;
+            wave_merge_add(peel_done, key, v[0], v[1], v[2], img_copy, plane, key_bits, s_merge[threadIdx.x >> 6]);
+        }
+        if (W.done && kind == WI_MOVE) {
             n_visits += W.visits;
             if (append) {
                 PacketState<R> s = pks[slot];
@@ -766,14 +775,6 @@ struct __align__(16) PeelMlpLds {
     float qx[kMlpWaves][kMlpIn][kMlpQueue];
     uint32_t qslot[kMlpWaves][kMlpQueue];
 };
-
-// orders the wave's LDS accesses before and after this point
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename R>
 __device__ __forceinline__ void peel_mlp_batch(const TransportParams &P, PeelMlpLds &L, int w, int lane, int count,

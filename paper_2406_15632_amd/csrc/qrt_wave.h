@@ -176,6 +176,70 @@ __host__ __device__ inline uint64_t scatter_block(uint64_t item, uint64_t total,
     return (((b * stride) % nfull) << kOrderBlockLog2) | (item & (kOrderBlock - 1));
 }
 
+// orders the wave's LDS accesses before and after this point
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Image contributions of a wave, merged by pixel before the FP64 atomics.
+// Every lane with `on` adds (v0, v1, v2) to base[key], base[key + plane],
+// base[key + 2 plane].  Lanes of the wave that hold the same key are found
+// with one ballot per key bit; the lowest of them gathers the others' values
+// in the wave's LDS scratch (LDS atomics) and issues the three global atomics
+// alone.  Neighbouring packets' peel rays toward one observer often land in
+// one pixel, and same-address atomics serialize.  Called by every lane of the
+// wave; key < 2^key_bits.
+__device__ __forceinline__ void wave_merge_add(bool on, uint32_t key, double v0, double v1, double v2, double *base,
+                                               size_t plane, int key_bits, double (*scratch)[3])
+{
+    uint64_t peers = __ballot(on);
+    for (int b = 0; b < key_bits; ++b) {
+        const bool one = (key >> b) & 1u;
+        const uint64_t m = __ballot(on && one);
+        peers &= one ? m : ~m;
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const bool lead = on && (peers & lanes_below_mask()) == 0;
+    if (__ballot(on && !lead) != 0) {
+        const int leader = on ? (int)__builtin_ctzll(peers) : lane;
+        if (lead) {
+            scratch[lane][0] = v0;
+            scratch[lane][1] = v1;
+            scratch[lane][2] = v2;
+        }
+        wave_lds_sync();
+        if (on && !lead) {
+            atomicAdd(&scratch[leader][0], v0);
+            atomicAdd(&scratch[leader][1], v1);
+            atomicAdd(&scratch[leader][2], v2);
+        }
+        wave_lds_sync();
+        if (lead) {
+            v0 = scratch[lane][0];
+            v1 = scratch[lane][1];
+            v2 = scratch[lane][2];
+        }
+        wave_lds_sync();
+    }
+    if (lead) {
+        double *dst = base + key;
+        unsafeAtomicAdd(dst, v0);
+        unsafeAtomicAdd(dst + plane, v1);
+        unsafeAtomicAdd(dst + 2 * plane, v2);
+    }
+}
+
+// bits that hold the values 0 .. n-1 (n >= 1)
+__host__ __device__ __forceinline__ int bits_for(uint64_t n)
+{
+    int b = 0;
+    while (b < 63 && (1ull << b) < n) ++b;
+    return b;
+}
+
 // Octahedral map of a direction to 2 x 8 bits, interleaved (nearby directions
 // get nearby keys).
 __device__ __forceinline__ uint32_t interleave2(uint32_t qu, uint32_t qv, int bits)
