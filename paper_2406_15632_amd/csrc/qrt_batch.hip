@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "qrt_internal.h"
+#include "qrt_packet.h"
 #include "qrt_physics.h"
 #include "qrt_wave.h"
 
@@ -59,67 +60,26 @@ __device__ __forceinline__ SeqParams scene_seq(const BatchParams &P, const BScen
     return q;
 }
 
-// first coordinate of the scattering flights and of the forced optical depth
-__device__ __forceinline__ int first_scatter_dim(const BScene &S) { return S.src_kind >= 1 ? 5 : 3; }
-__device__ __forceinline__ int forced_tau_dim(const BScene &S) { return S.src_kind == 1 ? 4 : 2; }
-
-// Emission of a packet of scene S (point source, or a sphere star in the
-// direct or the inverse order of the coordinates), as in the single-scene path.
-// Each branch computes into local arrays and p, k are assigned once at the
-// end: assignments to p and k on several paths would keep them in private
-// memory.
+// Emission of a packet of scene S: the single-scene emission with the scene's source.
 template <typename R, int KIND>
-__device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, uint64_t idx, R p_out[3],
-                                           R k_out[3])
+__device__ __forceinline__ void batch_emit(const BScene &S, const SeqParams &q, uint64_t idx, R p[3], R k[3])
 {
-    uint32_t xa[3], xb[3];
-    R p[3], k[3];
-    seq_triple<KIND>(q, idx, 0, xa);
-    if (S.src_kind == 0) {
-        R sp, cp;
-        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
-        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
-        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-        for (int a = 0; a < 3; ++a) p[a] = (R)S.src[a];
-        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-    } else {
-        seq_triple<KIND>(q, idx, 2, xb);
-        if (S.src_kind == 1) {
-            // direct order: point on the star (v1, v2), local direction (v3, v4)
-            R spe, cpe, spl, cpl;
-            sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
-            const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
-            const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
-            sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
-            const R ctl = sqrt(to_unit<R>(xb[1]));
-            const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
-            const R ne[3] = {ste * cpe, ste * spe, cte};
-            const R t1[3] = {cte * cpe, cte * spe, -ste};
-            const R t2[3] = {-spe, cpe, (R)0};
-            for (int a = 0; a < 3; ++a) {
-                p[a] = (R)S.src[a] + (R)S.r_star * ne[a];
-                k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
-            }
-        } else {
-            // inverse order: direction (v1, v2), emission point about it (v4, v5)
-            R sp, cp, spr, cpr;
-            sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
-            const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
-            const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-            k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-            sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
-            const R ca = sqrt(to_unit<R>(xb[2]));
-            const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
-            const R t1[3] = {ct * cp, ct * sp, -st};
-            const R t2[3] = {-sp, cp, (R)0};
-            for (int a = 0; a < 3; ++a)
-                p[a] = (R)S.src[a] + (R)S.r_star * (ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]));
-        }
-    }
-    for (int a = 0; a < 3; ++a) {
-        p_out[a] = p[a];
-        k_out[a] = k[a];
-    }
+    emit_packet<R, KIND>(S.src_kind, S.src, S.r_star, q, idx, p, k);
+}
+
+template <typename R>
+__device__ __forceinline__ SceneView<R> scene_view(const BScene &S)
+{
+    SceneView<R> V;
+    V.g = (R)S.g;
+    V.p_lin = (R)S.p_lin;
+    V.albedo = (R)S.albedo;
+    V.half_width = (R)S.half_width;
+    V.npix = S.npix;
+    V.src_kind = S.src_kind;
+    for (int a = 0; a < 3; ++a) V.src[a] = (R)S.src[a];
+    V.r_star2 = (R)(S.r_star * S.r_star);
+    return V;
 }
 
 // ---------------------------------------------------------------- emission sort
@@ -172,7 +132,7 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             } else {
                 const double W1 = -expm1(-tau1);
                 const uint64_t idx = S.first + (b0 + j - S.begin);
-                const double u = (double)seq_point<KIND>(scene_seq(P, S), idx, forced_tau_dim(S)) * 0x1p-32;
+                const double u = (double)seq_point<KIND>(scene_seq(P, S), idx, forced_tau_dim(S.src_kind)) * 0x1p-32;
                 S0 = (R)W1;
                 walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
                 phase = BF_FORCED;
@@ -181,16 +141,8 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
             n_visits += W.visits;
             const BScene &S = P.scenes[s];
             PacketState<R> st;
-            for (int a = 0; a < 3; ++a) {
-                st.p[a] = p[a] + W.t_out * k[a];
-                st.k[a] = k[a];
-            }
-            basis_of(k, st.m);
-            st.S[0] = S0; st.S[1] = (R)0; st.S[2] = (R)0;
-            st.target = 0.0;
-            st.idx = S.first + (b0 + j - S.begin);
-            st.next_dim = (uint32_t)s;   // the batch keeps the scene here
-            st.order = 1;
+            // the batch keeps the scene in the tag
+            first_state<R>(p, k, W.t_out, S0, S.first + (b0 + j - S.begin), (uint32_t)s, st);
             out[pos] = st;
             phase = BF_IDLE;
         }
@@ -260,19 +212,18 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
             n_scat++;
         }
         const BScene &S = P.scenes[s];
+        const SceneView<R> V = scene_view<R>(S);
         if (valid) {
-            const R albedo = (R)S.albedo;
-            st.S[0] *= albedo; st.S[1] *= albedo; st.S[2] *= albedo;
+            st.S[0] *= V.albedo; st.S[1] *= V.albedo; st.S[2] *= V.albedo;
         }
         R n_ax[3];
         cross3(st.k, st.m, n_ax);
-        const R Rw = (R)S.half_width;
         bool visv[kBatchObs];
         R cv[kBatchObs][3];
         uint32_t pixv[kBatchObs];
 #pragma unroll
         for (int ob = 0; ob < kBatchObs; ++ob) {
-            bool vis = false;
+            bool vis = false, occ = false;
             R c3[3] = {(R)0, (R)0, (R)0};
             uint32_t pix = 0;
             if (valid && ob < S.n_obs) {
@@ -280,43 +231,8 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
                 const R o[3] = {(R)O.o[0], (R)O.o[1], (R)O.o[2]};
                 const R ex[3] = {(R)O.ex[0], (R)O.ex[1], (R)O.ex[2]};
                 const R ey[3] = {(R)O.ey[0], (R)O.ey[1], (R)O.ey[2]};
-                const R X = dot3(st.p, ex), Y = dot3(st.p, ey);
-                const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)S.npix);
-                const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)S.npix);
-                vis = fx >= (R)0 && fy >= (R)0 && fx < (R)S.npix && fy < (R)S.npix;
-                if (vis && S.src_kind >= 1) {
-                    R d[3] = {st.p[0] - (R)S.src[0], st.p[1] - (R)S.src[1], st.p[2] - (R)S.src[2]};
-                    const R b = dot3(d, o), cc = dot3(d, d) - (R)(S.r_star * S.r_star);
-                    if (b < (R)0 && b * b > cc) {   // the star blocks the ray
-                        n_occ++;
-                        vis = false;
-                    }
-                }
-                if (vis) {
-                    R c = dot3(st.k, o);
-                    c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
-                    const R sn = sqrt(fmax((R)0, (R)1 - c * c));
-                    R Sv[3] = {st.S[0], st.S[1], st.S[2]};
-                    R mi[3];
-                    if (sn < (R)1e-12) {
-                        mi[0] = st.m[0]; mi[1] = st.m[1]; mi[2] = st.m[2];
-                    } else {
-                        const R inv_s = (R)1 / sn;
-                        for (int a = 0; a < 3; ++a) mi[a] = (o[a] - c * st.k[a]) * inv_s;
-                        rotate_stokes(Sv, dot3(st.m, mi), dot3(n_ax, mi));
-                    }
-                    R p11, r12, r33;
-                    mueller((R)S.g, (R)S.p_lin, c, p11, r12, r33);
-                    const R w = p11 * (R)(0.25 / 3.14159265358979323846);
-                    c3[0] = w * (Sv[0] + r12 * Sv[1]);
-                    c3[1] = w * (r12 * Sv[0] + Sv[1]);
-                    c3[2] = w * (r33 * Sv[2]);
-                    R mo[3], no[3];
-                    for (int a = 0; a < 3; ++a) mo[a] = c * mi[a] - sn * st.k[a];
-                    cross3(o, mo, no);
-                    rotate_stokes(c3, dot3(mo, ex), dot3(no, ex));
-                    pix = (uint32_t)((int)fy * S.npix + (int)fx);
-                }
+                peel_contribution<R>(V, st, n_ax, o, ex, ey, vis, occ, c3, pix);
+                n_occ += occ ? 1u : 0u;
             }
             visv[ob] = valid && vis;
             cv[ob][0] = c3[0]; cv[ob][1] = c3[1]; cv[ob][2] = c3[2];
@@ -352,27 +268,9 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         }
         if (valid) {
             if (order < S.max_orders) {
-                const int dim = first_scatter_dim(S) + 3 * (order - 1);
                 uint32_t x[3];
-                seq_triple<KIND>(scene_seq(P, S), st.idx, dim, x);
-                R si, ci;
-                sincos_2pi<R>(to_unit<R>(x[0]), si, ci);
-                const R ct = hg_cos<R>((R)S.g, to_unit<R>(x[1]));
-                const R sth = sqrt(fmax((R)0, (R)1 - ct * ct));
-                R mi[3];
-                for (int a = 0; a < 3; ++a) mi[a] = ci * st.m[a] + si * n_ax[a];
-                rotate_stokes(st.S, ci, si);
-                R p11, r12, r33;
-                mueller((R)S.g, (R)S.p_lin, ct, p11, r12, r33);
-                const R I1 = st.S[0] + r12 * st.S[1], Q1 = r12 * st.S[0] + st.S[1], U1 = r33 * st.S[2];
-                st.S[0] = I1; st.S[1] = Q1; st.S[2] = U1;
-                for (int a = 0; a < 3; ++a) {
-                    const R kn = ct * st.k[a] + sth * mi[a];
-                    const R mn = ct * mi[a] - sth * st.k[a];
-                    st.k[a] = kn;
-                    st.m[a] = mn;
-                }
-                st.target = -log((double)x[2] * 0x1p-32);
+                seq_triple<KIND>(scene_seq(P, S), st.idx, first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
+                scatter_packet<R>(V, st, n_ax, x);
             } else {
                 st.target = -1.0;   // the scene's last scattering: no further flight
             }
@@ -404,6 +302,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
     const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
+    __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
     uint64_t n_visits = 0;
     uint32_t n_peels = 0, n_esc = 0;
     int kind = BW_NONE;
@@ -418,19 +317,30 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
         // packets whose flight stopped inside their mesh go to the next live list, in place pos
         const bool append = W.done && kind == BW_MOVE && W.stopped;
         const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
-        if (W.done && kind == BW_PEEL) {
-            n_visits += W.visits;
-            n_peels++;
-            const BScene &S = P.scenes[s];
-            const size_t plane = (size_t)S.npix * (size_t)S.npix;
-            const double att = exp(-W.tau);
-            // image copy of this block: blocks go round-robin to the XCDs
-            double *dst = S.img + (size_t)(blockIdx.x % kImageCopies) * S.img_set + (size_t)obs * 3 * plane + (size_t)pix;
-            unsafeAtomicAdd(dst, att * (double)c3[0]);
-            unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
-            unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
-            kind = BW_NONE;
-        } else if (W.done && kind == BW_MOVE) {
+        const bool peel_done = W.done && kind == BW_PEEL;
+        if (__ballot(peel_done) != 0) {
+            double v[3] = {0.0, 0.0, 0.0};
+            uint64_t key = 0;
+            size_t plane = 1;
+            if (peel_done) {
+                n_visits += W.visits;
+                n_peels++;
+                const BScene &S = P.scenes[s];
+                plane = (size_t)S.npix * (size_t)S.npix;
+                const double att = exp(-W.tau);
+                v[0] = att * (double)c3[0];
+                v[1] = att * (double)c3[1];
+                v[2] = att * (double)c3[2];
+                // image copy of this block (blocks go round-robin to the XCDs); the key is
+                // the offset of the pixel's I value from the base of all images
+                key = (uint64_t)(S.img - P.img_base) + (uint64_t)(blockIdx.x % kImageCopies) * S.img_set +
+                      (uint64_t)obs * 3 * plane + pix;
+                kind = BW_NONE;
+            }
+            wave_merge_add(peel_done, key, v[0], v[1], v[2], P.img_base, plane, P.img_key_bits,
+                           s_merge[threadIdx.x >> 6]);
+        }
+        if (W.done && kind == BW_MOVE) {
             n_visits += W.visits;
             if (append) {
                 PacketState<R> st = pks[slot];

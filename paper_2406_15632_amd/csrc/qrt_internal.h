@@ -12,6 +12,14 @@
 namespace qrt {
 
 constexpr int kMaxDims = 128;
+
+// bits that hold the values 0 .. n-1 (n >= 1)
+__host__ __device__ __forceinline__ int bits_for(uint64_t n)
+{
+    int b = 0;
+    while (b < 63 && (1ull << b) < n) ++b;
+    return b;
+}
 constexpr int kMaxObs = 16;
 constexpr uint64_t kChunk = 1ull << 22;   // packets per transport chunk (queue capacity)
 constexpr int kImageCopies = 16;          // image accumulators (two per XCD: blocks go to the XCDs in turn), folded on read
@@ -290,6 +298,8 @@ struct BatchParams {
     uint32_t group_cap;         // peel rays per append group: group g owns [g group_cap, (g+1) group_cap),
                                 // kPeelGroups group_cap rays at most the peel buffer's capacity
     unsigned long long *counters;  // [kCounterCopies][kCounterLine]
+    double *img_base;           // all scenes' images, one after the other (scene images point into it)
+    int img_key_bits;           // bits that hold an element offset from img_base
 };
 
 // All `total` batch numbers of a batch, in chunks of at most `chunk`; begin[s]

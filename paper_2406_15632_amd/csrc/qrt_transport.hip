@@ -53,6 +53,7 @@
 
 #include "qrt_internal.h"
 #include "qrt_mlp.h"
+#include "qrt_packet.h"
 #include "qrt_physics.h"
 #include "qrt_wave.h"
 
@@ -244,58 +245,7 @@ hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream
 template <typename R, int KIND, int SRC>
 __device__ __forceinline__ void emit(const TransportParams &P, uint64_t idx, R p[3], R k[3])
 {
-    if constexpr (SRC == 2) {
-        // inverse order: v1,v2 -> propagation direction as for a point source,
-        // v3 -> tau, v4,v5 -> emission point relative to the direction:
-        // azimuth 2 pi v4 about k, cos(alpha) = sqrt(v5) (uniform-brightness
-        // surface seen from direction k: density ~ max(0, n.k))
-        uint32_t xa[3], xb[3];
-        seq_triple<KIND>(P.seq, idx, 0, xa);
-        seq_triple<KIND>(P.seq, idx, 2, xb);
-        R sp, cp, spr, cpr;
-        sincos_2pi<R>(to_unit<R>(xa[0]), sp, cp);
-        const R ct = (R)2 * to_unit<R>(xa[1]) - (R)1;
-        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-        sincos_2pi<R>(to_unit<R>(xb[1]), spr, cpr);
-        const R ca = sqrt(to_unit<R>(xb[2]));
-        const R sa = sqrt(fmax((R)0, (R)1 - ca * ca));
-        const R t1[3] = {ct * cp, ct * sp, -st};
-        const R t2[3] = {-sp, cp, (R)0};
-        for (int a = 0; a < 3; ++a) {
-            const R n = ca * k[a] + sa * (cpr * t1[a] + spr * t2[a]);
-            p[a] = (R)P.src[a] + (R)P.r_star * n;
-        }
-    } else if constexpr (SRC == 1) {
-        // direct order: v1,v2 -> point on the star; v3,v4 -> local direction
-        // (cos theta_l = sqrt(v4): uniform-brightness surface); v5 -> tau
-        uint32_t xa[3], xb[3];
-        seq_triple<KIND>(P.seq, idx, 0, xa);
-        seq_triple<KIND>(P.seq, idx, 2, xb);
-        R spe, cpe, spl, cpl;
-        sincos_2pi<R>(to_unit<R>(xa[0]), spe, cpe);
-        const R cte = (R)2 * to_unit<R>(xa[1]) - (R)1;
-        const R ste = sqrt(fmax((R)0, (R)1 - cte * cte));
-        sincos_2pi<R>(to_unit<R>(xb[0]), spl, cpl);
-        const R ctl = sqrt(to_unit<R>(xb[1]));
-        const R stl = sqrt(fmax((R)0, (R)1 - ctl * ctl));
-        const R ne[3] = {ste * cpe, ste * spe, cte};
-        const R t1[3] = {cte * cpe, cte * spe, -ste};
-        const R t2[3] = {-spe, cpe, (R)0};
-        for (int a = 0; a < 3; ++a) {
-            p[a] = (R)P.src[a] + (R)P.r_star * ne[a];
-            k[a] = ctl * ne[a] + stl * (cpl * t1[a] + spl * t2[a]);
-        }
-    } else {
-        uint32_t x[3];
-        seq_triple<KIND>(P.seq, idx, 0, x);
-        R sp, cp;
-        sincos_2pi<R>(to_unit<R>(x[0]), sp, cp);
-        const R ct = (R)2 * to_unit<R>(x[1]) - (R)1;
-        const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-        p[0] = (R)P.src[0]; p[1] = (R)P.src[1]; p[2] = (R)P.src[2];
-        k[0] = st * cp; k[1] = st * sp; k[2] = ct;
-    }
+    emit_packet<R, KIND>(SRC, P.src, P.r_star, P.seq, idx, p, k);
 }
 
 enum FirstPhase : int { FF_IDLE = 0, FF_EDGE = 1, FF_FORCED = 2 };
@@ -328,7 +278,7 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
             } else {
                 const double W1 = -expm1(-tau1);
                 // optical-depth targets use all 32 bits of the coordinate in FP64, in both precisions
-                const double u = (double)seq_point<KIND>(P.seq, first + j, SRC == 1 ? 4 : 2) * 0x1p-32;
+                const double u = (double)seq_point<KIND>(P.seq, first + j, forced_tau_dim(SRC)) * 0x1p-32;
                 S0 = (R)W1;
                 walk_begin(W, G, p, k, WALK_MOVE, -log1p(-u * W1));
                 phase = FF_FORCED;
@@ -337,16 +287,7 @@ __global__ void __launch_bounds__(256) k_first(const TransportParams P, uint64_t
             n_visits += W.visits;
             // if rounding lets the walk reach the edge first, scatter at the exit point
             PacketState<R> s;
-            for (int a = 0; a < 3; ++a) {
-                s.p[a] = p[a] + W.t_out * k[a];
-                s.k[a] = k[a];
-            }
-            basis_of(k, s.m);
-            s.S[0] = S0; s.S[1] = (R)0; s.S[2] = (R)0;
-            s.target = 0.0;
-            s.idx = first + j;
-            s.next_dim = 0;
-            s.order = 1;
+            first_state<R>(p, k, W.t_out, S0, first + j, 0u, s);
             out[pos] = s;
             phase = FF_IDLE;
         }
@@ -396,6 +337,21 @@ __device__ __forceinline__ void load_obs(const TransportParams &P, ObsTable<R> &
     __syncthreads();
 }
 
+template <typename R>
+__device__ __forceinline__ SceneView<R> scene_view(const TransportParams &P, int src_kind)
+{
+    SceneView<R> V;
+    V.g = (R)P.g;
+    V.p_lin = (R)P.p_lin;
+    V.albedo = (R)P.albedo;
+    V.half_width = (R)P.half_width;
+    V.npix = P.npix;
+    V.src_kind = src_kind;
+    for (int a = 0; a < 3; ++a) V.src[a] = (R)P.src[a];
+    V.r_star2 = (R)(P.r_star * P.r_star);
+    return V;
+}
+
 template <typename R, int KIND, int SRC>
 __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
                                                  int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
@@ -411,7 +367,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
     const uint32_t stride = gridDim.x * blockDim.x;
-    const R Rw = (R)P.half_width;
+    const SceneView<R> V = scene_view<R>(P, SRC);
     uint32_t n_scat = 0, n_occ = 0;
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
@@ -420,58 +376,20 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         if (valid) {
             s = pks[i];
             n_scat++;
-            const R albedo = (R)P.albedo;
-            s.S[0] *= albedo; s.S[1] *= albedo; s.S[2] *= albedo;
+            s.S[0] *= V.albedo; s.S[1] *= V.albedo; s.S[2] *= V.albedo;
         }
         R n_ax[3];
         cross3(s.k, s.m, n_ax);
         for (int ob = 0; ob < P.n_obs; ++ob) {
-            bool vis = false;
+            bool vis = false, occ = false;
             R c3[3] = {(R)0, (R)0, (R)0};
             uint32_t pix = 0;
             if (valid) {
                 const R o[3] = {T.o[ob][0], T.o[ob][1], T.o[ob][2]};
                 const R ex[3] = {T.ex[ob][0], T.ex[ob][1], T.ex[ob][2]};
                 const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
-                const R X = dot3(s.p, ex), Y = dot3(s.p, ey);
-                const R fx = floor((X + Rw) / ((R)2 * Rw) * (R)P.npix);
-                const R fy = floor((Y + Rw) / ((R)2 * Rw) * (R)P.npix);
-                vis = fx >= (R)0 && fy >= (R)0 && fx < (R)P.npix && fy < (R)P.npix;
-                if constexpr (SRC >= 1) {
-                    if (vis) {
-                        R d[3] = {s.p[0] - (R)P.src[0], s.p[1] - (R)P.src[1], s.p[2] - (R)P.src[2]};
-                        const R b = dot3(d, o), cc = dot3(d, d) - (R)(P.r_star * P.r_star);
-                        if (b < (R)0 && b * b > cc) {   // the star blocks the ray
-                            n_occ++;
-                            vis = false;
-                        }
-                    }
-                }
-                if (vis) {
-                    R c = dot3(s.k, o);
-                    c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
-                    const R sn = sqrt(fmax((R)0, (R)1 - c * c));
-                    R St[3] = {s.S[0], s.S[1], s.S[2]};
-                    R mi[3];
-                    if (sn < (R)1e-12) {
-                        mi[0] = s.m[0]; mi[1] = s.m[1]; mi[2] = s.m[2];
-                    } else {
-                        const R inv_s = (R)1 / sn;
-                        for (int a = 0; a < 3; ++a) mi[a] = (o[a] - c * s.k[a]) * inv_s;
-                        rotate_stokes(St, dot3(s.m, mi), dot3(n_ax, mi));
-                    }
-                    R p11, r12, r33;
-                    mueller((R)P.g, (R)P.p_lin, c, p11, r12, r33);
-                    const R w = p11 * (R)(0.25 / 3.14159265358979323846);
-                    c3[0] = w * (St[0] + r12 * St[1]);
-                    c3[1] = w * (r12 * St[0] + St[1]);
-                    c3[2] = w * (r33 * St[2]);
-                    R mo[3], no[3];
-                    for (int a = 0; a < 3; ++a) mo[a] = c * mi[a] - sn * s.k[a];
-                    cross3(o, mo, no);
-                    rotate_stokes(c3, dot3(mo, ex), dot3(no, ex));
-                    pix = (uint32_t)((int)fy * P.npix + (int)fx);
-                }
+                peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
+                n_occ += occ ? 1u : 0u;
             }
             {
                 // slot layout: blocks of 64 rays, one observer per block, observers
@@ -488,29 +406,9 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
             }
         }
         if (valid && order < P.max_orders) {
-            // new direction: i1 from the first number of the triple, cos(Theta) from the second
-            const int dim = (SRC >= 1 ? 5 : 3) + 3 * (order - 1);
             uint32_t x[3];
-            seq_triple<KIND>(P.seq, s.idx, dim, x);
-            R si, ci;
-            sincos_2pi<R>(to_unit<R>(x[0]), si, ci);
-            const R ct = hg_cos<R>((R)P.g, to_unit<R>(x[1]));
-            const R st = sqrt(fmax((R)0, (R)1 - ct * ct));
-            R mi[3];
-            for (int a = 0; a < 3; ++a) mi[a] = ci * s.m[a] + si * n_ax[a];
-            rotate_stokes(s.S, ci, si);
-            R p11, r12, r33;
-            mueller((R)P.g, (R)P.p_lin, ct, p11, r12, r33);
-            const R I1 = s.S[0] + r12 * s.S[1], Q1 = r12 * s.S[0] + s.S[1], U1 = r33 * s.S[2];
-            s.S[0] = I1; s.S[1] = Q1; s.S[2] = U1;
-            for (int a = 0; a < 3; ++a) {
-                const R kn = ct * s.k[a] + st * mi[a];
-                const R mn = ct * mi[a] - st * s.k[a];
-                s.k[a] = kn;
-                s.m[a] = mn;
-            }
-            // free flight tau2 = -ln w, all 32 bits of w in FP64
-            s.target = -log((double)x[2] * 0x1p-32);
+            seq_triple<KIND>(P.seq, s.idx, first_scatter_dim(SRC) + 3 * (order - 1), x);
+            scatter_packet<R>(V, s, n_ax, x);
             pks[i] = s;
         }
     }

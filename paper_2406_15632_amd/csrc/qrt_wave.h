@@ -191,13 +191,13 @@ __device__ __forceinline__ void wave_lds_sync()
 // in the wave's LDS scratch (LDS atomics) and issues the three global atomics
 // alone.  Neighbouring packets' peel rays toward one observer often land in
 // one pixel, and same-address atomics serialize.  Called by every lane of the
-// wave; key < 2^key_bits.
-__device__ __forceinline__ void wave_merge_add(bool on, uint32_t key, double v0, double v1, double v2, double *base,
+// wave; key < 2^key_bits.  Equal keys must mean equal addresses (and planes).
+__device__ __forceinline__ void wave_merge_add(bool on, uint64_t key, double v0, double v1, double v2, double *base,
                                                size_t plane, int key_bits, double (*scratch)[3])
 {
     uint64_t peers = __ballot(on);
     for (int b = 0; b < key_bits; ++b) {
-        const bool one = (key >> b) & 1u;
+        const bool one = (key >> b) & 1ull;
         const uint64_t m = __ballot(on && one);
         peers &= one ? m : ~m;
     }
@@ -230,14 +230,6 @@ __device__ __forceinline__ void wave_merge_add(bool on, uint32_t key, double v0,
         unsafeAtomicAdd(dst + plane, v1);
         unsafeAtomicAdd(dst + 2 * plane, v2);
     }
-}
-
-// bits that hold the values 0 .. n-1 (n >= 1)
-__host__ __device__ __forceinline__ int bits_for(uint64_t n)
-{
-    int b = 0;
-    while (b < 63 && (1ull << b) < n) ++b;
-    return b;
 }
 
 // Octahedral map of a direction to 2 x 8 bits, interleaved (nearby directions
