@@ -169,7 +169,8 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
    of 2^16 packets; it calls no hipMalloc, hipFree or other allocating routine.
    The grid, images, counters and tables are the context's, allocated by the
    set-up calls.  Limits: QRT_UNSUPPORTED when a chunk's buffers exceed the
-   scratch (more than 4 observers in FP64, more than 11 in FP32);
+   scratch (more than 4 observers in FP64, more than 11 in FP32; with the
+   surrogate peel-off, whose queue takes scratch too, more than 2 and 4);
    QRT_BAD_STATE for Faure points whose tables no earlier qrt_run or
    qrt_generate_points built for this many coordinates.  All contexts on one
    device share its scratch: calls that overlap on one device (other streams,

@@ -232,6 +232,8 @@ int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, ui
     return QRT_OK;
 }
 
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
 // Queues for chunks of up to `count` packets (at most kChunk) at the given
 // precision and peel slots per packet; grown on demand, never shrunk.
 int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
@@ -243,7 +245,11 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
     const uint64_t cap = std::max<uint64_t>(want, c->tb_packets);
     const size_t pb = packet_state_bytes(precision) * cap * 2;   // two state lists
     const size_t rb = peel_ray_bytes(precision) * (want + 64) * (size_t)n_obs;
-    if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb_packets >= want) return QRT_OK;
+    const uint64_t qcap = std::max<uint64_t>(want, c->tb_packets);
+    const size_t qn = sur_queue_entries(qcap, n_obs);
+    const size_t qb = align256(qn * sizeof(SurQuery)) + sur_count_entries(qcap) * sizeof(uint32_t);
+    if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb.sur_entries >= qn && c->tb_packets >= want)
+        return QRT_OK;
     HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
     if (c->tb.packet_bytes < pb) {
         if (c->tb.packets) (void)hipFree(c->tb.packets);
@@ -252,12 +258,19 @@ int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
         HIP_TRY(c, hipMalloc(&c->tb.packets, pb), "packet states");
         c->tb.packet_bytes = pb;
     }
-    if (c->tb.peel_bytes < rb) {
+    if (c->tb.peel_bytes < rb || c->tb.sur_entries < qn) {
         if (c->tb.peels) (void)hipFree(c->tb.peels);
         c->tb.peels = nullptr;
+        c->tb.sur_q = nullptr;
+        c->tb.sur_n = nullptr;
         c->tb.peel_bytes = 0;
-        HIP_TRY(c, hipMalloc(&c->tb.peels, rb), "peel-ray queue");
+        c->tb.sur_entries = 0;
+        // the rays, then the surrogate queue and its per-block counts
+        HIP_TRY(c, hipMalloc(&c->tb.peels, align256(rb) + qb), "peel-ray queue");
         c->tb.peel_bytes = rb;
+        c->tb.sur_entries = qn;
+        c->tb.sur_q = (SurQuery *)((char *)c->tb.peels + align256(rb));
+        c->tb.sur_n = (uint32_t *)((char *)c->tb.sur_q + align256(qn * sizeof(SurQuery)));
     }
     if (c->tb_packets < want) {
         uint32_t **lists[3] = {&c->tb.order, &c->tb.keys, &c->tb.sort_tmp};
@@ -346,11 +359,10 @@ hipError_t scratch_address(int device, unsigned char **out)
     return hipSuccess;
 }
 
-size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
-
 // The transport buffers of one kStaticChunk-packet chunk carved from the
-// scratch at base (null: only the size); returns the bytes they take.
-size_t static_buffers(unsigned char *base, int precision, int n_obs, TransportBuffers &B)
+// scratch at base (null: only the size); returns the bytes they take.  The
+// surrogate queue is carved only for runs with the surrogate peel-off.
+size_t static_buffers(unsigned char *base, int precision, int n_obs, int peel_mode, TransportBuffers &B)
 {
     const uint64_t cap = kStaticChunk;
     const size_t pb = packet_state_bytes(precision) * cap * 2;
@@ -364,6 +376,9 @@ size_t static_buffers(unsigned char *base, int precision, int n_obs, TransportBu
     B = TransportBuffers{};
     B.packets = take(pb);
     B.peels = take(rb);
+    const size_t qn = peel_mode == QRT_PEEL_SURROGATE ? sur_queue_entries(cap, n_obs) : 0;
+    B.sur_q = qn ? (SurQuery *)take(qn * sizeof(SurQuery)) : nullptr;
+    B.sur_n = qn ? (uint32_t *)take(sur_count_entries(cap) * sizeof(uint32_t)) : nullptr;
     B.order = (uint32_t *)take(cap * sizeof(uint32_t));
     B.keys = (uint32_t *)take(cap * sizeof(uint32_t));
     B.sort_tmp = (uint32_t *)take(2 * cap * sizeof(uint32_t));
@@ -371,6 +386,7 @@ size_t static_buffers(unsigned char *base, int precision, int n_obs, TransportBu
     B.q = (Queues *)take(sizeof(Queues));
     B.packet_bytes = pb;
     B.peel_bytes = rb;
+    B.sur_entries = qn;
     B.cap = cap;
     return off;
 }
@@ -751,16 +767,17 @@ int qrt_run_static(qrt_ctx *c, uint64_t first, uint64_t count)
                     "the Faure tables for %d coordinates are built by qrt_run or qrt_generate_points; "
                     "the allocation-free run does not build them", point_dims(c));
     TransportBuffers B;
-    const size_t need = static_buffers(nullptr, c->precision, c->n_obs, B);
+    const size_t need = static_buffers(nullptr, c->precision, c->n_obs, c->peel_mode, B);
     if (need > kStaticScratchBytes)
         return fail(c, QRT_UNSUPPORTED,
                     "%d observers at %s need %zu bytes of scratch per chunk of %llu packets; the static "
-                    "scratch holds %zu (at most 4 observers in FP64, 11 in FP32)",
+                    "scratch holds %zu (exact peel-off: at most 4 observers in FP64, 11 in FP32; surrogate "
+                    "peel-off: 2 in FP64, 4 in FP32)",
                     c->n_obs, c->precision == QRT_FP64 ? "FP64" : "FP32", need,
                     (unsigned long long)kStaticChunk, kStaticScratchBytes);
     if (count == 0) return QRT_OK;
     DeviceGuard dg(c->device);
-    static_buffers(c->scratch, c->precision, c->n_obs, B);
+    static_buffers(c->scratch, c->precision, c->n_obs, c->peel_mode, B);
     TransportParams P;
     transport_params(c, P);
     for (uint64_t done = 0; done < count;) {

@@ -233,6 +233,24 @@ struct Queues {
     uint32_t n_peel[2][kPeelGroups][32];
 };
 
+// A peel-off ray queued for the surrogate network: its network inputs, the
+// offset of its pixel's I value in the image set [obs][3][npix][npix], and its
+// contribution before attenuation.
+struct alignas(16) SurQuery {
+    float x[5];
+    uint32_t key;
+    double c[3];
+};
+
+// The surrogate queue of an order: the rays queued by the 64-packet block b of
+// the live list sit at the start of the block's region of 64 n_obs entries,
+// and sur_n[b] counts them (no atomics: a wave owns its block).
+__host__ __device__ inline size_t sur_queue_entries(uint64_t cap, int n_obs)
+{
+    return (size_t)((cap + 63) / 64) * 64 * (size_t)n_obs;
+}
+__host__ __device__ inline size_t sur_count_entries(uint64_t cap) { return (size_t)((cap + 63) / 64); }
+
 constexpr int kSortBits = 16;                 // bits of the coherence sort keys
 constexpr int kSortItems = 4096;              // items per block of the radix-sort passes
 constexpr int kSortDigit = 256;               // values of an 8-bit digit
@@ -244,12 +262,15 @@ struct TransportBuffers {
     void *packets;        // PacketState<R>[2][cap]: the live packets of a scattering order, dense and in
                           // the order they were appended, ping-pong by order (list in, then list in ^ 1)
     void *peels;          // PeelRay<R>[n_obs * (chunk + 64)], blocks of 64 per observer
+    SurQuery *sur_q;      // [sur_queue_entries(cap, n_obs)] peel-off rays queued for the network
+    uint32_t *sur_n;      // [sur_count_entries(cap)] queued rays per 64-packet block
     uint32_t *order;      // [chunk] packets in coherence order
     uint32_t *keys;       // [chunk] sort keys
     uint32_t *sort_tmp;   // [2 chunk] keys and packets after the first sort pass
     uint32_t *hist;       // [kSortHist] histograms of a sort pass
     Queues *q;
     size_t packet_bytes, peel_bytes;
+    size_t sur_entries;   // entries of sur_q
     uint64_t cap;         // packets per state list
 };
 

@@ -337,6 +337,104 @@ __device__ __forceinline__ void load_obs(const TransportParams &P, ObsTable<R> &
     __syncthreads();
 }
 
+// The image copy of this block (blocks go round-robin to the XCDs), in the set
+// of the scattering order when orders are kept apart.
+__device__ __forceinline__ double *image_copy(const TransportParams &P, int order, size_t plane)
+{
+    const size_t set = (size_t)P.n_obs * 3 * plane;
+    const size_t s = P.order_images > 0 ? (size_t)(order - 1) : 0;
+    return P.img + (s * kImageCopies + (size_t)(blockIdx.x % kImageCopies)) * set;
+}
+
+// --------------------------------------------------------------------------
+// surrogate peel-off (an addition to the method): inside the validated domain
+// the network gives the optical depth to the observer
+// --------------------------------------------------------------------------
+
+// cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
+__device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
+{
+    const InputMap &D = S.in;
+    const double dx = x - D.center[0], dy = y - D.center[1], dz = z - D.center[2];
+    const double R = sqrt(dx * dx + dy * dy);
+    if (!(R >= S.r_in && R < D.r_out)) return -1;
+    const double zh = dz / (D.h0 * pow(R, D.beta));
+    if (!(fabs(zh) < D.zmax)) return -1;
+    const int ir = (int)floor((R - S.r_in) / (D.r_out - S.r_in) * (double)S.n_r);
+    const int iz = (int)floor((zh + D.zmax) / (2.0 * D.zmax) * (double)S.n_z);
+    if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
+    return ir * S.n_z + iz;
+}
+
+// Surrogate peel-off of one order.  The scattering kernel queues the visible
+// peel rays that start in a valid cell of the surrogate's domain, with their
+// network inputs, pixel and contribution (one reservation per wave), and
+// leaves them out of the walk; this kernel takes the queue in batches of 64
+// rays per wave, so every batch but the last is full, runs the network on the
+// matrix cores with the forward weight tiles in LDS, and adds the
+// contributions attenuated by e^-max(tau_hat, 0) to the image, merged by
+// pixel.  Its loads are coalesced reads of the queue.
+struct __align__(16) PeelNetLds {
+    bf16x8 Wt[kFwdTiles * 64];
+    float bias[260];
+    double merge[4][64][3];
+};
+
+__global__ void __launch_bounds__(256) k_peel_net(const TransportParams P, int order, int in,
+                                                  const SurQuery *__restrict__ sur_q, const uint32_t *__restrict__ sur_n,
+                                                  const Queues *__restrict__ Q)
+{
+    __shared__ PeelNetLds L;
+    const int lane = threadIdx.x & 63;
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t n_blocks = (Q->n_live[in] + 63) / 64;
+    // a wave takes `span` consecutive blocks at a time (at most 64, so that the
+    // launch spreads over all waves): their counts, scanned over the wave, give
+    // each queued ray its position in the wave's batches
+    const uint32_t span = n_blocks > waves * 64 ? 64u : (n_blocks + waves - 1) / waves;
+    // a block whose first wave has no blocks has no work at all (the late
+    // orders): it leaves before loading the weights
+    if ((uint64_t)blockIdx.x * (blockDim.x >> 6) * span >= n_blocks) return;
+    mlp_tiles_to_lds(L.Wt, (const bf16x8 *)P.sur.tiles);
+    mlp_bias_to_lds(L.bias, P.sur.params);
+    __syncthreads();
+    const size_t plane = (size_t)P.npix * (size_t)P.npix;
+    double *img_copy = image_copy(P, order, plane);
+    const int key_bits = bits_for((uint64_t)P.n_obs * 3 * plane);
+    const size_t region = (size_t)64 * P.n_obs;
+    for (uint32_t b0 = wave * span; b0 < n_blocks; b0 += waves * span) {
+        const uint32_t b = b0 + (uint32_t)lane;
+        const uint32_t cnt = ((uint32_t)lane < span && b < n_blocks) ? sur_n[b] : 0u;
+        uint32_t incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t v = __shfl_up(incl, off, 64);
+            incl += lane >= off ? v : 0u;
+        }
+        const uint32_t excl = incl - cnt;
+        const uint32_t total = __shfl(incl, 63, 64);
+        for (uint32_t j = 0; j < total; j += 64) {
+            const uint32_t qi = j + (uint32_t)lane;
+            const bool on = qi < total;
+            // the block holding ray qi: the last lane whose exclusive sum is <= qi
+            int k = 0;
+#pragma unroll
+            for (int step = 32; step >= 1; step >>= 1) {
+                const uint32_t e = __shfl(excl, k + step, 64);
+                k = (k + step < 64 && e <= qi) ? k + step : k;
+            }
+            const uint32_t ek = __shfl(excl, k, 64);
+            SurQuery q = {};
+            if (on) q = sur_q[(size_t)(b0 + (uint32_t)k) * region + (qi - ek)];
+            const float t = mlp_wave_lds(L.Wt, L.bias, q.x, lane);
+            const double att = exp(-(double)fmaxf(t, 0.0f));
+            wave_merge_add(on, q.key, att * q.c[0], att * q.c[1], att * q.c[2], img_copy, plane, key_bits,
+                           L.merge[threadIdx.x >> 6]);
+        }
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ SceneView<R> scene_view(const TransportParams &P, int src_kind)
 {
@@ -352,9 +450,15 @@ __device__ __forceinline__ SceneView<R> scene_view(const TransportParams &P, int
     return V;
 }
 
-template <typename R, int KIND, int SRC>
+// Scattering of the live packets of one order, one lane per packet: albedo,
+// the peel-off contribution toward every observer (written as a peel ray for
+// the walk), then the new direction and flight depth.  SUR: surrogate mode,
+// in which the visible rays that start in a valid cell of the surrogate's
+// domain are also queued for k_peel_net.
+template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
-                                                 int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+                                                 int in, PeelRay<R> *__restrict__ peels, SurQuery *__restrict__ sur_q,
+                                                 uint32_t *__restrict__ sur_n, Queues *__restrict__ Q)
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
@@ -368,7 +472,8 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
     const uint32_t stride = gridDim.x * blockDim.x;
     const SceneView<R> V = scene_view<R>(P, SRC);
-    uint32_t n_scat = 0, n_occ = 0;
+    const size_t cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
+    uint32_t n_scat = 0, n_occ = 0, n_sur = 0, n_fb = 0;
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
         const bool valid = i < n;
@@ -380,6 +485,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         }
         R n_ax[3];
         cross3(s.k, s.m, n_ax);
+        uint32_t queued = 0;   // rays of this wave's 64-packet block queued for the network (wave-uniform)
         for (int ob = 0; ob < P.n_obs; ++ob) {
             bool vis = false, occ = false;
             R c3[3] = {(R)0, (R)0, (R)0};
@@ -391,6 +497,27 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
                 peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
                 n_occ += occ ? 1u : 0u;
             }
+            bool use = false;
+            if constexpr (SUR) {
+                if (vis) {
+                    const int cell = dom_cell(P.sur, (double)s.p[0], (double)s.p[1], (double)s.p[2]);
+                    use = cell >= 0 && P.sur.valid[(size_t)ob * cells + (size_t)cell] != 0;
+                }
+                n_fb += (vis && !use) ? 1u : 0u;
+                n_sur += use ? 1u : 0u;
+                // the block's queue region: its queued rays, observer after observer
+                const uint64_t m = __ballot(use);
+                if (use) {
+                    SurQuery q;
+                    mlp_inputs(P.sur.in, (double)s.p[0], (double)s.p[1], (double)s.p[2], ob, q.x);
+                    q.key = (uint32_t)ob * 3u * (uint32_t)((size_t)P.npix * (size_t)P.npix) + pix;
+                    q.c[0] = (double)c3[0];
+                    q.c[1] = (double)c3[1];
+                    q.c[2] = (double)c3[2];
+                    sur_q[(size_t)(i >> 6) * 64 * (size_t)P.n_obs + queued + (uint32_t)__popcll(m & lanes_below_mask())] = q;
+                }
+                queued += (uint32_t)__popcll(m);
+            }
             {
                 // slot layout: blocks of 64 rays, one observer per block, observers
                 // cycling between blocks: a wave walks 64 neighbouring packets'
@@ -400,10 +527,13 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
                 PeelRay<R> r;
                 r.p[0] = s.p[0]; r.p[1] = s.p[1]; r.p[2] = s.p[2];
                 r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
-                r.pix = (valid && vis) ? pix : kNoPixel;
+                r.pix = (valid && vis && !use) ? pix : kNoPixel;   // a queued ray is not walked
                 r.obs = (uint32_t)ob;
                 peels[peel_slot(i, ob, P.n_obs)] = r;
             }
+        }
+        if constexpr (SUR) {
+            if (lane == 0) sur_n[i >> 6] = queued;
         }
         if (valid && order < P.max_orders) {
             uint32_t x[3];
@@ -412,20 +542,17 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
             pks[i] = s;
         }
     }
-    flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
+    if constexpr (SUR)
+        flush_counters<5>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED, CNT_SURROGATE, CNT_FALLBACKS, CNT_PEELS},
+                          {n_scat, n_occ, n_sur, n_fb, n_sur});
+    else
+        flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
 }
 
 // --------------------------------------------------------------------------
 // walks of one order: peel-off rays and flights
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
-
-__device__ __forceinline__ double *image_copy(const TransportParams &P, int order, size_t plane)
-{
-    const size_t set = (size_t)P.n_obs * 3 * plane;
-    const size_t s = P.order_images > 0 ? (size_t)(order - 1) : 0;
-    return P.img + (s * kImageCopies + (size_t)(blockIdx.x % kImageCopies)) * set;
-}
 
 template <typename R>
 __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order,
@@ -637,123 +764,6 @@ static int peel_lds_blocks(size_t bytes)
     return per_cu * device_cu_count();
 }
 
-// --------------------------------------------------------------------------
-// surrogate peel-off (an addition to the method): inside the validated
-// domain the network gives tau to the observer; the ray is then binned here
-// and marked done, so that the walk kernel skips it
-// --------------------------------------------------------------------------
-
-// cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
-__device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
-{
-    const InputMap &D = S.in;
-    const double dx = x - D.center[0], dy = y - D.center[1], dz = z - D.center[2];
-    const double R = sqrt(dx * dx + dy * dy);
-    if (!(R >= S.r_in && R < D.r_out)) return -1;
-    const double zh = dz / (D.h0 * pow(R, D.beta));
-    if (!(fabs(zh) < D.zmax)) return -1;
-    const int ir = (int)floor((R - S.r_in) / (D.r_out - S.r_in) * (double)S.n_r);
-    const int iz = (int)floor((zh + D.zmax) / (2.0 * D.zmax) * (double)S.n_z);
-    if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
-    return ir * S.n_z + iz;
-}
-
-// Surrogate pass over the peel slots of one order.  Each wave scans blocks of
-// 64 slots, queues the visible rays that fall in valid cells of the domain in
-// LDS (network inputs and slot), and runs the network on the matrix cores
-// whenever 64 are queued, so every batch is full; the remainder is run at the
-// end.  The forward weight tiles sit in LDS and each is applied to the four
-// 16-query tiles of a batch in turn.
-constexpr int kMlpWaves = 4;    // waves per block
-constexpr int kMlpQueue = 128;  // queued rays per wave (a batch of 64 plus one block of 64)
-
-struct __align__(16) PeelMlpLds {
-    bf16x8 Wt[kFwdTiles * 64];
-    float bias[260];
-    float qx[kMlpWaves][kMlpIn][kMlpQueue];
-    uint32_t qslot[kMlpWaves][kMlpQueue];
-};
-
-template <typename R>
-__device__ __forceinline__ void peel_mlp_batch(const TransportParams &P, PeelMlpLds &L, int w, int lane, int count,
-                                               PeelRay<R> *__restrict__ peels, double *img_copy, size_t plane)
-{
-    const bool live = lane < count;
-    float x[kMlpIn];
-#pragma unroll
-    for (int a = 0; a < kMlpIn; ++a) x[a] = live ? L.qx[w][a][lane] : 0.0f;
-    const uint32_t slot = live ? L.qslot[w][lane] : 0u;
-    const float t = mlp_wave_lds(L.Wt, L.bias, x, lane);
-    if (live) {
-        PeelRay<R> *rp = peels + slot;
-        const PeelRay<R> r = *rp;
-        const double att = exp(-(double)fmaxf(t, 0.0f));
-        double *dst = img_copy + (size_t)r.obs * 3 * plane + (size_t)r.pix;
-        unsafeAtomicAdd(dst, att * (double)r.c[0]);
-        unsafeAtomicAdd(dst + plane, att * (double)r.c[1]);
-        unsafeAtomicAdd(dst + 2 * plane, att * (double)r.c[2]);
-        rp->pix = kNoPixel;
-    }
-}
-
-template <typename R>
-__global__ void __launch_bounds__(256) k_peel_mlp(const TransportParams P, int order, PeelRay<R> *__restrict__ peels,
-                                                  const Queues *__restrict__ Q, int in)
-{
-    __shared__ PeelMlpLds L;
-    mlp_tiles_to_lds(L.Wt, (const bf16x8 *)P.sur.tiles);
-    mlp_bias_to_lds(L.bias, P.sur.params);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_blocks = (uint64_t)P.n_obs * ((n_live + 63) / 64);
-    const size_t plane = (size_t)P.npix * (size_t)P.npix;
-    double *img_copy = image_copy(P, order, plane);
-    const uint64_t waves = (uint64_t)gridDim.x * kMlpWaves;
-    const uint64_t wave = (uint64_t)blockIdx.x * kMlpWaves + w;
-    const size_t cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
-    uint32_t n_sur = 0, n_fb = 0;
-    int count = 0;   // queued rays of this wave (wave-uniform)
-    for (uint64_t g = wave; g < n_blocks; g += waves) {
-        const uint32_t slot = (uint32_t)(g * 64 + lane);
-        const PeelRay<R> r = peels[slot];
-        const bool vis = r.pix != kNoPixel;
-        bool use = false;
-        if (vis) {
-            const int cell = dom_cell(P.sur, (double)r.p[0], (double)r.p[1], (double)r.p[2]);
-            use = cell >= 0 && P.sur.valid[(size_t)r.obs * cells + (size_t)cell] != 0;
-        }
-        n_fb += (vis && !use) ? 1u : 0u;
-        n_sur += use ? 1u : 0u;
-        const uint64_t m = __ballot(use);
-        if (m == 0) continue;
-        if (use) {
-            float x[kMlpIn];
-            mlp_inputs(P.sur.in, (double)r.p[0], (double)r.p[1], (double)r.p[2], (int)r.obs, x);
-            const int pos = count + (int)__popcll(m & lanes_below_mask());
-#pragma unroll
-            for (int a = 0; a < kMlpIn; ++a) L.qx[w][a][pos] = x[a];
-            L.qslot[w][pos] = slot;
-        }
-        count += (int)__popcll(m);
-        wave_lds_sync();
-        if (count >= 64) {
-            peel_mlp_batch<R>(P, L, w, lane, 64, peels, img_copy, plane);
-            // move the rest of the queue to its front (disjoint ranges)
-            const int rest = count - 64;
-            if (lane < rest) {
-#pragma unroll
-                for (int a = 0; a < kMlpIn; ++a) L.qx[w][a][lane] = L.qx[w][a][64 + lane];
-                L.qslot[w][lane] = L.qslot[w][64 + lane];
-            }
-            count = rest;
-            wave_lds_sync();
-        }
-    }
-    if (count > 0) peel_mlp_batch<R>(P, L, w, lane, count, peels, img_copy, plane);
-    flush_counters<3>(P.counters, {CNT_SURROGATE, CNT_FALLBACKS, CNT_PEELS}, {n_sur, n_fb, n_sur});
-}
-
 // Pilot capture: (position, observer) of every visible peel ray inside the
 // surrogate domain, appended while the buffer has room (the count goes on).
 template <typename R>
@@ -802,12 +812,12 @@ template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
                             hipStream_t st, KernelTimer *T)
 {
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_mlp = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0;
     if (!nb_first) {
         nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
-        nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC>);
+        nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC, false>);
         nb_walk = resident_blocks_of(k_walk<R>);
-        nb_mlp = resident_blocks_of(k_peel_mlp<R>);
+        nb_net = resident_blocks_of(k_peel_net);
     }
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
@@ -834,18 +844,22 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         const int in = (order - 1) & 1;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
-            hipLaunchKernelGGL((k_scatter<R, KIND, SRC>), dim3(bs), dim3(256), 0, st, P, order,
-                               state_list<R>(B, in), in, peels, B.q);
+            if (P.peel_mode == 1)
+                hipLaunchKernelGGL((k_scatter<R, KIND, SRC, true>), dim3(bs), dim3(256), 0, st, P, order,
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q);
+            else
+                hipLaunchKernelGGL((k_scatter<R, KIND, SRC, false>), dim3(bs), dim3(256), 0, st, P, order,
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q);
+        }
+        if (P.peel_mode == 1) {
+            TimedLaunch tl(T, st, TC_PEEL_MLP);
+            hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, order, in, (const SurQuery *)B.sur_q,
+                               (const uint32_t *)B.sur_n, (const Queues *)B.q);
         }
         if (P.sur.cap) {
             TimedLaunch tl(T, st, TC_OTHER);
             hipLaunchKernelGGL((k_capture<R>), dim3(bs), dim3(256), 0, st, P, (const PeelRay<R> *)peels,
                                (const Queues *)B.q, in);
-        }
-        if (P.peel_mode == 1) {
-            TimedLaunch tl(T, st, TC_PEEL_MLP);
-            hipLaunchKernelGGL((k_peel_mlp<R>), dim3(nb_mlp), dim3(256), 0, st, P, order, peels, (const Queues *)B.q,
-                               in);
         }
         // the last order walks peel rays only (no flights): those want every resident
         // wave, and an image set that fits in LDS is summed there first

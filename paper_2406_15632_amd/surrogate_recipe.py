@@ -13,15 +13,15 @@ TRAIN = dict(steps=20000, batch=8192, lr=2e-3, lr_final=5e-5, seed=7, tau_cap=12
 VALIDATE = dict(max_err=0.02, floor_frac=0.3, min_count=16)
 
 
-def train_disk_surrogate(ctx, timer=None):
+def train_disk_surrogate(ctx, timer=None, h0: float = DISK_DOMAIN["h0"]):
     """Domain, pilot samples (exact labels), training and validity mask on a
-    context set up with the disk scene.  timer(fn) -> (result, seconds) times a
-    step (default: untimed).  Returns (pilot_packets, train_report, mask_report,
-    {step: seconds})."""
+    context set up with a disk scene of scale height h0 R^1.125.  timer(fn) ->
+    (result, seconds) times a step (default: untimed).  Returns (pilot_packets,
+    train_report, mask_report, {step: seconds})."""
     import torch
     if timer is None:
         timer = lambda fn: (fn(), 0.0)   # noqa: E731
-    ctx.surrogate_set_domain(**DOMAIN_CELLS, **DISK_DOMAIN)
+    ctx.surrogate_set_domain(**DOMAIN_CELLS, **dict(DISK_DOMAIN, h0=h0))
     pos = torch.zeros((N_TRAIN, 4), dtype=torch.float32, device="cuda")
     tau = torch.zeros(N_TRAIN, dtype=torch.float32, device="cuda")
     pilot, t_sample = timer(lambda: ctx.surrogate_sample(pos, tau, seed=PILOT_SEED))

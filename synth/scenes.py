@@ -101,21 +101,23 @@ def envelope32(n_packets: int = 1 << 16) -> Scene:
                  npix=64, half_width=1.0, max_orders=1, fp64=True, n_packets=n_packets)
 
 
-def disk_density(n: int) -> np.ndarray:
-    """Flared disk rho ~ (R/R0)^-2.25 exp(-z^2/2h^2), h = 0.1 R^1.125, R0 = 1, 0.05<=R<=1."""
+def disk_density(n: int, h0: float = 0.1) -> np.ndarray:
+    """Flared disk rho ~ (R/R0)^-2.25 exp(-z^2/2h^2), h = h0 R^1.125 (h0 = 0.1), R0 = 1, 0.05<=R<=1."""
     x, y, z = _mesh(n)
     R = np.sqrt(x * x + y * y)
     Rs = np.maximum(R, 1e-30)
-    hR = 0.1 * Rs ** 1.125
+    hR = h0 * Rs ** 1.125
     rho = Rs ** -2.25 * np.exp(-0.5 * (z / hR) ** 2)
     return np.where((R >= 0.05) & (R <= 1.0), rho, 0.0)
 
 
-def disk128(n_packets: int = 1 << 22, n: int = 128) -> Scene:
-    """Flared disk, midplane tau 10, 20 orders, three inclinations, 256^2 images, FP32 transport."""
-    kr = _scale_to_x_ray(disk_density(n), 10.0).astype(np.float32)
+def disk128(n_packets: int = 1 << 22, n: int = 128, tau_mid: float = 10.0, h0: float = 0.1) -> Scene:
+    """Flared disk, midplane tau 10 (or tau_mid), scale height h0 R^1.125 (h0 = 0.1), 20 orders, three
+    inclinations, 256^2 images, FP32 transport."""
+    kr = _scale_to_x_ray(disk_density(n, h0), tau_mid).astype(np.float32)
     obs = [(math.radians(t), 0.0) for t in (0.0, 45.0, 90.0)]
-    return Scene(name=f"disk{n}", n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
+    name = f"disk{n}" if (tau_mid == 10.0 and h0 == 0.1) else f"disk{n}_tau{tau_mid:g}_h{h0:g}"
+    return Scene(name=name, n=(n, n, n), lo=(-1.0,) * 3, hi=(1.0,) * 3, kappa_rho=kr,
                  albedo=0.5, g=0.6, p_lin=0.5, observers=obs, npix=256, half_width=1.0,
                  max_orders=20, fp64=False, n_packets=n_packets)
 
