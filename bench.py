@@ -30,6 +30,9 @@ The JSON line carries
                 sampling, GPU training and validation times, the share of
                 peel-off rays the network answers, the image bias against the
                 plain method, and the time to 1 % image RMS error of both;
+  surrogate_resolved  the same on a thick disk (h0 = 0.3, midplane tau 1)
+                on a 256^3 mesh, where peel-off rays are long and the density
+                is resolved;
   workloads     packets/s of the other scenes (dust envelope 32^3 in FP64,
                 clumpy envelope 256^3 with a spherical star);
   sphere_star   time to 5 % and 1 % image error for the spherical star in the
@@ -236,11 +239,11 @@ def _timed_run(ctx, stream, n):
     return img[:, 0], e0.elapsed_time(e1) * 1e-3
 
 
-def surrogate_section(ctx, qrt, sc, stream, ref):
-    """Learned peel-off on the disk scene: pilot samples (Philox, exact labels),
-    training on the GPU, validity mask, then plain against surrogate transport
-    of the same Sobol points; `ref` is an independent high-N image set (exact
-    Halton) or None."""
+def surrogate_section(ctx, qrt, sc, stream, ref, h0: float = 0.1):
+    """Learned peel-off on a disk scene (scale height h0 R^1.125): pilot samples
+    (Philox, exact labels), training on the GPU, validity mask, then plain
+    against surrogate transport of the same Sobol points, with per-kernel times;
+    `ref` is an independent high-N image set (exact Halton) or None."""
     import numpy as np
     import torch
 
@@ -254,14 +257,14 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
         return out, time.perf_counter() - t0
 
     from paper_2406_15632_amd import surrogate_recipe as SR
-    pilot, rep, mrep, times = SR.train_disk_surrogate(ctx, timer=sync_time)
+    pilot, rep, mrep, times = SR.train_disk_surrogate(ctx, timer=sync_time, h0=h0)
     t_sample, t_train, t_val = times["sample_s"], times["train_s"], times["validate_s"]
     steps, batch = SR.TRAIN["steps"], SR.TRAIN["batch"]
     N = 1 << 24
-    out = {"config": "disk128 scene, cylindrical domain R in [0.05, 1), |z| < 3 h(R), 16 x 12 cells per observer; "
-                     "2^20 pilot samples (Philox), 2^17 validation samples, 20000 Adam steps of 8192, "
-                     "cell error <= 2 % with a transmission floor of 0.3 x the observer mean; runs of 2^24 "
-                     "Sobol packets, FP32 transport",
+    out = {"config": f"{sc.name} scene ({sc.n[0]}^3), cylindrical domain R in [0.05, 1), |z| < 3 h(R), "
+                     "16 x 12 cells per observer; 2^20 pilot samples (Philox), 2^17 validation samples, "
+                     "20000 Adam steps of 8192, cell error <= 2 % with a transmission floor of 0.3 x the observer "
+                     "mean; runs of 2^24 Sobol packets, FP32 transport",
            "pilot_packets": pilot, "sample_s": t_sample, "train_s": t_train, "validate_s": t_val,
            "train_loss": [rep["loss_first"], rep["loss_final"]], "mask": mrep}
     # training throughput: forward plus backward (input and weight gradients) = 3 forward passes per sample
@@ -280,10 +283,17 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
                 pts.append((t, metrics.rms_error(img, ref), 1 << lg))
         img, t = _timed_run(ctx, stream, N)
         cnt = ctx.counters()
+        ctx.set_timing(True)
+        ctx.timing(reset=True)
+        ctx.reset_images()
+        ctx.run(1, 1 << 22)
+        tm = ctx.timing(reset=True)
+        ctx.set_timing(False)
         out[name] = {"packets_per_s": N / t, "ms": t * 1e3,
                      "rms_error": metrics.rms_error(img, ref) if ref is not None else None,
                      "surrogate_share_of_peels": cnt["surrogate"] / max(1, cnt["peels"]),
-                     "visits_per_packet": cnt["visits"] / cnt["packets"]}
+                     "visits_per_packet": cnt["visits"] / cnt["packets"],
+                     "kernel_ms_per_2e22_packets": {k: round(v[0], 3) for k, v in tm.items() if v[0]}}
         out[name + "_image"] = img
         curves[name] = pts
     out["bias_rms_vs_plain"] = metrics.rms_error(out.pop("surrogate_image"), out.pop("plain_image"))
@@ -293,6 +303,24 @@ def surrogate_section(ctx, qrt, sc, stream, ref):
         out["time_to_1pct_s"] = t1
         out["speedup_at_1pct"] = (t1["plain"] / t1["surrogate"]) if (t1["plain"] and t1["surrogate"]) else None
     ctx.set_transport(sc.max_orders, sc.tau_min, qrt.FP32, qrt.PEEL_EXACT)
+    return out
+
+
+def surrogate_resolved_section(qrt, stream):
+    """The learned peel-off where rays are long and the density is resolved: a
+    thick flared disk (h0 = 0.3, midplane optical depth 1) on a 256^3 mesh, the
+    same recipe and domain rule as the disk128 run, against a Halton reference
+    of 2^28 packets."""
+    import torch
+
+    from synth import scenes
+    sc = scenes.disk128(n=256, tau_mid=1.0, h0=0.3)
+    ctx = qrt.Context(0, stream.cuda_stream)
+    ctx.set_scene(sc, kind=qrt.HALTON, n_total=1 << 28, grid=torch.from_numpy(sc.kappa_rho).cuda())
+    ref, _ = _timed_run(ctx, stream, 1 << 28)
+    out = surrogate_section(ctx, qrt, sc, stream, ref, h0=0.3)
+    out["reference"] = "halton, 2^28 packets, exact peel-off"
+    ctx.close()
     return out
 
 
@@ -758,6 +786,8 @@ def main():
         result["envelope_time_to_error"] = envelope_time_to_error(qrt, stream)
     if not args.no_surrogate:
         result["surrogate"] = surrogate_section(ctx, qrt, sc, stream, ref)
+        if ref is not None:
+            result["surrogate_resolved"] = surrogate_resolved_section(qrt, stream)
     if not args.no_workloads:
         result["workloads"] = other_workloads(qrt, stream)
         result["sphere_star"] = sphere_star_section(qrt, stream)
