@@ -160,6 +160,22 @@ int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precisio
    add their contributions to the images.  Asynchronous on the context stream. */
 int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
 
+/* Overlapped runs (off by default).  While enabled, qrt_run puts each chunk
+   on one of two internal streams of the context, with buffers of its own,
+   after everything already enqueued on the context stream; its completion
+   joins the context stream at the next call of the library on this context
+   (any call but the host-side setters), or at qrt_join.  Consecutive runs then
+   overlap: the next run starts while the last scattering orders of the
+   previous one, which occupy few compute units, are still walking.  Callers
+   that time qrt_run with their own events, or enqueue work that reads the
+   images without calling the library first, call qrt_join before.  Disabling
+   joins whatever is pending.  qrt_run_static and batches never overlap. */
+int qrt_set_overlap(qrt_ctx *ctx, int enable);
+
+/* The context stream waits for every overlapped run still pending
+   (asynchronous, like qrt_run). */
+int qrt_join(qrt_ctx *ctx);
+
 /* qrt_run for callers that cannot allocate device memory: code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc.  It transports
    the same packets with the same kernels and adds the same contributions to

@@ -105,6 +105,17 @@ struct qrt_ctx {
     // kernel timing (qrt_set_timing)
     bool timing = false;
     KernelTimer timer;
+    // overlapped runs (qrt_set_overlap): chunks alternate between two lanes, each
+    // an internal stream with its own transport buffers (lane 0 uses tb); a
+    // lane's completion event joins the context stream at the next call
+    bool overlap = false;
+    hipStream_t lane[2] = {nullptr, nullptr};
+    hipEvent_t lane_done[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr;
+    bool lane_pending[2] = {false, false};
+    int next_lane = 0;
+    TransportBuffers tb1 = {};
+    uint64_t tb1_packets = 0;
 };
 
 namespace {
@@ -144,6 +155,27 @@ int hip_fail(qrt_ctx *c, hipError_t e, const char *what)
         hipError_t e_ = (expr);                    \
         if (e_ != hipSuccess) return hip_fail(c, e_, what); \
     } while (0)
+
+// The context stream waits for the overlapped runs still pending on the lanes.
+void join_lanes(qrt_ctx *c)
+{
+    for (int b = 0; b < 2; ++b)
+        if (c->lane_pending[b]) {
+            (void)hipStreamWaitEvent(c->stream, c->lane_done[b], 0);
+            c->lane_pending[b] = false;
+        }
+}
+
+// Finishes everything the context has enqueued: its stream and both lanes of
+// overlapped runs (a buffer is freed or reallocated only after this).
+int sync_all(qrt_ctx *c)
+{
+    join_lanes(c);
+    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
+    for (int b = 0; b < 2; ++b)
+        if (c->lane[b]) HIP_TRY(c, hipStreamSynchronize(c->lane[b]), "lane sync");
+    return QRT_OK;
+}
 
 int point_dims(const qrt_ctx *c)
 {
@@ -234,59 +266,75 @@ int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, ui
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Queues for chunks of up to `count` packets (at most kChunk) at the given
-// precision and peel slots per packet; grown on demand, never shrunk.
-int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
+// Transport buffers T (holding T_packets packets per list) for chunks of up to
+// `count` packets (at most kChunk) at the given precision and peel slots per
+// packet; grown on demand, never shrunk.
+int ensure_buffers(qrt_ctx *c, TransportBuffers &T, uint64_t &T_packets, uint64_t count, int n_obs, int precision)
 {
     uint64_t want = 1u << 16;
     while (want < count && want < kChunk) want <<= 1;
     if (want > kChunk) want = kChunk;
     // the state lists hold as many packets as the other lists (which never shrink)
-    const uint64_t cap = std::max<uint64_t>(want, c->tb_packets);
+    const uint64_t cap = std::max<uint64_t>(want, T_packets);
     const size_t pb = packet_state_bytes(precision) * cap * 2;   // two state lists
     const size_t rb = peel_ray_bytes(precision) * (want + 64) * (size_t)n_obs;
-    const uint64_t qcap = std::max<uint64_t>(want, c->tb_packets);
-    const size_t qn = sur_queue_entries(qcap, n_obs);
-    const size_t qb = align256(qn * sizeof(SurQuery)) + sur_count_entries(qcap) * sizeof(uint32_t);
-    if (c->tb.packet_bytes >= pb && c->tb.peel_bytes >= rb && c->tb.sur_entries >= qn && c->tb_packets >= want)
+    const size_t qn = sur_queue_entries(cap, n_obs);
+    const size_t qb = align256(qn * sizeof(SurQuery)) + sur_count_entries(cap) * sizeof(uint32_t);
+    if (T.q && T.hist && T.packet_bytes >= pb && T.peel_bytes >= rb && T.sur_entries >= qn && T_packets >= want)
         return QRT_OK;
-    HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
-    if (c->tb.packet_bytes < pb) {
-        if (c->tb.packets) (void)hipFree(c->tb.packets);
-        c->tb.packets = nullptr;
-        c->tb.packet_bytes = 0;
-        HIP_TRY(c, hipMalloc(&c->tb.packets, pb), "packet states");
-        c->tb.packet_bytes = pb;
+    int rc = sync_all(c);
+    if (rc) return rc;
+    if (!T.q) HIP_TRY(c, hipMalloc(&T.q, sizeof(Queues)), "queue counters");
+    if (!T.hist) HIP_TRY(c, hipMalloc(&T.hist, sizeof(uint32_t) * kSortHist), "sort histograms");
+    if (T.packet_bytes < pb) {
+        if (T.packets) (void)hipFree(T.packets);
+        T.packets = nullptr;
+        T.packet_bytes = 0;
+        HIP_TRY(c, hipMalloc(&T.packets, pb), "packet states");
+        T.packet_bytes = pb;
     }
-    if (c->tb.peel_bytes < rb || c->tb.sur_entries < qn) {
-        if (c->tb.peels) (void)hipFree(c->tb.peels);
-        c->tb.peels = nullptr;
-        c->tb.sur_q = nullptr;
-        c->tb.sur_n = nullptr;
-        c->tb.peel_bytes = 0;
-        c->tb.sur_entries = 0;
+    if (T.peel_bytes < rb || T.sur_entries < qn) {
+        if (T.peels) (void)hipFree(T.peels);
+        T.peels = nullptr;
+        T.sur_q = nullptr;
+        T.sur_n = nullptr;
+        T.peel_bytes = 0;
+        T.sur_entries = 0;
         // the rays, then the surrogate queue and its per-block counts
-        HIP_TRY(c, hipMalloc(&c->tb.peels, align256(rb) + qb), "peel-ray queue");
-        c->tb.peel_bytes = rb;
-        c->tb.sur_entries = qn;
-        c->tb.sur_q = (SurQuery *)((char *)c->tb.peels + align256(rb));
-        c->tb.sur_n = (uint32_t *)((char *)c->tb.sur_q + align256(qn * sizeof(SurQuery)));
+        HIP_TRY(c, hipMalloc(&T.peels, align256(rb) + qb), "peel-ray queue");
+        T.peel_bytes = rb;
+        T.sur_entries = qn;
+        T.sur_q = (SurQuery *)((char *)T.peels + align256(rb));
+        T.sur_n = (uint32_t *)((char *)T.sur_q + align256(qn * sizeof(SurQuery)));
     }
-    if (c->tb_packets < want) {
-        uint32_t **lists[3] = {&c->tb.order, &c->tb.keys, &c->tb.sort_tmp};
+    if (T_packets < want) {
+        uint32_t **lists[3] = {&T.order, &T.keys, &T.sort_tmp};
         for (uint32_t **l : lists) {
             if (*l) (void)hipFree(*l);
             *l = nullptr;
         }
-        c->tb_packets = 0;
-        c->tb.cap = 0;
-        HIP_TRY(c, hipMalloc(&c->tb.order, want * sizeof(uint32_t)), "packet lists");
-        HIP_TRY(c, hipMalloc(&c->tb.keys, want * sizeof(uint32_t)), "packet lists");
-        HIP_TRY(c, hipMalloc(&c->tb.sort_tmp, 2 * want * sizeof(uint32_t)), "packet lists");
-        c->tb_packets = want;
+        T_packets = 0;
+        T.cap = 0;
+        HIP_TRY(c, hipMalloc(&T.order, want * sizeof(uint32_t)), "packet lists");
+        HIP_TRY(c, hipMalloc(&T.keys, want * sizeof(uint32_t)), "packet lists");
+        HIP_TRY(c, hipMalloc(&T.sort_tmp, 2 * want * sizeof(uint32_t)), "packet lists");
+        T_packets = want;
     }
-    c->tb.cap = c->tb_packets;
+    T.cap = T_packets;
     return QRT_OK;
+}
+
+int ensure_queues(qrt_ctx *c, uint64_t count, int n_obs, int precision)
+{
+    return ensure_buffers(c, c->tb, c->tb_packets, count, n_obs, precision);
+}
+
+void free_buffers(TransportBuffers &T)
+{
+    void *ptrs[] = {T.packets, T.peels, T.q, T.order, T.keys, T.sort_tmp, T.hist};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    T = TransportBuffers{};
 }
 
 size_t image_sets(const qrt_ctx *c) { return c->order_images > 0 ? (size_t)c->order_images : 1; }
@@ -445,8 +493,13 @@ void qrt_destroy(qrt_ctx *c)
 {
     if (!c) return;
     DeviceGuard dg(c->device);
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
-    else (void)hipDeviceSynchronize();
+    (void)sync_all(c);
+    for (int b = 0; b < 2; ++b) {
+        if (c->lane[b]) (void)hipStreamDestroy(c->lane[b]);
+        if (c->lane_done[b]) (void)hipEventDestroy(c->lane_done[b]);
+    }
+    if (c->fork) (void)hipEventDestroy(c->fork);
+    free_buffers(c->tb1);
     if (c->grid) (void)hipFree(c->grid);
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
@@ -480,6 +533,7 @@ const char *qrt_last_error(const qrt_ctx *c)
 int qrt_set_stream(qrt_ctx *c, void *hip_stream)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     c->stream = (hipStream_t)hip_stream;
     return QRT_OK;
 }
@@ -488,6 +542,7 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
                  const float *kappa_rho, int flags)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (nx < 1 || ny < 1 || nz < 1 || !lo || !hi || !kappa_rho)
         return fail(c, QRT_INVALID_ARG, "bad grid arguments");
     const int64_t bricked = mesh_cells(nx, ny, nz);
@@ -590,6 +645,7 @@ int qrt_set_observers(qrt_ctx *c, int n_obs, const double *theta, const double *
                       double half_width)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (n_obs < 1 || n_obs > QRT_MAX_OBSERVERS || !theta || !phi)
         return fail(c, QRT_INVALID_ARG, "need 1..%d observers", QRT_MAX_OBSERVERS);
     if (npix < 1 || npix > 8192) return fail(c, QRT_INVALID_ARG, "npix must be in 1..8192");
@@ -742,23 +798,75 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
     if (c->kind == QRT_FAURE && (rc = ensure_faure(c, point_dims(c)))) return rc;
     TransportParams P;
     transport_params(c, P);
-    rc = ensure_queues(c, count, c->n_obs, c->precision);
-    if (rc) return rc;
-    // chunks never exceed the queue capacity
+    if (!c->overlap) {
+        join_lanes(c);
+        rc = ensure_queues(c, count, c->n_obs, c->precision);
+        if (rc) return rc;
+        // chunks never exceed the queue capacity
+        for (uint64_t done = 0; done < count;) {
+            const uint64_t n = count - done < c->tb_packets ? count - done : c->tb_packets;
+            HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream,
+                                        c->timing ? &c->timer : nullptr),
+                    "transport launch");
+            done += n;
+        }
+        c->packets_run += count;
+        return QRT_OK;
+    }
+    // Overlapped: each chunk goes to the next lane, after everything already on the
+    // context stream; then the other lane's pending chunk joins the context stream.
+    // The newest chunk stays pending, so that the next run starts beside its last
+    // scattering orders, which occupy few compute units.
+    for (int b = 0; b < 2; ++b) {
+        if (!c->lane[b]) HIP_TRY(c, hipStreamCreateWithFlags(&c->lane[b], hipStreamNonBlocking), "lane stream");
+        if (!c->lane_done[b]) HIP_TRY(c, hipEventCreateWithFlags(&c->lane_done[b], hipEventDisableTiming), "lane event");
+    }
+    if (!c->fork) HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
     for (uint64_t done = 0; done < count;) {
-        const uint64_t n = count - done < c->tb_packets ? count - done : c->tb_packets;
-        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, c->tb, c->stream,
+        const int b = c->next_lane;
+        TransportBuffers &T = b == 0 ? c->tb : c->tb1;
+        uint64_t &T_packets = b == 0 ? c->tb_packets : c->tb1_packets;
+        if ((rc = ensure_buffers(c, T, T_packets, count - done, c->n_obs, c->precision))) return rc;
+        const uint64_t n = count - done < T_packets ? count - done : T_packets;
+        HIP_TRY(c, hipEventRecord(c->fork, c->stream), "fork");
+        HIP_TRY(c, hipStreamWaitEvent(c->lane[b], c->fork, 0), "fork");
+        HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, T, c->lane[b],
                                     c->timing ? &c->timer : nullptr),
                 "transport launch");
+        HIP_TRY(c, hipEventRecord(c->lane_done[b], c->lane[b]), "lane done");
+        c->lane_pending[b] = true;
+        if (c->lane_pending[b ^ 1]) {
+            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lane_done[b ^ 1], 0), "join");
+            c->lane_pending[b ^ 1] = false;
+        }
+        c->next_lane = b ^ 1;
         done += n;
     }
     c->packets_run += count;
     return QRT_OK;
 }
 
+int qrt_set_overlap(qrt_ctx *c, int enable)
+{
+    if (!c) return QRT_INVALID_ARG;
+    DeviceGuard dg(c->device);
+    join_lanes(c);
+    c->overlap = enable != 0;
+    return QRT_OK;
+}
+
+int qrt_join(qrt_ctx *c)
+{
+    if (!c) return QRT_INVALID_ARG;
+    DeviceGuard dg(c->device);
+    join_lanes(c);
+    return QRT_OK;
+}
+
 int qrt_run_static(qrt_ctx *c, uint64_t first, uint64_t count)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     int rc = run_checks(c, c->kind, c->n_total, first, count);
     if (rc) return rc;
     if (!c->scratch) return fail(c, QRT_HIP_ERROR, "no static scratch on device %d", c->device);
@@ -792,6 +900,7 @@ int qrt_run_static(qrt_ctx *c, uint64_t first, uint64_t count)
 int qrt_read_images(qrt_ctx *c, int obs, double *I, double *Q, double *U, int normalized)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
     if (obs < 0 || obs >= c->n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
     DeviceGuard dg(c->device);
@@ -827,6 +936,7 @@ int qrt_read_images(qrt_ctx *c, int obs, double *I, double *Q, double *U, int no
 int qrt_image_device_ptr(qrt_ctx *c, double **dev_ptr)
 {
     if (!c || !dev_ptr) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
     if (c->order_images > 0) return fail(c, QRT_BAD_STATE, "per-order images: read them with qrt_read_order_images");
     DeviceGuard dg(c->device);
@@ -839,6 +949,7 @@ int qrt_image_device_ptr(qrt_ctx *c, double **dev_ptr)
 int qrt_set_order_images(qrt_ctx *c, int enable)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "set the observers first");
     DeviceGuard dg(c->device);
     c->order_images = enable ? c->max_orders : 0;
@@ -850,6 +961,7 @@ int qrt_set_order_images(qrt_ctx *c, int enable)
 int qrt_read_order_images(qrt_ctx *c, int obs, int order, double *I, double *Q, double *U, int normalized)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "no observers set");
     if (c->order_images <= 0) return fail(c, QRT_BAD_STATE, "per-order images are off");
     if (obs < 0 || obs >= c->n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
@@ -878,6 +990,7 @@ int qrt_read_order_images(qrt_ctx *c, int obs, int order, double *I, double *Q, 
 int qrt_reset_images(qrt_ctx *c)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     DeviceGuard dg(c->device);
     if (c->img)
         HIP_TRY(c, hipMemsetAsync(c->img, 0, c->img_alloc * sizeof(double), c->stream), "image reset");
@@ -889,6 +1002,7 @@ int qrt_reset_images(qrt_ctx *c)
 int qrt_get_counters(qrt_ctx *c, qrt_counters *out)
 {
     if (!c || !out) return QRT_INVALID_ARG;
+    join_lanes(c);
     DeviceGuard dg(c->device);
     unsigned long long copies[kCounterCopies][kCounterLine];
     HIP_TRY(c, hipMemcpyAsync(copies, c->counters, sizeof(copies), hipMemcpyDeviceToHost, c->stream), "counter copy");
@@ -920,6 +1034,7 @@ int qrt_set_timing(qrt_ctx *c, int enable)
 int qrt_get_timing(qrt_ctx *c, qrt_timing *out, int reset)
 {
     if (!c || !out) return QRT_INVALID_ARG;
+    join_lanes(c);
     static_assert(QRT_T_CLASSES == TC_COUNT, "timing classes of the ABI and the library agree");
     DeviceGuard dg(c->device);
     HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "timing sync");
@@ -940,6 +1055,7 @@ int qrt_generate_points(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total, u
                         int dims, uint32_t *out, int out_on_device)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (dims < 1 || dims > kMaxDims) return fail(c, QRT_UNSUPPORTED, "dims must be in 1..%d", kMaxDims);
     if (!out && count) return fail(c, QRT_INVALID_ARG, "null output");
@@ -969,6 +1085,7 @@ int qrt_generate_points(qrt_ctx *c, int kind, uint64_t seed, uint64_t n_total, u
 int qrt_trace_tau(qrt_ctx *c, int64_t n, const double *p, const double *k, double *tau, int64_t *visits)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_grid) return fail(c, QRT_BAD_STATE, "no grid");
     if (n < 0 || (n > 0 && (!p || !k || !tau))) return fail(c, QRT_INVALID_ARG, "bad ray buffers");
     DeviceGuard dg(c->device);
@@ -1038,6 +1155,7 @@ static int host_dom_cell(const qrt_ctx *c, double x, double y, double z)
 int qrt_mlp_set_params(qrt_ctx *c, const float *params, int64_t n)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!params || n != kMlpParams) return fail(c, QRT_INVALID_ARG, "the network has %d parameters", kMlpParams);
     for (int64_t i = 0; i < n; ++i)
         if (!isfinite(params[i])) return fail(c, QRT_INVALID_ARG, "parameter %lld is not finite", (long long)i);
@@ -1058,6 +1176,7 @@ int qrt_mlp_set_params(qrt_ctx *c, const float *params, int64_t n)
 int qrt_mlp_get_params(qrt_ctx *c, float *params, int64_t n)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!params || n != kMlpParams) return fail(c, QRT_INVALID_ARG, "the network has %d parameters", kMlpParams);
     if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
     DeviceGuard dg(c->device);
@@ -1070,6 +1189,7 @@ int qrt_mlp_get_params(qrt_ctx *c, float *params, int64_t n)
 int qrt_mlp_init(qrt_ctx *c, uint64_t seed)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     std::vector<float> h(kMlpParams, 0.0f);
     uint64_t st = seed;
     for (int l = 0; l < 5; ++l) {
@@ -1086,6 +1206,7 @@ int qrt_mlp_init(qrt_ctx *c, uint64_t seed)
 int qrt_mlp_forward(qrt_ctx *c, int64_t n, const float *X, float *y)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
     if (n < 0 || (n > 0 && (!X || !y))) return fail(c, QRT_INVALID_ARG, "bad buffers");
     DeviceGuard dg(c->device);
@@ -1096,6 +1217,7 @@ int qrt_mlp_forward(qrt_ctx *c, int64_t n, const float *X, float *y)
 int qrt_mlp_backward(qrt_ctx *c, int64_t n, const float *X, const float *dy, float *grad)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
     if (n < 1 || !X || !dy || !grad) return fail(c, QRT_INVALID_ARG, "bad buffers");
     if (n > (int64_t)1 << 24) return fail(c, QRT_UNSUPPORTED, "at most 2^24 rows per call");
@@ -1115,6 +1237,7 @@ int qrt_surrogate_set_domain(qrt_ctx *c, const double center[3], double r_in, do
                              double zmax_over_h, int n_r, int n_z)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!center || !(r_in >= 0.0) || !(r_out > r_in) || !(h0 > 0.0) || !isfinite(beta) || !(zmax_over_h > 0.0) ||
         !isfinite(r_out) || !isfinite(h0) || !isfinite(zmax_over_h))
         return fail(c, QRT_INVALID_ARG, "bad domain: need 0 <= r_in < r_out, h0 > 0, zmax > 0");
@@ -1138,6 +1261,7 @@ int qrt_surrogate_set_domain(qrt_ctx *c, const double center[3], double r_in, do
 int qrt_surrogate_set_mask(qrt_ctx *c, const uint8_t *mask)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_domain || !c->has_obs) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (!mask) return fail(c, QRT_INVALID_ARG, "null mask");
     DeviceGuard dg(c->device);
@@ -1150,6 +1274,7 @@ int qrt_surrogate_set_mask(qrt_ctx *c, const uint8_t *mask)
 int qrt_surrogate_get_mask(qrt_ctx *c, uint8_t *mask)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_domain || !c->has_obs) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (!mask) return fail(c, QRT_INVALID_ARG, "null mask");
     DeviceGuard dg(c->device);
@@ -1162,6 +1287,7 @@ int qrt_surrogate_get_mask(qrt_ctx *c, uint8_t *mask)
 int qrt_surrogate_inputs(qrt_ctx *c, int64_t n, const float *pos_obs, float *X)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_obs || !c->has_domain) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (n < 0 || (n > 0 && (!pos_obs || !X))) return fail(c, QRT_INVALID_ARG, "bad buffers");
     DeviceGuard dg(c->device);
@@ -1172,6 +1298,7 @@ int qrt_surrogate_inputs(qrt_ctx *c, int64_t n, const float *pos_obs, float *X)
 int qrt_surrogate_sample(qrt_ctx *c, int64_t n, uint64_t seed, float *pos_obs, float *tau, int64_t *pilot_packets)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_domain) return fail(c, QRT_BAD_STATE, "set a surrogate domain first");
     if (n < 1 || !pos_obs || !tau) return fail(c, QRT_INVALID_ARG, "bad buffers");
     if (n > (int64_t)1 << 26) return fail(c, QRT_UNSUPPORTED, "at most 2^26 samples");
@@ -1303,6 +1430,7 @@ int qrt_surrogate_train(qrt_ctx *c, int64_t n, const float *pos_obs, const float
                         qrt_train_report *rep)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!cfg || n < 1 || !pos_obs || !tau) return fail(c, QRT_INVALID_ARG, "bad arguments");
     if (!c->has_obs || !c->has_domain) return fail(c, QRT_BAD_STATE, "set observers and a domain first");
     if (cfg->steps < 0 || cfg->batch < 64 || cfg->batch > 65536 || cfg->batch % 64)
@@ -1358,6 +1486,7 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
                            double floor_frac, int64_t min_count, qrt_mask_report *rep)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!c->has_mlp) return fail(c, QRT_NOT_TRAINED, "no network parameters");
     if (!c->has_domain || !c->has_obs || !c->has_grid) return fail(c, QRT_BAD_STATE, "set grid, observers, domain");
     if (n < 1 || !pos_obs || !tau || !(max_err >= 0.0) || !(floor_frac >= 0.0) || min_count < 1)
@@ -1454,6 +1583,7 @@ static size_t state_bytes(uint32_t n_obs, int n_r, int n_z)
 int qrt_surrogate_get_state(qrt_ctx *c, void *blob, size_t *nbytes)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!nbytes) return fail(c, QRT_INVALID_ARG, "null size");
     if (!c->has_mlp || !c->has_domain || !c->has_obs)
         return fail(c, QRT_NOT_TRAINED, "the surrogate needs network parameters, a domain and observers");
@@ -1494,6 +1624,7 @@ int qrt_surrogate_get_state(qrt_ctx *c, void *blob, size_t *nbytes)
 int qrt_surrogate_set_state(qrt_ctx *c, const void *blob, size_t nbytes)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (!blob || nbytes < sizeof(SurrogateStateHeader)) return fail(c, QRT_INVALID_ARG, "state too short");
     if (!c->has_obs) return fail(c, QRT_BAD_STATE, "set the observers first");
     SurrogateStateHeader h;
@@ -1576,6 +1707,7 @@ static int batch_scene_check(qrt_ctx *c, int i, const qrt_batch_scene &S)
 int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (n_scenes < 1 || n_scenes > QRT_BATCH_MAX_SCENES || !scenes)
         return fail(c, QRT_INVALID_ARG, "need 1..%d scenes", QRT_BATCH_MAX_SCENES);
     size_t cells = 0, pixels = 0;
@@ -1673,6 +1805,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
 int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (c->batch.empty()) return fail(c, QRT_BAD_STATE, "set the batch scenes first");
     if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (kind == QRT_FAURE) return fail(c, QRT_UNSUPPORTED, "Faure points are not served in batches");
@@ -1714,6 +1847,7 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
 int qrt_batch_read_images(qrt_ctx *c, int scene, int obs, double *I, double *Q, double *U, int normalized)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     if (scene < 0 || scene >= (int)c->batch.size()) return fail(c, QRT_INVALID_ARG, "scene %d out of range", scene);
     const BScene &B = c->batch[(size_t)scene];
     if (obs < 0 || obs >= B.n_obs) return fail(c, QRT_INVALID_ARG, "observer %d out of range", obs);
@@ -1740,6 +1874,7 @@ int qrt_batch_read_images(qrt_ctx *c, int scene, int obs, double *I, double *Q, 
 int qrt_batch_reset(qrt_ctx *c)
 {
     if (!c) return QRT_INVALID_ARG;
+    join_lanes(c);
     DeviceGuard dg(c->device);
     if (c->batch_img && c->batch_img_used)
         HIP_TRY(c, hipMemsetAsync(c->batch_img, 0, c->batch_img_used * sizeof(double), c->stream), "batch image reset");

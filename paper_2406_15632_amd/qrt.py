@@ -92,6 +92,8 @@ SIGNATURES = {
     "qrt_set_transport": (C.c_int, [_P, C.c_int, C.c_double, C.c_int, C.c_int]),
     "qrt_run": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
     "qrt_run_static": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
+    "qrt_set_overlap": (C.c_int, [_P, C.c_int]),
+    "qrt_join": (C.c_int, [_P]),
     "qrt_read_images": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_image_device_ptr": (C.c_int, [_P, C.POINTER(C.c_void_p)]),
     "qrt_reset_images": (C.c_int, [_P]),
@@ -255,6 +257,14 @@ class Context:
     # -------- work
     def run(self, first: int, count: int):
         self._ck(self.lib.qrt_run(self.h, first, count))
+
+    def set_overlap(self, enable: bool):
+        """Overlapped runs on two internal streams (see qrt_set_overlap)."""
+        self._ck(self.lib.qrt_set_overlap(self.h, int(enable)))
+
+    def join(self):
+        """The context stream waits for the overlapped runs still pending."""
+        self._ck(self.lib.qrt_join(self.h))
 
     def run_static(self, first: int, count: int):
         """qrt_run on the device's static scratch (no allocation)."""

@@ -440,6 +440,65 @@ def test_failed_image_allocation_leaves_no_observers(ctx, Q):
     assert np.allclose(ctx.read_images(), ref, rtol=1e-12, atol=1e-15 * ref.max())
 
 
+def test_overlapped_runs(ctx, Q):
+    """Overlapped runs (two internal streams, completion joined at the next
+    call): consecutive calls sum to the oracle's run over all their packets;
+    a sequence of calls with several point sets, and a call of two chunks,
+    equal the same calls in stream order up to the order of the FP64 image
+    sums, with equal counters; a reset or new observers right after
+    overlapped runs see them finished."""
+    sc = scenes.disk128(n_packets=1 << 12, n=32).replace(max_orders=5, npix=32, fp64=True)
+    _say("overlapped runs: oracle parity over two calls")
+    ctx.set_scene(sc, kind=O.SOBOL)
+    ctx.set_overlap(True)
+    ctx.reset_images()
+    ctx.run(1, 2000)
+    ctx.run(2001, 2096)
+    g = ctx.read_images(normalized=False) / 4096
+    o, co, _ = O.run(sc, O.SOBOL, 1, 4096, nthreads=8)
+    assert_fp64_parity(g, o)
+    assert_counters_equal(ctx.counters(), co)
+
+    def sequence(overlap):
+        ctx.set_overlap(overlap)
+        ctx.reset_images()
+        for kind, seed in ((O.SOBOL, 0), (O.HALTON, 0), (O.PHILOX, 7), (O.NIEDERREITER2, 0)):
+            ctx.set_sequence(kind, seed, 0)
+            ctx.run(1, 3000)
+        return ctx.read_images(normalized=False), ctx.counters()
+    _say("overlapped runs: four point sets, on and off")
+    a, ca = sequence(True)
+    b, cb = sequence(False)
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-15 * np.abs(b).max())
+    assert ca == cb
+    # one call of two chunks (2^22 + 1000 packets), overlapped and not
+    env = scenes.envelope32()
+    ctx.set_scene(env, kind=O.SOBOL)
+    n = (1 << 22) + 1000
+    _say("overlapped runs: two chunks")
+    res = []
+    for overlap in (True, False):
+        ctx.set_overlap(overlap)
+        ctx.reset_images()
+        ctx.run(1, n)
+        res.append((ctx.read_images(normalized=False), ctx.counters()))
+    assert np.allclose(res[0][0], res[1][0], rtol=1e-12, atol=1e-15 * np.abs(res[1][0]).max())
+    assert res[0][1] == res[1][1] and res[0][1]["packets"] == n
+    # a reset and new observers right after overlapped runs
+    ctx.set_overlap(True)
+    ctx.run(1, 1 << 20)
+    ctx.reset_images()
+    ctx.run(1, 4096)
+    small = ctx.read_images(normalized=False)
+    ctx.run(1, 1 << 20)
+    ctx.set_observers(env.observers, 48, env.half_width)
+    ctx.set_observers(env.observers, env.npix, env.half_width)
+    ctx.run(1, 4096)
+    assert np.allclose(ctx.read_images(normalized=False), small, rtol=1e-12, atol=1e-15 * small.max())
+    assert ctx.counters()["packets"] == 4096
+    ctx.set_overlap(False)
+
+
 # ------------------------------------------------------------------ full benchmark size
 def test_disk128_full_size_properties(ctx, Q):
     """The benchmark configuration (2^22 packets per sequence, FP32): the run
