@@ -356,8 +356,8 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
     envelope or disk, point source or sphere star, 1 to 4 observers, 1 to 20
     orders, 128^2 images, FP32 rays with FP64 sums), Sobol points.  One batch
     run (every scene's packets in one launch sequence) against the same scenes
-    run one after another through the single-scene calls, meshes resident in
-    HBM for both."""
+    run one after another through the single-scene calls, in stream order and
+    overlapped; meshes resident in HBM for all."""
     import torch
 
     from synth import scenes
@@ -368,12 +368,14 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
     ctx.batch_set(bs)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)               # warm-up
+    ctx.join()
     torch.cuda.synchronize()
     ctx.batch_reset()
     w0 = time.perf_counter()
     e0.record(stream)
     for _ in range(steps):
         ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)
+    ctx.join()
     e1.record(stream)
     torch.cuda.synchronize()
     batch_wall = (time.perf_counter() - w0) / steps
@@ -385,23 +387,27 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
         seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
         seq.run(1, min(sc.n_packets, 1 << 16))
     torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    for sc, g in zip(bs, grids):
-        seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
-        seq.run(1, sc.n_packets)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    seq_wall = time.perf_counter() - w0
-    seq_s = e0.elapsed_time(e1) * 1e-3
+    seq_s = {}
+    for overlap in (False, True):
+        seq.set_overlap(overlap)
+        e0.record(stream)
+        for sc, g in zip(bs, grids):
+            seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
+            seq.run(1, sc.n_packets)
+        seq.join()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_s["overlapped" if overlap else "stream_order"] = e0.elapsed_time(e1) * 1e-3
     ctx.close()
     seq.close()
     return {
         "scenes": len(bs), "packets": total, "seed": seed,
         "batch_packets_per_s": total / batch_s, "batch_ms": batch_s * 1e3, "batch_wall_ms": batch_wall * 1e3,
-        "sequential_packets_per_s": total / seq_s, "sequential_ms": seq_s * 1e3,
-        "sequential_wall_ms": seq_wall * 1e3,
-        "speedup": seq_s / batch_s,
+        "sequential_packets_per_s": total / seq_s["stream_order"], "sequential_ms": seq_s["stream_order"] * 1e3,
+        "sequential_overlapped_packets_per_s": total / seq_s["overlapped"],
+        "sequential_overlapped_ms": seq_s["overlapped"] * 1e3,
+        "speedup": seq_s["stream_order"] / batch_s,
+        "speedup_vs_sequential_overlapped": seq_s["overlapped"] / batch_s,
         "visits_per_packet": cnt["visits"] / cnt["packets"],
         "algorithmic_GBps": (4.0 * cnt["visits"] + 24.0 * cnt["peels"]) / (batch_s * steps) / 1e9,
     }

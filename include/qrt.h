@@ -169,7 +169,8 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
    previous one, which occupy few compute units, are still walking.  Callers
    that time qrt_run with their own events, or enqueue work that reads the
    images without calling the library first, call qrt_join before.  Disabling
-   joins whatever is pending.  qrt_run_static and batches never overlap. */
+   joins whatever is pending.  qrt_run_static and qrt_batch_run never
+   overlap. */
 int qrt_set_overlap(qrt_ctx *ctx, int enable);
 
 /* The context stream waits for every overlapped run still pending

@@ -1805,7 +1805,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
 int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
 {
     if (!c) return QRT_INVALID_ARG;
-    join_lanes(c);
+    join_lanes(c);   // a batch runs in stream order (overlapping its chunks measured no gain)
     if (c->batch.empty()) return fail(c, QRT_BAD_STATE, "set the batch scenes first");
     if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (kind == QRT_FAURE) return fail(c, QRT_UNSUPPORTED, "Faure points are not served in batches");
@@ -1838,7 +1838,7 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     const uint64_t unit = 64 * kPeelGroups, per_unit = 64 * kBatchObs;
     const uint64_t chunk = std::min<uint64_t>(c->tb_packets, (P.group_cap / per_unit) * unit);
     if (chunk == 0) return fail(c, QRT_HIP_ERROR, "peel-ray buffer too small for a batch");
-    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, c->batch_total, c->tb, chunk, c->stream,
+    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, 0, c->batch_total, c->tb, chunk, c->stream,
                             c->timing ? &c->timer : nullptr),
             "batch launch");
     return QRT_OK;

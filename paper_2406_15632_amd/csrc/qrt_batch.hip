@@ -495,10 +495,12 @@ static int host_scene_of(const uint64_t *begin, int n_scenes, uint64_t b)
     return lo;
 }
 
-hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precision, int kind, uint64_t total,
-                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream, KernelTimer *timer)
+hipError_t launch_batch(const BatchParams &P0, const uint64_t *begin, int precision, int kind, uint64_t b_first,
+                        uint64_t b_count, const TransportBuffers &B, uint64_t chunk, hipStream_t stream,
+                        KernelTimer *timer)
 {
-    for (uint64_t done = 0; done < total;) {
+    const uint64_t total = b_first + b_count;
+    for (uint64_t done = b_first; done < total;) {
         const uint32_t n = (uint32_t)(total - done < chunk ? total - done : chunk);
         // the sort key spends only the bits that the chunk's scenes need on the scene
         BatchParams P = P0;

@@ -323,10 +323,11 @@ struct BatchParams {
     int img_key_bits;           // bits that hold an element offset from img_base
 };
 
-// All `total` batch numbers of a batch, in chunks of at most `chunk`; begin[s]
-// (host) is the first batch number of scene s.
-hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precision, int kind, uint64_t total,
-                        const TransportBuffers &B, uint64_t chunk, hipStream_t stream, KernelTimer *timer = nullptr);
+// Batch numbers b_first .. b_first+b_count-1 of a batch, in chunks of at most
+// `chunk`; begin[s] (host) is the first batch number of scene s.
+hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precision, int kind, uint64_t b_first,
+                        uint64_t b_count, const TransportBuffers &B, uint64_t chunk, hipStream_t stream,
+                        KernelTimer *timer = nullptr);
 
 // order[0 .. count) = the packets 0 .. count-1 sorted by keys[j] (kSortBits bits), stably; count <= kChunk.
 // Two radix passes of 8 bits through B.sort_tmp, histograms in B.hist.

@@ -251,15 +251,22 @@ def test_full_batch_fp64_sampled_against_oracle(ctx, Q, full_batch):
         assert_fp64_parity(ctx.batch_read_images(i), o, f"scene {i} n={sc.n[0]} orders={sc.max_orders}")
 
 
-def test_full_batch_fp32_equals_single_runs(ctx, Q, full_batch):
+@pytest.mark.parametrize("overlap", [False, True])
+def test_full_batch_fp32_equals_single_runs(ctx, Q, full_batch, overlap):
     """The workload as timed (FP32, full packet counts, 2^23 to 2^31 batch
-    numbers in chunks) against single-scene runs of every scene."""
-    _say(f"full batch fp32, {sum(s.n_packets for s in full_batch)} packets")
+    numbers in chunks) against single-scene runs of every scene; with the
+    overlap mode on, the batch still runs in stream order after the pending
+    runs."""
+    _say(f"full batch fp32 overlap={overlap}, {sum(s.n_packets for s in full_batch)} packets")
     single, cs = single_runs(ctx, Q, full_batch, Q.SOBOL, 0, Q.FP32)
     ctx.batch_set(full_batch)
-    ctx.batch_reset()
-    ctx.batch_run(Q.SOBOL, 0, Q.FP32)
-    cb = ctx.counters()
+    ctx.set_overlap(overlap)
+    try:
+        ctx.batch_reset()
+        ctx.batch_run(Q.SOBOL, 0, Q.FP32)
+        cb = ctx.counters()
+    finally:
+        ctx.set_overlap(False)
     for i in range(len(full_batch)):
         assert_sum_order_equal(ctx.batch_read_images(i, normalized=False), single[i], f"scene {i}")
     assert cb == sum_counters(cs)
