@@ -106,7 +106,9 @@ struct WorkPool {
             }
         }
         const uint64_t rest = total > fixed ? total - fixed : 0;
-        const uint64_t len = (rest + kPoolParts - 1) / kPoolParts;
+        // parts start on block boundaries, so a wave's 64 items stay inside one
+        // aligned group of 64 (the peel rays of 64 packets toward one observer)
+        const uint64_t len = ((rest + kPoolParts - 1) / kPoolParts + blk - 1) / blk * blk;
         while (tried < kPoolParts) {
             const uint64_t lo = fixed + (uint64_t)part * len;
             const uint64_t hi = lo + len < total ? lo + len : total;
