@@ -173,6 +173,20 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
    overlap. */
 int qrt_set_overlap(qrt_ctx *ctx, int enable);
 
+/* Late scattering orders in one launch (Sec. 2.2, 3.5: the same transport,
+   launched differently).  From order first_order on (default 4; 0 turns it
+   off) a run carries each live packet through its remaining orders in one
+   kernel, a lane per packet, and walks the peel-off rays of all those orders
+   in one launch afterwards, instead of two launches per order.  Images differ
+   from the per-order launches only in the order of the FP64 sums, counters not
+   at all.  max_deferred bounds the peel-off rays held for that walk (0: as many
+   as the peel-ray buffer holds); rays beyond it are walked at once by the lane
+   that made them.  Used for exact peel-offs with one image set (not in the
+   surrogate mode, with per-order images or for batches); a first_order above
+   max_orders leaves every order to the per-order launches.  Joins pending
+   overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
+int qrt_set_tail(qrt_ctx *ctx, int first_order, uint64_t max_deferred);
+
 /* The context stream waits for every overlapped run still pending
    (asynchronous, like qrt_run). */
 int qrt_join(qrt_ctx *ctx);

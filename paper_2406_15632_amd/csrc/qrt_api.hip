@@ -116,6 +116,9 @@ struct qrt_ctx {
     int next_lane = 0;
     TransportBuffers tb1 = {};
     uint64_t tb1_packets = 0;
+    // late-order launch (qrt_set_tail): first order it takes, deferred-ray limit
+    int tail_from = kTailFrom;
+    uint64_t def_limit = 0;
 };
 
 namespace {
@@ -765,6 +768,8 @@ static void transport_params(const qrt_ctx *c, TransportParams &P)
     P.order_images = c->order_images;
     P.counters = c->counters;
     P.peel_mode = c->peel_mode;
+    P.tail_from = c->tail_from;
+    P.def_limit = c->def_limit;
     if (c->has_domain) {
         SurrogateParams &S = P.sur;
         S.in = input_map(c);
@@ -852,6 +857,19 @@ int qrt_set_overlap(qrt_ctx *c, int enable)
     DeviceGuard dg(c->device);
     join_lanes(c);
     c->overlap = enable != 0;
+    return QRT_OK;
+}
+
+int qrt_set_tail(qrt_ctx *c, int first_order, uint64_t max_deferred)
+{
+    if (!c) return QRT_INVALID_ARG;
+    if (first_order != 0 && first_order < 2)
+        return fail(c, QRT_INVALID_ARG, "the late-order launch starts at order 2 or later (0: off), not %d",
+                    first_order);
+    DeviceGuard dg(c->device);
+    join_lanes(c);
+    c->tail_from = first_order;
+    c->def_limit = max_deferred;
     return QRT_OK;
 }
 

@@ -185,7 +185,14 @@ struct TransportParams {
     unsigned long long *counters;  // [kCounterCopies][kCounterLine]
     int peel_mode;                 // 0 exact traversal, 1 surrogate inside its valid cells
     SurrogateParams sur;
+    int tail_from;                 // first order of the late-order launch (0: every order has its own launches)
+    uint64_t def_limit;            // at most this many deferred peel rays (0: as many as the buffer holds)
 };
+
+// First scattering order that the late-order launch takes over by default:
+// from it on the live packets are few, and per-order launches would each wait
+// for their longest walk at low occupancy.
+constexpr int kTailFrom = 4;
 
 // one training batch of the surrogate network
 struct MlpBatch {
@@ -231,6 +238,9 @@ struct Queues {
     // appended peel rays per order parity and group (batched launches), one
     // counter per 128-byte line so that the groups' atomics do not share one
     uint32_t n_peel[2][kPeelGroups][32];
+    // peel rays deferred by the late-order launch, per region of the peel-ray
+    // buffer (one region per work-pool part), one counter per 128-byte line
+    uint32_t n_def[8][32];
 };
 
 // A peel-off ray queued for the surrogate network: its network inputs, the

@@ -554,11 +554,49 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
+// The peel rays deferred by the late-order launch lie in kPoolParts regions of
+// def_cap rays each, region r holding min(n_def[r], def_cap) of them: item i of
+// a walk over all of them is ray i - start[r] of the region r with
+// start[r] <= i < end[r].
+struct DeferredRays {
+    uint64_t end[kPoolParts];
+    uint32_t cap;
+};
+
+__device__ __forceinline__ DeferredRays deferred_rays(const Queues *Q, uint32_t def_cap)
+{
+    DeferredRays d;
+    d.cap = def_cap;
+    uint64_t acc = 0;
+    for (int r = 0; r < kPoolParts; ++r) {
+        const uint32_t n = Q->n_def[r][0];
+        acc += n < def_cap ? n : def_cap;
+        d.end[r] = acc;
+    }
+    return d;
+}
+
+__device__ __forceinline__ uint64_t deferred_slot(const DeferredRays &d, uint64_t item)
+{
+    uint64_t start = 0, slot = 0;
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < kPoolParts; ++r) {
+        const bool here = !found && item < d.end[r];
+        slot = here ? (uint64_t)r * d.cap + (item - start) : slot;
+        found = found || here;
+        start = d.end[r];
+    }
+    return slot;
+}
+
+// def_cap > 0: the launch walks the peel rays deferred by the late-order
+// launch (and no flights); else the peel rays and flights of one order.
 template <typename R>
 __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
-                                              Queues *__restrict__ Q)
+                                              Queues *__restrict__ Q, uint32_t def_cap)
 {
     __shared__ R s_o[kMaxObs][3];
     __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
@@ -567,8 +605,9 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     __syncthreads();
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
-    const uint64_t n_move = order < P.max_orders ? n_live : 0;
+    const DeferredRays D = deferred_rays(Q, def_cap);
+    const uint64_t n_peel = def_cap ? D.end[kPoolParts - 1] : (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t n_move = !def_cap && order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
@@ -619,7 +658,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
         if (pool.take(kind == WI_NONE, total, &Q->work[1][0][0], item)) {
             item = scatter_block(item, total, stride);
             if (item < n_peel) {
-                const PeelRay<R> r = peels[item];
+                const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : item];
                 if (r.pix != kNoPixel) {
                     const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
                     c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
@@ -672,7 +711,7 @@ constexpr int kPeelLdsThreads = 1024;
 template <typename R>
 __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const TransportParams P, int order, int in,
                                                                   const PeelRay<R> *__restrict__ peels,
-                                                                  Queues *__restrict__ Q)
+                                                                  Queues *__restrict__ Q, uint32_t def_cap)
 {
     extern __shared__ double tile[];   // [n_obs][3][npix][npix]
     __shared__ R s_o[kMaxObs][3];
@@ -684,7 +723,8 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
     __syncthreads();
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t total = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const DeferredRays D = deferred_rays(Q, def_cap);
+    const uint64_t total = def_cap ? D.end[kPoolParts - 1] : (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     uint64_t n_visits = 0;
     uint32_t n_peels = 0;
@@ -708,7 +748,7 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
         uint64_t item = 0;
         if (pool.take(!busy, total, &Q->work[1][0][0], item)) {
             item = scatter_block(item, total, stride);
-            const PeelRay<R> r = peels[item];
+            const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : item];
             if (r.pix != kNoPixel) {
                 const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
                 c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
@@ -736,6 +776,151 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
         if (v != 0.0) unsafeAtomicAdd(img_copy + i, v);
     }
     flush_counters<3>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS}, {n_visits, n_peels, n_peels});
+}
+
+// --------------------------------------------------------------------------
+// late orders in one launch
+// --------------------------------------------------------------------------
+// Scattering orders order0 .. max_orders of the packets live after order
+// order0 - 1, in one launch.  A lane takes a packet and carries it through its
+// remaining orders: scattering (albedo, the peel-off contributions, the new
+// direction and flight depth, as k_scatter computes them), then its flight (as
+// k_walk walks it), then the next scattering where the flight stopped inside
+// the mesh.  The visible peel-off rays are not walked here: each wave appends
+// them to the peel-ray buffer region of its block's work-pool part (one atomic
+// per wave and observer), and one k_walk launch over every region walks them
+// afterwards, so no order waits for the longest walk of the one before.  A
+// wave whose region is full walks its rays itself, to the edge, before the
+// flight.  The per-order launches would run these orders at low occupancy,
+// each ended by its longest walk; here a packet's chain of flights is the
+// longest wait.  Lanes go back to the pool as their packets end (coherence
+// among the few late packets is low anyway): a wave stops walking once half
+// of its flights have ended.  Every packet gets the arithmetic of the
+// per-order launches, so images differ only in the order of the FP64 sums.
+template <typename R, int KIND, int SRC>
+__global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
+                                              const PacketState<R> *__restrict__ pks, int in,
+                                              PeelRay<R> *__restrict__ peels, uint32_t def_cap,
+                                              Queues *__restrict__ Q)
+{
+    __shared__ ObsTable<R> T;
+    load_obs(P, T);
+    // the pool of the walk of the deferred rays starts at zero (the walk of
+    // order order0 - 1, its last user, has ended)
+    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) Q->work[1][threadIdx.x][0] = 0;
+    const RayGrid<R> G = ray_grid<R>(P.grid);
+    const SceneView<R> V = scene_view<R>(P, SRC);
+    const uint64_t n = Q->n_live[in];
+    const size_t plane = (size_t)P.npix * (size_t)P.npix;
+    double *img_copy = image_copy(P, order0, plane);
+    const int region = (int)(blockIdx.x % kPoolParts);
+    PeelRay<R> *reg = peels + (size_t)region * def_cap;
+    uint32_t *reg_n = &Q->n_def[region][0];
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t n_visits = 0;
+    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0;
+    PacketState<R> s = {};
+    int order = 0;
+    bool has = false, moving = false, at_scatter = false;
+    Walk<R> W = {};
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        // flights that ended: scatter where they stopped, or the packet left
+        if (moving && W.done) {
+            n_visits += W.visits;
+            if (W.stopped) {
+                for (int a = 0; a < 3; ++a) s.p[a] = s.p[a] + W.t_out * s.k[a];
+                ++order;
+                at_scatter = true;
+            } else {
+                n_esc++;
+                has = false;
+            }
+            moving = false;
+        }
+        uint64_t item = 0;
+        if (pool.take(!has, n, &Q->work[2][0][0], item)) {
+            s = pks[item];
+            order = order0;
+            has = true;
+            at_scatter = true;
+        }
+        if (__ballot(has) == 0 && pool.dry) break;
+        if (__ballot(at_scatter) != 0) {
+            R n_ax[3] = {(R)0, (R)0, (R)0};
+            if (at_scatter) {
+                n_scat++;
+                s.S[0] *= V.albedo; s.S[1] *= V.albedo; s.S[2] *= V.albedo;
+                cross3(s.k, s.m, n_ax);
+            }
+            for (int ob = 0; ob < P.n_obs; ++ob) {
+                bool vis = false, occ = false;
+                R c3[3] = {(R)0, (R)0, (R)0};
+                uint32_t pix = 0;
+                const R o[3] = {T.o[ob][0], T.o[ob][1], T.o[ob][2]};
+                if (at_scatter) {
+                    const R ex[3] = {T.ex[ob][0], T.ex[ob][1], T.ex[ob][2]};
+                    const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
+                    peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
+                    n_occ += occ ? 1u : 0u;
+                }
+                const uint64_t m = __ballot(vis);
+                if (m == 0) continue;
+                const uint32_t cnt = (uint32_t)__popcll(m);
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(reg_n, cnt);
+                base = __shfl(base, 0, 64);
+                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below_mask());
+                PeelRay<R> r;
+                r.p[0] = s.p[0]; r.p[1] = s.p[1]; r.p[2] = s.p[2];
+                r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
+                r.obs = (uint32_t)ob;
+                if ((uint64_t)base + cnt <= (uint64_t)def_cap) {
+                    r.pix = pix;
+                    if (vis) reg[slot] = r;
+                } else {
+                    // region full: the reserved slots inside it are marked empty, and the
+                    // rays walked here (W is free: these lanes' flights have ended)
+                    r.pix = kNoPixel;
+                    if (vis && slot < def_cap) reg[slot] = r;
+                    if (vis) {
+                        walk_begin(W, G, s.p, o, WALK_EDGE, 0.0);
+                        walk_run<R, kFlightBatch>(W, G);
+                        n_visits += W.visits;
+                        n_peels++;
+                        const double att = exp(-W.tau);
+                        double *dst = img_copy + (size_t)ob * 3 * plane + pix;
+                        unsafeAtomicAdd(dst, att * (double)c3[0]);
+                        unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
+                        unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
+                    }
+                }
+            }
+            if (at_scatter) {
+                if (order < P.max_orders) {
+                    uint32_t x[3];
+                    seq_triple<KIND>(P.seq, s.idx, first_scatter_dim(SRC) + 3 * (order - 1), x);
+                    scatter_packet<R>(V, s, n_ax, x);
+                    walk_begin(W, G, s.p, s.k, WALK_MOVE, s.target);
+                    moving = true;
+                } else {
+                    has = false;   // the last order scatters without a flight
+                }
+                at_scatter = false;
+            }
+        }
+        const int movers = __popcll(__ballot(moving));
+        if (movers == 0) continue;
+        for (;;) {
+            // only lanes with a flight under way step (the call's own test of W.done
+            // alone gave visit counts that varied from run to run in this kernel)
+            if (moving && !W.done) walk_batch<R, kFlightBatch>(W, G);
+            if (2 * __popcll(__ballot(moving && W.done)) >= movers) break;
+        }
+    }
+    flush_counters<6>(P.counters, {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},
+                      {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels});
 }
 
 // Blocks and dynamic LDS bytes of k_walk_peel_lds for an image set of `bytes`,
@@ -812,12 +997,13 @@ template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
                             hipStream_t st, KernelTimer *T)
 {
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0, nb_tail = 0;
     if (!nb_first) {
         nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
         nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC, false>);
         nb_walk = resident_blocks_of(k_walk<R>);
         nb_net = resident_blocks_of(k_peel_net);
+        nb_tail = resident_blocks_of(k_tail<R, KIND, SRC>);
     }
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
@@ -840,7 +1026,12 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
     const size_t tile_bytes = (size_t)P.n_obs * 3 * (size_t)P.npix * (size_t)P.npix * sizeof(double);
-    for (int order = 1; order <= P.max_orders; ++order) {
+    // orders from `tail` on run in one launch, their peel rays deferred to one walk
+    // (exact peel-offs with one image set only)
+    const bool tail_on = P.tail_from >= 2 && P.tail_from <= P.max_orders && P.peel_mode == 0 && !P.sur.cap &&
+                         P.order_images == 0;
+    const int last = tail_on ? P.tail_from - 1 : P.max_orders;
+    for (int order = 1; order <= last; ++order) {
         const int in = (order - 1) & 1;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
@@ -869,11 +1060,36 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             TimedLaunch tl(T, st, TC_WALK);
             if (lds_blocks > 0)
                 hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
-                                   order, in, (const PeelRay<R> *)peels, B.q);
+                                   order, in, (const PeelRay<R> *)peels, B.q, 0u);
             else
                 hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
                                    (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                                   (const PeelRay<R> *)peels, B.q);
+                                   (const PeelRay<R> *)peels, B.q, 0u);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (tail_on) {
+        // the peel-ray buffer split into kPoolParts regions for the deferred rays
+        uint64_t cap = B.peel_bytes / sizeof(PeelRay<R>) / kPoolParts;
+        if (P.def_limit) cap = std::min<uint64_t>(cap, (P.def_limit + kPoolParts - 1) / kPoolParts);
+        const uint32_t def_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, 0xFFFFFFFFull / kPoolParts));
+        const int in = last & 1;   // the live list of order `tail`
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            hipLaunchKernelGGL((k_tail<R, KIND, SRC>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
+                               (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.q);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int lds_blocks = peel_lds_blocks<R>(tile_bytes);
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            if (lds_blocks > 0)
+                hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
+                                   P.max_orders, in, (const PeelRay<R> *)peels, B.q, def_cap);
+            else
+                hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, P.max_orders,
+                                   (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                                   (const PeelRay<R> *)peels, B.q, def_cap);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

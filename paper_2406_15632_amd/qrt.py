@@ -93,6 +93,7 @@ SIGNATURES = {
     "qrt_run": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
     "qrt_run_static": (C.c_int, [_P, C.c_uint64, C.c_uint64]),
     "qrt_set_overlap": (C.c_int, [_P, C.c_int]),
+    "qrt_set_tail": (C.c_int, [_P, C.c_int, C.c_uint64]),
     "qrt_join": (C.c_int, [_P]),
     "qrt_read_images": (C.c_int, [_P, C.c_int, _P, _P, _P, C.c_int]),
     "qrt_image_device_ptr": (C.c_int, [_P, C.POINTER(C.c_void_p)]),
@@ -261,6 +262,10 @@ class Context:
     def set_overlap(self, enable: bool):
         """Overlapped runs on two internal streams (see qrt_set_overlap)."""
         self._ck(self.lib.qrt_set_overlap(self.h, int(enable)))
+
+    def set_tail(self, first_order: int, max_deferred: int = 0):
+        """Late orders in one launch from first_order on (0: off; see qrt_set_tail)."""
+        self._ck(self.lib.qrt_set_tail(self.h, int(first_order), int(max_deferred)))
 
     def join(self):
         """The context stream waits for the overlapped runs still pending."""
