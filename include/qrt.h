@@ -182,9 +182,10 @@ int qrt_set_overlap(qrt_ctx *ctx, int enable);
    at all.  max_deferred bounds the peel-off rays held for that walk (0: as many
    as the peel-ray buffer holds); rays beyond it are walked at once by the lane
    that made them.  Used for exact peel-offs with one image set (not in the
-   surrogate mode, with per-order images or for batches); a first_order above
-   max_orders leaves every order to the per-order launches.  Joins pending
-   overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
+   surrogate mode or with per-order images) and for batches, where the orders
+   counted are those of the batch's deepest scene; a first_order above the
+   largest max_orders leaves every order to the per-order launches.  Joins
+   pending overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
 int qrt_set_tail(qrt_ctx *ctx, int first_order, uint64_t max_deferred);
 
 /* The context stream waits for every overlapped run still pending

@@ -1849,6 +1849,8 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     P.counters = c->counters;
     P.img_base = c->batch_img;
     P.img_key_bits = bits_for(c->batch_img_used);
+    P.tail_from = c->tail_from;
+    P.def_limit = c->def_limit;
     // the peel-ray buffer split into equal append regions (launch_batch checks that every chunk fits)
     const size_t peel_capacity = c->tb.peel_bytes / peel_ray_bytes(precision);
     P.group_cap = (uint32_t)std::min<size_t>(peel_capacity / kPeelGroups, 0xFFFFFFFFu);

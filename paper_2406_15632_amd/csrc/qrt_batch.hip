@@ -283,23 +283,28 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
 // ---------------------------------------------------------------- walks of one order
 enum BatchWalkItem : int { BW_NONE = 0, BW_PEEL = 1, BW_MOVE = 2 };
 
+// def_cap > 0: the launch walks the peel rays deferred by the late-order
+// launch (and no flights); else the peel rays and flights of one order.
 template <typename R>
 __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                                                const PacketState<R> *__restrict__ pks, int in,
                                                PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
-                                               Queues *__restrict__ Q)
+                                               Queues *__restrict__ Q, uint32_t def_cap)
 {
-    if (blockIdx.x == 0 && threadIdx.x < kPeelGroups) Q->n_peel[(order + 1) & 1][threadIdx.x][0] = 0;   // next scatter
+    if (!def_cap && blockIdx.x == 0 && threadIdx.x < kPeelGroups)
+        Q->n_peel[(order + 1) & 1][threadIdx.x][0] = 0;   // next scatter
     // peel rays of the groups, numbered one group after the other
     uint32_t g_count[kPeelGroups];
     uint64_t n_peel = 0;
 #pragma unroll
     for (int g = 0; g < kPeelGroups; ++g) {
-        g_count[g] = Q->n_peel[order & 1][g][0];
+        g_count[g] = def_cap ? 0u : Q->n_peel[order & 1][g][0];
         n_peel += g_count[g];
     }
+    const DeferredRays D = deferred_rays(Q, def_cap);
+    if (def_cap) n_peel = D.end[kPoolParts - 1];
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_move = order < P.max_orders ? n_live : 0;
+    const uint64_t n_move = !def_cap && order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
@@ -363,16 +368,20 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                     at -= past ? g_count[q] : 0;
                     g += past ? 1 : 0;
                 }
-                const PeelRay<R> r = peels[(uint64_t)g * P.group_cap + at];
-                s = (int)(r.obs >> 4);
-                obs = (int)(r.obs & 15u);
-                const BScene &S = P.scenes[s];
-                const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
-                c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
-                pix = r.pix;
-                G = lane_grid<R>(S);
-                walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
-                kind = BW_PEEL;
+                const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : (uint64_t)g * P.group_cap + at];
+                // appended rays are all visible; a deferred region can hold slots marked
+                // empty (reserved when the region was full)
+                if (r.pix != kNoPixel) {
+                    s = (int)(r.obs >> 4);
+                    obs = (int)(r.obs & 15u);
+                    const BScene &S = P.scenes[s];
+                    const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
+                    c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                    pix = r.pix;
+                    G = lane_grid<R>(S);
+                    walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                    kind = BW_PEEL;
+                }
             } else {
                 slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
@@ -406,6 +415,139 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
     flush_counters<4>(P.counters, {CNT_VISITS, CNT_PEELS, CNT_PEEL_RAYS, CNT_ESCAPES}, {n_visits, n_peels, n_peels, n_esc});
 }
 
+// ---------------------------------------------------------------- late orders in one launch
+// The batched form of k_tail (qrt_transport.hip): from order order0 on, a lane
+// carries each live packet through its scene's remaining orders (scattering as
+// k_bscatter, flight on the scene's mesh as k_bwalk); the visible peel rays go
+// to the deferred regions of the peel-ray buffer for one k_bwalk launch, or,
+// where a region is full, are walked at once by the lane.
+template <typename R, int KIND>
+__global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
+                                               const PacketState<R> *__restrict__ pks, int in,
+                                               PeelRay<R> *__restrict__ peels, uint32_t def_cap,
+                                               Queues *__restrict__ Q)
+{
+    // the pool of the walk of the deferred rays starts at zero (its last user, the
+    // walk of order order0 - 1, has ended)
+    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) Q->work[1][threadIdx.x][0] = 0;
+    const uint64_t n = Q->n_live[in];
+    const int region = (int)(blockIdx.x % kPoolParts);
+    PeelRay<R> *reg = peels + (size_t)region * def_cap;
+    uint32_t *reg_n = &Q->n_def[region][0];
+    const int lane = (int)(threadIdx.x & 63);
+    uint64_t n_visits = 0;
+    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0;
+    PacketState<R> st = {};
+    int s = 0, order = 0;
+    bool has = false, moving = false, at_scatter = false;
+    LaneGrid<R> G = {};
+    Walk<R> W = {};
+    W.done = true;
+    WorkPool pool;
+    for (;;) {
+        if (moving && W.done) {
+            n_visits += W.visits;
+            if (W.stopped) {
+                for (int a = 0; a < 3; ++a) st.p[a] = st.p[a] + W.t_out * st.k[a];
+                ++order;
+                at_scatter = true;
+            } else {
+                n_esc++;
+                has = false;
+            }
+            moving = false;
+        }
+        uint64_t item = 0;
+        if (pool.take(!has, n, &Q->work[2][0][0], item)) {
+            st = pks[item];
+            s = (int)st.next_dim;
+            order = order0;
+            has = true;
+            at_scatter = true;
+        }
+        if (__ballot(has) == 0 && pool.dry) break;
+        if (__ballot(at_scatter) != 0) {
+            const BScene &S = P.scenes[s];
+            const SceneView<R> V = scene_view<R>(S);
+            R n_ax[3] = {(R)0, (R)0, (R)0};
+            if (at_scatter) {
+                n_scat++;
+                st.S[0] *= V.albedo; st.S[1] *= V.albedo; st.S[2] *= V.albedo;
+                cross3(st.k, st.m, n_ax);
+                G = lane_grid<R>(S);
+            }
+            for (int ob = 0; ob < kBatchObs; ++ob) {
+                bool vis = false, occ = false;
+                R c3[3] = {(R)0, (R)0, (R)0};
+                uint32_t pix = 0;
+                R o[3] = {(R)0, (R)0, (R)1};
+                if (at_scatter && ob < S.n_obs) {
+                    const DevObserver &O = S.obs[ob];
+                    const R ex[3] = {(R)O.ex[0], (R)O.ex[1], (R)O.ex[2]};
+                    const R ey[3] = {(R)O.ey[0], (R)O.ey[1], (R)O.ey[2]};
+                    o[0] = (R)O.o[0]; o[1] = (R)O.o[1]; o[2] = (R)O.o[2];
+                    peel_contribution<R>(V, st, n_ax, o, ex, ey, vis, occ, c3, pix);
+                    n_occ += occ ? 1u : 0u;
+                }
+                const uint64_t m = __ballot(vis);
+                if (m == 0) continue;
+                const uint32_t cnt = (uint32_t)__popcll(m);
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(reg_n, cnt);
+                base = __shfl(base, 0, 64);
+                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below_mask());
+                PeelRay<R> r;
+                r.p[0] = st.p[0]; r.p[1] = st.p[1]; r.p[2] = st.p[2];
+                r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
+                r.obs = ((uint32_t)s << 4) | (uint32_t)ob;
+                if ((uint64_t)base + cnt <= (uint64_t)def_cap) {
+                    r.pix = pix;
+                    if (vis) reg[slot] = r;
+                } else {
+                    // region full: the reserved slots inside it are marked empty, and the
+                    // rays walked here (W is free: these lanes' flights have ended)
+                    r.pix = kNoPixel;
+                    if (vis && slot < def_cap) reg[slot] = r;
+                    if (vis) {
+                        walk_begin(W, G, st.p, o, WALK_EDGE, 0.0);
+                        walk_run<R, kFlightBatch>(W, G);
+                        n_visits += W.visits;
+                        n_peels++;
+                        const double att = exp(-W.tau);
+                        const size_t plane = (size_t)S.npix * (size_t)S.npix;
+                        double *dst = S.img + (size_t)(blockIdx.x % kImageCopies) * S.img_set +
+                                      (size_t)ob * 3 * plane + pix;
+                        unsafeAtomicAdd(dst, att * (double)c3[0]);
+                        unsafeAtomicAdd(dst + plane, att * (double)c3[1]);
+                        unsafeAtomicAdd(dst + 2 * plane, att * (double)c3[2]);
+                    }
+                }
+            }
+            if (at_scatter) {
+                if (order < S.max_orders) {
+                    uint32_t x[3];
+                    seq_triple<KIND>(scene_seq(P, S), st.idx, first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
+                    scatter_packet<R>(V, st, n_ax, x);
+                    walk_begin(W, G, st.p, st.k, WALK_MOVE, st.target);
+                    moving = true;
+                } else {
+                    has = false;   // the scene's last order scatters without a flight
+                }
+                at_scatter = false;
+            }
+        }
+        const int movers = __popcll(__ballot(moving));
+        if (movers == 0) continue;
+        for (;;) {
+            // only lanes with a flight under way step, as in k_tail
+            if (moving && !W.done) walk_batch<R, kFlightBatch>(W, G);
+            if (2 * __popcll(__ballot(moving && W.done)) >= movers) break;
+        }
+    }
+    flush_counters<6>(P.counters, {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},
+                      {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels});
+}
+
 // ---------------------------------------------------------------- launch sequence
 template <typename F>
 static int batch_resident_blocks(F kernel)
@@ -424,11 +566,12 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
                               hipStream_t st, KernelTimer *T)
 {
     // P.scene_base and P.scene_bits are set per chunk by launch_batch
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_tail = 0;
     if (!nb_first) {
         nb_first = batch_resident_blocks(k_bfirst<R, KIND>);
         nb_scatter = batch_resident_blocks(k_bscatter<R, KIND>);
         nb_walk = batch_resident_blocks(k_bwalk<R>);
+        nb_tail = batch_resident_blocks(k_btail<R, KIND>);
     }
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
@@ -449,7 +592,10 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int bs = (int)(cblocks < (uint32_t)nb_scatter ? cblocks : (uint32_t)nb_scatter);
-    for (int order = 1; order <= P.max_orders; ++order) {
+    // orders from `tail` on run in one launch, their peel rays deferred to one walk
+    const bool tail_on = P.tail_from >= 2 && P.tail_from <= P.max_orders;
+    const int last = tail_on ? P.tail_from - 1 : P.max_orders;
+    for (int order = 1; order <= last; ++order) {
         const int in = (order - 1) & 1;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
@@ -461,7 +607,27 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
             TimedLaunch tl(T, st, TC_WALK);
             hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order,
                                (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                               (const PeelRay<R> *)peels, B.q);
+                               (const PeelRay<R> *)peels, B.q, 0u);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (tail_on) {
+        // the peel-ray buffer split into kPoolParts regions for the deferred rays
+        uint64_t cap = B.peel_bytes / sizeof(PeelRay<R>) / kPoolParts;
+        if (P.def_limit) cap = std::min<uint64_t>(cap, (P.def_limit + kPoolParts - 1) / kPoolParts);
+        const uint32_t def_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, 0xFFFFFFFFull / kPoolParts));
+        const int in = last & 1;   // the live list of order `tail`
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            hipLaunchKernelGGL((k_btail<R, KIND>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
+                               (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.q);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        {
+            TimedLaunch tl(T, st, TC_WALK);
+            hipLaunchKernelGGL((k_bwalk<R>), dim3(nb_walk), dim3(256), 0, st, P, P.max_orders,
+                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                               (const PeelRay<R> *)peels, B.q, def_cap);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -331,6 +331,8 @@ struct BatchParams {
     unsigned long long *counters;  // [kCounterCopies][kCounterLine]
     double *img_base;           // all scenes' images, one after the other (scene images point into it)
     int img_key_bits;           // bits that hold an element offset from img_base
+    int tail_from;              // first order of the late-order launch (0: every order has its own launches)
+    uint64_t def_limit;         // at most this many deferred peel rays (0: as many as the buffer holds)
 };
 
 // Batch numbers b_first .. b_first+b_count-1 of a batch, in chunks of at most

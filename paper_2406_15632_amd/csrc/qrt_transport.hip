@@ -554,42 +554,6 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
-// The peel rays deferred by the late-order launch lie in kPoolParts regions of
-// def_cap rays each, region r holding min(n_def[r], def_cap) of them: item i of
-// a walk over all of them is ray i - start[r] of the region r with
-// start[r] <= i < end[r].
-struct DeferredRays {
-    uint64_t end[kPoolParts];
-    uint32_t cap;
-};
-
-__device__ __forceinline__ DeferredRays deferred_rays(const Queues *Q, uint32_t def_cap)
-{
-    DeferredRays d;
-    d.cap = def_cap;
-    uint64_t acc = 0;
-    for (int r = 0; r < kPoolParts; ++r) {
-        const uint32_t n = Q->n_def[r][0];
-        acc += n < def_cap ? n : def_cap;
-        d.end[r] = acc;
-    }
-    return d;
-}
-
-__device__ __forceinline__ uint64_t deferred_slot(const DeferredRays &d, uint64_t item)
-{
-    uint64_t start = 0, slot = 0;
-    bool found = false;
-#pragma unroll
-    for (int r = 0; r < kPoolParts; ++r) {
-        const bool here = !found && item < d.end[r];
-        slot = here ? (uint64_t)r * d.cap + (item - start) : slot;
-        found = found || here;
-        start = d.end[r];
-    }
-    return slot;
-}
-
 // def_cap > 0: the launch walks the peel rays deferred by the late-order
 // launch (and no flights); else the peel rays and flights of one order.
 template <typename R>

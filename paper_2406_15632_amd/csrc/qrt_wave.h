@@ -178,6 +178,42 @@ __host__ __device__ inline uint64_t scatter_block(uint64_t item, uint64_t total,
     return (((b * stride) % nfull) << kOrderBlockLog2) | (item & (kOrderBlock - 1));
 }
 
+// The peel rays deferred by the late-order launch lie in kPoolParts regions of
+// def_cap rays each, region r holding min(n_def[r], def_cap) of them: item i of
+// a walk over all of them is ray i - start[r] of the region r with
+// start[r] <= i < end[r].
+struct DeferredRays {
+    uint64_t end[kPoolParts];
+    uint32_t cap;
+};
+
+__device__ __forceinline__ DeferredRays deferred_rays(const Queues *Q, uint32_t def_cap)
+{
+    DeferredRays d;
+    d.cap = def_cap;
+    uint64_t acc = 0;
+    for (int r = 0; r < kPoolParts; ++r) {
+        const uint32_t n = Q->n_def[r][0];
+        acc += n < def_cap ? n : def_cap;
+        d.end[r] = acc;
+    }
+    return d;
+}
+
+__device__ __forceinline__ uint64_t deferred_slot(const DeferredRays &d, uint64_t item)
+{
+    uint64_t start = 0, slot = 0;
+    bool found = false;
+#pragma unroll
+    for (int r = 0; r < kPoolParts; ++r) {
+        const bool here = !found && item < d.end[r];
+        slot = here ? (uint64_t)r * d.cap + (item - start) : slot;
+        found = found || here;
+        start = d.end[r];
+    }
+    return slot;
+}
+
 // orders the wave's LDS accesses before and after this point
 __device__ __forceinline__ void wave_lds_sync()
 {

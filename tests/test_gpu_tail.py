@@ -126,3 +126,28 @@ def test_tail_sphere_star_and_off_cases(ctx, Q):
     for bad in (1, -1):
         with pytest.raises(Q.QRTError):
             ctx.set_tail(bad)
+
+
+def test_batch_tail_equals_per_order_launches(ctx, Q):
+    """Twelve uneven scenes (1 to 12 orders, 1 to 4 observers, envelopes and
+    disks, point sources and stars) in one batch, FP32: the late-order launch
+    from order 2 and from order 5, and from order 2 with at most 128 deferred
+    rays, against every order launched on its own; per scene images up to the
+    order of the sums, counters equal."""
+    bs = scenes.uneven_batch(31, 12, sizes=(32, 64, 16), log2_packets=(14.0, 16.0), npix=64, orders=(1, 12))
+    assert max(sc.max_orders for sc in bs) >= 5
+
+    def batch(tail, limit=0):
+        ctx.set_tail(tail, limit)
+        ctx.batch_set(bs)
+        ctx.batch_reset()
+        ctx.batch_run(Q.SOBOL, 0, Q.FP32)
+        return [ctx.batch_read_images(i, normalized=False) for i in range(len(bs))], ctx.counters()
+    _say("batch tail: per-order reference")
+    ref, cref = batch(0)
+    for tail, limit in ((2, 0), (5, 0), (2, 128)):
+        _say(f"batch tail from {tail}, deferred limit {limit}")
+        img, cnt = batch(tail, limit)
+        assert cnt == cref, f"tail {tail} limit {limit}"
+        for i in range(len(bs)):
+            assert_sum_order_equal(img[i], ref[i], f"scene {i} tail {tail} limit {limit}")
