@@ -181,11 +181,14 @@ int qrt_set_overlap(qrt_ctx *ctx, int enable);
    from the per-order launches only in the order of the FP64 sums, counters not
    at all.  max_deferred bounds the peel-off rays held for that walk (0: as many
    as the peel-ray buffer holds); rays beyond it are walked at once by the lane
-   that made them.  Used for exact peel-offs with one image set (not in the
-   surrogate mode or with per-order images) and for batches, where the orders
-   counted are those of the batch's deepest scene; a first_order above the
-   largest max_orders leaves every order to the per-order launches.  Joins
-   pending overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
+   that made them.  In the surrogate mode the late orders' network queries
+   are deferred the same way, to one network launch (as many as the query
+   queue holds; a query beyond that walks exactly and counts as a
+   fall-back).  Used with one image set (not with per-order images), and for
+   batches, where the orders counted are those of the batch's deepest scene;
+   a first_order above the largest max_orders leaves every order to the
+   per-order launches.  Joins pending overlapped runs.  QRT_INVALID_ARG for
+   first_order 1 or below 0. */
 int qrt_set_tail(qrt_ctx *ctx, int first_order, uint64_t max_deferred);
 
 /* The context stream waits for every overlapped run still pending
@@ -356,10 +359,13 @@ int qrt_surrogate_inputs(qrt_ctx *ctx, int64_t n, const float *pos_obs, float *X
 /* Training samples from a pilot run: Philox packets (key seed) of the current
    scene, exact peel-off, chunk by chunk until n visible peel-off rays inside
    the domain are captured; of all captured rays the n with the smallest hash
-   of their bytes are kept (a reproducible uniform subsample).  Labels are the
-   exact FP64 optical depths toward the observer.  pos_obs[n][4] and tau[n]
-   are device pointers; *pilot_packets (may be NULL) gets the packets run.
-   Resets the images and counters.  Synchronous; 1 <= n <= 2^26. */
+   of their bytes and the seed are kept (a reproducible uniform subsample;
+   rays whose 64-bit hashes collide keep the order of their capture).  Labels
+   are the exact FP64 optical depths toward the observer.  Capture, selection
+   (a device radix sort) and labels run on the device; only the per-chunk
+   capture count comes back to the host.  pos_obs[n][4] and tau[n] are device
+   pointers; *pilot_packets (may be NULL) gets the packets run.  Resets the
+   images and counters.  Synchronous; 1 <= n <= 2^26. */
 int qrt_surrogate_sample(qrt_ctx *ctx, int64_t n, uint64_t seed, float *pos_obs, float *tau,
                          int64_t *pilot_packets);
 
@@ -376,7 +382,9 @@ int qrt_surrogate_train(qrt_ctx *ctx, int64_t n, const float *pos_obs, const flo
    over them is at most max_err, where T_floor = floor_frac times the mean
    transmission of that observer's samples in the domain (floor_frac = 0: the
    plain relative error; a floor keeps cells whose light is too faint to
-   matter from failing on their relative error alone).
+   matter from failing on their relative error alone).  The sums run on the
+   device in fixed point (each term rounded to 2^-40 or coarser for very large
+   n), so the mask does not depend on the order of the additions.
    Device sample buffers; rep may be NULL.  Synchronous. */
 int qrt_surrogate_validate(qrt_ctx *ctx, int64_t n, const float *pos_obs, const float *tau, double max_err,
                            double floor_frac, int64_t min_count, qrt_mask_report *rep);

@@ -21,7 +21,8 @@ LIB = os.path.join(PKG, "libqrt.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["qrt_api.hip", "qrt_transport.hip", "qrt_batch.hip", "qrt_points.hip", "qrt_mlp.hip", "qrt_tables.cpp"]
+SOURCES = ["qrt_api.hip", "qrt_transport.hip", "qrt_batch.hip", "qrt_points.hip", "qrt_mlp.hip", "qrt_sample.hip",
+           "qrt_tables.cpp"]
 
 COMMON = [
     "-O3", "-std=c++17", "-fPIC",

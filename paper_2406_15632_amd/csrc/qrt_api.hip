@@ -1157,19 +1157,6 @@ static int ensure_train_x(qrt_ctx *c, size_t n)
 }
 
 // host copy of the domain cell rule used by the kernels
-static int host_dom_cell(const qrt_ctx *c, double x, double y, double z)
-{
-    const double dx = x - c->dom_center[0], dy = y - c->dom_center[1], dz = z - c->dom_center[2];
-    const double R = sqrt(dx * dx + dy * dy);
-    if (!(R >= c->dom_r_in && R < c->dom_r_out)) return -1;
-    const double zh = dz / (c->dom_h0 * pow(R, c->dom_beta));
-    if (!(fabs(zh) < c->dom_zmax)) return -1;
-    const int ir = (int)floor((R - c->dom_r_in) / (c->dom_r_out - c->dom_r_in) * (double)c->dom_nr);
-    const int iz = (int)floor((zh + c->dom_zmax) / (2.0 * c->dom_zmax) * (double)c->dom_nz);
-    if (ir < 0 || ir >= c->dom_nr || iz < 0 || iz >= c->dom_nz) return -1;
-    return ir * c->dom_nz + iz;
-}
-
 int qrt_mlp_set_params(qrt_ctx *c, const float *params, int64_t n)
 {
     if (!c) return QRT_INVALID_ARG;
@@ -1330,95 +1317,67 @@ int qrt_surrogate_sample(qrt_ctx *c, int64_t n, uint64_t seed, float *pos_obs, f
     const uint64_t capacity = chunk * per_packet;
     rc = ensure_queues(c, chunk, c->n_obs, c->precision);
     if (rc) return rc;
-    float *cap = nullptr;
+    // the pilot's captured rays stay on the device: each chunk appends to `all`
+    // (room for the n wanted plus one chunk's capacity), then the selection,
+    // the labels and the copies to the caller's buffers run there too
+    const uint64_t want = (uint64_t)n, all_cap = want + capacity;
+    float *all = nullptr;
     uint32_t *cap_count = nullptr;
     double *pk = nullptr, *tau64 = nullptr;
-    std::vector<float> all;
-    uint64_t first = 1;
+    void *temp = nullptr;
+    auto release = [&]() {
+        if (all) (void)hipFree(all);
+        if (cap_count) (void)hipFree(cap_count);
+        if (pk) (void)hipFree(pk);
+        if (tau64) (void)hipFree(tau64);
+        if (temp) (void)hipFree(temp);
+    };
+    uint64_t m = 0, first = 1;
     int save_mode = c->peel_mode;
-    hipError_t e = hipMalloc(&cap, capacity * 4 * sizeof(float));
+    hipError_t e = hipMalloc(&all, all_cap * 4 * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&cap_count, sizeof(uint32_t));
     TransportParams P;
     c->peel_mode = QRT_PEEL_EXACT;
     transport_params(c, P);
     c->peel_mode = save_mode;
     P.seq = seq_params(c, QRT_PHILOX, seed, 0);
-    P.sur.cap = cap;
     P.sur.cap_count = cap_count;
     P.sur.cap_capacity = (uint32_t)capacity;
     // pilot: chunks of Philox packets until enough in-domain peel rays are captured
-    while (e == hipSuccess && all.size() < (size_t)n * 4) {
+    while (e == hipSuccess && m < want) {
         if (first > (1ull << 36)) {
-            (void)hipFree(cap);
-            (void)hipFree(cap_count);
+            release();
             return fail(c, QRT_UNSUPPORTED, "the pilot finds too few peel-off rays inside the domain");
         }
         uint32_t got = 0;
+        P.sur.cap = all + m * 4;
         e = hipMemsetAsync(cap_count, 0, sizeof(uint32_t), c->stream);
         if (e == hipSuccess) e = launch_transport(P, c->precision, QRT_PHILOX, first, chunk, c->tb, c->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(&got, cap_count, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) break;
-        if (got > capacity) got = (uint32_t)capacity;   // cannot happen: capacity bounds every chunk
-        const size_t old = all.size();
-        all.resize(old + (size_t)got * 4);
-        e = hipMemcpy(all.data() + old, cap, (size_t)got * 4 * sizeof(float), hipMemcpyDeviceToHost);
+        m += got < capacity ? got : capacity;   // the capture stops at the chunk's capacity
         first += chunk;
     }
-    (void)hipFree(cap);
-    (void)hipFree(cap_count);
-    if (e != hipSuccess) return hip_fail(c, e, "pilot run");
-    // canonical order: sort the captured rays by a hash of their bytes, keep the first n
-    const size_t m = all.size() / 4;
-    std::vector<std::pair<uint64_t, uint32_t>> key(m);
-    for (size_t i = 0; i < m; ++i) {
-        uint64_t a, b;
-        memcpy(&a, &all[4 * i], 8);
-        memcpy(&b, &all[4 * i + 2], 8);
-        uint64_t st = a ^ (b * 0xD6E8FEB86659FD93ull) ^ seed;
-        key[i] = {host_splitmix64(st), (uint32_t)i};
+    if (e != hipSuccess) {
+        release();
+        return hip_fail(c, e, "pilot run");
     }
-    std::sort(key.begin(), key.end(), [&](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
-        if (x.first != y.first) return x.first < y.first;
-        return memcmp(&all[4 * (size_t)x.second], &all[4 * (size_t)y.second], 16) < 0;
-    });
-    std::vector<float> sel((size_t)n * 4);
-    std::vector<double> pk_h((size_t)n * 6);
-    for (int64_t j = 0; j < n; ++j) {
-        const float *r = &all[4 * (size_t)key[(size_t)j].second];
-        memcpy(&sel[4 * (size_t)j], r, 16);
-        int ob = (int)r[3];
-        ob = ob < 0 ? 0 : (ob >= c->n_obs ? c->n_obs - 1 : ob);
-        const double st = sin(c->theta[ob]), ct = cos(c->theta[ob]), sp = sin(c->phi[ob]), cp = cos(c->phi[ob]);
-        double *q = &pk_h[6 * (size_t)j];
-        q[0] = r[0]; q[1] = r[1]; q[2] = r[2];
-        q[3] = st * cp; q[4] = st * sp; q[5] = ct;
-    }
-    // labels: exact optical depth toward the observer (FP64 traversal)
-    e = hipMalloc(&pk, (size_t)n * 6 * sizeof(double));
+    // canonical order: the captured rays sorted by a hash of their bytes, the first n kept
+    std::vector<DevObserver> obs((size_t)c->n_obs);
+    for (int i = 0; i < c->n_obs; ++i) obs[(size_t)i] = dev_observer(c->theta[i], c->phi[i]);
+    e = hipMalloc(&temp, sample_select_temp_bytes(m));
+    if (e == hipSuccess) e = hipMalloc(&pk, (size_t)n * 6 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&tau64, (size_t)n * sizeof(double));
-    std::vector<double> t64((size_t)n);
-    std::vector<double> p_h((size_t)n * 3), k_h((size_t)n * 3);
-    for (int64_t j = 0; j < n; ++j)
-        for (int a = 0; a < 3; ++a) {
-            p_h[3 * (size_t)j + a] = pk_h[6 * (size_t)j + a];
-            k_h[3 * (size_t)j + a] = pk_h[6 * (size_t)j + 3 + a];
-        }
-    if (e == hipSuccess) e = hipMemcpy(pk, p_h.data(), (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = hipMemcpy(pk + (size_t)n * 3, k_h.data(), (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice);
+        e = launch_sample_select(all, m, (uint64_t)n, seed, obs.data(), c->n_obs, temp, pos_obs, pk, c->stream);
+    // labels: exact optical depth toward the observer (FP64 traversal)
     if (e == hipSuccess)
         e = launch_trace_tau(dev_grid(c), QRT_FP64, n, pk, pk + (size_t)n * 3, tau64, nullptr, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(t64.data(), tau64, (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
-                                            c->stream);
+    if (e == hipSuccess) e = launch_to_float(tau64, tau, (uint64_t)n, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(pk);
-    (void)hipFree(tau64);
-    if (e != hipSuccess) return hip_fail(c, e, "pilot labels");
-    std::vector<float> t32((size_t)n);
-    for (int64_t j = 0; j < n; ++j) t32[(size_t)j] = (float)t64[(size_t)j];
-    HIP_TRY(c, hipMemcpy(pos_obs, sel.data(), (size_t)n * 4 * sizeof(float), hipMemcpyHostToDevice), "sample copy");
-    HIP_TRY(c, hipMemcpy(tau, t32.data(), (size_t)n * sizeof(float), hipMemcpyHostToDevice), "label copy");
+    release();
+    if (e != hipSuccess) return hip_fail(c, e, "pilot samples");
     if (pilot_packets) *pilot_packets = (int64_t)(first - 1);
     return qrt_reset_images(c);
 }
@@ -1512,67 +1471,38 @@ int qrt_surrogate_validate(qrt_ctx *c, int64_t n, const float *pos_obs, const fl
     DeviceGuard dg(c->device);
     int rc = ensure_train_x(c, (size_t)n);
     if (rc) return rc;
-    float *y = nullptr;
-    HIP_TRY(c, hipMalloc(&y, (size_t)n * sizeof(float)), "prediction buffer");
-    std::vector<float> hp((size_t)n * 4), ht((size_t)n), hy((size_t)n);
-    hipError_t e = launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), c->train_x, c->stream);
-    if (e == hipSuccess) e = launch_mlp_forward(c->mlp, c->tiles, c->train_x, (uint64_t)n, y, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hy.data(), y, (size_t)n * sizeof(float), hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(hp.data(), pos_obs, (size_t)n * 16, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ht.data(), tau, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    (void)hipFree(y);
-    if (e != hipSuccess) return hip_fail(c, e, "validation");
+    // network outputs, then the per-cell sums, the mask and the report on the device
     const size_t cells = (size_t)c->dom_nr * c->dom_nz;
     const size_t total = (size_t)c->n_obs * cells;
-    std::vector<double> num(total, 0.0), den(total, 0.0);
-    std::vector<int64_t> cnt(total, 0);
-    std::vector<int> cell_of((size_t)n, -1);
-    // mean transmission per observer over the samples inside the domain
-    std::vector<double> t_sum((size_t)c->n_obs, 0.0), t_cnt((size_t)c->n_obs, 0.0);
-    int64_t inside = 0;
-    for (int64_t j = 0; j < n; ++j) {
-        const float *r = &hp[4 * (size_t)j];
-        const int ob = (int)r[3];
-        if (ob < 0 || ob >= c->n_obs) continue;
-        const int cell = host_dom_cell(c, r[0], r[1], r[2]);
-        if (cell < 0) continue;
-        cell_of[(size_t)j] = cell;
-        inside++;
-        t_sum[(size_t)ob] += exp(-(double)ht[(size_t)j]);
-        t_cnt[(size_t)ob] += 1.0;
-    }
-    for (int64_t j = 0; j < n; ++j) {
-        const int cell = cell_of[(size_t)j];
-        if (cell < 0) continue;
-        const int ob = (int)hp[4 * (size_t)j + 3];
-        const double floor_t = floor_frac * t_sum[(size_t)ob] / t_cnt[(size_t)ob];
-        const double T = exp(-(double)ht[(size_t)j]);
-        const double Th = exp(-(double)(hy[(size_t)j] > 0.0f ? hy[(size_t)j] : 0.0f));
-        const size_t k = (size_t)ob * cells + (size_t)cell;
-        num[k] += fabs(Th - T);
-        den[k] += T > floor_t ? T : floor_t;
-        cnt[k]++;
-    }
-    std::vector<uint8_t> mask(total, 0);
-    int64_t valid_cells = 0, samples_valid = 0;
-    double worst = 0.0;
-    for (size_t k = 0; k < total; ++k) {
-        if (cnt[k] >= min_count && den[k] > 0.0 && num[k] <= max_err * den[k]) {
-            mask[k] = 1;
-            valid_cells++;
-            samples_valid += cnt[k];
-            worst = std::max(worst, num[k] / den[k]);
-        }
-    }
-    HIP_TRY(c, hipMemcpyAsync(c->dom_valid, mask.data(), total, hipMemcpyHostToDevice, c->stream), "mask copy");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "mask sync");
+    SurrogateParams S = {};
+    S.in = input_map(c);
+    S.r_in = c->dom_r_in;
+    S.n_r = c->dom_nr;
+    S.n_z = c->dom_nz;
+    float *y = nullptr;
+    void *work = nullptr;
+    uint64_t *rep_d = nullptr, rep_h[5] = {0, 0, 0, 0, 0};
+    hipError_t e = hipMalloc(&y, (size_t)n * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&work, validate_work_bytes(c->n_obs, cells));
+    if (e == hipSuccess) e = hipMalloc(&rep_d, sizeof(rep_h));
+    if (e == hipSuccess) e = launch_mlp_inputs(pos_obs, (uint64_t)n, input_map(c), c->train_x, c->stream);
+    if (e == hipSuccess) e = launch_mlp_forward(c->mlp, c->tiles, c->train_x, (uint64_t)n, y, c->stream);
+    if (e == hipSuccess)
+        e = launch_validate(S, c->n_obs, (uint64_t)n, pos_obs, tau, y, max_err, floor_frac, min_count, work,
+                            c->dom_valid, rep_d, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(rep_h, rep_d, sizeof(rep_h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (y) (void)hipFree(y);
+    if (work) (void)hipFree(work);
+    if (rep_d) (void)hipFree(rep_d);
+    if (e != hipSuccess) return hip_fail(c, e, "validation");
     if (rep) {
         rep->cells = (int64_t)total;
-        rep->valid_cells = valid_cells;
-        rep->samples = inside;
-        rep->samples_valid = samples_valid;
+        rep->valid_cells = (int64_t)rep_h[1];
+        rep->samples = (int64_t)rep_h[2];
+        rep->samples_valid = (int64_t)rep_h[3];
+        double worst = 0.0;
+        memcpy(&worst, &rep_h[4], sizeof(worst));
         rep->max_err_valid = worst;
     }
     return QRT_OK;

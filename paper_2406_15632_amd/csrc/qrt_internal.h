@@ -168,6 +168,21 @@ struct SurrogateParams {
     uint32_t cap_capacity;
 };
 
+// cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
+__device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
+{
+    const InputMap &D = S.in;
+    const double dx = x - D.center[0], dy = y - D.center[1], dz = z - D.center[2];
+    const double R = sqrt(dx * dx + dy * dy);
+    if (!(R >= S.r_in && R < D.r_out)) return -1;
+    const double zh = dz / (D.h0 * pow(R, D.beta));
+    if (!(fabs(zh) < D.zmax)) return -1;
+    const int ir = (int)floor((R - S.r_in) / (D.r_out - S.r_in) * (double)S.n_r);
+    const int iz = (int)floor((zh + D.zmax) / (2.0 * D.zmax) * (double)S.n_z);
+    if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
+    return ir * S.n_z + iz;
+}
+
 struct TransportParams {
     DevGrid grid;
     int src_kind;            // 0 point, 1 sphere star (direct order), 2 sphere star (inverse order)
@@ -241,6 +256,9 @@ struct Queues {
     // peel rays deferred by the late-order launch, per region of the peel-ray
     // buffer (one region per work-pool part), one counter per 128-byte line
     uint32_t n_def[8][32];
+    // network queries deferred by the late-order launch (surrogate mode), per
+    // region of the query queue, one counter per 128-byte line
+    uint32_t n_sdef[8][32];
 };
 
 // A peel-off ray queued for the surrogate network: its network inputs, the
@@ -381,5 +399,29 @@ hipError_t launch_points(const SeqParams &S, int kind, uint64_t first, uint64_t 
 
 hipError_t launch_trace_tau(const DevGrid &g, int precision, int64_t n, const double *p,
                             const double *k, double *tau, int64_t *visits, hipStream_t stream);
+
+// Surrogate training data (qrt_sample.hip).  Canonical selection: the m
+// captured rays (x, y, z, observer) sorted by a hash of their 16 bytes and the
+// seed, the first n kept in that order (out), with their start points and
+// observer directions as FP64 (pk: [n][3] points, then [n][3] directions) for
+// the exact labels.  temp: scratch of sample_select_temp_bytes(m) bytes.
+size_t sample_select_temp_bytes(uint64_t m);
+hipError_t launch_sample_select(const float *rays, uint64_t m, uint64_t n, uint64_t seed, const DevObserver *obs,
+                                int n_obs, void *temp, float *out, double *pk, hipStream_t st);
+// labels: tau32[j] = (float)tau64[j]
+hipError_t launch_to_float(const double *src, float *dst, uint64_t n, hipStream_t st);
+
+// Validity mask from validation samples (pos_obs [n][4], exact tau, network
+// output y): per cell (observer, R bin, z bin) the sums of |exp(-max(y,0)) -
+// exp(-tau)| and of max(exp(-tau), floor_frac * mean transmission of the
+// observer) over its samples in fixed point (so that the sums do not depend
+// on their order), and the count; mask[k] = count >= min_count, den > 0 and
+// num <= max_err den.  rep (device, 5 words): cells, valid cells, samples in
+// the domain, samples in valid cells, worst valid num/den as FP64 bits.
+hipError_t launch_validate(const SurrogateParams &S, int n_obs, uint64_t n, const float *pos_obs, const float *tau,
+                           const float *y, double max_err, double floor_frac, int64_t min_count, void *work,
+                           uint8_t *mask, uint64_t *rep, hipStream_t st);
+// bytes of the work buffer of launch_validate
+size_t validate_work_bytes(int n_obs, size_t cells);
 
 }  // namespace qrt

@@ -351,21 +351,6 @@ __device__ __forceinline__ double *image_copy(const TransportParams &P, int orde
 // the network gives the optical depth to the observer
 // --------------------------------------------------------------------------
 
-// cell ir * n_z + iz of a position in the cylindrical domain, -1 outside
-__device__ __forceinline__ int dom_cell(const SurrogateParams &S, double x, double y, double z)
-{
-    const InputMap &D = S.in;
-    const double dx = x - D.center[0], dy = y - D.center[1], dz = z - D.center[2];
-    const double R = sqrt(dx * dx + dy * dy);
-    if (!(R >= S.r_in && R < D.r_out)) return -1;
-    const double zh = dz / (D.h0 * pow(R, D.beta));
-    if (!(fabs(zh) < D.zmax)) return -1;
-    const int ir = (int)floor((R - S.r_in) / (D.r_out - S.r_in) * (double)S.n_r);
-    const int iz = (int)floor((zh + D.zmax) / (2.0 * D.zmax) * (double)S.n_z);
-    if (ir < 0 || ir >= S.n_r || iz < 0 || iz >= S.n_z) return -1;
-    return ir * S.n_z + iz;
-}
-
 // Surrogate peel-off of one order.  The scattering kernel queues the visible
 // peel rays that start in a valid cell of the surrogate's domain, with their
 // network inputs, pixel and contribution (one reservation per wave), and
@@ -380,14 +365,46 @@ struct __align__(16) PeelNetLds {
     double merge[4][64][3];
 };
 
+// sdef_cap > 0: the launch takes the queries deferred by the late-order
+// launch instead, kPoolParts regions of sdef_cap queries (as the deferred peel
+// rays), 64 at a time per wave.
 __global__ void __launch_bounds__(256) k_peel_net(const TransportParams P, int order, int in,
                                                   const SurQuery *__restrict__ sur_q, const uint32_t *__restrict__ sur_n,
-                                                  const Queues *__restrict__ Q)
+                                                  const Queues *__restrict__ Q, uint32_t sdef_cap)
 {
     __shared__ PeelNetLds L;
     const int lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (sdef_cap) {
+        DeferredRays D;
+        D.cap = sdef_cap;
+        uint64_t acc = 0;
+        for (int r = 0; r < kPoolParts; ++r) {
+            const uint32_t n = Q->n_sdef[r][0];
+            acc += n < sdef_cap ? n : sdef_cap;
+            D.end[r] = acc;
+        }
+        const uint64_t total = acc;
+        if ((uint64_t)blockIdx.x * (blockDim.x >> 6) * 64 >= total) return;
+        mlp_tiles_to_lds(L.Wt, (const bf16x8 *)P.sur.tiles);
+        mlp_bias_to_lds(L.bias, P.sur.params);
+        __syncthreads();
+        const size_t plane = (size_t)P.npix * (size_t)P.npix;
+        double *img_copy = image_copy(P, order, plane);
+        const int key_bits = bits_for((uint64_t)P.n_obs * 3 * plane);
+        for (uint64_t j = (uint64_t)wave * 64; j < total; j += (uint64_t)waves * 64) {
+            const uint64_t qi = j + (uint64_t)lane;
+            const bool on = qi < total;
+            SurQuery q = {};
+            if (on) q = sur_q[deferred_slot(D, qi)];
+            const float t = mlp_wave_lds(L.Wt, L.bias, q.x, lane);
+            const double att = exp(-(double)fmaxf(t, 0.0f));
+            wave_merge_add(on, q.key, att * q.c[0], att * q.c[1], att * q.c[2], img_copy, plane, key_bits,
+                           L.merge[threadIdx.x >> 6]);
+        }
+        return;
+    }
     const uint32_t n_blocks = (Q->n_live[in] + 63) / 64;
     // a wave takes `span` consecutive blocks at a time (at most 64, so that the
     // launch spreads over all waves): their counts, scanned over the wave, give
@@ -761,10 +778,11 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
 // among the few late packets is low anyway): a wave stops walking once half
 // of its flights have ended.  Every packet gets the arithmetic of the
 // per-order launches, so images differ only in the order of the FP64 sums.
-template <typename R, int KIND, int SRC>
+template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PeelRay<R> *__restrict__ peels, uint32_t def_cap,
+                                              SurQuery *__restrict__ sur_q, uint32_t sdef_cap,
                                               Queues *__restrict__ Q)
 {
     __shared__ ObsTable<R> T;
@@ -780,9 +798,12 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
     const int region = (int)(blockIdx.x % kPoolParts);
     PeelRay<R> *reg = peels + (size_t)region * def_cap;
     uint32_t *reg_n = &Q->n_def[region][0];
+    SurQuery *sreg = sur_q + (size_t)region * sdef_cap;
+    uint32_t *sreg_n = &Q->n_sdef[region][0];
+    const size_t dom_cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
     const int lane = (int)(threadIdx.x & 63);
     uint64_t n_visits = 0;
-    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0;
+    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0, n_sur = 0, n_fb = 0;
     PacketState<R> s = {};
     int order = 0;
     bool has = false, moving = false, at_scatter = false;
@@ -828,6 +849,38 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
                     const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
                     peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
                     n_occ += occ ? 1u : 0u;
+                }
+                if constexpr (SUR) {
+                    // rays from a valid cell of the surrogate's domain are queued for the
+                    // network (as k_scatter queues them); a full region sends them to the
+                    // walk below (counted as fall-backs)
+                    bool use = false;
+                    if (vis) {
+                        const int cell = dom_cell(P.sur, (double)s.p[0], (double)s.p[1], (double)s.p[2]);
+                        use = cell >= 0 && P.sur.valid[(size_t)ob * dom_cells + (size_t)cell] != 0;
+                    }
+                    const uint64_t mu = __ballot(use);
+                    if (mu) {
+                        const uint32_t cu = (uint32_t)__popcll(mu);
+                        uint32_t sb = 0;
+                        if (lane == 0) sb = atomicAdd(sreg_n, cu);
+                        sb = __shfl(sb, 0, 64);
+                        const uint32_t sslot = sb + (uint32_t)__popcll(mu & lanes_below_mask());
+                        const bool sfits = (uint64_t)sb + cu <= (uint64_t)sdef_cap;
+                        SurQuery q;
+                        mlp_inputs(P.sur.in, (double)s.p[0], (double)s.p[1], (double)s.p[2], ob, q.x);
+                        q.key = (uint32_t)ob * 3u * (uint32_t)plane + pix;
+                        // a reserved slot of a full region gets a zero contribution
+                        q.c[0] = sfits ? (double)c3[0] : 0.0;
+                        q.c[1] = sfits ? (double)c3[1] : 0.0;
+                        q.c[2] = sfits ? (double)c3[2] : 0.0;
+                        if (use && sslot < sdef_cap) sreg[sslot] = q;
+                        if (use && sfits) {
+                            n_sur++;
+                            vis = false;   // the network takes this ray
+                        }
+                    }
+                    n_fb += vis ? 1u : 0u;
                 }
                 const uint64_t m = __ballot(vis);
                 if (m == 0) continue;
@@ -883,8 +936,15 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
             if (2 * __popcll(__ballot(moving && W.done)) >= movers) break;
         }
     }
-    flush_counters<6>(P.counters, {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},
-                      {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels});
+    if constexpr (SUR)
+        flush_counters<8>(P.counters,
+                          {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS,
+                           CNT_SURROGATE, CNT_FALLBACKS},
+                          {n_visits, n_scat, n_occ, n_esc, (uint64_t)n_peels + n_sur, n_peels, n_sur, n_fb});
+    else
+        flush_counters<6>(P.counters,
+                          {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},
+                          {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels});
 }
 
 // Blocks and dynamic LDS bytes of k_walk_peel_lds for an image set of `bytes`,
@@ -961,13 +1021,14 @@ template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
                             hipStream_t st, KernelTimer *T)
 {
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0, nb_tail = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0, nb_tail = 0, nb_tail_sur = 0;
     if (!nb_first) {
         nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
         nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC, false>);
         nb_walk = resident_blocks_of(k_walk<R>);
         nb_net = resident_blocks_of(k_peel_net);
-        nb_tail = resident_blocks_of(k_tail<R, KIND, SRC>);
+        nb_tail = resident_blocks_of(k_tail<R, KIND, SRC, false>);
+        nb_tail_sur = resident_blocks_of(k_tail<R, KIND, SRC, true>);
     }
     PeelRay<R> *peels = (PeelRay<R> *)B.peels;
     const int walk_blocks = std::min(nb_walk, kWalkBlocksPerCu * device_cu_count());
@@ -992,8 +1053,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
     const size_t tile_bytes = (size_t)P.n_obs * 3 * (size_t)P.npix * (size_t)P.npix * sizeof(double);
     // orders from `tail` on run in one launch, their peel rays deferred to one walk
     // (exact peel-offs with one image set only)
-    const bool tail_on = P.tail_from >= 2 && P.tail_from <= P.max_orders && P.peel_mode == 0 && !P.sur.cap &&
-                         P.order_images == 0;
+    const bool tail_on = P.tail_from >= 2 && P.tail_from <= P.max_orders && !P.sur.cap && P.order_images == 0;
     const int last = tail_on ? P.tail_from - 1 : P.max_orders;
     for (int order = 1; order <= last; ++order) {
         const int in = (order - 1) & 1;
@@ -1009,7 +1069,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         if (P.peel_mode == 1) {
             TimedLaunch tl(T, st, TC_PEEL_MLP);
             hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, order, in, (const SurQuery *)B.sur_q,
-                               (const uint32_t *)B.sur_n, (const Queues *)B.q);
+                               (const uint32_t *)B.sur_n, (const Queues *)B.q, 0u);
         }
         if (P.sur.cap) {
             TimedLaunch tl(T, st, TC_OTHER);
@@ -1038,10 +1098,26 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         if (P.def_limit) cap = std::min<uint64_t>(cap, (P.def_limit + kPoolParts - 1) / kPoolParts);
         const uint32_t def_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, 0xFFFFFFFFull / kPoolParts));
         const int in = last & 1;   // the live list of order `tail`
+        // surrogate mode: the query queue split the same way
+        const uint32_t sdef_cap =
+            P.peel_mode == 1 ? (uint32_t)std::min<uint64_t>(B.sur_entries / kPoolParts, 0xFFFFFFFFull / kPoolParts)
+                             : 0u;
         {
             TimedLaunch tl(T, st, TC_WALK);
-            hipLaunchKernelGGL((k_tail<R, KIND, SRC>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
-                               (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.q);
+            if (P.peel_mode == 1)
+                hipLaunchKernelGGL((k_tail<R, KIND, SRC, true>), dim3(nb_tail_sur), dim3(256), 0, st, P, P.tail_from,
+                                   (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.sur_q,
+                                   sdef_cap, B.q);
+            else
+                hipLaunchKernelGGL((k_tail<R, KIND, SRC, false>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
+                                   (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.sur_q, 0u,
+                                   B.q);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (P.peel_mode == 1 && sdef_cap > 0) {
+            TimedLaunch tl(T, st, TC_PEEL_MLP);
+            hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, P.max_orders, in,
+                               (const SurQuery *)B.sur_q, (const uint32_t *)B.sur_n, (const Queues *)B.q, sdef_cap);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int lds_blocks = peel_lds_blocks<R>(tile_bytes);

@@ -282,6 +282,40 @@ def test_trained_surrogate_on_the_benchmark_scene_matches_oracle(ctx, Q):
             assert np.all(np.abs(g[ob, s] - o[ob, s]) <= 2e-3 * Io + 1e-11 * mx)
 
 
+@pytest.mark.parametrize("tail", [2, 4])
+def test_surrogate_with_late_order_launch(ctx, Q, tail):
+    """Surrogate peel-off with the late-order launch (the late orders' network
+    queries deferred to one network launch, their exact rays to one walk):
+    against every order launched on its own, images up to the order of the
+    FP64 sums and counters equal; against the oracle's surrogate transport,
+    the gates of the test above.  Small disk, 8 orders, half of the cells
+    valid."""
+    sc = _small_disk(orders=8).replace(n_packets=1 << 13)
+    th = _params(51, out_bias=1.5)
+    valid = (np.random.default_rng(52).random((3, 16, 12)) < 0.5).astype(np.uint8)
+    count = sc.n_packets
+    _say(f"surrogate, late-order launch from {tail}")
+    ctx.set_tail(0)
+    g0, c0 = _sur_run_gpu(ctx, Q, sc, th, valid, count)
+    ctx.set_tail(tail)
+    g, cg = _sur_run_gpu(ctx, Q, sc, th, valid, count)
+    assert cg == c0 and cg["surrogate"] > 0 and cg["scatterings"] > 1.2 * cg["packets"]
+    mx0 = np.abs(g0).max()
+    assert np.all(np.abs(g - g0) <= 1e-10 * np.abs(g0) + 1e-13 * mx0)
+    sg = O.Surrogate(th, valid=valid, **DISK_DOMAIN)
+    o, co, _ = O.run(sc, O.SOBOL, 1, count, nthreads=8, surrogate=sg)
+    for k in ("surrogate", "fallbacks", "peels"):
+        assert abs(cg[k] - co[k]) <= 4 + 1e-5 * co[k], k
+    for ob in range(3):
+        Io = o[ob, 0]
+        mx = Io.max()
+        assert abs(g[ob, 0].sum() - Io.sum()) <= 1e-4 * Io.sum()
+        d = np.abs(g[ob, 0] - Io)
+        assert np.all(d <= 2e-3 * Io + 1e-11 * mx), f"obs {ob}: max rel {np.max(d / np.maximum(Io, 1e-300)):.3e}"
+        for s in (1, 2):
+            assert np.all(np.abs(g[ob, s] - o[ob, s]) <= 2e-3 * Io + 1e-11 * mx)
+
+
 def test_zero_mask_is_the_exact_transport(ctx, Q):
     _say("surrogate zero mask vs exact")
     sc = _small_disk()
