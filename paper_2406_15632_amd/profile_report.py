@@ -156,8 +156,9 @@ def traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, launches, ou
     w_raw = sum(v["WRITE_SIZE"] for k, v in write.items() if _transport(k))
     fetch_b = f_raw * f_scale / launches
     write_b = w_raw * w_scale / launches
-    # the dominant kernel on its own: the per-order walks (every k_walk dispatch of a launch)
-    walk = lambda k: "qrt::k_walk<" in k   # noqa: E731
+    # the dominant kernels on their own, as the bench times them: every walk dispatch of a launch
+    # (k_walk, k_walk_peel_lds) and the late-order launch k_tail
+    walk = lambda k: "qrt::k_walk" in k or "qrt::k_tail<" in k   # noqa: E731
     wf = sum(v["FETCH_SIZE"] for k, v in fetch.items() if walk(k)) * f_scale / launches
     ww = sum(v["WRITE_SIZE"] for k, v in write.items() if walk(k)) * w_scale / launches
     lines = ["# HBM traffic of the transport step (disk128, 2^22 packets per launch)", "",
