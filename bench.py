@@ -8,10 +8,12 @@ FP64 optical-depth and image sums.  The mesh is resident in HBM before timing.
 
 The JSON line carries
   value         photon packets/s over the timed steps (HIP events);
-  roofline      of the dominant kernel, k_walk (the peel-off rays and free
-                flights of every order): its algorithmic bytes (4 B per voxel
-                visit + 24 B per peel-off contribution, exact counts from the
-                kernels' counters) over its time, measured with HIP events that
+  roofline      of the dominant kernels, the walks (k_walk: peel-off rays and
+                flights of orders 1-3, then the deferred peel rays of the later
+                orders; k_tail: orders 4-20 in one launch): their algorithmic
+                bytes (4 B per voxel visit + 24 B per peel-off contribution,
+                exact counts from the kernels' counters) over their time,
+                measured with HIP events that
                 the library records on its launch stream around every kernel in
                 a timing pass after the timed region; the same figure for the
                 whole transport step under "step"; HBM traffic from committed
@@ -762,11 +764,13 @@ def main():
             "unit": "GB/s",
             "frac": walk_gbps / HBM_PEAK_GBS,
             "traffic": walk_traffic,
-            "kernel": "k_walk, the dominant kernel: the peel-off rays and free flights of every scattering "
-                      "order (its 20 dispatches of one transport launch together)",
+            "kernel": "the walk kernels, dominant together: k_walk (peel-off rays and flights of orders 1-3, "
+                      "then the deferred peel rays of the later orders) and k_tail (orders 4-20 in one launch), "
+                      "all their dispatches of one transport launch together",
             "alg_bytes_per_launch": walk_bytes,
-            "alg_bytes": "4 B per cell visit of the walk (all visits but those of the first flights) + 24 B "
-                         "per binned peel-off contribution, exact counts from the kernels' counters",
+            "alg_bytes": "4 B per cell visit of the walks (all visits but those of the first flights; "
+                         "k_tail's flights included) + 24 B per binned peel-off contribution, exact counts "
+                         "from the kernels' counters",
             "avg_launch_ms": walk_ms,
             "avg_dispatch_us": 1e3 * tm["walk"][0] / max(1, tm["walk"][1]),
             "share_of_launch": walk_ms / timed_ms if timed_ms else None,
@@ -777,7 +781,8 @@ def main():
             "frac_of_measured_copy": walk_gbps / copy_gbps,
             "step": {
                 "kernel": "the whole transport step qrt_run (k_key_emit, the two-pass radix sort, k_first, "
-                          "then per scattering order k_scatter and k_walk) over the timed region",
+                          "per scattering order 1-3 k_scatter and k_walk, then k_tail and the deferred "
+                          "k_walk) over the timed region",
                 "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "alg_bytes_per_launch": alg_bytes / n_launch, "avg_launch_ms": elapsed_ms / n_launch,
                 "stream_ordered_launch_ms": sum(per_kind_ms.values()) / len(kinds),
