@@ -176,19 +176,20 @@ int qrt_set_overlap(qrt_ctx *ctx, int enable);
 /* Late scattering orders in one launch (Sec. 2.2, 3.5: the same transport,
    launched differently).  From order first_order on (default 4; 0 turns it
    off) a run carries each live packet through its remaining orders in one
-   kernel, a lane per packet, and walks the peel-off rays of all those orders
-   in one launch afterwards, instead of two launches per order.  Images differ
-   from the per-order launches only in the order of the FP64 sums, counters not
-   at all.  max_deferred bounds the peel-off rays held for that walk (0: as many
-   as the peel-ray buffer holds); rays beyond it are walked at once by the lane
-   that made them.  In the surrogate mode the late orders' network queries
-   are deferred the same way, to one network launch (as many as the query
-   queue holds; a query beyond that walks exactly and counts as a
-   fall-back).  Used with one image set (not with per-order images), and for
-   batches, where the orders counted are those of the batch's deepest scene;
-   a first_order above the largest max_orders leaves every order to the
-   per-order launches.  Joins pending overlapped runs.  QRT_INVALID_ARG for
-   first_order 1 or below 0. */
+   kernel, a lane per packet, keeping the state of every scattering it passes;
+   one launch then computes the peel-off contributions of all those
+   scatterings and one more walks their rays, instead of two launches per
+   order.  Images differ from the per-order launches only in the order of the
+   FP64 sums, counters not at all.  max_deferred bounds the scatterings held
+   (0: as many as the live-packet list and the peel-ray buffer hold); a
+   scattering beyond it has its peel-offs computed and walked at once by the
+   lane that reached it.  In the surrogate mode the deferred scatterings'
+   network queries go to one network launch (as many as the query queue
+   holds, which also bounds the scatterings held).  Used with one image set
+   (not with per-order images), and for batches, where the orders counted are
+   those of the batch's deepest scene; a first_order above the largest
+   max_orders leaves every order to the per-order launches.  Joins pending
+   overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
 int qrt_set_tail(qrt_ctx *ctx, int first_order, uint64_t max_deferred);
 
 /* The context stream waits for every overlapped run still pending

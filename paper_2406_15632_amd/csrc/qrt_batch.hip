@@ -187,27 +187,34 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
 // appends to group b % kPeelGroups, which has its own counter and region:
 // a group receives at most ceil(blocks / kPeelGroups) blocks of at most
 // 64 kBatchObs rays, which the host sizes group_cap for.  The observer field
-// holds scene * 16 + observer.
+// holds scene * 16 + observer.  def_cap > 0: the scatterings deferred by the
+// late-order launch, in regions of def_cap (as in k_scatter), peel-offs only.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
-                                                  int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q)
+                                                  int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q,
+                                                  uint32_t def_cap)
 {
     if (blockIdx.x == 0 && threadIdx.x < kPoolParts) {
         if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
         Q->work[1][threadIdx.x][0] = 0;
     }
-    const uint32_t n = Q->n_live[in];
+    const DeferredList D = deferred_list(Q, def_cap);
+    const uint32_t n = def_cap ? (uint32_t)D.end[kPoolParts - 1] : Q->n_live[in];
+    if (def_cap && blockIdx.x == 0 && threadIdx.x == 0) Q->n_live[in] = n;
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
     const uint32_t stride = gridDim.x * blockDim.x;
     uint32_t n_scat = 0, n_occ = 0;
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
-        const bool valid = i < n;
+        bool valid = i < n;
         PacketState<R> st = {};
         int s = 0;
         if (valid) {
-            st = pks[i];
+            st = pks[def_cap ? deferred_slot(D, i) : i];
+            valid = !def_cap || st.order != kNoState;
+        }
+        if (valid) {
             s = (int)st.next_dim;
             n_scat++;
         }
@@ -274,7 +281,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
             } else {
                 st.target = -1.0;   // the scene's last scattering: no further flight
             }
-            pks[i] = st;
+            if (!def_cap) pks[i] = st;
         }
     }
     flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
@@ -283,28 +290,24 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
 // ---------------------------------------------------------------- walks of one order
 enum BatchWalkItem : int { BW_NONE = 0, BW_PEEL = 1, BW_MOVE = 2 };
 
-// def_cap > 0: the launch walks the peel rays deferred by the late-order
-// launch (and no flights); else the peel rays and flights of one order.
 template <typename R>
 __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                                                const PacketState<R> *__restrict__ pks, int in,
                                                PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
-                                               Queues *__restrict__ Q, uint32_t def_cap)
+                                               Queues *__restrict__ Q)
 {
-    if (!def_cap && blockIdx.x == 0 && threadIdx.x < kPeelGroups)
+    if (blockIdx.x == 0 && threadIdx.x < kPeelGroups)
         Q->n_peel[(order + 1) & 1][threadIdx.x][0] = 0;   // next scatter
     // peel rays of the groups, numbered one group after the other
     uint32_t g_count[kPeelGroups];
     uint64_t n_peel = 0;
 #pragma unroll
     for (int g = 0; g < kPeelGroups; ++g) {
-        g_count[g] = def_cap ? 0u : Q->n_peel[order & 1][g][0];
+        g_count[g] = Q->n_peel[order & 1][g][0];
         n_peel += g_count[g];
     }
-    const DeferredRays D = deferred_rays(Q, def_cap);
-    if (def_cap) n_peel = D.end[kPoolParts - 1];
     const uint64_t n_live = Q->n_live[in];
-    const uint64_t n_move = !def_cap && order < P.max_orders ? n_live : 0;
+    const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
@@ -368,10 +371,9 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                     at -= past ? g_count[q] : 0;
                     g += past ? 1 : 0;
                 }
-                const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : (uint64_t)g * P.group_cap + at];
-                // appended rays are all visible; a deferred region can hold slots marked
-                // empty (reserved when the region was full)
-                if (r.pix != kNoPixel) {
+                // appended rays are all visible
+                const PeelRay<R> r = peels[(uint64_t)g * P.group_cap + at];
+                {
                     s = (int)(r.obs >> 4);
                     obs = (int)(r.obs & 15u);
                     const BScene &S = P.scenes[s];
@@ -417,23 +419,24 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
 
 // ---------------------------------------------------------------- late orders in one launch
 // The batched form of k_tail (qrt_transport.hip): from order order0 on, a lane
-// carries each live packet through its scene's remaining orders (scattering as
-// k_bscatter, flight on the scene's mesh as k_bwalk); the visible peel rays go
-// to the deferred regions of the peel-ray buffer for one k_bwalk launch, or,
-// where a region is full, are walked at once by the lane.
+// carries each live packet through its scene's remaining orders (flight on the
+// scene's mesh as k_bwalk walks it); every scattering's state is appended to
+// the deferred list (regions per work-pool part) for one k_bscatter launch and
+// one k_bwalk launch afterwards.  A wave whose reservation does not fit
+// computes its scatterings' peel-offs itself and walks their rays at once.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
                                                const PacketState<R> *__restrict__ pks, int in,
-                                               PeelRay<R> *__restrict__ peels, uint32_t def_cap,
+                                               PacketState<R> *__restrict__ states, uint32_t state_cap,
                                                Queues *__restrict__ Q)
 {
-    // the pool of the walk of the deferred rays starts at zero (its last user, the
-    // walk of order order0 - 1, has ended)
-    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) Q->work[1][threadIdx.x][0] = 0;
+    // the peel-ray counters that the scattering launch of the deferred list appends to
+    // (their last user, the walk of order order0 - 1, has ended)
+    if (blockIdx.x == 0 && threadIdx.x < kPeelGroups) Q->n_peel[P.max_orders & 1][threadIdx.x][0] = 0;
     const uint64_t n = Q->n_live[in];
     const int region = (int)(blockIdx.x % kPoolParts);
-    PeelRay<R> *reg = peels + (size_t)region * def_cap;
-    uint32_t *reg_n = &Q->n_def[region][0];
+    PacketState<R> *sreg = states + (size_t)region * state_cap;
+    uint32_t *sreg_n = &Q->n_def[region][0];
     const int lane = (int)(threadIdx.x & 63);
     uint64_t n_visits = 0;
     uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0;
@@ -466,49 +469,48 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
             at_scatter = true;
         }
         if (__ballot(has) == 0 && pool.dry) break;
-        if (__ballot(at_scatter) != 0) {
+        const uint64_t ms = __ballot(at_scatter);
+        if (ms != 0) {
+            // the scattering's state (before the albedo) to the deferred list
+            const uint32_t cnt = (uint32_t)__popcll(ms);
+            uint32_t sbase = 0;
+            if (lane == 0) sbase = atomicAdd(sreg_n, cnt);
+            sbase = __shfl(sbase, 0, 64);
+            const bool fits = (uint64_t)sbase + cnt <= (uint64_t)state_cap;
+            if (at_scatter) {
+                const uint32_t slot = sbase + (uint32_t)__popcll(ms & lanes_below_mask());
+                if (slot < state_cap) {
+                    PacketState<R> d = st;
+                    d.order = fits ? (uint32_t)order : kNoState;
+                    sreg[slot] = d;
+                }
+            }
             const BScene &S = P.scenes[s];
             const SceneView<R> V = scene_view<R>(S);
             R n_ax[3] = {(R)0, (R)0, (R)0};
             if (at_scatter) {
-                n_scat++;
                 st.S[0] *= V.albedo; st.S[1] *= V.albedo; st.S[2] *= V.albedo;
                 cross3(st.k, st.m, n_ax);
                 G = lane_grid<R>(S);
             }
-            for (int ob = 0; ob < kBatchObs; ++ob) {
-                bool vis = false, occ = false;
-                R c3[3] = {(R)0, (R)0, (R)0};
-                uint32_t pix = 0;
-                R o[3] = {(R)0, (R)0, (R)1};
-                if (at_scatter && ob < S.n_obs) {
-                    const DevObserver &O = S.obs[ob];
-                    const R ex[3] = {(R)O.ex[0], (R)O.ex[1], (R)O.ex[2]};
-                    const R ey[3] = {(R)O.ey[0], (R)O.ey[1], (R)O.ey[2]};
-                    o[0] = (R)O.o[0]; o[1] = (R)O.o[1]; o[2] = (R)O.o[2];
-                    peel_contribution<R>(V, st, n_ax, o, ex, ey, vis, occ, c3, pix);
-                    n_occ += occ ? 1u : 0u;
-                }
-                const uint64_t m = __ballot(vis);
-                if (m == 0) continue;
-                const uint32_t cnt = (uint32_t)__popcll(m);
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(reg_n, cnt);
-                base = __shfl(base, 0, 64);
-                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below_mask());
-                PeelRay<R> r;
-                r.p[0] = st.p[0]; r.p[1] = st.p[1]; r.p[2] = st.p[2];
-                r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
-                r.obs = ((uint32_t)s << 4) | (uint32_t)ob;
-                if ((uint64_t)base + cnt <= (uint64_t)def_cap) {
-                    r.pix = pix;
-                    if (vis) reg[slot] = r;
-                } else {
-                    // region full: the reserved slots inside it are marked empty, and the
-                    // rays walked here (W is free: these lanes' flights have ended)
-                    r.pix = kNoPixel;
-                    if (vis && slot < def_cap) reg[slot] = r;
+            if (!fits) {
+                // the list is full: this wave's scatterings peel off here
+                if (at_scatter) n_scat++;
+                for (int ob = 0; ob < kBatchObs; ++ob) {
+                    bool vis = false, occ = false;
+                    R c3[3] = {(R)0, (R)0, (R)0};
+                    uint32_t pix = 0;
+                    R o[3] = {(R)0, (R)0, (R)1};
+                    if (at_scatter && ob < S.n_obs) {
+                        const DevObserver &O = S.obs[ob];
+                        const R ex[3] = {(R)O.ex[0], (R)O.ex[1], (R)O.ex[2]};
+                        const R ey[3] = {(R)O.ey[0], (R)O.ey[1], (R)O.ey[2]};
+                        o[0] = (R)O.o[0]; o[1] = (R)O.o[1]; o[2] = (R)O.o[2];
+                        peel_contribution<R>(V, st, n_ax, o, ex, ey, vis, occ, c3, pix);
+                        n_occ += occ ? 1u : 0u;
+                    }
                     if (vis) {
+                        // W is free: this lane's flight has ended
                         walk_begin(W, G, st.p, o, WALK_EDGE, 0.0);
                         walk_run<R, kFlightBatch>(W, G);
                         n_visits += W.visits;
@@ -600,34 +602,44 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
         {
             TimedLaunch tl(T, st, TC_SCATTER);
             hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, state_list<R>(B, in), in,
-                               peels, B.q);
+                               peels, B.q, 0u);
         }
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;   // the last order walks peel rays only
         {
             TimedLaunch tl(T, st, TC_WALK);
             hipLaunchKernelGGL((k_bwalk<R>), dim3(wb), dim3(256), 0, st, P, order,
                                (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                               (const PeelRay<R> *)peels, B.q, 0u);
+                               (const PeelRay<R> *)peels, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (tail_on) {
-        // the peel-ray buffer split into kPoolParts regions for the deferred rays
-        uint64_t cap = B.peel_bytes / sizeof(PeelRay<R>) / kPoolParts;
-        if (P.def_limit) cap = std::min<uint64_t>(cap, (P.def_limit + kPoolParts - 1) / kPoolParts);
-        const uint32_t def_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, 0xFFFFFFFFull / kPoolParts));
-        const int in = last & 1;   // the live list of order `tail`
+        const int in = last & 1;   // the live list of order `tail`; the other list takes the deferred scatterings
+        // at most `count` in all, so that their peel rays fit the append groups as a chunk's
+        // first order does, in kPoolParts regions, one per work-pool part
+        uint64_t cap = std::min<uint64_t>(B.cap, count);
+        if (P.def_limit) cap = std::min<uint64_t>(cap, P.def_limit);
+        const uint32_t state_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap / kPoolParts, 0x1FFFFFFFull));
         {
             TimedLaunch tl(T, st, TC_WALK);
             hipLaunchKernelGGL((k_btail<R, KIND>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
-                               (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.q);
+                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                               state_cap, B.q);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // the deferred scatterings' peel-offs as the last order's, then the walk of their rays
+        const int din = in ^ 1;
+        {
+            TimedLaunch tl(T, st, TC_SCATTER);
+            hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(nb_scatter), dim3(256), 0, st, P, P.max_orders,
+                               state_list<R>(B, din), din, peels, B.q, state_cap);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         {
             TimedLaunch tl(T, st, TC_WALK);
             hipLaunchKernelGGL((k_bwalk<R>), dim3(nb_walk), dim3(256), 0, st, P, P.max_orders,
-                               (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                               (const PeelRay<R> *)peels, B.q, def_cap);
+                               (const PacketState<R> *)state_list<R>(B, din), din, state_list<R>(B, in),
+                               (const PeelRay<R> *)peels, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

@@ -253,12 +253,9 @@ struct Queues {
     // appended peel rays per order parity and group (batched launches), one
     // counter per 128-byte line so that the groups' atomics do not share one
     uint32_t n_peel[2][kPeelGroups][32];
-    // peel rays deferred by the late-order launch, per region of the peel-ray
-    // buffer (one region per work-pool part), one counter per 128-byte line
+    // scatterings deferred by the late-order launch, per region of their list
+    // (one region per work-pool part), one counter per 128-byte line
     uint32_t n_def[8][32];
-    // network queries deferred by the late-order launch (surrogate mode), per
-    // region of the query queue, one counter per 128-byte line
-    uint32_t n_sdef[8][32];
 };
 
 // A peel-off ray queued for the surrogate network: its network inputs, the

@@ -365,46 +365,14 @@ struct __align__(16) PeelNetLds {
     double merge[4][64][3];
 };
 
-// sdef_cap > 0: the launch takes the queries deferred by the late-order
-// launch instead, kPoolParts regions of sdef_cap queries (as the deferred peel
-// rays), 64 at a time per wave.
 __global__ void __launch_bounds__(256) k_peel_net(const TransportParams P, int order, int in,
                                                   const SurQuery *__restrict__ sur_q, const uint32_t *__restrict__ sur_n,
-                                                  const Queues *__restrict__ Q, uint32_t sdef_cap)
+                                                  const Queues *__restrict__ Q)
 {
     __shared__ PeelNetLds L;
     const int lane = threadIdx.x & 63;
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (sdef_cap) {
-        DeferredRays D;
-        D.cap = sdef_cap;
-        uint64_t acc = 0;
-        for (int r = 0; r < kPoolParts; ++r) {
-            const uint32_t n = Q->n_sdef[r][0];
-            acc += n < sdef_cap ? n : sdef_cap;
-            D.end[r] = acc;
-        }
-        const uint64_t total = acc;
-        if ((uint64_t)blockIdx.x * (blockDim.x >> 6) * 64 >= total) return;
-        mlp_tiles_to_lds(L.Wt, (const bf16x8 *)P.sur.tiles);
-        mlp_bias_to_lds(L.bias, P.sur.params);
-        __syncthreads();
-        const size_t plane = (size_t)P.npix * (size_t)P.npix;
-        double *img_copy = image_copy(P, order, plane);
-        const int key_bits = bits_for((uint64_t)P.n_obs * 3 * plane);
-        for (uint64_t j = (uint64_t)wave * 64; j < total; j += (uint64_t)waves * 64) {
-            const uint64_t qi = j + (uint64_t)lane;
-            const bool on = qi < total;
-            SurQuery q = {};
-            if (on) q = sur_q[deferred_slot(D, qi)];
-            const float t = mlp_wave_lds(L.Wt, L.bias, q.x, lane);
-            const double att = exp(-(double)fmaxf(t, 0.0f));
-            wave_merge_add(on, q.key, att * q.c[0], att * q.c[1], att * q.c[2], img_copy, plane, key_bits,
-                           L.merge[threadIdx.x >> 6]);
-        }
-        return;
-    }
     const uint32_t n_blocks = (Q->n_live[in] + 63) / 64;
     // a wave takes `span` consecutive blocks at a time (at most 64, so that the
     // launch spreads over all waves): their counts, scanned over the wave, give
@@ -472,10 +440,17 @@ __device__ __forceinline__ SceneView<R> scene_view(const TransportParams &P, int
 // the walk), then the new direction and flight depth.  SUR: surrogate mode,
 // in which the visible rays that start in a valid cell of the surrogate's
 // domain are also queued for k_peel_net.
+// def_cap > 0: the list holds the scatterings deferred by the late-order
+// launch, in kPoolParts regions of def_cap states (as the deferred rays: item i
+// is state deferred_slot(i)), some marked kNoState (reserved when a region was
+// full, never scattered here: their order field holds kNoState); their count
+// goes to n_live[in] for the walks.
+
 template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
                                                  int in, PeelRay<R> *__restrict__ peels, SurQuery *__restrict__ sur_q,
-                                                 uint32_t *__restrict__ sur_n, Queues *__restrict__ Q)
+                                                 uint32_t *__restrict__ sur_n, Queues *__restrict__ Q,
+                                                 uint32_t def_cap)
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
@@ -484,7 +459,9 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
         Q->work[1][threadIdx.x][0] = 0;
     }
-    const uint32_t n = Q->n_live[in];
+    const DeferredList D = deferred_list(Q, def_cap);
+    const uint32_t n = def_cap ? (uint32_t)D.end[kPoolParts - 1] : Q->n_live[in];
+    if (def_cap && blockIdx.x == 0 && threadIdx.x == 0) Q->n_live[in] = n;
     const int lane = threadIdx.x & 63;
     const uint32_t wave0 = (blockIdx.x * blockDim.x + threadIdx.x) - (uint32_t)lane;
     const uint32_t stride = gridDim.x * blockDim.x;
@@ -493,10 +470,13 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
     uint32_t n_scat = 0, n_occ = 0, n_sur = 0, n_fb = 0;
     for (uint32_t base = wave0; base < n; base += stride) {
         const uint32_t i = base + (uint32_t)lane;
-        const bool valid = i < n;
+        bool valid = i < n;
         PacketState<R> s = {};
         if (valid) {
-            s = pks[i];
+            s = pks[def_cap ? deferred_slot(D, i) : i];
+            valid = !def_cap || s.order != kNoState;
+        }
+        if (valid) {
             n_scat++;
             s.S[0] *= V.albedo; s.S[1] *= V.albedo; s.S[2] *= V.albedo;
         }
@@ -552,7 +532,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         if constexpr (SUR) {
             if (lane == 0) sur_n[i >> 6] = queued;
         }
-        if (valid && order < P.max_orders) {
+        if (valid && order < P.max_orders) {   // never for the deferred scatterings (order = max_orders)
             uint32_t x[3];
             seq_triple<KIND>(P.seq, s.idx, first_scatter_dim(SRC) + 3 * (order - 1), x);
             scatter_packet<R>(V, s, n_ax, x);
@@ -571,13 +551,11 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
-// def_cap > 0: the launch walks the peel rays deferred by the late-order
-// launch (and no flights); else the peel rays and flights of one order.
 template <typename R>
 __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
-                                              Queues *__restrict__ Q, uint32_t def_cap)
+                                              Queues *__restrict__ Q)
 {
     __shared__ R s_o[kMaxObs][3];
     __shared__ double s_merge[4][64][3];   // per wave: pixel merge of the image contributions
@@ -586,9 +564,8 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     __syncthreads();
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const uint64_t n_live = Q->n_live[in];
-    const DeferredRays D = deferred_rays(Q, def_cap);
-    const uint64_t n_peel = def_cap ? D.end[kPoolParts - 1] : (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
-    const uint64_t n_move = !def_cap && order < P.max_orders ? n_live : 0;
+    const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t n_move = order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
@@ -639,7 +616,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
         if (pool.take(kind == WI_NONE, total, &Q->work[1][0][0], item)) {
             item = scatter_block(item, total, stride);
             if (item < n_peel) {
-                const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : item];
+                const PeelRay<R> r = peels[item];
                 if (r.pix != kNoPixel) {
                     const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
                     c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
@@ -692,7 +669,7 @@ constexpr int kPeelLdsThreads = 1024;
 template <typename R>
 __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const TransportParams P, int order, int in,
                                                                   const PeelRay<R> *__restrict__ peels,
-                                                                  Queues *__restrict__ Q, uint32_t def_cap)
+                                                                  Queues *__restrict__ Q)
 {
     extern __shared__ double tile[];   // [n_obs][3][npix][npix]
     __shared__ R s_o[kMaxObs][3];
@@ -704,8 +681,7 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
     __syncthreads();
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const uint64_t n_live = Q->n_live[in];
-    const DeferredRays D = deferred_rays(Q, def_cap);
-    const uint64_t total = def_cap ? D.end[kPoolParts - 1] : (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
+    const uint64_t total = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     uint64_t n_visits = 0;
     uint32_t n_peels = 0;
@@ -729,7 +705,7 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
         uint64_t item = 0;
         if (pool.take(!busy, total, &Q->work[1][0][0], item)) {
             item = scatter_block(item, total, stride);
-            const PeelRay<R> r = peels[def_cap ? deferred_slot(D, item) : item];
+            const PeelRay<R> r = peels[item];
             if (r.pix != kNoPixel) {
                 const R o[3] = {s_o[r.obs][0], s_o[r.obs][1], s_o[r.obs][2]};
                 c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
@@ -764,46 +740,41 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
 // --------------------------------------------------------------------------
 // Scattering orders order0 .. max_orders of the packets live after order
 // order0 - 1, in one launch.  A lane takes a packet and carries it through its
-// remaining orders: scattering (albedo, the peel-off contributions, the new
-// direction and flight depth, as k_scatter computes them), then its flight (as
-// k_walk walks it), then the next scattering where the flight stopped inside
-// the mesh.  The visible peel-off rays are not walked here: each wave appends
-// them to the peel-ray buffer region of its block's work-pool part (one atomic
-// per wave and observer), and one k_walk launch over every region walks them
-// afterwards, so no order waits for the longest walk of the one before.  A
-// wave whose region is full walks its rays itself, to the edge, before the
-// flight.  The per-order launches would run these orders at low occupancy,
-// each ended by its longest walk; here a packet's chain of flights is the
-// longest wait.  Lanes go back to the pool as their packets end (coherence
-// among the few late packets is low anyway): a wave stops walking once half
-// of its flights have ended.  Every packet gets the arithmetic of the
+// remaining orders: at each scattering the packet's state is appended to the
+// list of deferred scatterings (one atomic per wave), the albedo and the new
+// direction and flight depth are applied as k_scatter applies them, and the
+// flight is walked as k_walk walks it, up to the next scattering where it
+// stopped inside the mesh.  The peel-offs of the deferred scatterings are left
+// to one k_scatter launch over the list after this kernel (converged, with the
+// peel rays in fixed slots), then one walk launch; per-order launches would
+// run these orders at low occupancy, each ended by its longest walk.  A wave
+// whose reservation does not fit the list computes its scatterings' peel-offs
+// itself and walks their rays to the edge at once (the reserved slots that fit
+// are marked kNoState); in the surrogate mode those rays all walk exactly and
+// count as fall-backs.  Lanes go back to the pool as their packets end
+// (coherence among the few late packets is low anyway): a wave stops walking
+// once half of its flights have ended.  Every packet gets the arithmetic of the
 // per-order launches, so images differ only in the order of the FP64 sums.
 template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
                                               const PacketState<R> *__restrict__ pks, int in,
-                                              PeelRay<R> *__restrict__ peels, uint32_t def_cap,
-                                              SurQuery *__restrict__ sur_q, uint32_t sdef_cap,
+                                              PacketState<R> *__restrict__ states, uint32_t state_cap,
                                               Queues *__restrict__ Q)
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
-    // the pool of the walk of the deferred rays starts at zero (the walk of
-    // order order0 - 1, its last user, has ended)
-    if (blockIdx.x == 0 && threadIdx.x < kPoolParts) Q->work[1][threadIdx.x][0] = 0;
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const SceneView<R> V = scene_view<R>(P, SRC);
     const uint64_t n = Q->n_live[in];
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
     double *img_copy = image_copy(P, order0, plane);
-    const int region = (int)(blockIdx.x % kPoolParts);
-    PeelRay<R> *reg = peels + (size_t)region * def_cap;
-    uint32_t *reg_n = &Q->n_def[region][0];
-    SurQuery *sreg = sur_q + (size_t)region * sdef_cap;
-    uint32_t *sreg_n = &Q->n_sdef[region][0];
-    const size_t dom_cells = (size_t)P.sur.n_r * (size_t)P.sur.n_z;
     const int lane = (int)(threadIdx.x & 63);
+    // the deferred scatterings of this block: the region of its work-pool part (XCD)
+    const int region = (int)(blockIdx.x % kPoolParts);
+    PacketState<R> *sreg = states + (size_t)region * state_cap;
+    uint32_t *sreg_n = &Q->n_def[region][0];
     uint64_t n_visits = 0;
-    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0, n_sur = 0, n_fb = 0;
+    uint32_t n_scat = 0, n_occ = 0, n_esc = 0, n_peels = 0, n_fb = 0;
     PacketState<R> s = {};
     int order = 0;
     bool has = false, moving = false, at_scatter = false;
@@ -832,76 +803,44 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
             at_scatter = true;
         }
         if (__ballot(has) == 0 && pool.dry) break;
-        if (__ballot(at_scatter) != 0) {
+        const uint64_t ms = __ballot(at_scatter);
+        if (ms != 0) {
+            // the scattering's state (before the albedo) to the deferred list
+            const uint32_t cnt = (uint32_t)__popcll(ms);
+            uint32_t sbase = 0;
+            if (lane == 0) sbase = atomicAdd(sreg_n, cnt);
+            sbase = __shfl(sbase, 0, 64);
+            const bool fits = (uint64_t)sbase + cnt <= (uint64_t)state_cap;
+            if (at_scatter) {
+                const uint32_t slot = sbase + (uint32_t)__popcll(ms & lanes_below_mask());
+                if (slot < state_cap) {
+                    PacketState<R> d = s;
+                    d.order = fits ? (uint32_t)order : kNoState;
+                    sreg[slot] = d;
+                }
+            }
             R n_ax[3] = {(R)0, (R)0, (R)0};
             if (at_scatter) {
-                n_scat++;
                 s.S[0] *= V.albedo; s.S[1] *= V.albedo; s.S[2] *= V.albedo;
                 cross3(s.k, s.m, n_ax);
             }
-            for (int ob = 0; ob < P.n_obs; ++ob) {
-                bool vis = false, occ = false;
-                R c3[3] = {(R)0, (R)0, (R)0};
-                uint32_t pix = 0;
-                const R o[3] = {T.o[ob][0], T.o[ob][1], T.o[ob][2]};
-                if (at_scatter) {
-                    const R ex[3] = {T.ex[ob][0], T.ex[ob][1], T.ex[ob][2]};
-                    const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
-                    peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
-                    n_occ += occ ? 1u : 0u;
-                }
-                if constexpr (SUR) {
-                    // rays from a valid cell of the surrogate's domain are queued for the
-                    // network (as k_scatter queues them); a full region sends them to the
-                    // walk below (counted as fall-backs)
-                    bool use = false;
-                    if (vis) {
-                        const int cell = dom_cell(P.sur, (double)s.p[0], (double)s.p[1], (double)s.p[2]);
-                        use = cell >= 0 && P.sur.valid[(size_t)ob * dom_cells + (size_t)cell] != 0;
+            if (!fits) {
+                // the list is full: this wave's scatterings peel off here
+                if (at_scatter) n_scat++;
+                for (int ob = 0; ob < P.n_obs; ++ob) {
+                    bool vis = false, occ = false;
+                    R c3[3] = {(R)0, (R)0, (R)0};
+                    uint32_t pix = 0;
+                    const R o[3] = {T.o[ob][0], T.o[ob][1], T.o[ob][2]};
+                    if (at_scatter) {
+                        const R ex[3] = {T.ex[ob][0], T.ex[ob][1], T.ex[ob][2]};
+                        const R ey[3] = {T.ey[ob][0], T.ey[ob][1], T.ey[ob][2]};
+                        peel_contribution<R>(V, s, n_ax, o, ex, ey, vis, occ, c3, pix);
+                        n_occ += occ ? 1u : 0u;
                     }
-                    const uint64_t mu = __ballot(use);
-                    if (mu) {
-                        const uint32_t cu = (uint32_t)__popcll(mu);
-                        uint32_t sb = 0;
-                        if (lane == 0) sb = atomicAdd(sreg_n, cu);
-                        sb = __shfl(sb, 0, 64);
-                        const uint32_t sslot = sb + (uint32_t)__popcll(mu & lanes_below_mask());
-                        const bool sfits = (uint64_t)sb + cu <= (uint64_t)sdef_cap;
-                        SurQuery q;
-                        mlp_inputs(P.sur.in, (double)s.p[0], (double)s.p[1], (double)s.p[2], ob, q.x);
-                        q.key = (uint32_t)ob * 3u * (uint32_t)plane + pix;
-                        // a reserved slot of a full region gets a zero contribution
-                        q.c[0] = sfits ? (double)c3[0] : 0.0;
-                        q.c[1] = sfits ? (double)c3[1] : 0.0;
-                        q.c[2] = sfits ? (double)c3[2] : 0.0;
-                        if (use && sslot < sdef_cap) sreg[sslot] = q;
-                        if (use && sfits) {
-                            n_sur++;
-                            vis = false;   // the network takes this ray
-                        }
-                    }
-                    n_fb += vis ? 1u : 0u;
-                }
-                const uint64_t m = __ballot(vis);
-                if (m == 0) continue;
-                const uint32_t cnt = (uint32_t)__popcll(m);
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(reg_n, cnt);
-                base = __shfl(base, 0, 64);
-                const uint32_t slot = base + (uint32_t)__popcll(m & lanes_below_mask());
-                PeelRay<R> r;
-                r.p[0] = s.p[0]; r.p[1] = s.p[1]; r.p[2] = s.p[2];
-                r.c[0] = c3[0]; r.c[1] = c3[1]; r.c[2] = c3[2];
-                r.obs = (uint32_t)ob;
-                if ((uint64_t)base + cnt <= (uint64_t)def_cap) {
-                    r.pix = pix;
-                    if (vis) reg[slot] = r;
-                } else {
-                    // region full: the reserved slots inside it are marked empty, and the
-                    // rays walked here (W is free: these lanes' flights have ended)
-                    r.pix = kNoPixel;
-                    if (vis && slot < def_cap) reg[slot] = r;
                     if (vis) {
+                        if constexpr (SUR) n_fb++;
+                        // W is free: this lane's flight has ended
                         walk_begin(W, G, s.p, o, WALK_EDGE, 0.0);
                         walk_run<R, kFlightBatch>(W, G);
                         n_visits += W.visits;
@@ -937,10 +876,10 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
         }
     }
     if constexpr (SUR)
-        flush_counters<8>(P.counters,
+        flush_counters<7>(P.counters,
                           {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS,
-                           CNT_SURROGATE, CNT_FALLBACKS},
-                          {n_visits, n_scat, n_occ, n_esc, (uint64_t)n_peels + n_sur, n_peels, n_sur, n_fb});
+                           CNT_FALLBACKS},
+                          {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels, n_fb});
     else
         flush_counters<6>(P.counters,
                           {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},
@@ -1061,15 +1000,15 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             TimedLaunch tl(T, st, TC_SCATTER);
             if (P.peel_mode == 1)
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, true>), dim3(bs), dim3(256), 0, st, P, order,
-                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q);
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u);
             else
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, false>), dim3(bs), dim3(256), 0, st, P, order,
-                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q);
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u);
         }
         if (P.peel_mode == 1) {
             TimedLaunch tl(T, st, TC_PEEL_MLP);
             hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, order, in, (const SurQuery *)B.sur_q,
-                               (const uint32_t *)B.sur_n, (const Queues *)B.q, 0u);
+                               (const uint32_t *)B.sur_n, (const Queues *)B.q);
         }
         if (P.sur.cap) {
             TimedLaunch tl(T, st, TC_OTHER);
@@ -1084,52 +1023,67 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             TimedLaunch tl(T, st, TC_WALK);
             if (lds_blocks > 0)
                 hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
-                                   order, in, (const PeelRay<R> *)peels, B.q, 0u);
+                                   order, in, (const PeelRay<R> *)peels, B.q);
             else
                 hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
                                    (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                                   (const PeelRay<R> *)peels, B.q, 0u);
+                                   (const PeelRay<R> *)peels, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (tail_on) {
-        // the peel-ray buffer split into kPoolParts regions for the deferred rays
-        uint64_t cap = B.peel_bytes / sizeof(PeelRay<R>) / kPoolParts;
-        if (P.def_limit) cap = std::min<uint64_t>(cap, (P.def_limit + kPoolParts - 1) / kPoolParts);
-        const uint32_t def_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, 0xFFFFFFFFull / kPoolParts));
-        const int in = last & 1;   // the live list of order `tail`
-        // surrogate mode: the query queue split the same way
-        const uint32_t sdef_cap =
-            P.peel_mode == 1 ? (uint32_t)std::min<uint64_t>(B.sur_entries / kPoolParts, 0xFFFFFFFFull / kPoolParts)
-                             : 0u;
+        const int in = last & 1;   // the live list of order `tail`; the other list takes the deferred scatterings
+        // as many as the list, the peel slots (64 n_obs per 64 scatterings) and, in the
+        // surrogate mode, the query queue hold
+        uint64_t cap = B.cap;
+        const uint64_t slot_groups = B.peel_bytes / sizeof(PeelRay<R>) / (64 * (uint64_t)P.n_obs);
+        cap = std::min<uint64_t>(cap, 64 * slot_groups);
+        if (P.peel_mode == 1) cap = std::min<uint64_t>(cap, 64 * (B.sur_entries / (64 * (uint64_t)P.n_obs)));
+        if (P.def_limit) cap = std::min<uint64_t>(cap, P.def_limit);
+        // in kPoolParts regions, one per work-pool part
+        const uint32_t state_cap = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap / kPoolParts, 0x1FFFFFFFull));
+        const bool sur = P.peel_mode == 1;
         {
             TimedLaunch tl(T, st, TC_WALK);
-            if (P.peel_mode == 1)
+            if (sur)
                 hipLaunchKernelGGL((k_tail<R, KIND, SRC, true>), dim3(nb_tail_sur), dim3(256), 0, st, P, P.tail_from,
-                                   (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.sur_q,
-                                   sdef_cap, B.q);
+                                   (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                                   state_cap, B.q);
             else
                 hipLaunchKernelGGL((k_tail<R, KIND, SRC, false>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
-                                   (const PacketState<R> *)state_list<R>(B, in), in, peels, def_cap, B.sur_q, 0u,
-                                   B.q);
+                                   (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
+                                   state_cap, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (P.peel_mode == 1 && sdef_cap > 0) {
+        // the deferred scatterings' peel-offs, as the last order's: scatter (no new direction), the
+        // network in the surrogate mode, the walk of the peel rays
+        const int din = in ^ 1;
+        {
+            TimedLaunch tl(T, st, TC_SCATTER);
+            if (sur)
+                hipLaunchKernelGGL((k_scatter<R, KIND, SRC, true>), dim3(nb_scatter), dim3(256), 0, st, P,
+                                   P.max_orders, state_list<R>(B, din), din, peels, B.sur_q, B.sur_n, B.q,
+                                   state_cap);
+            else
+                hipLaunchKernelGGL((k_scatter<R, KIND, SRC, false>), dim3(nb_scatter), dim3(256), 0, st, P,
+                                   P.max_orders, state_list<R>(B, din), din, peels, B.sur_q, B.sur_n, B.q,
+                                   state_cap);
+        }
+        if (sur) {
             TimedLaunch tl(T, st, TC_PEEL_MLP);
-            hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, P.max_orders, in,
-                               (const SurQuery *)B.sur_q, (const uint32_t *)B.sur_n, (const Queues *)B.q, sdef_cap);
+            hipLaunchKernelGGL(k_peel_net, dim3(nb_net), dim3(256), 0, st, P, P.max_orders, din,
+                               (const SurQuery *)B.sur_q, (const uint32_t *)B.sur_n, (const Queues *)B.q);
         }
-        if ((e = hipGetLastError()) != hipSuccess) return e;
         const int lds_blocks = peel_lds_blocks<R>(tile_bytes);
         {
             TimedLaunch tl(T, st, TC_WALK);
             if (lds_blocks > 0)
                 hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
-                                   P.max_orders, in, (const PeelRay<R> *)peels, B.q, def_cap);
+                                   P.max_orders, din, (const PeelRay<R> *)peels, B.q);
             else
                 hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, P.max_orders,
-                                   (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                                   (const PeelRay<R> *)peels, B.q, def_cap);
+                                   (const PacketState<R> *)state_list<R>(B, din), din, state_list<R>(B, in),
+                                   (const PeelRay<R> *)peels, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

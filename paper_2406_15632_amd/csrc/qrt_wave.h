@@ -178,18 +178,21 @@ __host__ __device__ inline uint64_t scatter_block(uint64_t item, uint64_t total,
     return (((b * stride) % nfull) << kOrderBlockLog2) | (item & (kOrderBlock - 1));
 }
 
-// The peel rays deferred by the late-order launch lie in kPoolParts regions of
-// def_cap rays each, region r holding min(n_def[r], def_cap) of them: item i of
-// a walk over all of them is ray i - start[r] of the region r with
-// start[r] <= i < end[r].
-struct DeferredRays {
+// order field of a deferred scattering that was reserved but not deferred
+constexpr uint32_t kNoState = 0xFFFFFFFFu;
+
+// The items deferred by the late-order launch (scatterings) lie in kPoolParts
+// regions of def_cap items each, region r holding min(n_def[r], def_cap) of
+// them: item i of a launch over all of them is item i - start[r] of the region
+// r with start[r] <= i < end[r].
+struct DeferredList {
     uint64_t end[kPoolParts];
     uint32_t cap;
 };
 
-__device__ __forceinline__ DeferredRays deferred_rays(const Queues *Q, uint32_t def_cap)
+__device__ __forceinline__ DeferredList deferred_list(const Queues *Q, uint32_t def_cap)
 {
-    DeferredRays d;
+    DeferredList d;
     d.cap = def_cap;
     uint64_t acc = 0;
     for (int r = 0; r < kPoolParts; ++r) {
@@ -200,7 +203,7 @@ __device__ __forceinline__ DeferredRays deferred_rays(const Queues *Q, uint32_t 
     return d;
 }
 
-__device__ __forceinline__ uint64_t deferred_slot(const DeferredRays &d, uint64_t item)
+__device__ __forceinline__ uint64_t deferred_slot(const DeferredList &d, uint64_t item)
 {
     uint64_t start = 0, slot = 0;
     bool found = false;

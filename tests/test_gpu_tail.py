@@ -1,12 +1,13 @@
 """The late-order launch (qrt_set_tail): orders from a given one on carried
-through in one kernel, their peel-off rays walked in one launch afterwards.
+through in one kernel, the peel-offs of their scatterings computed in one
+launch afterwards and the peel-off rays walked in one more.
 
 It changes how the work is launched, not what is computed, so against the
 per-order launches of the same run the images agree up to the order of the
 FP64 sums (per pixel |d| <= 1e-10 (I + 1e-12 max I)) and the event counters
 are equal; against the oracle the FP64 gates of the parity tests hold.  The
-region-full path (rays walked by the lane that made them) is forced with a
-small limit of deferred rays.
+region-full path (peel-offs computed and walked by the lane that reached the
+scattering) is forced with a small limit of deferred scatterings.
 """
 import sys
 
@@ -82,8 +83,8 @@ def assert_counters_close(cg, co, what):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tail_equals_per_order_launches(ctx, Q, precision):
     """disk at 64^3, 20 orders, three observers, 2^18 packets: the late-order
-    launch from order 2, 7 and 15, and with at most 256 deferred rays (most
-    walked by the lanes that made them), against every order launched on its
+    launch from order 2, 7 and 15, and with at most 256 deferred scatterings
+    (most peel-offs taken by the lanes that reached them), against every order launched on its
     own."""
     sc = scenes.disk128(n=64).replace(npix=64)
     n = 1 << 18
@@ -132,7 +133,7 @@ def test_batch_tail_equals_per_order_launches(ctx, Q):
     """Twelve uneven scenes (1 to 12 orders, 1 to 4 observers, envelopes and
     disks, point sources and stars) in one batch, FP32: the late-order launch
     from order 2 and from order 5, and from order 2 with at most 128 deferred
-    rays, against every order launched on its own; per scene images up to the
+    scatterings, against every order launched on its own; per scene images up to the
     order of the sums, counters equal."""
     bs = scenes.uneven_batch(31, 12, sizes=(32, 64, 16), log2_packets=(14.0, 16.0), npix=64, orders=(1, 12))
     assert max(sc.max_orders for sc in bs) >= 5
