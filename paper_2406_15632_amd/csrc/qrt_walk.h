@@ -153,8 +153,7 @@ struct Walk {
     R tx, ty, tz;                  // next face distance per axis
     R t, t_exit;
     uint32_t ox, oy, oz;           // each axis' part of the cell's byte offset
-    uint32_t ux, uy, uz;           // per axis: the bits outside its part for a step up, 0 for a step down
-    int sx, sy, sz;                // step of the part per axis: -4, 0 or +4 (one cell)
+    uint32_t ax, ay, az;           // per axis: the addend of a one-cell step of its part (walk_begin)
     double tau, target;
     int mode;
     bool done, stopped;
@@ -215,12 +214,14 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
     W.ox = (uint32_t)brick_index(cx, 0, 0, G.nbx, G.nby) << 2;
     W.oy = (uint32_t)brick_index(0, cy, 0, G.nbx, G.nby) << 2;
     W.oz = (uint32_t)brick_index(0, 0, cz, G.nbx, G.nby) << 2;
-    W.ux = sx > 0 ? ~G.m[0] : 0u;
-    W.uy = sy > 0 ? ~G.m[1] : 0u;
-    W.uz = sz > 0 ? ~G.m[2] : 0u;
-    W.sx = 4 * sx;
-    W.sy = 4 * sy;
-    W.sz = 4 * sz;
+    // An axis' part holds only the bits of its mask m.  A step up adds 4 (one
+    // cell) with every bit outside m set, so that the carry runs through the
+    // other axes' bits; since the part has none of those bits, setting them is
+    // the same as adding ~m.  A step down subtracts 4, the borrow running
+    // through them likewise.  Masking with m afterwards clears them again.
+    W.ax = sx > 0 ? ~G.m[0] + 4u : (sx < 0 ? (uint32_t)-4 : 0u);
+    W.ay = sy > 0 ? ~G.m[1] + 4u : (sy < 0 ? (uint32_t)-4 : 0u);
+    W.az = sz > 0 ? ~G.m[2] + 4u : (sz < 0 ? (uint32_t)-4 : 0u);
     return ok;
 }
 
@@ -234,10 +235,11 @@ __device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&c
 {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const bool mx = W.tx <= W.ty && W.tx <= W.tz;
-        const bool my = !mx && W.ty <= W.tz;
-        const bool mz = !mx && !my;
+        // the nearest face; ties go to x, then y
         const R tn = fmin(W.tx, fmin(W.ty, W.tz));
+        const bool mx = W.tx == tn;
+        const bool my = !mx && W.ty == tn;
+        const bool mz = !mx && !my;
         nv += alive ? 1u : 0u;
         cells[b] = W.ox | W.oy | W.oz;
         t0s[b] = W.t;
@@ -247,12 +249,10 @@ __device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&c
         W.t = t1;
         // the face about to be crossed is a boundary face: the walk ends in this cell
         const bool adv = tn < W.t_exit;
-        // the chosen axis' part moves by one cell: the carry (or borrow) runs
-        // through the other axes' bits, set beforehand for a step up, and the
-        // mask clears them again
-        const uint32_t nox = ((W.ox | W.ux) + (uint32_t)W.sx) & G.m[0];
-        const uint32_t noy = ((W.oy | W.uy) + (uint32_t)W.sy) & G.m[1];
-        const uint32_t noz = ((W.oz | W.uz) + (uint32_t)W.sz) & G.m[2];
+        // the chosen axis' part moves by one cell
+        const uint32_t nox = (W.ox + W.ax) & G.m[0];
+        const uint32_t noy = (W.oy + W.ay) & G.m[1];
+        const uint32_t noz = (W.oz + W.az) & G.m[2];
         W.ox = (adv && mx) ? nox : W.ox;
         W.oy = (adv && my) ? noy : W.oy;
         W.oz = (adv && mz) ? noz : W.oz;
@@ -268,9 +268,10 @@ __device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&c
 
 // B steps of a walk in either mode (no effect once done).  The B cells are
 // computed first and loaded together; the optical depth is then accumulated
-// in order, in FP64, with the stop test of a move per step.  The stop position
-// of a move is computed once, after the batch, for the step that reached the
-// target.
+// in order, in FP64.  A move stops at the first step whose running sum
+// reaches the target: the steps before it are counted, and the sum before it
+// and that step's density and start are kept, from which the stop position is
+// computed once, after the batch.
 template <typename R, int B, typename GT>
 __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
 {
@@ -283,28 +284,29 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
     R kr[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
-    double tau = W.tau;
-    bool hit = false;
-    double rem = 0.0;
-    R kr_hit = (R)1, t0_hit = (R)0;
-    uint32_t nv_hit = 0;
+    const bool edge = W.mode != WALK_MOVE;
+    double tau = W.tau, before = W.tau;   // running sum; the sum before the stopping step
+    R kr_hit = (R)1, t0_hit = (R)0;       // the stopping step's density and start
+    uint32_t below = 0;                   // steps before the stopping step
+    bool run = true;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const double dtau = (double)(kr[b] * segs[b]);
-        const bool h = W.mode == WALK_MOVE && !hit && tau + dtau >= W.target;
-        rem = h ? W.target - tau : rem;
-        kr_hit = h ? kr[b] : kr_hit;
-        t0_hit = h ? t0s[b] : t0_hit;
-        nv_hit = h ? (uint32_t)(b + 1) : nv_hit;
-        hit = hit || h;
-        tau += hit ? 0.0 : dtau;
+        const double next = tau + (double)(kr[b] * segs[b]);
+        const bool go = run && (edge || !(next >= W.target));
+        below += go ? 1u : 0u;
+        before = go ? next : before;
+        kr_hit = run && !go ? kr[b] : kr_hit;
+        t0_hit = run && !go ? t0s[b] : t0_hit;
+        run = go;
+        tau = next;
     }
-    if (hit) {
+    if (!run) {
+        const double rem = W.target - before;
         W.t_out = t0_hit + (rem > 0.0 ? (R)((R)rem / kr_hit) : (R)0);
-        W.tau = rem > 0.0 ? W.target : tau;
+        W.tau = rem > 0.0 ? W.target : before;
         W.stopped = true;
         W.done = true;
-        W.visits += nv_hit < nv ? nv_hit : nv;
+        W.visits += below + 1 < nv ? below + 1 : nv;
         return;
     }
     W.tau = tau;
