@@ -113,8 +113,8 @@ int qrt_set_stream(qrt_ctx *ctx, void *hip_stream);
    fastest.  flags is one of QRT_GRID_*.  Cells must be finite and >= 0 (checked
    for host input).  The library copies the mesh into its own order (bricks of
    4x4x4 cells, the brick counts along x and y rounded up to powers of two; at
-   most 2^29 stored cells, else QRT_UNSUPPORTED); the caller's buffer is not
-   used after the call returns. */
+   most 2^29 stored cells and 2^20 cells per axis, else QRT_UNSUPPORTED); the
+   caller's buffer is not used after the call returns. */
 int qrt_set_grid(qrt_ctx *ctx, int nx, int ny, int nz, const double lo[3], const double hi[3],
                  const float *kappa_rho, int flags);
 

@@ -550,6 +550,9 @@ int qrt_set_grid(qrt_ctx *c, int nx, int ny, int nz, const double lo[3], const d
         return fail(c, QRT_INVALID_ARG, "bad grid arguments");
     const int64_t bricked = mesh_cells(nx, ny, nz);
     if (bricked > (int64_t)1 << 29) return fail(c, QRT_UNSUPPORTED, "grid too large (at most 2^29 stored cells)");
+    // a walk counts the faces it crosses per axis in FP32, exactly up to 2^24
+    if (nx > kMaxAxisCells || ny > kMaxAxisCells || nz > kMaxAxisCells)
+        return fail(c, QRT_UNSUPPORTED, "grid too large (at most 2^20 cells per axis)");
     for (int a = 0; a < 3; ++a)
         if (!(hi[a] > lo[a]) || !isfinite(lo[a]) || !isfinite(hi[a]))
             return fail(c, QRT_INVALID_ARG, "box must satisfy lo < hi on every axis");
@@ -1613,6 +1616,8 @@ static int batch_scene_check(qrt_ctx *c, int i, const qrt_batch_scene &S)
         return fail(c, QRT_INVALID_ARG, "scene %d: bad grid arguments", i);
     if (mesh_cells(S.nx, S.ny, S.nz) > (int64_t)1 << 29)
         return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large (at most 2^29 stored cells)", i);
+    if (S.nx > kMaxAxisCells || S.ny > kMaxAxisCells || S.nz > kMaxAxisCells)
+        return fail(c, QRT_UNSUPPORTED, "scene %d: grid too large (at most 2^20 cells per axis)", i);
     for (int a = 0; a < 3; ++a)
         if (!(S.hi[a] > S.lo[a]) || !isfinite(S.lo[a]) || !isfinite(S.hi[a]))
             return fail(c, QRT_INVALID_ARG, "scene %d: box must satisfy lo < hi on every axis", i);

@@ -53,6 +53,9 @@ __host__ __device__ inline void mesh_bricks(int nx, int ny, int nz, int nb[3])
 }
 
 // stored cells of a mesh (the cells past its edge hold 0)
+// cells per axis at most: a walk's face counts (FP32 in FP32 walks) stay exact
+constexpr int kMaxAxisCells = 1 << 20;
+
 __host__ __device__ inline int64_t mesh_cells(int nx, int ny, int nz)
 {
     int nb[3];
@@ -158,7 +161,7 @@ struct Walk {
     int mode;
     bool done, stopped;
     R t_out;                       // stop distance (MOVE), else exit distance
-    uint32_t visits;
+    uint32_t visits;               // cells visited, set when the walk ends
 };
 
 template <typename R, typename GT>
@@ -227,11 +230,13 @@ __device__ __forceinline__ bool walk_begin(Walk<R> &W, const GT &G, const R p[3]
 
 // The cells (byte offsets), start distances and lengths of the next B steps
 // of a walk, which do not depend on the densities.  After the exit step the
-// remaining steps repeat the last cell with zero length: they add nothing and
-// are not counted as visits (nv).  alive turns false at the exit step.
+// remaining steps repeat the last cell with zero length: they add nothing.
+// alive turns false at the exit step.  Every step before the exit crosses one
+// face, so a walk that is still going has visited jx + jy + jz cells, and one
+// that left the mesh one more.
 template <typename R, int B, typename GT>
 __device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&cells)[B], R (&t0s)[B],
-                                           R (&segs)[B], uint32_t &nv, bool &alive)
+                                           R (&segs)[B], bool &alive)
 {
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -240,7 +245,6 @@ __device__ __forceinline__ void walk_steps(Walk<R> &W, const GT &G, uint32_t (&c
         const bool mx = W.tx == tn;
         const bool my = !mx && W.ty == tn;
         const bool mz = !mx && !my;
-        nv += alive ? 1u : 0u;
         cells[b] = W.ox | W.oy | W.oz;
         t0s[b] = W.t;
         // length max(tn - t, 0), and t never decreases
@@ -278,9 +282,9 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
     if (W.done) return;
     uint32_t cells[B];
     R t0s[B], segs[B];
-    uint32_t nv = 0;
+    const uint32_t before_batch = (uint32_t)(W.jx + W.jy + W.jz);   // cells visited so far
     bool alive = true;
-    walk_steps<R, B>(W, G, cells, t0s, segs, nv, alive);
+    walk_steps<R, B>(W, G, cells, t0s, segs, alive);
     R kr[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
@@ -306,14 +310,15 @@ __device__ __forceinline__ void walk_batch(Walk<R> &W, const GT &G)
         W.tau = rem > 0.0 ? W.target : before;
         W.stopped = true;
         W.done = true;
-        W.visits += below + 1 < nv ? below + 1 : nv;
+        // the stopping step is at or before the exit step (after it no step adds depth)
+        W.visits = before_batch + below + 1;
         return;
     }
     W.tau = tau;
-    W.visits += nv;
     if (!alive) {
         W.done = true;
         W.t_out = W.t;
+        W.visits = (uint32_t)(W.jx + W.jy + W.jz) + 1;
     }
 }
 
@@ -326,9 +331,8 @@ __device__ __forceinline__ void walk_batch_edge(Walk<R> &W, const GT &G)
     if (W.done) return;
     uint32_t cells[B];
     R t0s[B], segs[B];
-    uint32_t nv = 0;
     bool alive = true;
-    walk_steps<R, B>(W, G, cells, t0s, segs, nv, alive);
+    walk_steps<R, B>(W, G, cells, t0s, segs, alive);
     R kr[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) kr[b] = load_kr(G, cells[b]);
@@ -336,10 +340,10 @@ __device__ __forceinline__ void walk_batch_edge(Walk<R> &W, const GT &G)
 #pragma unroll
     for (int b = 0; b < B; ++b) tau += (double)(kr[b] * segs[b]);
     W.tau = tau;
-    W.visits += nv;
     if (!alive) {
         W.done = true;
         W.t_out = W.t;
+        W.visits = (uint32_t)(W.jx + W.jy + W.jz) + 1;
     }
 }
 

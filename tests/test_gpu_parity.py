@@ -396,6 +396,10 @@ def test_errors_are_reported(ctx, Q):
         ctx.set_dust(0.5, 0.5, 0.5, 0.1)
     with pytest.raises(QRTError):
         ctx.set_point_source(2.0, 0.0, 0.0)
+    # more than 2^20 cells along one axis (4 Mi stored cells in all)
+    with pytest.raises(QRTError) as e:
+        ctx.set_grid(np.ones((1, 1, (1 << 20) + 1), np.float32))
+    assert e.value.code == Q.QRT_UNSUPPORTED
 
 
 def test_failed_image_allocation_leaves_no_observers(ctx, Q):
