@@ -781,8 +781,9 @@ def main():
             "frac_of_measured_copy": walk_gbps / copy_gbps,
             "step": {
                 "kernel": "the whole transport step qrt_run (k_key_emit, the two-pass radix sort, k_first, "
-                          "per scattering order 1-3 k_scatter and k_walk, then k_tail and the deferred "
-                          "k_walk) over the timed region",
+                          "per scattering order 1-3 k_scatter and k_walk, then k_tail, k_def_keys and the "
+                          "radix sort of the deferred scatterings, their k_scatter and k_walk) over the timed "
+                          "region",
                 "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "alg_bytes_per_launch": alg_bytes / n_launch, "avg_launch_ms": elapsed_ms / n_launch,
                 "stream_ordered_launch_ms": sum(per_kind_ms.values()) / len(kinds),

@@ -201,7 +201,7 @@ struct TransportParams {
     int peel_mode;                 // 0 exact traversal, 1 surrogate inside its valid cells
     SurrogateParams sur;
     int tail_from;                 // first order of the late-order launch (0: every order has its own launches)
-    uint64_t def_limit;            // at most this many deferred peel rays (0: as many as the buffer holds)
+    uint64_t def_limit;            // at most this many deferred scatterings (0: as many as the buffers hold)
 };
 
 // First scattering order that the late-order launch takes over by default:
@@ -256,6 +256,8 @@ struct Queues {
     // scatterings deferred by the late-order launch, per region of their list
     // (one region per work-pool part), one counter per 128-byte line
     uint32_t n_def[8][32];
+    // the deferred scatterings of all regions together (the count of their sort)
+    uint32_t n_def_all[32];
 };
 
 // A peel-off ray queued for the surrogate network: its network inputs, the
@@ -347,7 +349,7 @@ struct BatchParams {
     double *img_base;           // all scenes' images, one after the other (scene images point into it)
     int img_key_bits;           // bits that hold an element offset from img_base
     int tail_from;              // first order of the late-order launch (0: every order has its own launches)
-    uint64_t def_limit;         // at most this many deferred peel rays (0: as many as the buffer holds)
+    uint64_t def_limit;         // at most this many deferred scatterings (0: as many as the buffers hold)
 };
 
 // Batch numbers b_first .. b_first+b_count-1 of a batch, in chunks of at most
@@ -358,7 +360,10 @@ hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precisi
 
 // order[0 .. count) = the packets 0 .. count-1 sorted by keys[j] (kSortBits bits), stably; count <= kChunk.
 // Two radix passes of 8 bits through B.sort_tmp, histograms in B.hist.
-hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer = nullptr);
+// count_dev (optional): a device word that lowers the count when the kernels run;
+// passes 1 for keys below 256.
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer = nullptr,
+                            const uint32_t *count_dev = nullptr, int passes = 2);
 
 // One chunk of packets first .. first+count-1 (count <= kChunk) through every
 // scattering order: first flight, then per order a scatter kernel and a walk

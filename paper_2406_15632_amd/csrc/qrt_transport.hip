@@ -54,6 +54,8 @@
 #include "qrt_internal.h"
 #include "qrt_mlp.h"
 #include "qrt_packet.h"
+#include <cstddef>
+
 #include "qrt_physics.h"
 #include "qrt_wave.h"
 
@@ -103,9 +105,11 @@ __global__ void __launch_bounds__(256) k_key_emit(const TransportParams P, uint6
 
 // hist[d * nb + b] = items of block b whose digit (key >> shift) & 255 is d
 __global__ void __launch_bounds__(kSortDigit) k_digit_hist(const uint32_t *__restrict__ keys, uint32_t count, int shift,
-                                                           uint32_t *__restrict__ hist)
+                                                           uint32_t *__restrict__ hist,
+                                                           const uint32_t *__restrict__ count_dev)
 {
     __shared__ uint32_t h[kSortDigit];
+    if (count_dev) count = min(count, *count_dev);
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t b0 = blockIdx.x * (uint32_t)kSortItems;
@@ -169,9 +173,12 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
                                                               int shift, const uint32_t *__restrict__ hist,
                                                               const uint32_t *__restrict__ tot,
                                                               uint32_t *__restrict__ keys_out,
-                                                              uint32_t *__restrict__ vals_out)
+                                                              uint32_t *__restrict__ vals_out,
+                                                              const uint32_t *__restrict__ count_dev)
 {
     constexpr int kWaves = kSortDigit / 64;
+    if (count_dev) count = min(count, *count_dev);
+    if (blockIdx.x * (uint32_t)kSortItems >= count) return;   // past the items (device count)
     __shared__ uint32_t base[kSortDigit];
     __shared__ uint32_t wc[kWaves][kSortDigit];
     const int t = threadIdx.x, w = t >> 6;
@@ -215,7 +222,8 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
     }
 }
 
-hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer)
+hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer,
+                            const uint32_t *count_dev, int passes)
 {
     if (count == 0) return hipSuccess;
     if (count > kChunk) return hipErrorInvalidValue;
@@ -223,18 +231,22 @@ hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream
     const int nb = (int)((count + kSortItems - 1) / kSortItems);
     uint32_t *tot = B.hist + (size_t)kSortDigit * (kChunk / kSortItems);
     uint32_t *tmp_keys = B.sort_tmp, *tmp_vals = B.sort_tmp + B.cap;
-    // low digit: keys and packet numbers into the scratch lists
-    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys, count, 0, B.hist);
+    // low digit: keys and packet numbers into the scratch lists (or, for keys of
+    // one digit, the packet numbers into order)
+    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys, count, 0, B.hist,
+                       count_dev);
     hipLaunchKernelGGL(k_digit_scan, dim3(kSortDigit), dim3(kSortDigit), 0, st, B.hist, nb, tot);
     hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys,
                        (const uint32_t *)nullptr, count, 0, (const uint32_t *)B.hist, (const uint32_t *)tot,
-                       tmp_keys, tmp_vals);
+                       passes == 1 ? (uint32_t *)nullptr : tmp_keys, passes == 1 ? B.order : tmp_vals, count_dev);
+    if (passes == 1) return hipGetLastError();
     // high digit: the packet numbers into order
-    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys, count, 8, B.hist);
+    hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys, count, 8, B.hist,
+                       count_dev);
     hipLaunchKernelGGL(k_digit_scan, dim3(kSortDigit), dim3(kSortDigit), 0, st, B.hist, nb, tot);
     hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys,
                        (const uint32_t *)tmp_vals, count, 8, (const uint32_t *)B.hist, (const uint32_t *)tot,
-                       (uint32_t *)nullptr, B.order);
+                       (uint32_t *)nullptr, B.order, count_dev);
     return hipGetLastError();
 }
 
@@ -441,16 +453,16 @@ __device__ __forceinline__ SceneView<R> scene_view(const TransportParams &P, int
 // in which the visible rays that start in a valid cell of the surrogate's
 // domain are also queued for k_peel_net.
 // def_cap > 0: the list holds the scatterings deferred by the late-order
-// launch, in kPoolParts regions of def_cap states (as the deferred rays: item i
-// is state deferred_slot(i)), some marked kNoState (reserved when a region was
-// full, never scattered here: their order field holds kNoState); their count
-// goes to n_live[in] for the walks.
-
+// launch, in kPoolParts regions of def_cap states, some marked kNoState
+// (reserved when a region was full, never scattered here: their order field
+// holds kNoState); item i is state deferred_slot(perm[i]), perm being their
+// order by position (k_def_keys), and their count goes to n_live[in] for the
+// walks.
 template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int order, PacketState<R> *__restrict__ pks,
                                                  int in, PeelRay<R> *__restrict__ peels, SurQuery *__restrict__ sur_q,
                                                  uint32_t *__restrict__ sur_n, Queues *__restrict__ Q,
-                                                 uint32_t def_cap)
+                                                 uint32_t def_cap, const uint32_t *__restrict__ perm)
 {
     __shared__ ObsTable<R> T;
     load_obs(P, T);
@@ -473,7 +485,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         bool valid = i < n;
         PacketState<R> s = {};
         if (valid) {
-            s = pks[def_cap ? deferred_slot(D, i) : i];
+            s = pks[def_cap ? deferred_slot(D, perm[i]) : i];
             valid = !def_cap || s.order != kNoState;
         }
         if (valid) {
@@ -544,6 +556,47 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
                           {n_scat, n_occ, n_sur, n_fb, n_sur});
     else
         flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
+}
+
+// Bits dropped from the 15-bit keys of the deferred scatterings' sort, and its
+// radix passes (8 bits each)
+constexpr int kDefKeyShift = 0;
+constexpr int kDefSortPasses = 2;
+
+// Sort keys of the scatterings deferred by the late-order launch: the cell of
+// a 32^3 grid over the box that holds the scattering point, in Morton order
+// (15 bits); entries reserved but not deferred get the largest key.  Their
+// count goes to n_def_all.  Sorted by these keys, a wave of the deferred walk
+// takes the peel rays of 64 scatterings from one small part of the mesh
+// instead of those that a wave of k_tail happened to reach together.
+template <typename R>
+__global__ void __launch_bounds__(256) k_def_keys(const TransportParams P, const PacketState<R> *__restrict__ pks,
+                                                  Queues *__restrict__ Q, uint32_t def_cap, uint32_t *__restrict__ keys)
+{
+    const DeferredList D = deferred_list(Q, def_cap);
+    const uint32_t n = (uint32_t)D.end[kPoolParts - 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) Q->n_def_all[0] = n;
+    float lo[3], scale[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (float)P.grid.lo[a];
+        scale[a] = (float)(32.0 / (P.grid.hi[a] - P.grid.lo[a]));
+    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const PacketState<R> *s = pks + deferred_slot(D, i);
+        uint32_t key = 0xFFFFu;
+        if (s->order != kNoState) {
+            uint32_t c[3];
+            for (int a = 0; a < 3; ++a) {
+                const float u = ((float)s->p[a] - lo[a]) * scale[a];
+                c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
+            }
+            key = 0;
+            for (int b = 0; b < 5; ++b)
+                key |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) |
+                       ((c[2] >> b) & 1u) << (3 * b + 2);
+        }
+        keys[i] = key >> kDefKeyShift;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1000,10 +1053,12 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             TimedLaunch tl(T, st, TC_SCATTER);
             if (P.peel_mode == 1)
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, true>), dim3(bs), dim3(256), 0, st, P, order,
-                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u);
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u,
+                                   (const uint32_t *)nullptr);
             else
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, false>), dim3(bs), dim3(256), 0, st, P, order,
-                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u);
+                                   state_list<R>(B, in), in, peels, B.sur_q, B.sur_n, B.q, 0u,
+                                   (const uint32_t *)nullptr);
         }
         if (P.peel_mode == 1) {
             TimedLaunch tl(T, st, TC_PEEL_MLP);
@@ -1055,19 +1110,30 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
                                    state_cap, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // the deferred scatterings' peel-offs, as the last order's: scatter (no new direction), the
-        // network in the surrogate mode, the walk of the peel rays
+        // the deferred scatterings in the order of their positions (the sort's count is
+        // read on the device), then their peel-offs, as the last order's: scatter (no
+        // new direction), the network in the surrogate mode, the walk of the peel rays
         const int din = in ^ 1;
+        const uint32_t def_bound = (uint32_t)std::min<uint64_t>((uint64_t)kPoolParts * state_cap, B.cap);
+        {
+            TimedLaunch tl(T, st, TC_SORT);
+            const int kb = (int)std::min<uint32_t>((def_bound + 255) / 256, 512u);
+            hipLaunchKernelGGL((k_def_keys<R>), dim3(kb), dim3(256), 0, st, P,
+                               (const PacketState<R> *)state_list<R>(B, din), B.q, state_cap, B.keys);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const uint32_t *def_count = (const uint32_t *)((const char *)B.q + offsetof(Queues, n_def_all));
+        if ((e = launch_sort_keys(B, def_bound, st, T, def_count, kDefSortPasses)) != hipSuccess) return e;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
             if (sur)
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, true>), dim3(nb_scatter), dim3(256), 0, st, P,
                                    P.max_orders, state_list<R>(B, din), din, peels, B.sur_q, B.sur_n, B.q,
-                                   state_cap);
+                                   state_cap, (const uint32_t *)B.order);
             else
                 hipLaunchKernelGGL((k_scatter<R, KIND, SRC, false>), dim3(nb_scatter), dim3(256), 0, st, P,
                                    P.max_orders, state_list<R>(B, din), din, peels, B.sur_q, B.sur_n, B.q,
-                                   state_cap);
+                                   state_cap, (const uint32_t *)B.order);
         }
         if (sur) {
             TimedLaunch tl(T, st, TC_PEEL_MLP);
