@@ -18,6 +18,8 @@
 
 #include <algorithm>
 
+#include <cstddef>
+
 #include "qrt_internal.h"
 #include "qrt_packet.h"
 #include "qrt_physics.h"
@@ -188,11 +190,12 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
 // a group receives at most ceil(blocks / kPeelGroups) blocks of at most
 // 64 kBatchObs rays, which the host sizes group_cap for.  The observer field
 // holds scene * 16 + observer.  def_cap > 0: the scatterings deferred by the
-// late-order launch, in regions of def_cap (as in k_scatter), peel-offs only.
+// late-order launch, in regions of def_cap, item i being state
+// deferred_slot(perm[i]) (as in k_scatter), peel-offs only.
 template <typename R, int KIND>
 __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order, PacketState<R> *__restrict__ pks,
                                                   int in, PeelRay<R> *__restrict__ peels, Queues *__restrict__ Q,
-                                                  uint32_t def_cap)
+                                                  uint32_t def_cap, const uint32_t *__restrict__ perm)
 {
     if (blockIdx.x == 0 && threadIdx.x < kPoolParts) {
         if (threadIdx.x == 0) Q->n_live[in ^ 1] = 0;
@@ -211,7 +214,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         PacketState<R> st = {};
         int s = 0;
         if (valid) {
-            st = pks[def_cap ? deferred_slot(D, i) : i];
+            st = pks[def_cap ? deferred_slot(D, perm[i]) : i];
             valid = !def_cap || st.order != kNoState;
         }
         if (valid) {
@@ -550,6 +553,40 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
                       {n_visits, n_scat, n_occ, n_esc, n_peels, n_peels});
 }
 
+// Sort keys of a batch's deferred scatterings (k_def_keys of the single-scene
+// launch): the scene, relative to the chunk's first, in the top bits, then the
+// Morton index of the point's cell in a 32^3 grid over the scene's box in the
+// bits that remain of 15; entries reserved but not deferred get the largest key.
+template <typename R>
+__global__ void __launch_bounds__(256) k_bdef_keys(const BatchParams P, const PacketState<R> *__restrict__ pks,
+                                                   Queues *__restrict__ Q, uint32_t def_cap,
+                                                   uint32_t *__restrict__ keys)
+{
+    const DeferredList D = deferred_list(Q, def_cap);
+    const uint32_t n = (uint32_t)D.end[kPoolParts - 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) Q->n_def_all[0] = n;
+    const int pos_bits = P.scene_bits < 15 ? 15 - P.scene_bits : 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const PacketState<R> *st = pks + deferred_slot(D, i);
+        uint32_t key = 0xFFFFu;
+        if (st->order != kNoState) {
+            const int sc = (int)st->next_dim;
+            const BScene &S = P.scenes[sc];
+            uint32_t c[3];
+            for (int a = 0; a < 3; ++a) {
+                const float u = ((float)st->p[a] - (float)S.lo[a]) * (float)(32.0 / (S.n[a] * S.h[a]));
+                c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
+            }
+            uint32_t m = 0;
+            for (int b = 0; b < 5; ++b)
+                m |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) |
+                     ((c[2] >> b) & 1u) << (3 * b + 2);
+            key = ((uint32_t)(sc - P.scene_base) << pos_bits) | (m >> (15 - pos_bits));
+        }
+        keys[i] = key;
+    }
+}
+
 // ---------------------------------------------------------------- launch sequence
 template <typename F>
 static int batch_resident_blocks(F kernel)
@@ -602,7 +639,7 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
         {
             TimedLaunch tl(T, st, TC_SCATTER);
             hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(bs), dim3(256), 0, st, P, order, state_list<R>(B, in), in,
-                               peels, B.q, 0u);
+                               peels, B.q, 0u, (const uint32_t *)nullptr);
         }
         const int wb = order < P.max_orders ? walk_blocks : nb_walk;   // the last order walks peel rays only
         {
@@ -627,12 +664,23 @@ static hipError_t batch_chunk(const BatchParams &P, uint64_t b0, uint32_t count,
                                state_cap, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        // the deferred scatterings' peel-offs as the last order's, then the walk of their rays
+        // the deferred scatterings sorted by scene and position (as in the single-scene
+        // launch), their peel-offs as the last order's, then the walk of their rays
         const int din = in ^ 1;
+        const uint32_t def_bound = (uint32_t)std::min<uint64_t>((uint64_t)kPoolParts * state_cap, B.cap);
+        {
+            TimedLaunch tl(T, st, TC_SORT);
+            const int kb = (int)std::min<uint32_t>((def_bound + 255) / 256, 512u);
+            hipLaunchKernelGGL((k_bdef_keys<R>), dim3(kb), dim3(256), 0, st, P,
+                               (const PacketState<R> *)state_list<R>(B, din), B.q, state_cap, B.keys);
+        }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const uint32_t *def_count = (const uint32_t *)((const char *)B.q + offsetof(Queues, n_def_all));
+        if ((e = launch_sort_keys(B, def_bound, st, T, def_count)) != hipSuccess) return e;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
             hipLaunchKernelGGL((k_bscatter<R, KIND>), dim3(nb_scatter), dim3(256), 0, st, P, P.max_orders,
-                               state_list<R>(B, din), din, peels, B.q, state_cap);
+                               state_list<R>(B, din), din, peels, B.q, state_cap, (const uint32_t *)B.order);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         {
