@@ -164,12 +164,12 @@ __global__ void __launch_bounds__(256) k_bfirst(const BatchParams P, uint64_t b0
         if (__ballot(phase == BF_FORCED) == 0) {
             // no lane moves to a target: walks to the edge only
             for (;;) {
-                walk_batch_edge<R, kWalkBatch>(W, G);
+                walk_batch_edge<R, kBatchWalkBatch>(W, G);
                 if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
             }
         } else {
             for (;;) {
-                walk_batch<R, kWalkBatch>(W, G);
+                walk_batch<R, kBatchWalkBatch>(W, G);
                 if (__popcll(__ballot(W.done || phase == BF_IDLE)) >= kWaveRefill) break;
             }
         }

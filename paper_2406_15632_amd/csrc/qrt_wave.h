@@ -11,7 +11,8 @@
 
 namespace qrt {
 
-constexpr int kWalkBatch = 6;     // steps per load batch of the first flights
+constexpr int kWalkBatch = 8;     // steps per load batch of the first flights
+constexpr int kBatchWalkBatch = 6; // the same in batches (eight would take the kernel to two waves per SIMD)
 constexpr int kFlightBatch = 12;  // steps per load batch of the per-order walks (which run at low occupancy)
 
 // Blocks per CU of the per-order walk kernels (measured): at most three.  With
