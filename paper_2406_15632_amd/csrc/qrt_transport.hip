@@ -166,8 +166,11 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scan(uint32_t *__restrict_
 // Stable placement of the items of one block by digit.  The block takes its
 // items in rounds of kSortDigit, in order; inside a round, the lanes of a wave
 // with the same digit are found with one ballot per digit bit, and the waves'
-// counts per digit give each wave its start.  keys_out may be null (last
-// pass); vals_in null stands for the item numbers.
+// counts per digit give each item its place in an LDS tile that holds the
+// block's items ordered by digit (stably).  The tile is then written out in
+// order: its entries of one digit go to consecutive places, so the stores of a
+// wave coalesce instead of scattering over up to 64 digits.  keys_out may be
+// null (last pass); vals_in null stands for the item numbers.
 __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__restrict__ keys_in,
                                                               const uint32_t *__restrict__ vals_in, uint32_t count,
                                                               int shift, const uint32_t *__restrict__ hist,
@@ -178,18 +181,31 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
 {
     constexpr int kWaves = kSortDigit / 64;
     if (count_dev) count = min(count, *count_dev);
-    if (blockIdx.x * (uint32_t)kSortItems >= count) return;   // past the items (device count)
-    __shared__ uint32_t base[kSortDigit];
+    const uint32_t b0 = blockIdx.x * (uint32_t)kSortItems;
+    if (b0 >= count) return;   // past the items (device count)
+    __shared__ uint32_t base[kSortDigit];    // output place of the block's first item of each digit
+    __shared__ uint32_t next[kSortDigit];    // tile place of each digit's next item
+    __shared__ uint32_t first[kSortDigit];   // tile place of each digit's first item
     __shared__ uint32_t wc[kWaves][kSortDigit];
+    __shared__ uint32_t tile_key[kSortItems], tile_val[kSortItems];
     const int t = threadIdx.x, w = t >> 6;
+    const uint32_t n = count - b0 < (uint32_t)kSortItems ? count - b0 : (uint32_t)kSortItems;
     base[t] = tot[t];
     __syncthreads();
     const uint32_t start = block_exclusive_scan(base);
+    // this block's items of digit t: the blocks' starts inside the digit are scanned
+    const uint32_t off = hist[t * gridDim.x + blockIdx.x];
+    const uint32_t mine = (blockIdx.x + 1 < gridDim.x ? hist[t * gridDim.x + blockIdx.x + 1] : tot[t]) - off;
     __syncthreads();
-    base[t] = start + hist[t * gridDim.x + blockIdx.x];
+    base[t] = start + off;
+    next[t] = mine;
     for (int v = 0; v < kWaves; ++v) wc[v][t] = 0;
     __syncthreads();
-    const uint32_t b0 = blockIdx.x * (uint32_t)kSortItems;
+    const uint32_t tile_start = block_exclusive_scan(next);
+    __syncthreads();
+    next[t] = tile_start;
+    first[t] = tile_start;
+    __syncthreads();
     for (int r = 0; r < kSortItems / kSortDigit; ++r) {
         const uint32_t i = b0 + (uint32_t)(r * kSortDigit) + (uint32_t)t;
         const bool valid = i < count;
@@ -206,10 +222,10 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
         if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t pos = base[d] + rank;
+            uint32_t pos = next[d] + rank;
             for (int v = 0; v < w; ++v) pos += wc[v][d];
-            if (keys_out) keys_out[pos] = key;
-            vals_out[pos] = vals_in ? vals_in[i] : i;
+            tile_key[pos] = key;
+            tile_val[pos] = vals_in ? vals_in[i] : i;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -217,8 +233,15 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
             add += wc[v][t];
             wc[v][t] = 0;
         }
-        base[t] += add;
+        next[t] += add;
         __syncthreads();
+    }
+    for (uint32_t j = (uint32_t)t; j < n; j += kSortDigit) {
+        const uint32_t key = tile_key[j];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t pos = base[d] + (j - first[d]);
+        if (keys_out) keys_out[pos] = key;
+        vals_out[pos] = tile_val[j];
     }
 }
 
