@@ -23,9 +23,16 @@
 //   k_walk     persistent; walks every peel ray (adding e^-tau times its
 //              contribution to the image) and every flight (the states of the
 //              packets that stop inside the mesh go to the other live list).
-// Only the two persistent kernels walk the mesh; their per-ray events are a
-// few loads and stores, so they keep a small register footprint.  All physics
-// runs in k_first's events and in k_scatter, which is convergent.  Waves of
+//   from the first order of the late-order launch (qrt_set_tail) on:
+//   k_tail     persistent; a lane carries a live packet through its remaining
+//              orders (new direction, flight), keeping the state of every
+//              scattering it reaches in the other list (a region per XCD);
+//   k_def_keys and the radix sort: those scatterings in the order of their
+//              positions; then k_scatter (peel-offs only) and k_walk over them.
+// Only the persistent kernels walk the mesh; the per-ray events of the walks
+// are a few loads and stores, so they keep a small register footprint.  The
+// physics runs in k_first's events, in k_scatter, which is convergent, and in
+// k_tail's scattering events.  Waves of
 // the persistent kernels take work in blocks of 64 to 512 items from counters
 // of their XCD (WorkPool) and refill once every lane of the wave is idle, which
 // keeps a wave's rays together; the per-order walks hand out their items in
