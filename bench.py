@@ -9,8 +9,8 @@ FP64 optical-depth and image sums.  The mesh is resident in HBM before timing.
 The JSON line carries
   value         photon packets/s over the timed steps (HIP events);
   roofline      of the dominant kernels, the walks (k_walk: peel-off rays and
-                flights of orders 1-3, then the deferred peel rays of the later
-                orders; k_tail: orders 4-20 in one launch): their algorithmic
+                flights of order 1, then the peel rays of the deferred later
+                scatterings; k_tail: orders 2-20 in one launch): their algorithmic
                 bytes (4 B per voxel visit + 24 B per peel-off contribution,
                 exact counts from the kernels' counters) over their time,
                 measured with HIP events that
@@ -764,9 +764,9 @@ def main():
             "unit": "GB/s",
             "frac": walk_gbps / HBM_PEAK_GBS,
             "traffic": walk_traffic,
-            "kernel": "the walk kernels, dominant together: k_walk (peel-off rays and flights of orders 1-3, "
-                      "then the deferred peel rays of the later orders) and k_tail (orders 4-20 in one launch), "
-                      "all their dispatches of one transport launch together",
+            "kernel": "the walk kernels, dominant together: k_walk (peel-off rays and flights of order 1, "
+                      "then the peel rays of the deferred later scatterings) and k_tail (orders 2-20 in one "
+                      "launch), all their dispatches of one transport launch together",
             "alg_bytes_per_launch": walk_bytes,
             "alg_bytes": "4 B per cell visit of the walks (all visits but those of the first flights; "
                          "k_tail's flights included) + 24 B per binned peel-off contribution, exact counts "
@@ -781,7 +781,7 @@ def main():
             "frac_of_measured_copy": walk_gbps / copy_gbps,
             "step": {
                 "kernel": "the whole transport step qrt_run (k_key_emit, the two-pass radix sort, k_first, "
-                          "per scattering order 1-3 k_scatter and k_walk, then k_tail, k_def_keys and the "
+                          "k_scatter and k_walk of order 1, then k_tail, k_def_keys and the "
                           "radix sort of the deferred scatterings, their k_scatter and k_walk) over the timed "
                           "region",
                 "achieved": achieved, "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

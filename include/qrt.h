@@ -174,7 +174,7 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
 int qrt_set_overlap(qrt_ctx *ctx, int enable);
 
 /* Late scattering orders in one launch (Sec. 2.2, 3.5: the same transport,
-   launched differently).  From order first_order on (default 4; 0 turns it
+   launched differently).  From order first_order on (default 2; 0 turns it
    off) a run carries each live packet through its remaining orders in one
    kernel, a lane per packet, keeping the state of every scattering it passes;
    one launch then computes the peel-off contributions of all those

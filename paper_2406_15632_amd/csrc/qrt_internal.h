@@ -204,10 +204,12 @@ struct TransportParams {
     uint64_t def_limit;            // at most this many deferred scatterings (0: as many as the buffers hold)
 };
 
-// First scattering order that the late-order launch takes over by default:
-// from it on the live packets are few, and per-order launches would each wait
-// for their longest walk at low occupancy.
-constexpr int kTailFrom = 4;
+// First scattering order that the late-order launch takes over by default.
+// From the second order on the live packets no longer fill the GPU well, and
+// per-order launches would each wait for their longest walk; the deferred
+// scatterings, sorted by position, walk their peel rays as coherently as a
+// per-order list.
+constexpr int kTailFrom = 2;
 
 // one training batch of the surrogate network
 struct MlpBatch {
