@@ -588,45 +588,51 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
 }
 
-// Bits dropped from the 15-bit keys of the deferred scatterings' sort, and its
-// radix passes (8 bits each)
-constexpr int kDefKeyShift = 0;
-constexpr int kDefSortPasses = 2;
+// Sort key of a deferred scattering of the late-order launch: the cell of a
+// 32^3 grid over the box that holds the scattering point, in Morton order (15
+// bits).  Sorted by these keys, a wave of the deferred walk takes the peel rays
+// of 64 scatterings from one small part of the mesh instead of those that a
+// wave of k_tail happened to reach together.  lo and scale (32 / box size) per
+// axis come from box_key_frame.
+struct KeyFrame {
+    float lo[3], scale[3];
+};
 
-// Sort keys of the scatterings deferred by the late-order launch: the cell of
-// a 32^3 grid over the box that holds the scattering point, in Morton order
-// (15 bits); entries reserved but not deferred get the largest key.  Their
-// count goes to n_def_all.  Sorted by these keys, a wave of the deferred walk
-// takes the peel rays of 64 scatterings from one small part of the mesh
-// instead of those that a wave of k_tail happened to reach together.
+__device__ __forceinline__ KeyFrame box_key_frame(const DevGrid &g)
+{
+    KeyFrame f;
+    for (int a = 0; a < 3; ++a) {
+        f.lo[a] = (float)g.lo[a];
+        f.scale[a] = (float)(32.0 / (g.hi[a] - g.lo[a]));
+    }
+    return f;
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_def_keys(const TransportParams P, const PacketState<R> *__restrict__ pks,
-                                                  Queues *__restrict__ Q, uint32_t def_cap, uint32_t *__restrict__ keys)
+__device__ __forceinline__ uint32_t cell_key(const KeyFrame &f, const R p[3])
+{
+    uint32_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        const float u = ((float)p[a] - f.lo[a]) * f.scale[a];
+        c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
+    }
+    uint32_t key = 0;
+    for (int b = 0; b < 5; ++b)
+        key |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) | ((c[2] >> b) & 1u) << (3 * b + 2);
+    return key;
+}
+
+// The keys that k_tail stored beside its deferred scatterings (region layout,
+// 0xFFFF for entries reserved but not deferred), gathered in list order for the
+// sort; the scatterings' count goes to n_def_all.
+__global__ void __launch_bounds__(256) k_def_keys(const uint32_t *__restrict__ region_keys, Queues *__restrict__ Q,
+                                                  uint32_t def_cap, uint32_t *__restrict__ keys)
 {
     const DeferredList D = deferred_list(Q, def_cap);
     const uint32_t n = (uint32_t)D.end[kPoolParts - 1];
     if (blockIdx.x == 0 && threadIdx.x == 0) Q->n_def_all[0] = n;
-    float lo[3], scale[3];
-    for (int a = 0; a < 3; ++a) {
-        lo[a] = (float)P.grid.lo[a];
-        scale[a] = (float)(32.0 / (P.grid.hi[a] - P.grid.lo[a]));
-    }
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const PacketState<R> *s = pks + deferred_slot(D, i);
-        uint32_t key = 0xFFFFu;
-        if (s->order != kNoState) {
-            uint32_t c[3];
-            for (int a = 0; a < 3; ++a) {
-                const float u = ((float)s->p[a] - lo[a]) * scale[a];
-                c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
-            }
-            key = 0;
-            for (int b = 0; b < 5; ++b)
-                key |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) |
-                       ((c[2] >> b) & 1u) << (3 * b + 2);
-        }
-        keys[i] = key >> kDefKeyShift;
-    }
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        keys[i] = region_keys[deferred_slot(D, i)];
 }
 
 // --------------------------------------------------------------------------
@@ -842,8 +848,9 @@ template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PacketState<R> *__restrict__ states, uint32_t state_cap,
-                                              Queues *__restrict__ Q)
+                                              uint32_t *__restrict__ region_keys, Queues *__restrict__ Q)
 {
+    const KeyFrame kf = box_key_frame(P.grid);
     __shared__ ObsTable<R> T;
     load_obs(P, T);
     const RayGrid<R> G = ray_grid<R>(P.grid);
@@ -900,6 +907,7 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
                     PacketState<R> d = s;
                     d.order = fits ? (uint32_t)order : kNoState;
                     sreg[slot] = d;
+                    region_keys[(size_t)region * state_cap + slot] = fits ? cell_key(kf, s.p) : 0xFFFFu;
                 }
             }
             R n_ax[3] = {(R)0, (R)0, (R)0};
@@ -1133,11 +1141,11 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
             if (sur)
                 hipLaunchKernelGGL((k_tail<R, KIND, SRC, true>), dim3(nb_tail_sur), dim3(256), 0, st, P, P.tail_from,
                                    (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                                   state_cap, B.q);
+                                   state_cap, B.sort_tmp, B.q);
             else
                 hipLaunchKernelGGL((k_tail<R, KIND, SRC, false>), dim3(nb_tail), dim3(256), 0, st, P, P.tail_from,
                                    (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
-                                   state_cap, B.q);
+                                   state_cap, B.sort_tmp, B.q);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         // the deferred scatterings in the order of their positions (the sort's count is
@@ -1148,12 +1156,12 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
         {
             TimedLaunch tl(T, st, TC_SORT);
             const int kb = (int)std::min<uint32_t>((def_bound + 255) / 256, 512u);
-            hipLaunchKernelGGL((k_def_keys<R>), dim3(kb), dim3(256), 0, st, P,
-                               (const PacketState<R> *)state_list<R>(B, din), B.q, state_cap, B.keys);
+            hipLaunchKernelGGL(k_def_keys, dim3(kb), dim3(256), 0, st, (const uint32_t *)B.sort_tmp, B.q, state_cap,
+                               B.keys);
         }
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const uint32_t *def_count = (const uint32_t *)((const char *)B.q + offsetof(Queues, n_def_all));
-        if ((e = launch_sort_keys(B, def_bound, st, T, def_count, kDefSortPasses)) != hipSuccess) return e;
+        if ((e = launch_sort_keys(B, def_bound, st, T, def_count)) != hipSuccess) return e;
         {
             TimedLaunch tl(T, st, TC_SCATTER);
             if (sur)
