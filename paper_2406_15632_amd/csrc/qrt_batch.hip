@@ -572,16 +572,12 @@ __global__ void __launch_bounds__(256) k_bdef_keys(const BatchParams P, const Pa
         if (st->order != kNoState) {
             const int sc = (int)st->next_dim;
             const BScene &S = P.scenes[sc];
-            uint32_t c[3];
+            KeyFrame f;
             for (int a = 0; a < 3; ++a) {
-                const float u = ((float)st->p[a] - (float)S.lo[a]) * (float)(32.0 / (S.n[a] * S.h[a]));
-                c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
+                f.lo[a] = (float)S.lo[a];
+                f.scale[a] = (float)(32.0 / (S.n[a] * S.h[a]));
             }
-            uint32_t m = 0;
-            for (int b = 0; b < 5; ++b)
-                m |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) |
-                     ((c[2] >> b) & 1u) << (3 * b + 2);
-            key = ((uint32_t)(sc - P.scene_base) << pos_bits) | (m >> (15 - pos_bits));
+            key = ((uint32_t)(sc - P.scene_base) << pos_bits) | (cell_key(f, st->p) >> (15 - pos_bits));
         }
         keys[i] = key;
     }

@@ -362,10 +362,9 @@ hipError_t launch_batch(const BatchParams &P, const uint64_t *begin, int precisi
 
 // order[0 .. count) = the packets 0 .. count-1 sorted by keys[j] (kSortBits bits), stably; count <= kChunk.
 // Two radix passes of 8 bits through B.sort_tmp, histograms in B.hist.
-// count_dev (optional): a device word that lowers the count when the kernels run;
-// passes 1 for keys below 256.
+// count_dev (optional): a device word that lowers the count when the kernels run.
 hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer = nullptr,
-                            const uint32_t *count_dev = nullptr, int passes = 2);
+                            const uint32_t *count_dev = nullptr);
 
 // One chunk of packets first .. first+count-1 (count <= kChunk) through every
 // scattering order: first flight, then per order a scatter kernel and a walk

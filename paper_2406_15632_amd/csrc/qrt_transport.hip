@@ -253,7 +253,7 @@ __global__ void __launch_bounds__(kSortDigit) k_digit_scatter(const uint32_t *__
 }
 
 hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream_t st, KernelTimer *timer,
-                            const uint32_t *count_dev, int passes)
+                            const uint32_t *count_dev)
 {
     if (count == 0) return hipSuccess;
     if (count > kChunk) return hipErrorInvalidValue;
@@ -261,15 +261,13 @@ hipError_t launch_sort_keys(const TransportBuffers &B, uint32_t count, hipStream
     const int nb = (int)((count + kSortItems - 1) / kSortItems);
     uint32_t *tot = B.hist + (size_t)kSortDigit * (kChunk / kSortItems);
     uint32_t *tmp_keys = B.sort_tmp, *tmp_vals = B.sort_tmp + B.cap;
-    // low digit: keys and packet numbers into the scratch lists (or, for keys of
-    // one digit, the packet numbers into order)
+    // low digit: keys and packet numbers into the scratch lists
     hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys, count, 0, B.hist,
                        count_dev);
     hipLaunchKernelGGL(k_digit_scan, dim3(kSortDigit), dim3(kSortDigit), 0, st, B.hist, nb, tot);
     hipLaunchKernelGGL(k_digit_scatter, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)B.keys,
                        (const uint32_t *)nullptr, count, 0, (const uint32_t *)B.hist, (const uint32_t *)tot,
-                       passes == 1 ? (uint32_t *)nullptr : tmp_keys, passes == 1 ? B.order : tmp_vals, count_dev);
-    if (passes == 1) return hipGetLastError();
+                       tmp_keys, tmp_vals, count_dev);
     // high digit: the packet numbers into order
     hipLaunchKernelGGL(k_digit_hist, dim3(nb), dim3(kSortDigit), 0, st, (const uint32_t *)tmp_keys, count, 8, B.hist,
                        count_dev);
@@ -588,16 +586,6 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         flush_counters<2>(P.counters, {CNT_SCATTERINGS, CNT_OCCLUDED}, {n_scat, n_occ});
 }
 
-// Sort key of a deferred scattering of the late-order launch: the cell of a
-// 32^3 grid over the box that holds the scattering point, in Morton order (15
-// bits).  Sorted by these keys, a wave of the deferred walk takes the peel rays
-// of 64 scatterings from one small part of the mesh instead of those that a
-// wave of k_tail happened to reach together.  lo and scale (32 / box size) per
-// axis come from box_key_frame.
-struct KeyFrame {
-    float lo[3], scale[3];
-};
-
 __device__ __forceinline__ KeyFrame box_key_frame(const DevGrid &g)
 {
     KeyFrame f;
@@ -606,20 +594,6 @@ __device__ __forceinline__ KeyFrame box_key_frame(const DevGrid &g)
         f.scale[a] = (float)(32.0 / (g.hi[a] - g.lo[a]));
     }
     return f;
-}
-
-template <typename R>
-__device__ __forceinline__ uint32_t cell_key(const KeyFrame &f, const R p[3])
-{
-    uint32_t c[3];
-    for (int a = 0; a < 3; ++a) {
-        const float u = ((float)p[a] - f.lo[a]) * f.scale[a];
-        c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
-    }
-    uint32_t key = 0;
-    for (int b = 0; b < 5; ++b)
-        key |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) | ((c[2] >> b) & 1u) << (3 * b + 2);
-    return key;
 }
 
 // The keys that k_tail stored beside its deferred scatterings (region layout,

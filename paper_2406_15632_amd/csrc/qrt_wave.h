@@ -274,6 +274,30 @@ __device__ __forceinline__ void wave_merge_add(bool on, uint64_t key, double v0,
     }
 }
 
+// Sort key of a deferred scattering of the late-order launch: the cell of a
+// 32^3 grid over the box that holds the scattering point, in Morton order (15
+// bits).  Sorted by these keys, a wave of the deferred walk takes the peel rays
+// of 64 scatterings from one small part of the mesh instead of those that a
+// wave of the late-order kernel happened to reach together.  The frame holds
+// the box's low corner and 32 / its size per axis.
+struct KeyFrame {
+    float lo[3], scale[3];
+};
+
+template <typename R>
+__device__ __forceinline__ uint32_t cell_key(const KeyFrame &f, const R p[3])
+{
+    uint32_t c[3];
+    for (int a = 0; a < 3; ++a) {
+        const float u = ((float)p[a] - f.lo[a]) * f.scale[a];
+        c[a] = u > 0.0f ? (u < 31.0f ? (uint32_t)u : 31u) : 0u;
+    }
+    uint32_t key = 0;
+    for (int b = 0; b < 5; ++b)
+        key |= ((c[0] >> b) & 1u) << (3 * b) | ((c[1] >> b) & 1u) << (3 * b + 1) | ((c[2] >> b) & 1u) << (3 * b + 2);
+    return key;
+}
+
 // Octahedral map of a direction to 2 x 8 bits, interleaved (nearby directions
 // get nearby keys).
 __device__ __forceinline__ uint32_t interleave2(uint32_t qu, uint32_t qv, int bits)
