@@ -152,3 +152,43 @@ def test_batch_tail_equals_per_order_launches(ctx, Q):
         assert cnt == cref, f"tail {tail} limit {limit}"
         for i in range(len(bs)):
             assert_sum_order_equal(img[i], ref[i], f"scene {i} tail {tail} limit {limit}")
+
+
+def test_tail_ragged_runs_fp64_parity(ctx, Q):
+    """Runs of 1, 257 and 1000 packets (the deferred list and its sort nearly
+    empty, a ragged last block) with the late-order launch from order 2,
+    FP64, disk at 32^3, 20 orders, against the oracle."""
+    sc = scenes.disk128(n=32).replace(npix=64, fp64=True)
+    for first, count in ((1, 1), (2, 257), (7777, 1000)):
+        _say(f"tail ragged run first={first} count={count}")
+        ctx.set_scene(sc, kind=Q.HALTON, precision=None)
+        ctx.set_tail(2)
+        ctx.reset_images()
+        ctx.run(first, count)
+        g, cg = ctx.read_images(normalized=False), ctx.counters()
+        o, co, _ = O.run(sc, O.HALTON, first=first, count=count, nthreads=8)
+        if o[0, 0].max() > 0:
+            assert_fp64_parity(g / count, o, f"first {first} count {count}")
+        else:
+            assert np.all(g == 0)
+        assert_counters_close(cg, co, f"first {first} count {count}")
+
+
+def test_tail_across_chunks(ctx, Q):
+    """One run of 2^22 + 12345 packets, which the library splits into two
+    chunks (each with its own late-order launch and deferred sort), against
+    the same packets in two runs split elsewhere: disk at 32^3, 20 orders,
+    FP32; images up to the order of the sums, counters equal."""
+    sc = scenes.disk128(n=32).replace(npix=64)
+    n = (1 << 22) + 12345
+    _say("tail across chunks: one run")
+    one, c1 = run(ctx, sc, Q.SOBOL, n, 2)
+    _say("tail across chunks: two runs")
+    ctx.set_scene(sc, kind=Q.SOBOL)
+    ctx.set_tail(2)
+    ctx.reset_images()
+    ctx.run(1, 3000001)
+    ctx.run(3000002, n - 3000001)
+    two, c2 = ctx.read_images(normalized=False), ctx.counters()
+    assert c1 == c2
+    assert_sum_order_equal(two, one, "chunks")
