@@ -523,6 +523,20 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         R n_ax[3];
         cross3(s.k, s.m, n_ax);
         uint32_t queued = 0;   // rays of this wave's 64-packet block queued for the network (wave-uniform)
+        // the scattering point's cell of the surrogate's domain and its network inputs, which do not
+        // depend on the observer
+        int cell = -1;
+        float x_pos[3] = {0.0f, 0.0f, 0.0f};
+        if constexpr (SUR) {
+            if (valid) {
+                cell = dom_cell(P.sur, (double)s.p[0], (double)s.p[1], (double)s.p[2]);
+                if (cell >= 0) {
+                    float x[5];
+                    mlp_inputs(P.sur.in, (double)s.p[0], (double)s.p[1], (double)s.p[2], 0, x);
+                    x_pos[0] = x[0]; x_pos[1] = x[1]; x_pos[2] = x[2];
+                }
+            }
+        }
         for (int ob = 0; ob < P.n_obs; ++ob) {
             bool vis = false, occ = false;
             R c3[3] = {(R)0, (R)0, (R)0};
@@ -536,17 +550,16 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
             }
             bool use = false;
             if constexpr (SUR) {
-                if (vis) {
-                    const int cell = dom_cell(P.sur, (double)s.p[0], (double)s.p[1], (double)s.p[2]);
-                    use = cell >= 0 && P.sur.valid[(size_t)ob * cells + (size_t)cell] != 0;
-                }
+                if (vis) use = cell >= 0 && P.sur.valid[(size_t)ob * cells + (size_t)cell] != 0;
                 n_fb += (vis && !use) ? 1u : 0u;
                 n_sur += use ? 1u : 0u;
                 // the block's queue region: its queued rays, observer after observer
                 const uint64_t m = __ballot(use);
                 if (use) {
                     SurQuery q;
-                    mlp_inputs(P.sur.in, (double)s.p[0], (double)s.p[1], (double)s.p[2], ob, q.x);
+                    q.x[0] = x_pos[0]; q.x[1] = x_pos[1]; q.x[2] = x_pos[2];
+                    q.x[3] = P.sur.in.obs_in[ob][0];
+                    q.x[4] = P.sur.in.obs_in[ob][1];
                     q.key = (uint32_t)ob * 3u * (uint32_t)((size_t)P.npix * (size_t)P.npix) + pix;
                     q.c[0] = (double)c3[0];
                     q.c[1] = (double)c3[1];
