@@ -177,8 +177,8 @@ int qrt_set_overlap(qrt_ctx *ctx, int enable);
    launched differently).  From order first_order on (default 2; 0 turns it
    off) a run carries each live packet through its remaining orders in one
    kernel, a lane per packet, keeping the state of every scattering it passes;
-   one launch then computes the peel-off contributions of all those
-   scatterings and one more walks their rays, instead of two launches per
+   those scatterings are sorted by position, one launch computes their peel-off
+   contributions and one more walks their rays, instead of two launches per
    order.  Images differ from the per-order launches only in the order of the
    FP64 sums, counters not at all.  max_deferred bounds the scatterings held
    (0: as many as the live-packet list and the peel-ray buffer hold); a
@@ -189,7 +189,11 @@ int qrt_set_overlap(qrt_ctx *ctx, int enable);
    (not with per-order images), and for batches, where the orders counted are
    those of the batch's deepest scene; a first_order above the largest
    max_orders leaves every order to the per-order launches.  Joins pending
-   overlapped runs.  QRT_INVALID_ARG for first_order 1 or below 0. */
+   overlapped runs.  In very thick scenes, where packets scatter more often
+   than the list holds (more than about once per packet after the first
+   order), a later first_order (4) keeps the late orders' peel-offs from
+   spilling into the late-order kernel.  QRT_INVALID_ARG for first_order 1 or
+   below 0. */
 int qrt_set_tail(qrt_ctx *ctx, int first_order, uint64_t max_deferred);
 
 /* The context stream waits for every overlapped run still pending
