@@ -817,7 +817,9 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
 // Scattering orders order0 .. max_orders of the packets live after order
 // order0 - 1, in one launch.  A lane takes a packet and carries it through its
 // remaining orders: at each scattering the packet's state is appended to the
-// list of deferred scatterings (one atomic per wave), the albedo and the new
+// list of deferred scatterings (one atomic per wave; the list is split into
+// one region per XCD, and the sort key of the scattering's position goes to
+// region_keys at the same place), the albedo and the new
 // direction and flight depth are applied as k_scatter applies them, and the
 // flight is walked as k_walk walks it, up to the next scattering where it
 // stopped inside the mesh.  The peel-offs of the deferred scatterings are left
