@@ -157,7 +157,9 @@ int qrt_set_sequence(qrt_ctx *ctx, int kind, uint64_t seed, uint64_t n_total);
 int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precision, int peel_mode);
 
 /* Transport packets first_index .. first_index+count-1 (first_index >= 1) and
-   add their contributions to the images.  Asynchronous on the context stream. */
+   add their contributions to the images.  Asynchronous on the context stream.
+   Indices stay below 2^32 for the low-discrepancy sets and below 2^48 for
+   QRT_PHILOX, else QRT_UNSUPPORTED. */
 int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
 
 /* Overlapped runs (off by default).  While enabled, qrt_run puts each chunk
@@ -209,8 +211,8 @@ int qrt_join(qrt_ctx *ctx);
    of 2^16 packets; it calls no hipMalloc, hipFree or other allocating routine.
    The grid, images, counters and tables are the context's, allocated by the
    set-up calls.  Limits: QRT_UNSUPPORTED when a chunk's buffers exceed the
-   scratch (more than 4 observers in FP64, more than 11 in FP32; with the
-   surrogate peel-off, whose queue takes scratch too, more than 2 and 4);
+   scratch (more than 4 observers in FP64, more than 12 in FP32; with the
+   surrogate peel-off, whose queue takes scratch too, more than 2 and 5);
    QRT_BAD_STATE for Faure points whose tables no earlier qrt_run or
    qrt_generate_points built for this many coordinates.  All contexts on one
    device share its scratch: calls that overlap on one device (other streams,

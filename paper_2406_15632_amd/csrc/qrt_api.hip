@@ -261,6 +261,9 @@ int check_index_range(qrt_ctx *c, int kind, uint64_t n_total, uint64_t first, ui
     if (kind != QRT_PHILOX && last > 0xFFFFFFFFull)
         return fail(c, QRT_UNSUPPORTED, "low-discrepancy indices must stay below 2^32 (last %llu)",
                     (unsigned long long)last);
+    // a packet's state keeps its index in 48 bits
+    if (last >> kIdxBits) return fail(c, QRT_UNSUPPORTED, "indices must stay below 2^48 (last %llu)",
+                                      (unsigned long long)last);
     if (kind == QRT_HAMMERSLEY && last > n_total)
         return fail(c, QRT_UNSUPPORTED, "Hammersley index %llu beyond N = %llu", (unsigned long long)last,
                     (unsigned long long)n_total);
@@ -900,8 +903,8 @@ int qrt_run_static(qrt_ctx *c, uint64_t first, uint64_t count)
     if (need > kStaticScratchBytes)
         return fail(c, QRT_UNSUPPORTED,
                     "%d observers at %s need %zu bytes of scratch per chunk of %llu packets; the static "
-                    "scratch holds %zu (exact peel-off: at most 4 observers in FP64, 11 in FP32; surrogate "
-                    "peel-off: 2 in FP64, 4 in FP32)",
+                    "scratch holds %zu (exact peel-off: at most 4 observers in FP64, 12 in FP32; surrogate "
+                    "peel-off: 2 in FP64, 5 in FP32)",
                     c->n_obs, c->precision == QRT_FP64 ? "FP64" : "FP32", need,
                     (unsigned long long)kStaticChunk, kStaticScratchBytes);
     if (count == 0) return QRT_OK;

@@ -215,10 +215,10 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         int s = 0;
         if (valid) {
             st = pks[def_cap ? deferred_slot(D, perm[i]) : i];
-            valid = !def_cap || st.order != kNoState;
+            valid = !def_cap || state_order(st.word) != kNoState;
         }
         if (valid) {
-            s = (int)st.next_dim;
+            s = (int)state_tag(st.word);
             n_scat++;
         }
         const BScene &S = P.scenes[s];
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(256) k_bscatter(const BatchParams P, int order
         if (valid) {
             if (order < S.max_orders) {
                 uint32_t x[3];
-                seq_triple<KIND>(scene_seq(P, S), st.idx, first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
+                seq_triple<KIND>(scene_seq(P, S), state_idx(st.word), first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
                 scatter_packet<R>(V, st, n_ax, x);
             } else {
                 st.target = -1.0;   // the scene's last scattering: no further flight
@@ -391,7 +391,7 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                 slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
                 if (ps->target >= 0.0) {
-                    s = (int)ps->next_dim;
+                    s = (int)state_tag(ps->word);
                     const R p0[3] = {ps->p[0], ps->p[1], ps->p[2]};
                     const R k0[3] = {ps->k[0], ps->k[1], ps->k[2]};
                     G = lane_grid<R>(P.scenes[s]);
@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
         uint64_t item = 0;
         if (pool.take(!has, n, &Q->work[2][0][0], item)) {
             st = pks[item];
-            s = (int)st.next_dim;
+            s = (int)state_tag(st.word);
             order = order0;
             has = true;
             at_scatter = true;
@@ -484,7 +484,7 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
                 const uint32_t slot = sbase + (uint32_t)__popcll(ms & lanes_below_mask());
                 if (slot < state_cap) {
                     PacketState<R> d = st;
-                    d.order = fits ? (uint32_t)order : kNoState;
+                    d.word = with_order(d.word, fits ? (uint32_t)order : kNoState);
                     sreg[slot] = d;
                 }
             }
@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
             if (at_scatter) {
                 if (order < S.max_orders) {
                     uint32_t x[3];
-                    seq_triple<KIND>(scene_seq(P, S), st.idx, first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
+                    seq_triple<KIND>(scene_seq(P, S), state_idx(st.word), first_scatter_dim(S.src_kind) + 3 * (order - 1), x);
                     scatter_packet<R>(V, st, n_ax, x);
                     walk_begin(W, G, st.p, st.k, WALK_MOVE, st.target);
                     moving = true;
@@ -569,8 +569,8 @@ __global__ void __launch_bounds__(256) k_bdef_keys(const BatchParams P, const Pa
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const PacketState<R> *st = pks + deferred_slot(D, i);
         uint32_t key = 0xFFFFu;
-        if (st->order != kNoState) {
-            const int sc = (int)st->next_dim;
+        if (state_order(st->word) != kNoState) {
+            const int sc = (int)state_tag(st->word);
             const BScene &S = P.scenes[sc];
             KeyFrame f;
             for (int a = 0; a < 3; ++a) {

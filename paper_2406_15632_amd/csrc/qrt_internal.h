@@ -226,15 +226,34 @@ struct AdamStep {
 
 
 // A scattered packet between kernels: position, direction, reference axis,
-// Stokes weight, the optical depth of its next flight, point index and
-// bookkeeping.
+// Stokes weight, the optical depth of its next flight, and one word with the
+// point index (bits 0-47), a tag (bits 48-57: the scene of a batch) and a
+// scattering order (bits 58-63; the late-order launch's marks).  64 bytes in
+// FP32, so a state is one half of a 128-byte line.
 template <typename R>
 struct alignas(16) PacketState {
     R p[3], k[3], m[3], S[3];
     double target;
-    uint64_t idx;
-    uint32_t next_dim, order;
+    uint64_t word;
 };
+static_assert(sizeof(PacketState<float>) == 64, "an FP32 state fills 64 bytes");
+
+constexpr int kIdxBits = 48;        // point indices below 2^48
+constexpr uint32_t kTagMask = 1023; // scene numbers below 1024
+// order field of a deferred scattering that was reserved but not deferred
+constexpr uint32_t kNoState = 63;
+
+__host__ __device__ __forceinline__ uint64_t state_word(uint64_t idx, uint32_t tag, uint32_t order)
+{
+    return idx | ((uint64_t)(tag & kTagMask) << kIdxBits) | ((uint64_t)order << (kIdxBits + 10));
+}
+__host__ __device__ __forceinline__ uint64_t state_idx(uint64_t w) { return w & ((1ull << kIdxBits) - 1); }
+__host__ __device__ __forceinline__ uint32_t state_tag(uint64_t w) { return (uint32_t)(w >> kIdxBits) & kTagMask; }
+__host__ __device__ __forceinline__ uint32_t state_order(uint64_t w) { return (uint32_t)(w >> (kIdxBits + 10)); }
+__host__ __device__ __forceinline__ uint64_t with_order(uint64_t w, uint32_t order)
+{
+    return (w & ((1ull << (kIdxBits + 10)) - 1)) | ((uint64_t)order << (kIdxBits + 10));
+}
 
 // A peel-off ray waiting for its optical depth: start point, Stokes
 // contribution before attenuation, pixel offset and observer.

@@ -91,9 +91,9 @@ __device__ __forceinline__ void emit_packet(int src_kind, const double src[3], d
 // The state of a packet at its first scattering: position p + t k (the stop
 // of the forced flight; if rounding let the walk reach the edge first, the
 // exit point), direction k, reference axis the orthonormal completion of k,
-// Stokes weight (W1, 0, 0) with W1 = 1 - e^-tau1.  `tag` is the first
-// coordinate of the scattering flights in the single-scene path and the
-// scene number in a batch.
+// Stokes weight (W1, 0, 0) with W1 = 1 - e^-tau1.  `tag` is 0 in the
+// single-scene path and the scene number in a batch (below 1024); the point
+// index idx is below 2^48.
 template <typename R>
 __device__ __forceinline__ void first_state(const R p[3], const R k[3], R t, R W1, uint64_t idx, uint32_t tag,
                                             PacketState<R> &s)
@@ -105,9 +105,7 @@ __device__ __forceinline__ void first_state(const R p[3], const R k[3], R t, R W
     basis_of(k, s.m);
     s.S[0] = W1; s.S[1] = (R)0; s.S[2] = (R)0;
     s.target = 0.0;
-    s.idx = idx;
-    s.next_dim = tag;
-    s.order = 1;
+    s.word = state_word(idx, tag, 1);
 }
 
 // Dust and image geometry of one scene as the physics below needs them.

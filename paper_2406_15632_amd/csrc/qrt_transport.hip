@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         PacketState<R> s = {};
         if (valid) {
             s = pks[def_cap ? deferred_slot(D, perm[i]) : i];
-            valid = !def_cap || s.order != kNoState;
+            valid = !def_cap || state_order(s.word) != kNoState;
         }
         if (valid) {
             n_scat++;
@@ -587,7 +587,7 @@ __global__ void __launch_bounds__(256) k_scatter(const TransportParams P, int or
         }
         if (valid && order < P.max_orders) {   // never for the deferred scatterings (order = max_orders)
             uint32_t x[3];
-            seq_triple<KIND>(P.seq, s.idx, first_scatter_dim(SRC) + 3 * (order - 1), x);
+            seq_triple<KIND>(P.seq, state_idx(s.word), first_scatter_dim(SRC) + 3 * (order - 1), x);
             scatter_packet<R>(V, s, n_ax, x);
             pks[i] = s;
         }
@@ -894,7 +894,7 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
                 const uint32_t slot = sbase + (uint32_t)__popcll(ms & lanes_below_mask());
                 if (slot < state_cap) {
                     PacketState<R> d = s;
-                    d.order = fits ? (uint32_t)order : kNoState;
+                    d.word = with_order(d.word, fits ? (uint32_t)order : kNoState);
                     sreg[slot] = d;
                     region_keys[(size_t)region * state_cap + slot] = fits ? cell_key(kf, s.p) : 0xFFFFu;
                 }
@@ -936,7 +936,7 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
             if (at_scatter) {
                 if (order < P.max_orders) {
                     uint32_t x[3];
-                    seq_triple<KIND>(P.seq, s.idx, first_scatter_dim(SRC) + 3 * (order - 1), x);
+                    seq_triple<KIND>(P.seq, state_idx(s.word), first_scatter_dim(SRC) + 3 * (order - 1), x);
                     scatter_packet<R>(V, s, n_ax, x);
                     walk_begin(W, G, s.p, s.k, WALK_MOVE, s.target);
                     moving = true;

@@ -179,9 +179,6 @@ __host__ __device__ inline uint64_t scatter_block(uint64_t item, uint64_t total,
     return (((b * stride) % nfull) << kOrderBlockLog2) | (item & (kOrderBlock - 1));
 }
 
-// order field of a deferred scattering that was reserved but not deferred
-constexpr uint32_t kNoState = 0xFFFFFFFFu;
-
 // The items deferred by the late-order launch (scatterings) lie in kPoolParts
 // regions of def_cap items each, region r holding min(n_def[r], def_cap) of
 // them: item i of a launch over all of them is item i - start[r] of the region

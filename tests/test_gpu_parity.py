@@ -386,6 +386,13 @@ def test_errors_are_reported(ctx, Q):
     with pytest.raises(QRTError) as e:
         ctx.run((1 << 32) - 5, 10)
     assert e.value.code == Q.QRT_UNSUPPORTED
+    # Philox: any index below 2^48 (a packet's state keeps 48 bits of it)
+    ctx.set_sequence(Q.PHILOX, 7)
+    ctx.run((1 << 48) - 10, 9)
+    with pytest.raises(QRTError) as e:
+        ctx.run((1 << 48) - 5, 10)
+    assert e.value.code == Q.QRT_UNSUPPORTED
+    ctx.set_sequence(Q.SOBOL)
     ctx.set_transport(43, 1e-8, Q.FP64)
     with pytest.raises(QRTError) as e:
         ctx.run(1, 10)

@@ -81,12 +81,12 @@ def test_static_run_limits(Q):
             ctx.run_static(1, 100)
         assert e.value.code == Q.QRT_UNSUPPORTED
         ctx.set_transport(sc.max_orders, sc.tau_min, Q.FP32)
-        ctx.set_observers([(0.3 * i, 0.1) for i in range(12)], sc.npix, sc.half_width)
+        ctx.set_observers([(0.3 * i, 0.1) for i in range(13)], sc.npix, sc.half_width)
         with pytest.raises(QRTError) as e:
             ctx.run_static(1, 100)
         assert e.value.code == Q.QRT_UNSUPPORTED
-        # at the limits: 4 observers in FP64, 11 in FP32
-        ctx.set_observers([(0.3 * i, 0.1) for i in range(11)], sc.npix, sc.half_width)
+        # at the limits: 4 observers in FP64, 12 in FP32
+        ctx.set_observers([(0.3 * i, 0.1) for i in range(12)], sc.npix, sc.half_width)
         ctx.run_static(1, 100)
         ctx.set_transport(sc.max_orders, sc.tau_min, Q.FP64)
         ctx.set_observers([(0.3 * i, 0.1) for i in range(4)], sc.npix, sc.half_width)
