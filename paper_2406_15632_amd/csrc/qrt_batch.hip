@@ -376,17 +376,15 @@ __global__ void __launch_bounds__(256) k_bwalk(const BatchParams P, int order,
                 }
                 // appended rays are all visible
                 const PeelRay<R> r = peels[(uint64_t)g * P.group_cap + at];
-                {
-                    s = (int)(r.obs >> 4);
-                    obs = (int)(r.obs & 15u);
-                    const BScene &S = P.scenes[s];
-                    const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
-                    c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
-                    pix = r.pix;
-                    G = lane_grid<R>(S);
-                    walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
-                    kind = BW_PEEL;
-                }
+                s = (int)(r.obs >> 4);
+                obs = (int)(r.obs & 15u);
+                const BScene &S = P.scenes[s];
+                const R o[3] = {(R)S.obs[obs].o[0], (R)S.obs[obs].o[1], (R)S.obs[obs].o[2]};
+                c3[0] = r.c[0]; c3[1] = r.c[1]; c3[2] = r.c[2];
+                pix = r.pix;
+                G = lane_grid<R>(S);
+                walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
+                kind = BW_PEEL;
             } else {
                 slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
