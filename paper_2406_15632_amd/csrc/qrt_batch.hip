@@ -544,7 +544,7 @@ __global__ void __launch_bounds__(256) k_btail(const BatchParams P, int order0,
         for (;;) {
             // only lanes with a flight under way step, as in k_tail
             if (moving && !W.done) walk_batch<R, kFlightBatch>(W, G);
-            if (2 * __popcll(__ballot(moving && W.done)) >= movers) break;
+            if (8 * __popcll(__ballot(moving && W.done)) >= kTailDoneEighths * movers) break;
         }
     }
     flush_counters<6>(P.counters, {CNT_VISITS, CNT_SCATTERINGS, CNT_OCCLUDED, CNT_ESCAPES, CNT_PEELS, CNT_PEEL_RAYS},

@@ -831,8 +831,9 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
 // are marked kNoState); in the surrogate mode those rays all walk exactly and
 // count as fall-backs.  Lanes go back to the pool as their packets end
 // (coherence among the few late packets is low anyway): a wave stops walking
-// once half of its flights have ended.  Every packet gets the arithmetic of the
-// per-order launches, so images differ only in the order of the FP64 sums.
+// once kTailDoneEighths eighths of its flights have ended.  Every packet gets
+// the arithmetic of the per-order launches, so images differ only in the order
+// of the FP64 sums.
 template <typename R, int KIND, int SRC, bool SUR>
 __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
                                               const PacketState<R> *__restrict__ pks, int in,
@@ -951,8 +952,8 @@ __global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order
         for (;;) {
             // only lanes with a flight under way step (the call's own test of W.done
             // alone gave visit counts that varied from run to run in this kernel)
-            if (moving && !W.done) walk_batch<R, kFlightBatch>(W, G);
-            if (2 * __popcll(__ballot(moving && W.done)) >= movers) break;
+            if (moving && !W.done) walk_batch<R, kTailBatch>(W, G);
+            if (8 * __popcll(__ballot(moving && W.done)) >= kTailDoneEighths * movers) break;
         }
     }
     if constexpr (SUR)

@@ -14,6 +14,14 @@ namespace qrt {
 constexpr int kWalkBatch = 8;     // steps per load batch of the first flights
 constexpr int kBatchWalkBatch = 6; // the same in batches (eight would take the kernel to two waves per SIMD)
 constexpr int kFlightBatch = 12;  // steps per load batch of the per-order walks (which run at low occupancy)
+constexpr int kTailBatch = 8;     // the same in the late-order launch (flights of a few cells in thick scenes)
+
+// The late-order launch walks its flights until this share of them (in
+// eighths) has ended, then lets those lanes scatter and take new packets: a
+// lower share runs the scattering events at fewer active lanes, a higher one
+// leaves more lanes idle in the walk.  Five eighths measured best over thin
+// and thick discs and the uneven batch.
+constexpr int kTailDoneEighths = 5;
 
 // Blocks per CU of the per-order walk kernels (measured): at most three.  With
 // fewer waves the CU's vector L1 cache keeps more of each lane's current lines
