@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch-small", action="store_true", help="skip the batch of 256 small scenes")
     return ap.parse_args()
 
 
@@ -352,18 +353,20 @@ def other_workloads(qrt, stream):
     return res
 
 
-def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
+def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int = 64, **draw):
     """The batched workload: 64 uneven scenes drawn from `seed` (grids 32^3 to
     192^3, 2^16 to 2^24 packets, tau 0.1 to 20, g 0 to 0.8, albedo 0.3 to 0.9,
     envelope or disk, point source or sphere star, 1 to 4 observers, 1 to 20
-    orders, 128^2 images, FP32 rays with FP64 sums), Sobol points.  One batch
+    orders, 128^2 images, FP32 rays with FP64 sums), Sobol points; or another
+    draw of the same recipe (`n_scenes`, and the ranges in `draw`).  One batch
     run (every scene's packets in one launch sequence) against the same scenes
     run one after another through the single-scene calls, in stream order and
-    overlapped; meshes resident in HBM for all."""
+    overlapped (with the scene changes between runs, as a caller makes them),
+    and the runs alone; meshes resident in HBM for all."""
     import torch
 
     from synth import scenes
-    bs = scenes.uneven_batch(seed, 64)
+    bs = scenes.uneven_batch(seed, n_scenes, **draw)
     total = sum(sc.n_packets for sc in bs)
     grids = [torch.from_numpy(sc.kappa_rho).cuda() for sc in bs]
     ctx = qrt.Context(0, stream.cuda_stream)
@@ -392,14 +395,24 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
     seq_s = {}
     for overlap in (False, True):
         seq.set_overlap(overlap)
+        # in stream order, also the runs alone: events around each run leave out
+        # the scene changes between them (mesh upload, image buffers)
+        runs = [] if overlap else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                                   for _ in bs]
         e0.record(stream)
-        for sc, g in zip(bs, grids):
+        for i, (sc, g) in enumerate(zip(bs, grids)):
             seq.set_scene(sc, kind=qrt.SOBOL, grid=g, precision=qrt.FP32)
+            if runs:
+                runs[i][0].record(stream)
             seq.run(1, sc.n_packets)
+            if runs:
+                runs[i][1].record(stream)
         seq.join()
         e1.record(stream)
         torch.cuda.synchronize()
         seq_s["overlapped" if overlap else "stream_order"] = e0.elapsed_time(e1) * 1e-3
+        if runs:
+            seq_s["runs_only"] = sum(a.elapsed_time(b) for a, b in runs) * 1e-3
     ctx.close()
     seq.close()
     return {
@@ -410,6 +423,8 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2):
         "sequential_overlapped_ms": seq_s["overlapped"] * 1e3,
         "speedup": seq_s["stream_order"] / batch_s,
         "speedup_vs_sequential_overlapped": seq_s["overlapped"] / batch_s,
+        "sequential_runs_only_ms": seq_s["runs_only"] * 1e3,
+        "speedup_vs_sequential_runs_only": seq_s["runs_only"] / batch_s,
         "visits_per_packet": cnt["visits"] / cnt["packets"],
         "algorithmic_GBps": (4.0 * cnt["visits"] + 24.0 * cnt["peels"]) / (batch_s * steps) / 1e9,
     }
@@ -814,6 +829,11 @@ def main():
         result["sphere_star"] = sphere_star_section(qrt, stream)
     if not args.no_batch:
         result["batch"] = batch_section(qrt, stream)
+        # many small scenes, where one scene does not fill the GPU: 256 scenes,
+        # grids 32^3 to 96^3, 2^10 to 2^14 packets each
+        if not args.no_batch_small:
+            result["batch_small"] = batch_section(qrt, stream, n_scenes=256, sizes=(32, 96, 16),
+                                                  log2_packets=(10.0, 14.0))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()

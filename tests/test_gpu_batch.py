@@ -12,6 +12,10 @@ Gates:
   * the full-size workload of 64 scenes (grids 32^3 to 192^3, up to 20
     orders): FP64 with 2^10 packets per scene against the oracle, and FP32 at
     the full packet counts against single-scene runs.
+  * the workload of 256 small scenes (grids 32^3 to 96^3, 2^10 to 2^14
+    packets, so that a chunk spans many scenes and the sort keys spend eight
+    bits on the scene): FP32 against single-scene runs, FP64 of every eighth
+    scene against the oracle.
 """
 import sys
 
@@ -270,3 +274,37 @@ def test_full_batch_fp32_equals_single_runs(ctx, Q, full_batch, overlap):
     for i in range(len(full_batch)):
         assert_sum_order_equal(ctx.batch_read_images(i, normalized=False), single[i], f"scene {i}")
     assert cb == sum_counters(cs)
+
+
+# ------------------------------------------------------------------ many small scenes
+@pytest.fixture(scope="module")
+def small_scenes():
+    return scenes.uneven_batch(2406, 256, sizes=(32, 96, 16), log2_packets=(10.0, 14.0))
+
+
+def test_small_scenes_fp32_equals_single_runs(ctx, Q, small_scenes):
+    """256 scenes in one chunk (the timed small-scene workload) against one
+    single-scene run each."""
+    _say(f"256 small scenes fp32, {sum(s.n_packets for s in small_scenes)} packets")
+    single, cs = single_runs(ctx, Q, small_scenes, Q.SOBOL, 0, Q.FP32)
+    ctx.batch_set(small_scenes)
+    ctx.batch_reset()
+    ctx.batch_run(Q.SOBOL, 0, Q.FP32)
+    cb = ctx.counters()
+    for i in range(len(small_scenes)):
+        assert_sum_order_equal(ctx.batch_read_images(i, normalized=False), single[i], f"scene {i}")
+    assert cb == sum_counters(cs)
+
+
+def test_small_scenes_fp64_sampled_against_oracle(ctx, Q, small_scenes):
+    """The same batch in FP64 with 2^9 packets per scene; every eighth scene
+    against the oracle."""
+    n = 1 << 9
+    _say("256 small scenes fp64, 2^9 packets per scene")
+    ctx.batch_set(small_scenes, counts=[n] * len(small_scenes))
+    ctx.batch_reset()
+    ctx.batch_run(Q.SOBOL, 0, Q.FP64)
+    for i in range(0, len(small_scenes), 8):
+        sc = small_scenes[i]
+        o, _, _ = O.run(sc, O.SOBOL, 1, n, nthreads=8)
+        assert_fp64_parity(ctx.batch_read_images(i), o, f"scene {i} n={sc.n[0]} orders={sc.max_orders}")
