@@ -359,7 +359,8 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
     envelope or disk, point source or sphere star, 1 to 4 observers, 1 to 20
     orders, 128^2 images, FP32 rays with FP64 sums), Sobol points; or another
     draw of the same recipe (`n_scenes`, and the ranges in `draw`).  One batch
-    run (every scene's packets in one launch sequence) against the same scenes
+    run (every scene's packets in one launch sequence; in stream order, and with
+    its chunks overlapped on the internal streams) against the same scenes
     run one after another through the single-scene calls, in stream order and
     overlapped (with the scene changes between runs, as a caller makes them),
     and the runs alone; meshes resident in HBM for all."""
@@ -386,6 +387,15 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
     batch_wall = (time.perf_counter() - w0) / steps
     batch_s = e0.elapsed_time(e1) * 1e-3 / steps
     cnt = ctx.counters()
+    # the batch's chunks overlapped on the context's internal streams
+    ctx.set_overlap(True)
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)
+    ctx.join()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ov_s = e0.elapsed_time(e1) * 1e-3 / steps
     # the same scenes one after another
     seq = qrt.Context(0, stream.cuda_stream)
     for sc, g in zip(bs[:2], grids[:2]):             # warm-up of the single-scene kernels
@@ -422,7 +432,9 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
         "sequential_overlapped_packets_per_s": total / seq_s["overlapped"],
         "sequential_overlapped_ms": seq_s["overlapped"] * 1e3,
         "speedup": seq_s["stream_order"] / batch_s,
+        "batch_overlapped_packets_per_s": total / batch_ov_s, "batch_overlapped_ms": batch_ov_s * 1e3,
         "speedup_vs_sequential_overlapped": seq_s["overlapped"] / batch_s,
+        "speedup_overlapped_vs_sequential_overlapped": seq_s["overlapped"] / batch_ov_s,
         "sequential_runs_only_ms": seq_s["runs_only"] * 1e3,
         "speedup_vs_sequential_runs_only": seq_s["runs_only"] / batch_s,
         "visits_per_packet": cnt["visits"] / cnt["packets"],
@@ -696,7 +708,7 @@ def main():
             if events is not None:
                 events[j][1].record(stream)
 
-    # consecutive runs overlap on the context's two internal streams: the next run
+    # consecutive runs overlap on the context's three internal streams: the next run
     # starts beside the last scattering orders of the previous one
     overlap = not args.no_overlap
     ctx.set_overlap(overlap)
@@ -769,7 +781,7 @@ def main():
                         "hammersley (N=2^22), philox; FP32 rays, FP64 optical-depth and image sums",
             "packets_per_step": len(kinds) * N,
             "sequences": list(KIND_ORDER),
-            "runs": "five qrt_run calls per step; consecutive runs overlapped on the context's two internal "
+            "runs": "five qrt_run calls per step; consecutive runs overlapped on the context's three internal "
                     "streams (qrt_set_overlap)" if overlap else "five qrt_run calls per step, in stream order",
         },
         "roofline": {

@@ -163,16 +163,18 @@ int qrt_set_transport(qrt_ctx *ctx, int max_orders, double tau_min, int precisio
 int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
 
 /* Overlapped runs (off by default).  While enabled, qrt_run puts each chunk
-   on one of two internal streams of the context, with buffers of its own,
-   after everything already enqueued on the context stream; its completion
-   joins the context stream at the next call of the library on this context
-   (any call but the host-side setters), or at qrt_join.  Consecutive runs then
-   overlap: the next run starts while the last scattering orders of the
-   previous one, which occupy few compute units, are still walking.  Callers
+   on one of three internal streams of the context in turn, with buffers of
+   its own, after everything already enqueued on the context stream; its
+   completion joins the context stream once two more chunks have been put on
+   the other streams, at the next call of the library on this context other
+   than qrt_run (any call but the host-side setters), or at qrt_join.
+   Consecutive runs then overlap: the next runs start while the last
+   scattering orders of the previous ones, which occupy few compute units,
+   are still walking.  Callers
    that time qrt_run with their own events, or enqueue work that reads the
    images without calling the library first, call qrt_join before.  Disabling
-   joins whatever is pending.  qrt_run_static and qrt_batch_run never
-   overlap. */
+   joins whatever is pending.  qrt_batch_run puts its chunks on the streams
+   in the same way; qrt_run_static never overlaps. */
 int qrt_set_overlap(qrt_ctx *ctx, int enable);
 
 /* Late scattering orders in one launch (Sec. 2.2, 3.5: the same transport,
@@ -447,14 +449,15 @@ typedef struct {
 } qrt_batch_scene;
 
 /* Set the scenes of the batch (1 <= n_scenes <= QRT_BATCH_MAX_SCENES): copies
-   every mesh to the device, allocates the FP64 images of every scene (eight
+   every mesh to the device, allocates the FP64 images of every scene (sixteen
    accumulators each, folded when read) and zeroes them.  Replaces a previous
    batch.  Synchronous. */
 int qrt_batch_set(qrt_ctx *ctx, int n_scenes, const qrt_batch_scene *scenes);
 
 /* Transport every scene's packets once with point set `kind` and `seed` (as
    for qrt_set_sequence) at `precision` (QRT_FP32 or QRT_FP64), adding to the
-   batch images.  Asynchronous on the context stream. */
+   batch images.  Asynchronous on the context stream (its chunks overlapped on
+   the internal streams while qrt_set_overlap is on). */
 int qrt_batch_run(qrt_ctx *ctx, int kind, uint64_t seed, int precision);
 
 /* Copy the images of observer obs of scene `scene`, as qrt_read_images;

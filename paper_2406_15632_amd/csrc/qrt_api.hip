@@ -30,6 +30,11 @@ using namespace qrt;
 constexpr size_t kStaticScratchBytes = 36ull << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
+// Internal streams of overlapped runs: a run may start while the runs on the
+// other lanes are still in their last scattering orders.  Three measured best
+// (two: 1.15e9, three: 1.16e9, four: 1.12e9 packets/s on the benchmark disk).
+constexpr int kLanes = 3;
+
 struct qrt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -105,17 +110,18 @@ struct qrt_ctx {
     // kernel timing (qrt_set_timing)
     bool timing = false;
     KernelTimer timer;
-    // overlapped runs (qrt_set_overlap): chunks alternate between two lanes, each
+    // overlapped runs (qrt_set_overlap): chunks go round the kLanes lanes, each
     // an internal stream with its own transport buffers (lane 0 uses tb); a
-    // lane's completion event joins the context stream at the next call
+    // lane's completion event joins the context stream once the lanes have
+    // come round to it
     bool overlap = false;
-    hipStream_t lane[2] = {nullptr, nullptr};
-    hipEvent_t lane_done[2] = {nullptr, nullptr};
+    hipStream_t lane[kLanes] = {};
+    hipEvent_t lane_done[kLanes] = {};
     hipEvent_t fork = nullptr;
-    bool lane_pending[2] = {false, false};
+    bool lane_pending[kLanes] = {};
     int next_lane = 0;
-    TransportBuffers tb1 = {};
-    uint64_t tb1_packets = 0;
+    TransportBuffers tbl[kLanes - 1] = {};   // buffers of lanes 1 ..
+    uint64_t tbl_packets[kLanes - 1] = {};
     // late-order launch (qrt_set_tail): first order it takes, deferred-ray limit
     int tail_from = kTailFrom;
     uint64_t def_limit = 0;
@@ -162,21 +168,70 @@ int hip_fail(qrt_ctx *c, hipError_t e, const char *what)
 // The context stream waits for the overlapped runs still pending on the lanes.
 void join_lanes(qrt_ctx *c)
 {
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < kLanes; ++b)
         if (c->lane_pending[b]) {
             (void)hipStreamWaitEvent(c->stream, c->lane_done[b], 0);
             c->lane_pending[b] = false;
         }
 }
 
-// Finishes everything the context has enqueued: its stream and both lanes of
+// Finishes everything the context has enqueued: its stream and all lanes of
 // overlapped runs (a buffer is freed or reallocated only after this).
 int sync_all(qrt_ctx *c)
 {
     join_lanes(c);
     HIP_TRY(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize(), "sync");
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < kLanes; ++b)
         if (c->lane[b]) HIP_TRY(c, hipStreamSynchronize(c->lane[b]), "lane sync");
+    return QRT_OK;
+}
+
+// Overlapped runs: the lanes' streams and events, created on first use.
+int ensure_lanes(qrt_ctx *c)
+{
+    for (int b = 0; b < kLanes; ++b) {
+        if (!c->lane[b]) HIP_TRY(c, hipStreamCreateWithFlags(&c->lane[b], hipStreamNonBlocking), "lane stream");
+        if (!c->lane_done[b]) HIP_TRY(c, hipEventCreateWithFlags(&c->lane_done[b], hipEventDisableTiming), "lane event");
+    }
+    if (!c->fork) HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
+    return QRT_OK;
+}
+
+// The transport buffers of lane b and their packet capacity (lane 0 uses the
+// context's own set, which runs in stream order use too).
+TransportBuffers &lane_buffers(qrt_ctx *c, int b)
+{
+    return b == 0 ? c->tb : c->tbl[b - 1];
+}
+
+uint64_t &lane_capacity(qrt_ctx *c, int b)
+{
+    return b == 0 ? c->tb_packets : c->tbl_packets[b - 1];
+}
+
+// Lane b starts after everything enqueued on the context stream so far.
+int lane_fork(qrt_ctx *c, int b)
+{
+    HIP_TRY(c, hipEventRecord(c->fork, c->stream), "fork");
+    HIP_TRY(c, hipStreamWaitEvent(c->lane[b], c->fork, 0), "fork");
+    return QRT_OK;
+}
+
+// Lane b's chunk is enqueued and stays pending; the pending chunk of the lane
+// after it joins the context stream, so that the chunk which next uses that
+// lane (and its buffers) starts after it.  The newest kLanes - 1 chunks stay
+// pending, so that the next chunk starts beside their last scattering orders,
+// which occupy few compute units.
+int lane_close(qrt_ctx *c, int b)
+{
+    HIP_TRY(c, hipEventRecord(c->lane_done[b], c->lane[b]), "lane done");
+    c->lane_pending[b] = true;
+    const int nb = (b + 1) % kLanes;
+    if (c->lane_pending[nb]) {
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lane_done[nb], 0), "join");
+        c->lane_pending[nb] = false;
+    }
+    c->next_lane = nb;
     return QRT_OK;
 }
 
@@ -500,12 +555,12 @@ void qrt_destroy(qrt_ctx *c)
     if (!c) return;
     DeviceGuard dg(c->device);
     (void)sync_all(c);
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < kLanes; ++b) {
         if (c->lane[b]) (void)hipStreamDestroy(c->lane[b]);
         if (c->lane_done[b]) (void)hipEventDestroy(c->lane_done[b]);
     }
     if (c->fork) (void)hipEventDestroy(c->fork);
-    free_buffers(c->tb1);
+    for (int b = 0; b < kLanes - 1; ++b) free_buffers(c->tbl[b]);
     if (c->grid) (void)hipFree(c->grid);
     if (c->img) (void)hipFree(c->img);
     if (c->tables) (void)hipFree(c->tables);
@@ -824,33 +879,19 @@ int qrt_run(qrt_ctx *c, uint64_t first, uint64_t count)
         c->packets_run += count;
         return QRT_OK;
     }
-    // Overlapped: each chunk goes to the next lane, after everything already on the
-    // context stream; then the other lane's pending chunk joins the context stream.
-    // The newest chunk stays pending, so that the next run starts beside its last
-    // scattering orders, which occupy few compute units.
-    for (int b = 0; b < 2; ++b) {
-        if (!c->lane[b]) HIP_TRY(c, hipStreamCreateWithFlags(&c->lane[b], hipStreamNonBlocking), "lane stream");
-        if (!c->lane_done[b]) HIP_TRY(c, hipEventCreateWithFlags(&c->lane_done[b], hipEventDisableTiming), "lane event");
-    }
-    if (!c->fork) HIP_TRY(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming), "fork event");
+    // Overlapped: each chunk goes to the next lane (lane_fork, lane_close).
+    if ((rc = ensure_lanes(c))) return rc;
     for (uint64_t done = 0; done < count;) {
         const int b = c->next_lane;
-        TransportBuffers &T = b == 0 ? c->tb : c->tb1;
-        uint64_t &T_packets = b == 0 ? c->tb_packets : c->tb1_packets;
+        TransportBuffers &T = lane_buffers(c, b);
+        uint64_t &T_packets = lane_capacity(c, b);
         if ((rc = ensure_buffers(c, T, T_packets, count - done, c->n_obs, c->precision))) return rc;
         const uint64_t n = count - done < T_packets ? count - done : T_packets;
-        HIP_TRY(c, hipEventRecord(c->fork, c->stream), "fork");
-        HIP_TRY(c, hipStreamWaitEvent(c->lane[b], c->fork, 0), "fork");
+        if ((rc = lane_fork(c, b))) return rc;
         HIP_TRY(c, launch_transport(P, c->precision, c->kind, first + done, n, T, c->lane[b],
                                     c->timing ? &c->timer : nullptr),
                 "transport launch");
-        HIP_TRY(c, hipEventRecord(c->lane_done[b], c->lane[b]), "lane done");
-        c->lane_pending[b] = true;
-        if (c->lane_pending[b ^ 1]) {
-            HIP_TRY(c, hipStreamWaitEvent(c->stream, c->lane_done[b ^ 1], 0), "join");
-            c->lane_pending[b ^ 1] = false;
-        }
-        c->next_lane = b ^ 1;
+        if ((rc = lane_close(c, b))) return rc;
         done += n;
     }
     c->packets_run += count;
@@ -1761,7 +1802,7 @@ int qrt_batch_set(qrt_ctx *c, int n_scenes, const qrt_batch_scene *scenes)
 int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
 {
     if (!c) return QRT_INVALID_ARG;
-    join_lanes(c);   // a batch runs in stream order (overlapping its chunks measured no gain)
+    join_lanes(c);
     if (c->batch.empty()) return fail(c, QRT_BAD_STATE, "set the batch scenes first");
     if (kind < QRT_SOBOL || kind > QRT_SOBOL_OWEN) return fail(c, QRT_INVALID_ARG, "unknown sequence kind %d", kind);
     if (kind == QRT_FAURE) return fail(c, QRT_UNSUPPORTED, "Faure points are not served in batches");
@@ -1778,6 +1819,17 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     DeviceGuard dg(c->device);
     int rc = ensure_queues(c, c->batch_total, kBatchObs, precision);
     if (rc) return rc;
+    // overlapped runs: the chunks go round the lanes, each sized to fit every lane's buffers
+    const int lanes = c->overlap ? kLanes : 1;
+    if (lanes > 1 && (rc = ensure_lanes(c))) return rc;
+    size_t peel_bytes = c->tb.peel_bytes;
+    uint64_t lane_cap = c->tb_packets;
+    for (int b = 1; b < lanes; ++b) {
+        if ((rc = ensure_buffers(c, lane_buffers(c, b), lane_capacity(c, b), c->batch_total, kBatchObs, precision)))
+            return rc;
+        peel_bytes = std::min(peel_bytes, lane_buffers(c, b).peel_bytes);
+        lane_cap = std::min(lane_cap, lane_capacity(c, b));
+    }
     BatchParams P;
     memset(&P, 0, sizeof(P));
     P.scenes = c->batch_dev;
@@ -1790,15 +1842,28 @@ int qrt_batch_run(qrt_ctx *c, int kind, uint64_t seed, int precision)
     P.tail_from = c->tail_from;
     P.def_limit = c->def_limit;
     // the peel-ray buffer split into equal append regions (launch_batch checks that every chunk fits)
-    const size_t peel_capacity = c->tb.peel_bytes / peel_ray_bytes(precision);
+    const size_t peel_capacity = peel_bytes / peel_ray_bytes(precision);
     P.group_cap = (uint32_t)std::min<size_t>(peel_capacity / kPeelGroups, 0xFFFFFFFFu);
     // chunks of a multiple of 64 kPeelGroups packets put 64 kBatchObs rays per block in each group
     const uint64_t unit = 64 * kPeelGroups, per_unit = 64 * kBatchObs;
-    const uint64_t chunk = std::min<uint64_t>(c->tb_packets, (P.group_cap / per_unit) * unit);
+    const uint64_t chunk = std::min<uint64_t>(lane_cap, (P.group_cap / per_unit) * unit);
     if (chunk == 0) return fail(c, QRT_HIP_ERROR, "peel-ray buffer too small for a batch");
-    HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, 0, c->batch_total, c->tb, chunk, c->stream,
-                            c->timing ? &c->timer : nullptr),
-            "batch launch");
+    if (lanes == 1) {
+        HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, 0, c->batch_total, c->tb, chunk, c->stream,
+                                c->timing ? &c->timer : nullptr),
+                "batch launch");
+        return QRT_OK;
+    }
+    for (uint64_t done = 0; done < c->batch_total;) {
+        const uint64_t n = std::min<uint64_t>(chunk, c->batch_total - done);
+        const int b = c->next_lane;
+        if ((rc = lane_fork(c, b))) return rc;
+        HIP_TRY(c, launch_batch(P, c->batch_begin.data(), precision, kind, done, n, lane_buffers(c, b), chunk,
+                                c->lane[b], c->timing ? &c->timer : nullptr),
+                "batch launch");
+        if ((rc = lane_close(c, b))) return rc;
+        done += n;
+    }
     return QRT_OK;
 }
 

@@ -260,7 +260,7 @@ class Context:
         self._ck(self.lib.qrt_run(self.h, first, count))
 
     def set_overlap(self, enable: bool):
-        """Overlapped runs on two internal streams (see qrt_set_overlap)."""
+        """Overlapped runs on three internal streams (see qrt_set_overlap)."""
         self._ck(self.lib.qrt_set_overlap(self.h, int(enable)))
 
     def set_tail(self, first_order: int, max_deferred: int = 0):

@@ -259,8 +259,8 @@ def test_full_batch_fp64_sampled_against_oracle(ctx, Q, full_batch):
 def test_full_batch_fp32_equals_single_runs(ctx, Q, full_batch, overlap):
     """The workload as timed (FP32, full packet counts, 2^23 to 2^31 batch
     numbers in chunks) against single-scene runs of every scene; with the
-    overlap mode on, the batch still runs in stream order after the pending
-    runs."""
+    overlap mode on, the batch's chunks go round the internal streams after
+    the pending runs."""
     _say(f"full batch fp32 overlap={overlap}, {sum(s.n_packets for s in full_batch)} packets")
     single, cs = single_runs(ctx, Q, full_batch, Q.SOBOL, 0, Q.FP32)
     ctx.batch_set(full_batch)

@@ -452,8 +452,8 @@ def test_failed_image_allocation_leaves_no_observers(ctx, Q):
 
 
 def test_overlapped_runs(ctx, Q):
-    """Overlapped runs (two internal streams, completion joined at the next
-    call): consecutive calls sum to the oracle's run over all their packets;
+    """Overlapped runs (three internal streams, a chunk's completion joined
+    two chunks later or at the next other call): consecutive calls sum to the oracle's run over all their packets;
     a sequence of calls with several point sets, and a call of two chunks,
     equal the same calls in stream order up to the order of the FP64 image
     sums, with equal counters; a reset or new observers right after
