@@ -130,26 +130,32 @@ def committed_traffic(key: str = "bytes_per_step_launch"):
 
 
 def committed_walk_counters():
-    """The walk kernel's VALU, TA and TD busy and VALU lane share (fractions) from the committed
+    """The walk kernels' VALU, TA and TD busy and VALU lane share (fractions) from the committed
     counter summary, when it was taken with the committed traffic counters on the current kernel
-    sources (both come from one measurement run), else None."""
+    sources (both come from one measurement run), else None: k_walk with flights (order 1) and
+    k_walk of peel rays alone (the deferred scatterings)."""
     if committed_traffic() is None:
         return None
     try:
         lines = open(COUNTERS_FILE).read().splitlines()
     except OSError:
         return None
+    names = {"| `qrt::k_walk<float, true>`": "k_walk_flights", "| `qrt::k_walk<float, false>`": "k_walk_peel_rays"}
+    out = {}
     for ln in lines:
-        if ln.startswith("| `qrt::k_walk<float>`"):
-            cells = [c.strip() for c in ln.strip().strip("|").split("|")]
-            try:
-                _, _hit, busy, lanes, _wait, ta, td = cells[:7]
-                return {"valu_busy": float(busy) / 100, "valu_lanes_active": float(lanes) / 100,
-                        "ta_busy": float(ta) / 100, "td_busy": float(td) / 100,
-                        "source": "profiles/counters_disk128.md"}
-            except ValueError:
-                return None
-    return None
+        for prefix, name in names.items():
+            if ln.startswith(prefix):
+                cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+                try:
+                    _, _hit, busy, lanes, _wait, ta, td = cells[:7]
+                    out[name] = {"valu_busy": float(busy) / 100, "valu_lanes_active": float(lanes) / 100,
+                                 "ta_busy": float(ta) / 100, "td_busy": float(td) / 100}
+                except ValueError:
+                    return None
+    if not out:
+        return None
+    out["source"] = "profiles/counters_disk128.md"
+    return out
 
 
 def measured_copy_gbps(mib: int = 1024, reps: int = 5) -> float:

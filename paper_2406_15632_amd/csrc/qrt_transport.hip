@@ -627,7 +627,12 @@ __global__ void __launch_bounds__(256) k_def_keys(const uint32_t *__restrict__ r
 // --------------------------------------------------------------------------
 enum WalkItem : int { WI_NONE = 0, WI_PEEL = 1, WI_MOVE = 2 };
 
-template <typename R>
+// FLIGHTS = false builds the walk of peel rays alone (the deferred scatterings'
+// peel rays): without the stop test and the appends it needs 114 VGPRs in FP32
+// instead of 152, so four waves per SIMD are resident instead of three.  Those
+// rays come sorted by position and gain from the extra waves; the per-order
+// walks, whose flights gather incoherently, keep the full kernel at three.
+template <typename R, bool FLIGHTS>
 __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PacketState<R> *__restrict__ out, const PeelRay<R> *__restrict__ peels,
@@ -641,7 +646,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     const RayGrid<R> G = ray_grid<R>(P.grid);
     const uint64_t n_live = Q->n_live[in];
     const uint64_t n_peel = (uint64_t)P.n_obs * 64 * ((n_live + 63) / 64);
-    const uint64_t n_move = order < P.max_orders ? n_live : 0;
+    const uint64_t n_move = FLIGHTS && order < P.max_orders ? n_live : 0;
     const uint64_t total = n_peel + n_move;
     const uint64_t stride = block_stride(total >> kOrderBlockLog2);
     const size_t plane = (size_t)P.npix * (size_t)P.npix;
@@ -659,8 +664,8 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
     WorkPool pool;
     for (;;) {
         // packets whose flight stopped inside the mesh go to the next live list, in place pos
-        const bool append = W.done && kind == WI_MOVE && W.stopped;
-        const uint32_t pos = wave_append(append, &Q->n_live[in ^ 1]);
+        const bool append = FLIGHTS && W.done && kind == WI_MOVE && W.stopped;
+        const uint32_t pos = FLIGHTS ? wave_append(append, &Q->n_live[in ^ 1]) : 0u;
         const bool peel_done = W.done && kind == WI_PEEL;
         if (__ballot(peel_done) != 0) {
             double v[3] = {0.0, 0.0, 0.0};
@@ -677,7 +682,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
             const uint32_t key = peel_done ? obs * 3u * (uint32_t)plane + pix : 0u;
             wave_merge_add(peel_done, key, v[0], v[1], v[2], img_copy, plane, key_bits, s_merge[threadIdx.x >> 6]);
         }
-        if (W.done && kind == WI_MOVE) {
+        if (FLIGHTS && W.done && kind == WI_MOVE) {
             n_visits += W.visits;
             if (append) {
                 PacketState<R> s = pks[slot];
@@ -701,7 +706,7 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
                     walk_begin(W, G, r.p, o, WALK_EDGE, 0.0);
                     kind = WI_PEEL;
                 }
-            } else {
+            } else if constexpr (FLIGHTS) {
                 slot = (uint32_t)(item - n_peel);
                 const PacketState<R> *ps = pks + slot;
                 const R p0[3] = {ps->p[0], ps->p[1], ps->p[2]};
@@ -714,13 +719,13 @@ __global__ void __launch_bounds__(256) k_walk(const TransportParams P, int order
             if (pool.dry) break;
             continue;   // every item just taken was an invisible peel ray
         }
-        if (__ballot(kind == WI_MOVE) == 0) {
+        if (!FLIGHTS || __ballot(kind == WI_MOVE) == 0) {
             // no lane moves to a target: walks to the edge only
             for (;;) {
                 walk_batch_edge<R, kFlightBatch>(W, G);
                 if (__popcll(__ballot(W.done || kind == WI_NONE)) >= kWaveRefill) break;
             }
-        } else {
+        } else if constexpr (FLIGHTS) {
             for (;;) {
                 walk_batch<R, kFlightBatch>(W, G);
                 if (__popcll(__ballot(W.done || kind == WI_NONE)) >= kWaveRefill) break;
@@ -1041,11 +1046,12 @@ template <typename R, int KIND, int SRC>
 static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t count, const TransportBuffers &B,
                             hipStream_t st, KernelTimer *T)
 {
-    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_net = 0, nb_tail = 0, nb_tail_sur = 0;
+    static int nb_first = 0, nb_scatter = 0, nb_walk = 0, nb_walk_peels = 0, nb_net = 0, nb_tail = 0, nb_tail_sur = 0;
     if (!nb_first) {
         nb_first = resident_blocks_of(k_first<R, KIND, SRC>);
         nb_scatter = resident_blocks_of(k_scatter<R, KIND, SRC, false>);
-        nb_walk = resident_blocks_of(k_walk<R>);
+        nb_walk = resident_blocks_of(k_walk<R, true>);
+        nb_walk_peels = resident_blocks_of(k_walk<R, false>);
         nb_net = resident_blocks_of(k_peel_net);
         nb_tail = resident_blocks_of(k_tail<R, KIND, SRC, false>);
         nb_tail_sur = resident_blocks_of(k_tail<R, KIND, SRC, true>);
@@ -1108,7 +1114,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
                 hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
                                    order, in, (const PeelRay<R> *)peels, B.q);
             else
-                hipLaunchKernelGGL((k_walk<R>), dim3(wb), dim3(256), 0, st, P, order,
+                hipLaunchKernelGGL((k_walk<R, true>), dim3(wb), dim3(256), 0, st, P, order,
                                    (const PacketState<R> *)state_list<R>(B, in), in, state_list<R>(B, in ^ 1),
                                    (const PeelRay<R> *)peels, B.q);
         }
@@ -1175,7 +1181,7 @@ static hipError_t run_chunk(const TransportParams &P, uint64_t first, uint32_t c
                 hipLaunchKernelGGL((k_walk_peel_lds<R>), dim3(lds_blocks), dim3(kPeelLdsThreads), tile_bytes, st, P,
                                    P.max_orders, din, (const PeelRay<R> *)peels, B.q);
             else
-                hipLaunchKernelGGL((k_walk<R>), dim3(nb_walk), dim3(256), 0, st, P, P.max_orders,
+                hipLaunchKernelGGL((k_walk<R, false>), dim3(nb_walk_peels), dim3(256), 0, st, P, P.max_orders,
                                    (const PacketState<R> *)state_list<R>(B, din), din, state_list<R>(B, in),
                                    (const PeelRay<R> *)peels, B.q);
         }
