@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--no-workloads", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-batch-small", action="store_true", help="skip the batch of 256 small scenes")
+    ap.add_argument("--no-batch-overlap", action="store_true",
+                    help="time the batches in stream order only (kernel traces of whole batch runs)")
     return ap.parse_args()
 
 
@@ -359,7 +361,7 @@ def other_workloads(qrt, stream):
     return res
 
 
-def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int = 64, **draw):
+def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int = 64, overlap: bool = True, **draw):
     """The batched workload: 64 uneven scenes drawn from `seed` (grids 32^3 to
     192^3, 2^16 to 2^24 packets, tau 0.1 to 20, g 0 to 0.8, albedo 0.3 to 0.9,
     envelope or disk, point source or sphere star, 1 to 4 observers, 1 to 20
@@ -394,14 +396,16 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
     batch_s = e0.elapsed_time(e1) * 1e-3 / steps
     cnt = ctx.counters()
     # the batch's chunks overlapped on the context's internal streams
-    ctx.set_overlap(True)
-    e0.record(stream)
-    for _ in range(steps):
-        ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)
-    ctx.join()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    batch_ov_s = e0.elapsed_time(e1) * 1e-3 / steps
+    batch_ov_s = 0.0
+    if overlap:
+        ctx.set_overlap(True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.batch_run(qrt.SOBOL, 0, qrt.FP32)
+        ctx.join()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        batch_ov_s = e0.elapsed_time(e1) * 1e-3 / steps
     # the same scenes one after another
     seq = qrt.Context(0, stream.cuda_stream)
     for sc, g in zip(bs[:2], grids[:2]):             # warm-up of the single-scene kernels
@@ -409,11 +413,11 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
         seq.run(1, min(sc.n_packets, 1 << 16))
     torch.cuda.synchronize()
     seq_s = {}
-    for overlap in (False, True):
-        seq.set_overlap(overlap)
+    for seq_overlap in (False, True):
+        seq.set_overlap(seq_overlap)
         # in stream order, also the runs alone: events around each run leave out
         # the scene changes between them (mesh upload, image buffers)
-        runs = [] if overlap else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        runs = [] if seq_overlap else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                                    for _ in bs]
         e0.record(stream)
         for i, (sc, g) in enumerate(zip(bs, grids)):
@@ -426,7 +430,7 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
         seq.join()
         e1.record(stream)
         torch.cuda.synchronize()
-        seq_s["overlapped" if overlap else "stream_order"] = e0.elapsed_time(e1) * 1e-3
+        seq_s["overlapped" if seq_overlap else "stream_order"] = e0.elapsed_time(e1) * 1e-3
         if runs:
             seq_s["runs_only"] = sum(a.elapsed_time(b) for a, b in runs) * 1e-3
     ctx.close()
@@ -438,9 +442,10 @@ def batch_section(qrt, stream, seed: int = 2406, steps: int = 2, n_scenes: int =
         "sequential_overlapped_packets_per_s": total / seq_s["overlapped"],
         "sequential_overlapped_ms": seq_s["overlapped"] * 1e3,
         "speedup": seq_s["stream_order"] / batch_s,
-        "batch_overlapped_packets_per_s": total / batch_ov_s, "batch_overlapped_ms": batch_ov_s * 1e3,
+        "batch_overlapped_packets_per_s": total / batch_ov_s if overlap else None,
+        "batch_overlapped_ms": batch_ov_s * 1e3 if overlap else None,
         "speedup_vs_sequential_overlapped": seq_s["overlapped"] / batch_s,
-        "speedup_overlapped_vs_sequential_overlapped": seq_s["overlapped"] / batch_ov_s,
+        "speedup_overlapped_vs_sequential_overlapped": seq_s["overlapped"] / batch_ov_s if overlap else None,
         "sequential_runs_only_ms": seq_s["runs_only"] * 1e3,
         "speedup_vs_sequential_runs_only": seq_s["runs_only"] / batch_s,
         "visits_per_packet": cnt["visits"] / cnt["packets"],
@@ -846,12 +851,12 @@ def main():
         result["workloads"] = other_workloads(qrt, stream)
         result["sphere_star"] = sphere_star_section(qrt, stream)
     if not args.no_batch:
-        result["batch"] = batch_section(qrt, stream)
+        result["batch"] = batch_section(qrt, stream, overlap=not args.no_batch_overlap)
         # many small scenes, where one scene does not fill the GPU: 256 scenes,
         # grids 32^3 to 96^3, 2^10 to 2^14 packets each
         if not args.no_batch_small:
-            result["batch_small"] = batch_section(qrt, stream, n_scenes=256, sizes=(32, 96, 16),
-                                                  log2_packets=(10.0, 14.0))
+            result["batch_small"] = batch_section(qrt, stream, n_scenes=256, overlap=not args.no_batch_overlap,
+                                                  sizes=(32, 96, 16), log2_packets=(10.0, 14.0))
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sc, args.cpu_sample)
     ctx.close()

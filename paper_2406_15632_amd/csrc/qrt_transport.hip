@@ -840,7 +840,9 @@ __global__ void __launch_bounds__(kPeelLdsThreads) k_walk_peel_lds(const Transpo
 // the arithmetic of the per-order launches, so images differ only in the order
 // of the FP64 sums.
 template <typename R, int KIND, int SRC, bool SUR>
-__global__ void __launch_bounds__(256) k_tail(const TransportParams P, int order0,
+// three waves per SIMD in FP32 (168 VGPRs, no spills; the compiler's own choice
+// of 173 left two)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 3 : 1))) k_tail(const TransportParams P, int order0,
                                               const PacketState<R> *__restrict__ pks, int in,
                                               PacketState<R> *__restrict__ states, uint32_t state_cap,
                                               uint32_t *__restrict__ region_keys, Queues *__restrict__ Q)
