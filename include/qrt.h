@@ -170,11 +170,11 @@ int qrt_run(qrt_ctx *ctx, uint64_t first_index, uint64_t count);
    than qrt_run (any call but the host-side setters), or at qrt_join.
    Consecutive runs then overlap: the next runs start while the last
    scattering orders of the previous ones, which occupy few compute units,
-   are still walking.  Callers
-   that time qrt_run with their own events, or enqueue work that reads the
-   images without calling the library first, call qrt_join before.  Disabling
-   joins whatever is pending.  qrt_batch_run puts its chunks on the streams
-   in the same way; qrt_run_static never overlaps. */
+   are still walking.  Callers that time qrt_run with their own events, or
+   enqueue work that reads the images without calling the library first,
+   call qrt_join before.  Disabling joins whatever is pending.  qrt_batch_run
+   puts its chunks on the streams in the same way; qrt_run_static never
+   overlaps. */
 int qrt_set_overlap(qrt_ctx *ctx, int enable);
 
 /* Late scattering orders in one launch (Sec. 2.2, 3.5: the same transport,
